@@ -1,0 +1,178 @@
+/*
+ * flashviterbi.h -- C ABI of the MI355X (gfx950) FLASH Viterbi library.
+ *
+ * Problem (Sec. III-A of the FLASH Viterbi paper): an HMM with K hidden
+ * states, initial scores log pi[K], transition scores log A[K][K] and
+ * per-step emission scores log B_t[K] for t = 0..T-1.  Decoding returns the
+ * optimal state sequence q*_0..q*_{T-1} (int32) and its log score (float32):
+ *
+ *   delta_0(j) = log pi_j + log B_0(j)
+ *   delta_t(j) = max_i (delta_{t-1}(i) + log A(i, j)) + log B_t(j)
+ *   psi_t(j)   = lowest i attaining that max
+ *   q*_{T-1}   = lowest arg max_j delta_{T-1}(j),  q*_t = psi_{t+1}(q*_{t+1})
+ *
+ * Every value is an IEEE binary32 log-score and every candidate is one
+ * float32 add rounded to nearest even; all entry points return the same path
+ * and bit-identical scores as a plain sequential float32 evaluation of those
+ * formulas (ties to the lowest index; log B added after the max).
+ *
+ * Conventions for every entry point
+ *  - Array arguments are DEVICE pointers unless marked "host".  The caller
+ *    owns all buffers.  The library never allocates device memory in a
+ *    decode call: scratch space comes from the caller's workspace `ws` of at
+ *    least fv_workspace_size() bytes (256-byte aligned).
+ *  - Calls only enqueue work on `stream`; they do not synchronise it.
+ *    Device buffers must stay valid until the stream has run the work.
+ *  - Layouts (row-major):
+ *      log_a[i*K + j]   = log A(i -> j), row = source state
+ *      log_b[t*ld + j]  = log B_t(j), ld >= K
+ *      log_pi[j]        (may be NULL: no initial term)
+ *  - Inputs must be finite or -inf.  NaN / +inf give unspecified paths.
+ *  - Host-detectable errors are returned synchronously.  Data-dependent
+ *    outcomes go to the optional device array `status` (one int32 per
+ *    sequence): FV_OK, FV_E_INFEASIBLE (best score is -inf; the path is
+ *    filled with -1), FV_W_BEAM_FALLBACK (a beam subtask was re-decoded
+ *    exactly), FV_E_WORKSPACE / FV_E_DEVICE (the decode did not run or did
+ *    not finish; outputs unspecified).
+ *  - One call at a time per workspace; independent workspaces may run
+ *    concurrently on different streams.
+ */
+#ifndef FLASHVITERBI_H
+#define FLASHVITERBI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* fv_stream_t; /* a hipStream_t (NULL = default stream) */
+
+typedef enum {
+    FV_OK = 0,
+    FV_E_INVALID_ARG = -1,
+    FV_E_UNSUPPORTED = -2,
+    FV_E_WORKSPACE = -3,
+    FV_E_DEVICE = -4,
+    FV_E_INFEASIBLE = -5,
+    FV_W_BEAM_FALLBACK = 1
+} fv_status;
+
+enum { FV_DENSE = 0, FV_CSR = 1 };
+enum { FV_VANILLA = 0, FV_FLASH = 1, FV_BEAM = 2 };
+
+/* Transition model.  FV_DENSE: log_a[K*K] (device).  FV_CSR: out-edges of
+ * each source, row_ptr[K+1], col[nnz] (destination), val[nnz] (device);
+ * missing edges are -inf. */
+typedef struct {
+    int32_t kind;
+    int32_t K;
+    const float* log_a;
+    const int32_t* row_ptr;
+    const int32_t* col;
+    const float* val;
+    int64_t nnz;
+} fv_trans;
+
+/* One sequence of a batch (the array of these lives on the device). */
+typedef struct {
+    int32_t model;        /* index into the models array                  */
+    int32_t T;            /* length, >= 0 (T = 0: nothing decoded, score 0) */
+    const float* log_b;   /* [T][ld] emission scores                      */
+    int64_t ld;
+    int32_t* path;        /* [T] output                                   */
+    float* score;         /* [1] output                                   */
+} fv_seq;
+
+/* Bytes of workspace a decode needs.  method: FV_VANILLA / FV_FLASH /
+ * FV_BEAM.  models/n_models describe the transition models; T_host[n_seqs]
+ * and model_host[n_seqs] (host; model_host may be NULL when n_models == 1)
+ * give each sequence's length and model.  P and B as in the decode calls.
+ * The value depends only on these arguments.  (Sizes are the memory figures
+ * the library reports: Sec. VII-B's "all data structures used during
+ * decoding".) */
+fv_status fv_workspace_size(int32_t method, const fv_trans* models, int32_t n_models,
+                            const int32_t* T_host, const int32_t* model_host, int32_t n_seqs,
+                            int32_t P, int32_t B, size_t* bytes);
+
+/* Vanilla Viterbi (Sec. III-A): full backpointer table (K x T, packed) in
+ * the workspace, then backtracking.  path[T] and score[1] are device
+ * outputs; status may be NULL. */
+fv_status fv_decode_vanilla(const fv_trans* A, const float* log_pi, const float* log_b,
+                            int64_t ld, int32_t T, int32_t* path, float* score,
+                            int32_t* status, uint32_t flags, void* ws, size_t ws_bytes,
+                            fv_stream_t stream);
+
+/* FLASH Viterbi (Alg. 1 and 2; Sec. V-A/V-B): one pass over the sequence
+ * keeping only the P'-1 boundary states' pointers, a P'-way split
+ * P' = min(max(P,2),T), then midpoint bisection of the independent
+ * segments, each started from its single known boundary state.  The
+ * boundary state's float32 score is carried into the segment (retained
+ * pruning, Def. 3), so the result equals fv_decode_vanilla bit for bit for
+ * every P.  P <= 0 selects P automatically. */
+fv_status fv_decode_flash(const fv_trans* A, const float* log_pi, const float* log_b,
+                          int64_t ld, int32_t T, int32_t P, int32_t* path, float* score,
+                          int32_t* status, uint32_t flags, void* ws, size_t ws_bytes,
+                          fv_stream_t stream);
+
+/* FLASH-BS (Sec. V-C): the FLASH task structure where every step keeps only
+ * the B best states, ranked by (score desc, state asc).  B >= K behaves as
+ * FLASH.  For B < K the result depends on P (each segment restarts its beam
+ * from its boundary state), so P >= 1 is required.  A task's last step only
+ * evaluates its known end state; if no beam state reaches it the task is
+ * re-decoded exactly and status gets FV_W_BEAM_FALLBACK.  score is the
+ * step-by-step re-sum of the returned path. */
+fv_status fv_decode_beam(const fv_trans* A, const float* log_pi, const float* log_b,
+                         int64_t ld, int32_t T, int32_t B, int32_t P, int32_t* path,
+                         float* score, int32_t* status, uint32_t flags, void* ws,
+                         size_t ws_bytes, fv_stream_t stream);
+
+/* Many sequences, uneven lengths, one persistent launch.  models: host
+ * array [n_models]; log_pi: host array of n_models device pointers (entries
+ * may be NULL); seqs_dev: device array [n_seqs]; T_host / model_host: host
+ * copies of each sequence's T and model (used to lay out the workspace; the
+ * device copies must agree, otherwise every status is FV_E_INVALID_ARG).
+ * method FV_VANILLA / FV_FLASH / FV_BEAM with P, B as above.  Each
+ * sequence's result equals the single-sequence call's. */
+fv_status fv_decode_batch(const fv_trans* models, const float* const* log_pi, int32_t n_models,
+                          const fv_seq* seqs_dev, const int32_t* T_host,
+                          const int32_t* model_host, int32_t n_seqs, int32_t method,
+                          int32_t P, int32_t B, int32_t* status, uint32_t flags, void* ws,
+                          size_t ws_bytes, fv_stream_t stream);
+
+/* Gradient of the Viterbi scores S_b (the decoded path's summed log-scores)
+ * given upstream gradients grad_score[n]:
+ *   grad_log_b[b][t][j] = grad_score[b] * [j == paths[b][t]]   (t < lengths[b], else 0)
+ *   grad_log_a[i][j]    = sum over b ascending of fl(grad_score[b] * c_b(i,j)),
+ *                         c_b(i,j) = #{t >= 1 : (q_{b,t-1}, q_{b,t}) = (i, j)}
+ *   grad_log_pi[j]      = sum over b ascending of grad_score[b] * [q_{b,0} == j]
+ * paths is [n][Tmax] int32, lengths [n].  Any of the three outputs may be
+ * NULL.  accumulate != 0 adds the result to the outputs' current contents
+ * (old + total for the shared ones).  Deterministic: identical bits on
+ * every run. */
+fv_status fv_viterbi_backward(int32_t K, int32_t n_seqs, int32_t Tmax, const int32_t* lengths,
+                              const int32_t* paths, const float* grad_score, float* grad_log_b,
+                              float* grad_log_a, float* grad_log_pi, int32_t accumulate,
+                              void* ws, size_t ws_bytes, fv_stream_t stream);
+
+/* Workspace bytes for fv_viterbi_backward. */
+fv_status fv_backward_workspace_size(int32_t K, int32_t n_seqs, int32_t Tmax, size_t* bytes);
+
+/* score_out[b] = step-by-step float32 re-sum of paths[b] (dense model):
+ * s = log pi[q0] + log B_0[q0]; s = (s + log A[q_{t-1}][q_t]) + log B_t[q_t]. */
+fv_status fv_rescore(const fv_trans* A, const float* log_pi, const fv_seq* seqs_dev,
+                     int32_t n_seqs, float* score_out, fv_stream_t stream);
+
+/* Discrete-emission HMMs: log_b[t*ld + j] = log_e[j*V + obs[t]]. */
+fv_status fv_gather_emissions(int32_t K, int32_t V, const float* log_e, const int32_t* obs,
+                              int32_t T, float* log_b, int64_t ld, fv_stream_t stream);
+
+const char* fv_status_str(fv_status s);
+const char* fv_last_error(void);   /* thread-local message of the last failure */
+int32_t fv_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FLASHVITERBI_H */

@@ -1,0 +1,13 @@
+"""FLASH Viterbi decoding on MI355X (gfx950): HIP kernels behind a C ABI.
+
+The compute path lives in libflashviterbi.so (built from csrc/ by
+``paper_2510_19301_amd.build.build()``); this package only marshals torch
+tensors into its C entry points.
+"""
+from ._lib import (FV_OK, FV_E_INVALID_ARG, FV_E_UNSUPPORTED, FV_E_WORKSPACE, FV_E_DEVICE,
+                   FV_E_INFEASIBLE, FV_W_BEAM_FALLBACK, FvError, lib)
+from .decode import Batch, decode, decode_batch, dense_model, workspace_bytes
+
+__all__ = ["FV_OK", "FV_E_INVALID_ARG", "FV_E_UNSUPPORTED", "FV_E_WORKSPACE", "FV_E_DEVICE",
+           "FV_E_INFEASIBLE", "FV_W_BEAM_FALLBACK", "FvError", "lib", "Batch", "decode",
+           "decode_batch", "dense_model", "workspace_bytes"]

@@ -1,0 +1,319 @@
+// Host side of the C ABI: argument checks, workspace layout, launches.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "fv_internal.h"
+
+namespace fv {
+extern "C" __global__ void fv_engine_kernel(const float* __restrict__ Ap, EngineArgs a);
+extern "C" __global__ void fv_prep_dense_kernel(const float* __restrict__ log_a, int32_t K, int32_t Kp,
+                                                float* __restrict__ Ap);
+extern "C" __global__ void fv_setup_kernel(EngineArgs a, SetupArgs sa);
+extern "C" __global__ void fv_finish_kernel(EngineArgs a, int32_t* status);
+}  // namespace fv
+
+using namespace fv;
+
+static thread_local std::string g_last_error;
+
+static fv_status fail(fv_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+static fv_status fail(fv_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                       \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(FV_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));       \
+    } while (0)
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int32_t kMaxDenseK = 65535;   // packed uint16 backpointers
+
+struct Region {
+    size_t off = 0, bytes = 0;
+};
+
+struct DenseLayout {
+    int32_t method = 0, K = 0, Kp = 0, n_seqs = 0, n_slots = 0, max_rows = 0;
+    int64_t sum_T = 0, sum_root = 0, sum_psi = 0, n_tasks = 0, slot_floats = 0;
+    int32_t has_anc = 0;
+    Region Ap, seq1, seqinfo, keys, state, rows_full, rows_light, queue, free_stack, slots,
+        alpha, root, psi;
+    size_t total = 0;
+};
+
+size_t put(size_t& cur, Region& r, size_t bytes) {
+    r.off = (cur + kAlign - 1) / kAlign * kAlign;
+    r.bytes = bytes;
+    cur = r.off + bytes;
+    return r.off;
+}
+
+// Workspace layout of a dense decode.  Depends only on the arguments, so
+// fv_workspace_size and the decode calls agree.
+fv_status plan_dense(int32_t method, int32_t K, const int32_t* T_host, int32_t n_seqs, int32_t P,
+                     bool single, DenseLayout& L) {
+    L = DenseLayout{};
+    L.method = method;
+    L.K = K;
+    L.Kp = (int32_t)round_up(K, kKAlign);
+    L.n_seqs = n_seqs;
+    int64_t nonempty = 0;
+    for (int32_t b = 0; b < n_seqs; ++b) {
+        const int32_t T = T_host[b];
+        if (T < 0) return fail(FV_E_INVALID_ARG, "sequence %d has negative length %d", b, T);
+        L.sum_T += T;
+        if (T == 0) continue;
+        ++nonempty;
+        if (method == FV_VANILLA) {
+            L.sum_psi += (int64_t)T * K;
+            L.n_tasks += 1;
+        } else {
+            const int32_t pp = eff_parallelism(T, P);
+            L.sum_root += 2 * (int64_t)(pp - 1);
+            L.n_tasks += T - pp + 1;
+        }
+    }
+    L.has_anc = method == FV_FLASH;
+    L.slot_floats = (int64_t)L.Kp * (method == FV_FLASH ? 5 : 2);
+    const int64_t slot_bytes = L.slot_floats * 4;
+    int64_t slots;
+    if (method == FV_VANILLA) {
+        slots = nonempty;
+    } else {
+        // rows in flight: every root at once, then as many subtasks as a
+        // bounded budget of row buffers allows (parallelism vs memory)
+        const int64_t budget = (int64_t)128 << 20;
+        const int64_t cap = std::max<int64_t>(256, std::min<int64_t>(4096, budget / slot_bytes));
+        slots = std::min<int64_t>(L.n_tasks, std::max<int64_t>(std::min<int64_t>(nonempty, 1 << 16), cap));
+    }
+    if (slots < 1) slots = 1;
+    if (slots > (1 << 26)) return fail(FV_E_UNSUPPORTED, "too many concurrent sequences");
+    L.n_slots = (int32_t)slots;
+    L.max_rows = L.n_slots;
+    size_t cur = 0;
+    put(cur, L.Ap, L.Kp != K ? (size_t)L.Kp * L.Kp * 4 : 0);  // padded copy only when needed
+    put(cur, L.seq1, single ? sizeof(fv_seq) : 0);
+    put(cur, L.seqinfo, (size_t)std::max(n_seqs, 1) * sizeof(SeqInfo));
+    put(cur, L.keys, (size_t)std::max(n_seqs, 1) * 8);
+    put(cur, L.state, sizeof(EngineState));
+    put(cur, L.rows_full, (size_t)2 * L.max_rows * sizeof(Row));
+    put(cur, L.rows_light, (size_t)2 * L.max_rows * sizeof(Row));
+    put(cur, L.queue, (size_t)std::max<int64_t>(L.n_tasks, 1) * sizeof(Task));
+    put(cur, L.free_stack, (size_t)L.n_slots * 4);
+    put(cur, L.slots, (size_t)L.n_slots * slot_bytes);
+    put(cur, L.alpha, method == FV_FLASH ? (size_t)L.sum_T * 4 : 0);
+    put(cur, L.root, (size_t)L.sum_root * L.Kp * 4);
+    put(cur, L.psi, (size_t)L.sum_psi * 2);
+    L.total = (cur + kAlign - 1) / kAlign * kAlign;
+    return FV_OK;
+}
+
+fv_status check_dense_model(const fv_trans* A) {
+    if (!A) return fail(FV_E_INVALID_ARG, "null transition model");
+    if (A->kind != FV_DENSE) return fail(FV_E_UNSUPPORTED, "only dense transition models are supported by this entry point");
+    if (A->K < 1) return fail(FV_E_INVALID_ARG, "K must be >= 1 (got %d)", A->K);
+    if (A->K > kMaxDenseK) return fail(FV_E_UNSUPPORTED, "K=%d exceeds %d", A->K, kMaxDenseK);
+    if (!A->log_a) return fail(FV_E_INVALID_ARG, "null log_a");
+    return FV_OK;
+}
+
+struct DeviceInfo {
+    int cus = 0;
+    int engine_blocks_per_cu = 0;
+};
+
+fv_status device_info(DeviceInfo& di) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    hipDeviceProp_t p;
+    HIP_TRY(hipGetDeviceProperties(&p, dev));
+    di.cus = p.multiProcessorCount;
+    int nb = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(fv_engine_kernel),
+                                                         kBlock, 0));
+    di.engine_blocks_per_cu = nb;
+    if (nb < 1) return fail(FV_E_DEVICE, "engine kernel cannot be resident");
+    return FV_OK;
+}
+
+__global__ void write_seq_kernel(fv_seq* dst, fv_seq v) { *dst = v; }
+
+fv_status run_dense(int32_t method, const fv_trans* A, const float* log_pi, const fv_seq* seqs_dev,
+                    const int32_t* T_host, int32_t n_seqs, int32_t P, const fv_seq* single,
+                    int32_t* status, void* ws, size_t ws_bytes, hipStream_t stream) {
+    fv_status rc = check_dense_model(A);
+    if (rc != FV_OK) return rc;
+    DenseLayout L;
+    rc = plan_dense(method, A->K, T_host, n_seqs, P, single != nullptr, L);
+    if (rc != FV_OK) return rc;
+    if (!ws || ws_bytes < L.total)
+        return fail(FV_E_WORKSPACE, "workspace of %zu bytes is smaller than the %zu bytes required", ws_bytes, L.total);
+    if (reinterpret_cast<uintptr_t>(ws) % kAlign)
+        return fail(FV_E_INVALID_ARG, "workspace must be %zu-byte aligned", kAlign);
+    DeviceInfo di;
+    rc = device_info(di);
+    if (rc != FV_OK) return rc;
+
+    char* w = static_cast<char*>(ws);
+    auto at = [&](const Region& r) { return static_cast<void*>(w + r.off); };
+    if (single) {
+        hipLaunchKernelGGL(write_seq_kernel, dim3(1), dim3(1), 0, stream, static_cast<fv_seq*>(at(L.seq1)), *single);
+        seqs_dev = static_cast<const fv_seq*>(at(L.seq1));
+    }
+    const float* Ap = A->log_a;
+    if (L.Kp != A->K) {
+        float* pad = static_cast<float*>(at(L.Ap));
+        const int64_t cells = (int64_t)L.Kp * L.Kp;
+        hipLaunchKernelGGL(fv_prep_dense_kernel, dim3((unsigned)((cells + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                           stream, A->log_a, A->K, L.Kp, pad);
+        Ap = pad;
+    }
+
+    EngineArgs a{};
+    a.K = A->K;
+    a.Kp = L.Kp;
+    a.log_pi = log_pi;
+    a.Acol = Ap;
+    a.seqs = static_cast<SeqInfo*>(at(L.seqinfo));
+    a.n_seqs = n_seqs;
+    a.method = method;
+    a.slot_base = static_cast<float*>(at(L.slots));
+    a.slot_floats = L.slot_floats;
+    a.n_slots = L.n_slots;
+    a.has_anc = L.has_anc;
+    a.alpha_at = static_cast<float*>(at(L.alpha));
+    a.root_copy = static_cast<float*>(at(L.root));
+    a.psi16 = static_cast<uint16_t*>(at(L.psi));
+    a.keys = static_cast<unsigned long long*>(at(L.keys));
+    a.st = static_cast<EngineState*>(at(L.state));
+    a.rows_full = static_cast<Row*>(at(L.rows_full));
+    a.rows_light = static_cast<Row*>(at(L.rows_light));
+    a.max_rows = L.max_rows;
+    a.queue = static_cast<Task*>(at(L.queue));
+    a.q_cap = std::max<int64_t>(L.n_tasks, 1);
+    a.free_stack = static_cast<int32_t*>(at(L.free_stack));
+    const int per_cu = std::min(2, std::max(1, di.engine_blocks_per_cu - 1));
+    a.n_compute_blocks = std::max(1, std::min(di.cus * per_cu, di.cus * di.engine_blocks_per_cu - 1));
+    a.spin_limit = (int64_t)1 << 24;
+    a.max_steps = 8 * (L.sum_T + L.n_tasks) + 4096;
+
+    SetupArgs sa{};
+    sa.seqs_dev = seqs_dev;
+    sa.n_seqs = n_seqs;
+    sa.P = P;
+    sa.host_sum_T = L.sum_T;
+    sa.host_sum_root = L.sum_root;
+    sa.host_sum_psi = L.sum_psi;
+    sa.kind = method == FV_VANILLA ? KIND_VANILLA : KIND_ROOT;
+    sa.K = A->K;
+    hipLaunchKernelGGL(fv_setup_kernel, dim3(1), dim3(kBlock), 0, stream, a, sa);
+
+    if (n_seqs > 0) {
+        void* args[] = {&Ap, &a};
+        HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(fv_engine_kernel),
+                                           dim3(a.n_compute_blocks + 1), dim3(kBlock), args, 0, stream));
+        hipLaunchKernelGGL(fv_finish_kernel, dim3((n_seqs + kBlock - 1) / kBlock), dim3(kBlock), 0, stream,
+                           a, status);
+    }
+    HIP_TRY(hipGetLastError());
+    return FV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t fv_abi_version(void) { return 1; }
+
+const char* fv_last_error(void) { return g_last_error.c_str(); }
+
+const char* fv_status_str(fv_status s) {
+    switch (s) {
+        case FV_OK: return "FV_OK";
+        case FV_E_INVALID_ARG: return "FV_E_INVALID_ARG: invalid argument";
+        case FV_E_UNSUPPORTED: return "FV_E_UNSUPPORTED: size or model kind beyond this build";
+        case FV_E_WORKSPACE: return "FV_E_WORKSPACE: workspace too small";
+        case FV_E_DEVICE: return "FV_E_DEVICE: HIP launch/runtime failure or engine watchdog";
+        case FV_E_INFEASIBLE: return "FV_E_INFEASIBLE: best score is -inf";
+        case FV_W_BEAM_FALLBACK: return "FV_W_BEAM_FALLBACK: a beam subtask was re-decoded exactly";
+    }
+    return "unknown fv_status";
+}
+
+fv_status fv_workspace_size(int32_t method, const fv_trans* models, int32_t n_models,
+                            const int32_t* T_host, const int32_t* model_host, int32_t n_seqs,
+                            int32_t P, int32_t B, size_t* bytes) {
+    (void)model_host;
+    (void)B;
+    if (!bytes) return fail(FV_E_INVALID_ARG, "null bytes");
+    if (n_models != 1) return fail(FV_E_UNSUPPORTED, "exactly one model per call is supported");
+    if (n_seqs < 0 || (n_seqs > 0 && !T_host)) return fail(FV_E_INVALID_ARG, "bad sequence list");
+    fv_status rc = check_dense_model(models);
+    if (rc != FV_OK) return rc;
+    if (method != FV_VANILLA && method != FV_FLASH) return fail(FV_E_UNSUPPORTED, "method %d", method);
+    DenseLayout L;
+    // single-sequence calls reserve room for their device descriptor too
+    rc = plan_dense(method, models->K, T_host, n_seqs, P, n_seqs == 1, L);
+    if (rc != FV_OK) return rc;
+    *bytes = L.total;
+    return FV_OK;
+}
+
+fv_status fv_decode_vanilla(const fv_trans* A, const float* log_pi, const float* log_b, int64_t ld,
+                            int32_t T, int32_t* path, float* score, int32_t* status, uint32_t flags,
+                            void* ws, size_t ws_bytes, fv_stream_t stream) {
+    (void)flags;
+    if (T < 1) return fail(FV_E_INVALID_ARG, "T must be >= 1 (got %d)", T);
+    if (!A || !log_b || !path || !score) return fail(FV_E_INVALID_ARG, "null argument");
+    if (ld < A->K) return fail(FV_E_INVALID_ARG, "ld=%lld < K=%d", (long long)ld, A->K);
+    fv_seq s{0, T, log_b, ld, path, score};
+    return run_dense(FV_VANILLA, A, log_pi, nullptr, &T, 1, 1, &s, status, ws, ws_bytes,
+                     reinterpret_cast<hipStream_t>(stream));
+}
+
+fv_status fv_decode_flash(const fv_trans* A, const float* log_pi, const float* log_b, int64_t ld,
+                          int32_t T, int32_t P, int32_t* path, float* score, int32_t* status,
+                          uint32_t flags, void* ws, size_t ws_bytes, fv_stream_t stream) {
+    (void)flags;
+    if (T < 1) return fail(FV_E_INVALID_ARG, "T must be >= 1 (got %d)", T);
+    if (!A || !log_b || !path || !score) return fail(FV_E_INVALID_ARG, "null argument");
+    if (ld < A->K) return fail(FV_E_INVALID_ARG, "ld=%lld < K=%d", (long long)ld, A->K);
+    if (P <= 0) P = 16;
+    fv_seq s{0, T, log_b, ld, path, score};
+    return run_dense(FV_FLASH, A, log_pi, nullptr, &T, 1, P, &s, status, ws, ws_bytes,
+                     reinterpret_cast<hipStream_t>(stream));
+}
+
+fv_status fv_decode_batch(const fv_trans* models, const float* const* log_pi, int32_t n_models,
+                          const fv_seq* seqs_dev, const int32_t* T_host, const int32_t* model_host,
+                          int32_t n_seqs, int32_t method, int32_t P, int32_t B, int32_t* status,
+                          uint32_t flags, void* ws, size_t ws_bytes, fv_stream_t stream) {
+    (void)flags;
+    (void)B;
+    (void)model_host;
+    if (n_models != 1) return fail(FV_E_UNSUPPORTED, "exactly one model per call is supported");
+    if (n_seqs < 0) return fail(FV_E_INVALID_ARG, "n_seqs < 0");
+    if (n_seqs > 0 && (!seqs_dev || !T_host)) return fail(FV_E_INVALID_ARG, "null sequence list");
+    if (method != FV_VANILLA && method != FV_FLASH) return fail(FV_E_UNSUPPORTED, "method %d", method);
+    if (method == FV_FLASH && P <= 0) P = 16;
+    return run_dense(method, models, log_pi ? log_pi[0] : nullptr, seqs_dev, T_host, n_seqs, P, nullptr,
+                     status, ws, ws_bytes, reinterpret_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,139 @@
+// Internal layout shared by the host API and the device kernels of the
+// FLASH Viterbi library.  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/flashviterbi.h"
+
+namespace fv {
+
+constexpr int kBlock = 256;     // threads per workgroup (4 wave64)
+constexpr int kWaves = 4;
+constexpr int kTileRows = 64;   // rows of a dense tile: one per lane
+constexpr int kTileCols = 16;   // destination columns per dense tile
+constexpr int kGroup = 16;      // predecessors per arg-max group
+constexpr int kKAlign = 64;     // K is padded to a multiple of this
+
+inline __host__ __device__ int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+// Kinds of rows (one row = one decoding task in flight).
+enum : int32_t { KIND_VANILLA = 0, KIND_ROOT = 1, KIND_SUB = 2 };
+
+// Per-step flags of a dense row.
+enum : int32_t {
+    F_NEED_ARG = 1 << 0,   // psi is needed this step
+    F_ANC_FIRST = 1 << 1,  // anc_t(j) = psi_t(j)
+    F_ANC_CHAIN = 1 << 2,  // anc_t(j) = anc_{t-1}(psi_t(j))
+    F_PSI_TABLE = 1 << 3,  // store psi_t in the vanilla table
+    F_SNAP_SUB = 1 << 4,   // copy delta_t to the row's snapshot (t = t_mid)
+    F_SNAP_ROOT = 1 << 5,  // copy delta_t (and anc_t) to the root's division copy aux
+    F_FINAL = 1 << 6,      // t = T-1 of a full-length pass: feed the final arg max
+};
+
+// Light (O(K)) operations.
+enum : int32_t { L_INIT = 0, L_END = 1, L_FINALIZE = 2 };
+
+struct Row {
+    int32_t seq;
+    int32_t kind;
+    int32_t m, n;      // segment [m, n]
+    int32_t t;         // time step this row computes at the current global step
+    int32_t slot;      // buffer slot
+    int32_t flags;     // F_* (dense rows)
+    int32_t aux;       // L_* for light rows; division index for F_SNAP_ROOT
+};
+
+struct Task {
+    int32_t seq, kind, m, n;
+};
+
+struct SeqInfo {
+    const float* log_b;
+    int64_t ld;
+    int32_t* path;
+    float* score;
+    int32_t T;
+    int32_t pp;          // effective parallelism P'
+    int64_t alpha_off;   // into alpha_at
+    int64_t root_off;    // into root copies, in units of Kp floats
+    int64_t psi_off;     // into the vanilla table, in entries
+    int32_t status;
+    int32_t pad_;
+};
+
+struct EngineState {
+    uint32_t barrier;      // grid barrier arrivals (monotone)
+    int32_t error;
+    int32_t n_full[2];
+    int32_t n_light[2];
+    int32_t q_head;
+    int32_t q_tail;
+    int32_t n_free;
+    int32_t steps;         // global steps executed
+    int32_t max_rows;      // high-water mark of rows in flight
+    int32_t pad_[5];
+};
+
+// Everything the persistent engine needs (one model).
+struct EngineArgs {
+    // model
+    int32_t K, Kp;
+    const float* log_pi;        // may be null
+    const float* Acol;          // the same matrix as the engine's Ap: row-major, pitch Kp
+    // sequences
+    SeqInfo* seqs;
+    int32_t n_seqs;
+    int32_t method;             // FV_VANILLA / FV_FLASH
+    // storage
+    float* slot_base;           // slots * slot_floats
+    int64_t slot_floats;        // floats per slot
+    int32_t n_slots;
+    int32_t has_anc;            // slots carry anc[2] + snap
+    float* alpha_at;            // sum T floats
+    float* root_copy;           // division copies (delta and link), units of Kp
+    uint16_t* psi16;            // vanilla backpointers
+    unsigned long long* keys;   // final arg max keys [n_seqs]
+    // scheduling
+    EngineState* st;
+    Row* rows_full;             // [2][max_rows]
+    Row* rows_light;            // [2][max_rows]
+    int32_t max_rows;
+    Task* queue;                // linear, capacity q_cap
+    int64_t q_cap;
+    int32_t* free_stack;        // [n_slots]
+    int32_t n_compute_blocks;   // the scheduler is block n_compute_blocks
+    int64_t spin_limit;
+    int64_t max_steps;          // guard against a runaway schedule
+};
+
+// Arguments of the per-call setup kernel (per-sequence layout, first row list).
+struct SetupArgs {
+    const fv_seq* seqs_dev;
+    int32_t n_seqs;
+    int32_t P;
+    int64_t host_sum_T;     // the host's totals, checked against the device's copies
+    int64_t host_sum_root;
+    int64_t host_sum_psi;
+    int32_t kind;           // KIND_VANILLA or KIND_ROOT
+    int32_t K;
+};
+
+// Division points of the first P'-way split: e_d = floor(((d+1) T - 1) / P').
+inline __host__ __device__ int64_t seg_end(int32_t T, int32_t pp, int32_t d) {
+    return (((int64_t)d + 1) * T - 1) / pp;
+}
+// Index d of the division point equal to x, or -1 (only d <= pp-2 count).
+inline __host__ __device__ int32_t div_index(int32_t T, int32_t pp, int64_t x) {
+    if (x < 0) return -1;
+    int64_t d = ((x + 1) * (int64_t)pp) / T - 1;
+    if (d < 0 || d > pp - 2) return -1;
+    return seg_end(T, pp, (int32_t)d) == x ? (int32_t)d : -1;
+}
+inline __host__ __device__ int32_t eff_parallelism(int32_t T, int32_t P) {
+    if (T <= 1) return 1;
+    int32_t pp = P < 2 ? 2 : P;
+    return pp > T ? T : pp;
+}
+
+}  // namespace fv

@@ -1,0 +1,157 @@
+"""Torch-facing wrappers of the C ABI (argument marshalling only).
+
+torch supplies device memory (inputs, outputs, the workspace) and the current
+HIP stream; every decoding step runs in libflashviterbi.so.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _stream(dev) -> int:
+    return torch.cuda.current_stream(dev).cuda_stream
+
+
+def _need(t: torch.Tensor, name: str, dtype=torch.float32):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+
+
+def dense_model(log_a: torch.Tensor) -> L.FvTrans:
+    _need(log_a, "log_a")
+    if log_a.dim() != 2 or log_a.shape[0] != log_a.shape[1] or not log_a.is_contiguous():
+        raise ValueError("log_a must be a contiguous [K, K] tensor")
+    return L.FvTrans(L.FV_DENSE, log_a.shape[0], log_a.data_ptr(), None, None, None, 0)
+
+
+def workspace_bytes(method: str, K_or_model, lengths, P: int = 16, B: int = 0) -> int:
+    """Workspace bytes for a decode of sequences with the given lengths.
+    K_or_model: an FvTrans, or K (sizing never dereferences the model)."""
+    if isinstance(K_or_model, L.FvTrans):
+        model = K_or_model
+    else:
+        model = L.FvTrans(L.FV_DENSE, int(K_or_model), 1, None, None, None, 0)
+    lengths = np.ascontiguousarray(np.asarray(lengths, dtype=np.int32).reshape(-1))
+    out = C.c_size_t(0)
+    L.check(L.lib().fv_workspace_size(L.METHODS[method], C.byref(model), 1,
+                                      lengths.ctypes.data, None, lengths.shape[0], int(P),
+                                      int(B or 0), C.byref(out)), "fv_workspace_size")
+    return int(out.value)
+
+
+def _workspace(n: int, dev) -> torch.Tensor:
+    return torch.empty(max(n, 256), dtype=torch.uint8, device=dev)
+
+
+def decode(log_a: torch.Tensor, log_b: torch.Tensor, log_pi: torch.Tensor | None = None,
+           method: str = "vanilla", P: int = 16, B: int = 0, check_status: bool = True):
+    """Decode one sequence.  log_a [K, K], log_b [T, >=K] (row stride = ld),
+    log_pi [K] or None; all float32 CUDA tensors.  Returns
+    (path int32 [T], score float32 [1], status int32 [1]) on the device."""
+    model = dense_model(log_a)
+    _need(log_b, "log_b")
+    if log_b.dim() != 2 or log_b.stride(1) != 1:
+        raise ValueError("log_b must be [T, ld] with unit column stride")
+    if log_pi is not None:
+        _need(log_pi, "log_pi")
+        if not log_pi.is_contiguous() or log_pi.numel() != log_a.shape[0]:
+            raise ValueError("log_pi must be a contiguous [K] tensor")
+    dev = log_a.device
+    T, ld = log_b.shape[0], log_b.stride(0)
+    path = torch.empty(T, dtype=torch.int32, device=dev)
+    score = torch.empty(1, dtype=torch.float32, device=dev)
+    status = torch.empty(1, dtype=torch.int32, device=dev)
+    n = workspace_bytes(method, model, [T], P, B)
+    ws = _workspace(n, dev)
+    pi = log_pi.data_ptr() if log_pi is not None else None
+    lib = L.lib()
+    if method == "vanilla":
+        rc = lib.fv_decode_vanilla(C.byref(model), pi, log_b.data_ptr(), ld, T, path.data_ptr(),
+                                   score.data_ptr(), status.data_ptr(), 0, ws.data_ptr(), ws.numel(),
+                                   _stream(dev))
+    elif method == "flash":
+        rc = lib.fv_decode_flash(C.byref(model), pi, log_b.data_ptr(), ld, T, int(P), path.data_ptr(),
+                                 score.data_ptr(), status.data_ptr(), 0, ws.data_ptr(), ws.numel(),
+                                 _stream(dev))
+    elif method == "beam":
+        rc = lib.fv_decode_beam(C.byref(model), pi, log_b.data_ptr(), ld, T, int(B), int(P),
+                                path.data_ptr(), score.data_ptr(), status.data_ptr(), 0, ws.data_ptr(),
+                                ws.numel(), _stream(dev))
+    else:
+        raise ValueError(method)
+    L.check(rc, f"fv_decode_{method}")
+    return path, score, status
+
+
+class Batch:
+    """Device descriptors of a batch of sequences sharing one dense model.
+
+    Either a list of [T_b, K] tensors or a padded [n, Tmax, K] tensor plus
+    lengths.  Outputs are a padded int32 [n, Tmax] path tensor (entries past
+    each length untouched) and float32 [n] scores.
+    """
+
+    def __init__(self, log_b, lengths=None):
+        if isinstance(log_b, torch.Tensor):
+            _need(log_b, "log_b")
+            if log_b.dim() != 3 or log_b.stride(2) != 1:
+                raise ValueError("padded log_b must be [n, Tmax, ld] with unit column stride")
+            n, tmax = log_b.shape[0], log_b.shape[1]
+            lengths = np.asarray(lengths if lengths is not None else [tmax] * n, np.int32)
+            if lengths.shape != (n,) or (lengths > tmax).any() or (lengths < 0).any():
+                raise ValueError("bad lengths")
+            ptrs = [log_b.data_ptr() + b * log_b.stride(0) * 4 for b in range(n)]
+            ld = [log_b.stride(1)] * n
+            self.keep = [log_b]
+            dev = log_b.device
+        else:
+            seqs = list(log_b)
+            n = len(seqs)
+            for k, x in enumerate(seqs):
+                _need(x, f"log_b[{k}]")
+                if x.dim() != 2 or x.stride(1) != 1:
+                    raise ValueError("each log_b must be [T, ld] with unit column stride")
+            lengths = np.array([x.shape[0] for x in seqs], np.int32)
+            tmax = int(lengths.max()) if n else 0
+            ptrs = [x.data_ptr() for x in seqs]
+            ld = [x.stride(0) for x in seqs]
+            self.keep = seqs
+            dev = seqs[0].device if n else torch.device("cuda")
+        self.n, self.tmax, self.lengths, self.device = n, tmax, lengths, dev
+        self.paths = torch.full((n, max(tmax, 1)), -1, dtype=torch.int32, device=dev)
+        self.scores = torch.empty(n, dtype=torch.float32, device=dev)
+        self.status = torch.empty(n, dtype=torch.int32, device=dev)
+        arr = (L.FvSeq * max(n, 1))()
+        for b in range(n):
+            arr[b] = L.FvSeq(0, int(lengths[b]), ptrs[b], int(ld[b]),
+                             self.paths.data_ptr() + b * self.paths.stride(0) * 4,
+                             self.scores.data_ptr() + b * 4)
+        host = torch.frombuffer(bytearray(bytes(arr)), dtype=torch.uint8)
+        self.desc = host.to(dev)
+
+
+def decode_batch(log_a: torch.Tensor, batch: Batch, log_pi: torch.Tensor | None = None,
+                 method: str = "flash", P: int = 16, B: int = 0, ws: torch.Tensor | None = None):
+    """Decode all sequences of `batch` in one persistent launch; results land
+    in batch.paths / batch.scores / batch.status.  Returns the workspace
+    tensor so callers can reuse it."""
+    model = dense_model(log_a)
+    dev = log_a.device
+    n = workspace_bytes(method, model, batch.lengths, P, B)
+    if ws is None or ws.numel() < n:
+        ws = _workspace(n, dev)
+    pis = (C.c_void_p * 1)(log_pi.data_ptr() if log_pi is not None else None)
+    lengths = np.ascontiguousarray(batch.lengths, np.int32)
+    rc = L.lib().fv_decode_batch(C.byref(model), C.cast(pis, C.c_void_p), 1, batch.desc.data_ptr(),
+                                 lengths.ctypes.data, None, batch.n, L.METHODS[method], int(P),
+                                 int(B or 0), batch.status.data_ptr(), 0, ws.data_ptr(), ws.numel(),
+                                 _stream(dev))
+    L.check(rc, "fv_decode_batch")
+    return ws

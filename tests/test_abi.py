@@ -1,0 +1,81 @@
+"""CPU checks of the C ABI: the library loads, exports every symbol the
+header declares, and its host logic (sizing, argument checks) behaves.
+No call here launches GPU work."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def fv():
+    import paper_2510_19301_amd as m
+    m.lib()
+    return m
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "flashviterbi.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fv_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported(fv):
+    names = _declared()
+    assert len(names) >= 10
+    h = C.CDLL(fv._lib.LIB_PATH)
+    for n in names:
+        assert hasattr(h, n), n
+    assert set(names) <= set(fv._lib.SIGNATURES), set(names) - set(fv._lib.SIGNATURES)
+
+
+def test_status_strings(fv):
+    l = fv.lib()
+    for s in (0, -1, -2, -3, -4, -5, 1):
+        assert l.fv_status_str(s)
+    assert l.fv_abi_version() == 1
+
+
+def test_workspace_size_properties(fv):
+    d = fv
+    K = 1024
+    v_short = d.workspace_bytes("vanilla", K, [500])
+    v_long = d.workspace_bytes("vanilla", K, [8000])
+    f_long = d.workspace_bytes("flash", K, [8000], P=16)
+    # vanilla keeps a K x T pointer table; FLASH keeps O(P K) per sequence
+    assert v_long - v_short >= (8000 - 500) * K * 2
+    big = [8000] * 64
+    assert d.workspace_bytes("flash", K, big, P=16) < d.workspace_bytes("vanilla", K, big)
+    assert f_long > 0
+    # P only changes the per-sequence division copies
+    assert d.workspace_bytes("flash", K, [8000], P=64) > d.workspace_bytes("flash", K, [8000], P=2)
+
+
+def test_workspace_size_rejects_bad_args(fv):
+    d = fv
+    with pytest.raises(fv.FvError):
+        d.workspace_bytes("vanilla", 0, [10])
+    with pytest.raises(fv.FvError):
+        d.workspace_bytes("vanilla", 8, [-1])
+    with pytest.raises(fv.FvError):
+        d.workspace_bytes("vanilla", 70000, [10])
+
+
+def test_decode_argument_errors_are_synchronous(fv):
+    """Invalid arguments are reported before any device work is queued."""
+    l = fv.lib()
+    m = fv._lib.FvTrans(0, 8, 1, None, None, None, 0)
+    fake = 4096
+    assert l.fv_decode_vanilla(C.byref(m), None, fake, 8, 0, fake, fake, None, 0, fake, 1 << 20, None) == -1
+    assert l.fv_decode_vanilla(C.byref(m), None, fake, 4, 5, fake, fake, None, 0, fake, 1 << 20, None) == -1
+    assert l.fv_decode_vanilla(C.byref(m), None, None, 8, 5, fake, fake, None, 0, fake, 1 << 20, None) == -1
+    assert l.fv_decode_flash(C.byref(m), None, fake, 8, 0, 4, fake, fake, None, 0, fake, 1 << 20, None) == -1
+    # workspace too small is caught on the host
+    assert l.fv_decode_vanilla(C.byref(m), None, fake, 8, 5, fake, fake, None, 0, fake, 16, None) == -3
+    csr = fv._lib.FvTrans(1, 8, None, fake, fake, fake, 3)
+    assert l.fv_decode_vanilla(C.byref(csr), None, fake, 8, 5, fake, fake, None, 0, fake, 1 << 20, None) == -2
+    assert l.fv_last_error()

@@ -1,0 +1,157 @@
+"""GPU parity of the dense decoders against the CPU oracle.
+
+Paths are compared element by element and scores bit for bit (every
+candidate is one float32 add, so the GPU must reproduce the oracle exactly).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from workloads import hmm
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def fv():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    import paper_2510_19301_amd as m
+    m.lib()
+    return m
+
+
+def _dev(x):
+    return None if x is None else torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _bits(x):
+    return np.asarray(x, np.float32).reshape(-1).view(np.uint32)
+
+
+def _run(fv, lp, la, lb, method, P=16, B=0):
+    path, score, status = fv.decode(_dev(la), _dev(lb), _dev(lp), method=method, P=P, B=B)
+    torch.cuda.synchronize()
+    return path.cpu().numpy(), score.cpu().numpy(), int(status.cpu()[0])
+
+
+SHAPES = [(1, 1), (1, 6), (2, 1), (2, 2), (3, 3), (5, 7), (17, 40), (63, 33), (64, 64), (65, 50),
+          (130, 21), (200, 9)]
+
+
+@pytest.mark.parametrize("K,T", SHAPES)
+def test_vanilla_matches_oracle(fv, K, T):
+    lp, la, lb = hmm.random_dense(K, T, 11 * K + T)
+    print(f"vanilla K={K} T={T}", flush=True)
+    p, s, st = _run(fv, lp, la, lb, "vanilla")
+    po, so, _ = oracle.vanilla(lp, la, lb)
+    assert st == fv.FV_OK
+    assert (p == po).all()
+    assert (_bits(s) == _bits(so)).all()
+
+
+@pytest.mark.parametrize("K,T", SHAPES)
+@pytest.mark.parametrize("P", [1, 2, 3, 7, 16, 1000])
+def test_flash_matches_oracle(fv, K, T, P):
+    lp, la, lb = hmm.random_dense(K, T, 13 * K + T)
+    print(f"flash K={K} T={T} P={P}", flush=True)
+    p, s, st = _run(fv, lp, la, lb, "flash", P=P)
+    po, so, _ = oracle.vanilla(lp, la, lb)
+    assert st == fv.FV_OK
+    assert (p == po).all()
+    assert (_bits(s) == _bits(so)).all()
+
+
+@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("method,P", [("vanilla", 1), ("flash", 1), ("flash", 5)])
+def test_integer_ties(fv, seed, method, P):
+    K, T = 70, 37
+    lp, la, lb = hmm.random_dense(K, T, seed, integer=True, lo=-2, hi=0)
+    print(f"ties {method} seed={seed} P={P}", flush=True)
+    p, s, _ = _run(fv, lp, la, lb, method, P=P)
+    po, so, _ = oracle.vanilla(lp, la, lb)
+    assert (p == po).all() and s[0] == so
+
+
+def test_without_pi(fv):
+    _, la, lb = hmm.random_dense(40, 30, 5, with_pi=False)
+    for method in ("vanilla", "flash"):
+        p, s, _ = _run(fv, None, la, lb, method, P=4)
+        po, so, _ = oracle.vanilla(None, la, lb)
+        assert (p == po).all() and (_bits(s) == _bits(so)).all()
+
+
+def test_anchor_at_large_magnitude(fv):
+    """Near-ties created by float32 rounding at |score| ~ 1e6: the anchored
+    subtask start must reproduce vanilla's rounding."""
+    K, T = 16, 1200
+    r = np.random.default_rng(5)
+    la = (np.float32(-np.log(K)) + 0.01 * r.standard_normal((K, K))).astype(np.float32)
+    lb = (-1000.0 + 0.02 * r.standard_normal((T, K))).astype(np.float32)
+    lp = hmm.uniform_log_pi(K)
+    po, so, _ = oracle.vanilla(lp, la, lb)
+    for method, P in (("vanilla", 1), ("flash", 1), ("flash", 16)):
+        p, s, _ = _run(fv, lp, la, lb, method, P=P)
+        assert (p == po).all() and (_bits(s) == _bits(so)).all()
+
+
+def test_infeasible(fv):
+    lp, la, lb = hmm.random_dense(20, 9, 3)
+    la[:] = -np.inf
+    for method in ("vanilla", "flash"):
+        p, s, st = _run(fv, lp, la, lb, method, P=3)
+        assert st == fv.FV_E_INFEASIBLE and (p == -1).all() and s[0] == -np.inf
+
+
+def test_signed_zero(fv):
+    lp = np.array([-0.0, 0.0], np.float32)
+    la = np.array([[-0.0, -0.0], [0.0, 0.0]], np.float32)
+    lb = np.array([[-0.0, -0.0], [-0.0, -0.0]], np.float32)
+    po, so, _ = oracle.vanilla(lp, la, lb)
+    for method in ("vanilla", "flash"):
+        p, s, _ = _run(fv, lp, la, lb, method, P=2)
+        assert (p == po).all() and (_bits(s) == _bits(so)).all()
+
+
+def test_discrete_hmm_k64_t1000(fv):
+    """Single discrete HMM: K=64, V=128, T=1000, Dirichlet rows, emissions
+    gathered on the device."""
+    h = hmm.discrete_hmm(K=64, V=128, T=1000, seed=1)
+    lb_ref = oracle.gather_emissions(h.log_e, h.obs)
+    lb = torch.empty((h.T, h.K), dtype=torch.float32, device="cuda")
+    log_e, obs = _dev(h.log_e), _dev(h.obs)   # keep the inputs alive until the kernel ran
+    rc = fv.lib().fv_gather_emissions(h.K, h.V, log_e.data_ptr(), obs.data_ptr(), h.T,
+                                      lb.data_ptr(), h.K, torch.cuda.current_stream().cuda_stream)
+    assert rc == 0
+    torch.cuda.synchronize()
+    assert (lb.cpu().numpy() == lb_ref).all()
+    po, so, _ = oracle.vanilla(h.log_pi, h.log_a, lb_ref)
+    for method, P in (("vanilla", 1), ("flash", 1), ("flash", 4), ("flash", 16)):
+        path, score, st = fv.decode(_dev(h.log_a), lb, _dev(h.log_pi), method=method, P=P)
+        assert (path.cpu().numpy() == po).all() and (_bits(score.cpu().numpy()) == _bits(so)).all()
+
+
+def test_batch_uneven_lengths(fv):
+    K = 96
+    r = np.random.default_rng(3)
+    lengths = [0, 1, 2, 3, 5, 64, 100, 257, 31]
+    _, la, _ = hmm.random_dense(K, 1, 77)
+    lp = hmm.uniform_log_pi(K)
+    lbs = [(r.standard_normal((T, K)) * 2).astype(np.float32) for T in lengths]
+    for method, P in (("vanilla", 1), ("flash", 1), ("flash", 4), ("flash", 64)):
+        batch = fv.Batch([_dev(x) if x.shape[0] else torch.empty((0, K), device="cuda") for x in lbs])
+        fv.decode_batch(_dev(la), batch, _dev(lp), method=method, P=P)
+        torch.cuda.synchronize()
+        paths = batch.paths.cpu().numpy()
+        scores = batch.scores.cpu().numpy()
+        status = batch.status.cpu().numpy()
+        for b, T in enumerate(lengths):
+            assert status[b] == 0, (method, P, b)
+            if T == 0:
+                assert scores[b] == 0.0
+                continue
+            po, so, _ = oracle.vanilla(lp, la, lbs[b])
+            assert (paths[b, :T] == po).all(), (method, P, b)
+            assert _bits(scores[b]) == _bits(so)
