@@ -1,0 +1,221 @@
+#!/usr/bin/env python3
+"""Benchmark: batched FLASH Viterbi decoding on one MI355X.
+
+Workload (synthetic, seeded): 256 sequences sharing a dense K=1024 float32
+log-transition matrix (rows ~ Dirichlet(0.1), logged), lengths uniform in
+[500, 8000], emission scores N(0, 2^2).  One "step" is one batched decode of
+the whole workload (one persistent launch).  The metric is state-steps/s =
+sum_b T_b * K / wall time, inputs resident in HBM before timing starts.
+
+Prints ONE JSON line.  Besides the headline method it reports vanilla and
+the other P values, the workspace memory of each, the engine kernel's
+roofline fraction and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks
+PEAK_HBM_GBS = 8000.0
+CU, LANES, CLOCK_GHZ = 256, 64, 2.4
+# max-plus: one candidate = one add + one max (2 flops).  If every lane
+# evaluated one candidate per clock the chip would reach
+# 256 CU x 64 lanes x 2.4 GHz = 39.3e12 candidates/s = 78.6 TFLOP/s.
+PEAK_MAXPLUS_TFLOPS = CU * LANES * CLOCK_GHZ * 1e9 * 2 / 1e12
+PEAK_FP32_VECTOR_TFLOPS = 157.3
+
+
+# ------------------------------------------------------------------ work model
+def _sub_candidates(m: int, n: int, K: int, memo: dict) -> int:
+    """Candidates the GPU evaluates for subtask (m, n) and its descendants:
+    anchored start (K, none at m = 0), full steps m+1..n-1 (K^2 each), the
+    end-only last step (K)."""
+    key = (n - m, m == 0)
+    if key in memo:
+        return memo[key]
+    c = (K if m > 0 else 0) + (n - m - 1) * K * K + K
+    tmid = (m + n) // 2
+    if n - m > 2:
+        c += _sub_candidates(m, tmid, K, memo) + _sub_candidates(tmid + 1, n, K, memo)
+    elif n - m == 2:
+        c += _sub_candidates(m, tmid, K, memo)
+    memo[key] = c
+    return c
+
+
+def flash_candidates(T: int, P: int, K: int) -> int:
+    """Candidates of one FLASH decode: root pass + every subtask."""
+    if T <= 1:
+        return 0
+    pp = min(max(P, 2), T)
+    total = (T - 1) * K * K
+    memo: dict = {}
+    for d in range(pp):
+        m = 0 if d == 0 else ((d * T - 1) // pp) + 1
+        n = ((d + 1) * T - 1) // pp
+        if n - m >= 1:
+            total += _sub_candidates(m, n, K, memo)
+    return total
+
+
+def vanilla_candidates(T: int, K: int) -> int:
+    return max(T - 1, 0) * K * K
+
+
+# ------------------------------------------------------------------ helpers
+def _make_inputs(wl, torch, dev):
+    with ThreadPoolExecutor(max_workers=8) as ex:
+        host = list(ex.map(wl.log_b, range(wl.n)))
+    return [torch.from_numpy(x).to(dev) for x in host]
+
+
+def _time_method(fv, torch, la, lp, batch, method, P, B, steps, warmup, ws=None):
+    """Mean ms per decode over `steps` timed decodes (torch events on the
+    current stream, which is the stream the library launches on) and the
+    engine kernel's own duration in the last timed decode (HIP events the
+    library records around that launch)."""
+    import ctypes as C
+    lib = fv.lib()
+    for _ in range(warmup):
+        ws = fv.decode_batch(la, batch, lp, method=method, P=P, B=B, ws=ws)
+    torch.cuda.synchronize()
+    fv._lib.check(lib.fv_profile_engine(1), "fv_profile_engine")
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        ws = fv.decode_batch(la, batch, lp, method=method, P=P, B=B, ws=ws)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = C.c_float(0)
+    fv._lib.check(lib.fv_profile_engine_ms(C.byref(ms)), "fv_profile_engine_ms")
+    lib.fv_profile_engine(0)
+    st = batch.status.cpu().numpy()
+    return start.elapsed_time(stop) / steps, float(ms.value), ws, int((st != 0).sum())
+
+
+def cpu_baseline(wl, budget_s: float):
+    """The oracle's vanilla decode on a prefix of the workload's sequences,
+    all host cores in parallel (one sequence per thread at a time)."""
+    import oracle
+    cores = min(os.cpu_count() or 1, 16)
+    per_core_rate = 0.9e9  # candidates/s, for sizing the sample only
+    budget_cand = budget_s * cores * per_core_rate
+    chosen, cand = [], 0
+    for b in range(wl.n):
+        c = vanilla_candidates(int(wl.lengths[b]), wl.K)
+        if chosen and cand + c > budget_cand:
+            break
+        chosen.append(b)
+        cand += c
+    lbs = {b: wl.log_b(b) for b in chosen}
+
+    def run(b):
+        oracle.vanilla(wl.log_pi, wl.log_a, lbs[b])
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=cores) as ex:
+        list(ex.map(run, chosen))
+    dt = time.perf_counter() - t0
+    steps = int(sum(int(wl.lengths[b]) for b in chosen))
+    return {"value": steps * wl.K / dt, "unit": "state-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"vanilla oracle (plain C, float32) on sequences 0..{len(chosen) - 1} "
+                      f"({len(chosen)} of {wl.n}, sum T = {steps}), one sequence per thread",
+            "seconds": round(dt, 3)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--P", type=int, default=64, help="FLASH parallelism of the headline run")
+    ap.add_argument("--sweep", default="vanilla,flash:1,flash:4,flash:16",
+                    help="extra methods timed once each (method[:P])")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--n", type=int, default=256)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported on this build "
+              "(sequences shard across GPUs with no exchange; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2510_19301_amd as fv
+    from workloads import hmm
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    wl = hmm.batched_flash_workload(n=args.n)
+    K = wl.K
+    print(f"[bench] generating workload: {wl.n} sequences, K={K}, sum T={wl.total_steps()}", file=sys.stderr, flush=True)
+    lbs = _make_inputs(wl, torch, dev)
+    la = torch.from_numpy(wl.log_a).to(dev)
+    lp = torch.from_numpy(wl.log_pi).to(dev)
+    batch = fv.Batch(lbs)
+    torch.cuda.synchronize()
+    state_steps = wl.total_steps() * K
+
+    results = {}
+    ws = None
+    runs = [("flash", args.P, args.steps, args.warmup)]
+    for item in [s for s in args.sweep.split(",") if s]:
+        name, _, p = item.partition(":")
+        runs.append((name, int(p or 1), 1, 1))
+    for method, P, steps, warmup in runs:
+        print(f"[bench] {method} P={P}: warmup {warmup}, timed {steps}", file=sys.stderr, flush=True)
+        ms, eng_ms, ws_new, bad = _time_method(fv, torch, la, lp, batch, method, P, 0, steps, warmup)
+        if ws is None or ws_new.numel() > ws.numel():
+            ws = ws_new
+        if method == "flash":
+            cand = sum(flash_candidates(int(T), P, K) for T in wl.lengths)
+        else:
+            cand = sum(vanilla_candidates(int(T), K) for T in wl.lengths)
+        results[f"{method}_P{P}" if method == "flash" else method] = {
+            "ms_per_step": round(ms, 3), "engine_ms": round(eng_ms, 3),
+            "state_steps_per_s": state_steps / (ms / 1e3),
+            "candidates": cand, "candidates_per_s": cand / (eng_ms / 1e3),
+            "workspace_bytes": fv.workspace_bytes(method, K, wl.lengths, P),
+            "bad_status": bad}
+        print(f"[bench] {method} P={P}: {ms:.2f} ms/step, engine {eng_ms:.2f} ms", file=sys.stderr, flush=True)
+
+    head = results[f"flash_P{args.P}"]
+    ach_tflops = head["candidates"] * 2 / (head["engine_ms"] / 1e3) / 1e12
+    out = {
+        "metric": "state-steps/s (sum T*K /s), FLASH & beam vs vanilla GPU, bit-exact paths",
+        "value": head["state_steps_per_s"],
+        "unit": "state-steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic (seeded generators; no dataset)",
+        "config": {"workload": f"batched FLASH decode: {wl.n} sequences, dense K={K}, "
+                               f"T~U[500,8000] (sum T={wl.total_steps()}), log A rows Dirichlet(0.1), "
+                               f"log B ~ N(0,2^2); FLASH P={args.P}, one persistent launch",
+                   "method": "flash", "P": args.P, "K": K, "n_seqs": wl.n, "sum_T": wl.total_steps()},
+        "roofline": {"bound": "alu", "achieved": round(ach_tflops, 3), "peak": round(PEAK_MAXPLUS_TFLOPS, 1),
+                     "unit": "TFLOP/s", "frac": round(ach_tflops / PEAK_MAXPLUS_TFLOPS, 4), "traffic": None,
+                     "kernel": "fv_engine_kernel",
+                     "flops_per_candidate": 2,
+                     "frac_of_fp32_vector_peak": round(ach_tflops / PEAK_FP32_VECTOR_TFLOPS, 4)},
+        "methods": results,
+    }
+    if not args.no_cpu:
+        print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

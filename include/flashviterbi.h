@@ -168,6 +168,14 @@ fv_status fv_rescore(const fv_trans* A, const float* log_pi, const fv_seq* seqs_
 fv_status fv_gather_emissions(int32_t K, int32_t V, const float* log_e, const int32_t* obs,
                               int32_t T, float* log_b, int64_t ld, fv_stream_t stream);
 
+/* Measurement hook: while enabled (enable != 0, host thread-local), every
+ * decode records a pair of HIP events on its stream immediately before and
+ * after its persistent engine kernel.  fv_profile_engine_ms waits for the
+ * last pair and returns the engine kernel's duration in milliseconds.
+ * Enable outside stream capture (it creates the events). */
+fv_status fv_profile_engine(int32_t enable);
+fv_status fv_profile_engine_ms(float* ms);
+
 const char* fv_status_str(fv_status s);
 const char* fv_last_error(void);   /* thread-local message of the last failure */
 int32_t fv_abi_version(void);

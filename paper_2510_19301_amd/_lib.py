@@ -50,6 +50,8 @@ SIGNATURES = {
     "fv_backward_workspace_size": (_i32, [_i32, _i32, _i32, _P(_sz)]),
     "fv_rescore": (_i32, [_P(FvTrans), _vp, _vp, _i32, _vp, _vp]),
     "fv_gather_emissions": (_i32, [_i32, _i32, _vp, _vp, _i32, _vp, _i64, _vp]),
+    "fv_profile_engine": (_i32, [_i32]),
+    "fv_profile_engine_ms": (_i32, [_P(_f)]),
     "fv_status_str": (C.c_char_p, [_i32]),
     "fv_last_error": (C.c_char_p, []),
     "fv_abi_version": (_i32, []),

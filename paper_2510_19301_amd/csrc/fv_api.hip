@@ -20,6 +20,9 @@ extern "C" __global__ void fv_finish_kernel(EngineArgs a, int32_t* status);
 using namespace fv;
 
 static thread_local std::string g_last_error;
+static thread_local bool g_prof_on = false;
+static thread_local hipEvent_t g_prof_ev[2] = {nullptr, nullptr};
+static thread_local bool g_prof_recorded = false;
 
 static fv_status fail(fv_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 static fv_status fail(fv_status s, const char* fmt, ...) {
@@ -43,16 +46,18 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int32_t kMaxDenseK = 65535;   // packed uint16 backpointers
+constexpr int32_t kMaxBlocks = 4096;    // engine grid size limit (arrival flags)
+constexpr int kEngineBlock = 1024;      // engine threads per block (one block per CU)
 
 struct Region {
     size_t off = 0, bytes = 0;
 };
 
 struct DenseLayout {
-    int32_t method = 0, K = 0, Kp = 0, n_seqs = 0, n_slots = 0, max_rows = 0;
+    int32_t method = 0, K = 0, Kp = 0, n_seqs = 0, n_slots = 0, pool = 0;
     int64_t sum_T = 0, sum_root = 0, sum_psi = 0, n_tasks = 0, slot_floats = 0;
     int32_t has_anc = 0;
-    Region Ap, seq1, seqinfo, keys, state, rows_full, rows_light, queue, free_stack, slots,
+    Region Ap, seq1, seqinfo, keys, state, arrive, rows_full, rows_light, queue, free_stack, slots,
         alpha, root, psi;
     size_t total = 0;
 };
@@ -103,17 +108,19 @@ fv_status plan_dense(int32_t method, int32_t K, const int32_t* T_host, int32_t n
         slots = std::min<int64_t>(L.n_tasks, std::max<int64_t>(std::min<int64_t>(nonempty, 1 << 16), cap));
     }
     if (slots < 1) slots = 1;
+    slots = round_up(slots, kXcd);  // equal slot pools, one per XCD
     if (slots > (1 << 26)) return fail(FV_E_UNSUPPORTED, "too many concurrent sequences");
     L.n_slots = (int32_t)slots;
-    L.max_rows = L.n_slots;
+    L.pool = L.n_slots / kXcd;
     size_t cur = 0;
     put(cur, L.Ap, L.Kp != K ? (size_t)L.Kp * L.Kp * 4 : 0);  // padded copy only when needed
     put(cur, L.seq1, single ? sizeof(fv_seq) : 0);
     put(cur, L.seqinfo, (size_t)std::max(n_seqs, 1) * sizeof(SeqInfo));
     put(cur, L.keys, (size_t)std::max(n_seqs, 1) * 8);
     put(cur, L.state, sizeof(EngineState));
-    put(cur, L.rows_full, (size_t)2 * L.max_rows * sizeof(Row));
-    put(cur, L.rows_light, (size_t)2 * L.max_rows * sizeof(Row));
+    put(cur, L.arrive, (size_t)kMaxBlocks * 4);
+    put(cur, L.rows_full, (size_t)2 * L.n_slots * sizeof(Row));
+    put(cur, L.rows_light, (size_t)2 * L.n_slots * sizeof(Row));
     put(cur, L.queue, (size_t)std::max<int64_t>(L.n_tasks, 1) * sizeof(Task));
     put(cur, L.free_stack, (size_t)L.n_slots * 4);
     put(cur, L.slots, (size_t)L.n_slots * slot_bytes);
@@ -146,7 +153,7 @@ fv_status device_info(DeviceInfo& di) {
     di.cus = p.multiProcessorCount;
     int nb = 0;
     HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(fv_engine_kernel),
-                                                         kBlock, 0));
+                                                         kEngineBlock, 0));
     di.engine_blocks_per_cu = nb;
     if (nb < 1) return fail(FV_E_DEVICE, "engine kernel cannot be resident");
     return FV_OK;
@@ -202,14 +209,16 @@ fv_status run_dense(int32_t method, const fv_trans* A, const float* log_pi, cons
     a.psi16 = static_cast<uint16_t*>(at(L.psi));
     a.keys = static_cast<unsigned long long*>(at(L.keys));
     a.st = static_cast<EngineState*>(at(L.state));
+    a.arrive = static_cast<uint32_t*>(at(L.arrive));
     a.rows_full = static_cast<Row*>(at(L.rows_full));
     a.rows_light = static_cast<Row*>(at(L.rows_light));
-    a.max_rows = L.max_rows;
+    a.pool = L.pool;
     a.queue = static_cast<Task*>(at(L.queue));
     a.q_cap = std::max<int64_t>(L.n_tasks, 1);
     a.free_stack = static_cast<int32_t*>(at(L.free_stack));
-    const int per_cu = std::min(2, std::max(1, di.engine_blocks_per_cu - 1));
-    a.n_compute_blocks = std::max(1, std::min(di.cus * per_cu, di.cus * di.engine_blocks_per_cu - 1));
+    // one engine block per CU: block 0 schedules, the others compute
+    a.n_compute_blocks = std::min(di.cus, kMaxBlocks) - 1;
+    if (a.n_compute_blocks < kXcd) return fail(FV_E_UNSUPPORTED, "device has too few compute units");
     a.spin_limit = (int64_t)1 << 24;
     a.max_steps = 8 * (L.sum_T + L.n_tasks) + 4096;
 
@@ -226,8 +235,13 @@ fv_status run_dense(int32_t method, const fv_trans* A, const float* log_pi, cons
 
     if (n_seqs > 0) {
         void* args[] = {&Ap, &a};
+        if (g_prof_on) HIP_TRY(hipEventRecord(g_prof_ev[0], stream));
         HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(fv_engine_kernel),
-                                           dim3(a.n_compute_blocks + 1), dim3(kBlock), args, 0, stream));
+                                           dim3(a.n_compute_blocks + 1), dim3(kEngineBlock), args, 0, stream));
+        if (g_prof_on) {
+            HIP_TRY(hipEventRecord(g_prof_ev[1], stream));
+            g_prof_recorded = true;
+        }
         hipLaunchKernelGGL(fv_finish_kernel, dim3((n_seqs + kBlock - 1) / kBlock), dim3(kBlock), 0, stream,
                            a, status);
     }
@@ -254,6 +268,24 @@ const char* fv_status_str(fv_status s) {
         case FV_W_BEAM_FALLBACK: return "FV_W_BEAM_FALLBACK: a beam subtask was re-decoded exactly";
     }
     return "unknown fv_status";
+}
+
+fv_status fv_profile_engine(int32_t enable) {
+    if (enable && !g_prof_ev[0]) {
+        HIP_TRY(hipEventCreate(&g_prof_ev[0]));
+        HIP_TRY(hipEventCreate(&g_prof_ev[1]));
+    }
+    g_prof_on = enable != 0;
+    g_prof_recorded = false;
+    return FV_OK;
+}
+
+fv_status fv_profile_engine_ms(float* ms) {
+    if (!ms) return fail(FV_E_INVALID_ARG, "null ms");
+    if (!g_prof_recorded) return fail(FV_E_INVALID_ARG, "no engine launch recorded since profiling was enabled");
+    HIP_TRY(hipEventSynchronize(g_prof_ev[1]));
+    HIP_TRY(hipEventElapsedTime(ms, g_prof_ev[0], g_prof_ev[1]));
+    return FV_OK;
 }
 
 fv_status fv_workspace_size(int32_t method, const fv_trans* models, int32_t n_models,

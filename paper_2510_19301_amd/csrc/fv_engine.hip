@@ -3,10 +3,19 @@
 // One cooperative launch runs every step of every decoding task of a batch:
 // vanilla passes (Sec. III-A), FLASH root passes and FLASH subtasks
 // (Alg. 1 / Alg. 2).  A "row" is one task in flight; at every global step each
-// row advances one time step.  Blocks 0..n_compute_blocks-1 execute the rows
-// of the current step; the last block is the scheduler, which meanwhile
-// builds the next step's row list (task creation, slot reuse).  One grid
-// barrier separates steps.
+// row advances one time step.  Compute blocks execute the rows of the current
+// step; the last block is the scheduler, which meanwhile builds the next
+// step's row lists (task creation, slot reuse) and then acts as the master of
+// the step barrier.
+//
+// MI355X layout: the 256 CUs sit in 8 XCDs, each with its own L2.  Row
+// buffer slot s belongs to XCD s % 8 and only blocks running on that XCD
+// (read from the XCC_ID hardware register) compute or read its rows, so a
+// row's state moves between steps through one L2: publishing it needs only
+// "my stores are done" and reading it only an L1 invalidate.  The small
+// state shared across XCDs (row lists, counts, path entries, anchors, status)
+// is read and written with coherent (sc1) accesses.  No L2 write-back or
+// invalidate is issued per step, and log A stays resident in every L2.
 //
 // Dense step of a row at time t (Sec. III-A recurrence, log domain):
 //     c(j)   = max_i delta_{t-1}(i) + log A(i, j)     (one float32 add per candidate)
@@ -22,6 +31,58 @@
 #include "fv_internal.h"
 
 namespace fv {
+
+static_assert(sizeof(Row) == 64, "Row is moved as 8 coherent 64-bit words");
+
+// The engine runs one 1024-thread block per CU: 16 waves = 4 tile groups of
+// 4 waves (one wave per SIMD each), which keeps 4 waves per SIMD for latency
+// hiding while the step barrier has one participant per CU.
+constexpr int kEngBlock = 1024;
+constexpr int kEngWaves = kEngBlock / 64;
+
+// ---------------------------------------------------------------- access helpers
+template <typename T>
+__device__ __forceinline__ T ld_c(const T* p) {  // coherent across XCDs
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_c(T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ float ld_cf(const float* p) {
+    return __uint_as_float(ld_c(reinterpret_cast<const uint32_t*>(p)));
+}
+__device__ __forceinline__ void st_cf(float* p, float v) {
+    st_c(reinterpret_cast<uint32_t*>(p), __float_as_uint(v));
+}
+__device__ __forceinline__ Row ld_row(const Row* p) {
+    const uint64_t* q = reinterpret_cast<const uint64_t*>(p);
+    uint64_t w[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) w[k] = ld_c(q + k);
+    Row r;
+    __builtin_memcpy(&r, w, sizeof r);
+    return r;
+}
+__device__ __forceinline__ void st_row(Row* p, const Row& r) {
+    uint64_t w[8];
+    __builtin_memcpy(w, &r, sizeof r);
+    uint64_t* q = reinterpret_cast<uint64_t*>(p);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) st_c(q + k, w[k]);
+}
+__device__ __forceinline__ int32_t clampi(int32_t v, int32_t hi) { return v < 0 ? 0 : (v >= hi ? hi - 1 : v); }
+
+// Final arg-max keys are combined by tiles and read by the finalize step
+// with coherent loads, so the max is performed at the memory side (sc1).
+__device__ __forceinline__ void key_max(unsigned long long* p, unsigned long long v) {
+    __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+__device__ __forceinline__ uint32_t my_xcd() {
+    return __builtin_amdgcn_s_getreg((15 << 11) | (0 << 6) | 20) & (kXcd - 1);  // HW_REG_XCC_ID
+}
+__device__ __forceinline__ void l1_invalidate() { asm volatile("buffer_inv sc0" ::: "memory"); }
 
 __device__ __forceinline__ unsigned long long order_key(float v, int32_t j) {
     if (v == 0.0f) v = 0.0f;  // -0 and +0 compare equal; the lower index must win
@@ -40,57 +101,25 @@ __device__ __forceinline__ int32_t* slot_anc(const EngineArgs& a, int32_t slot, 
 __device__ __forceinline__ float* slot_snap(const EngineArgs& a, int32_t slot) {
     return a.slot_base + (int64_t)slot * a.slot_floats + (int64_t)4 * a.Kp;
 }
-__device__ __forceinline__ float* root_dsnap(const EngineArgs& a, const SeqInfo& s, int32_t d) {
-    return a.root_copy + (s.root_off + d) * (int64_t)a.Kp;
+__device__ __forceinline__ float* root_dsnap(const EngineArgs& a, int64_t root_off, int32_t d) {
+    return a.root_copy + (root_off + d) * (int64_t)a.Kp;
 }
-__device__ __forceinline__ int32_t* root_link(const EngineArgs& a, const SeqInfo& s, int32_t d) {
-    return reinterpret_cast<int32_t*>(a.root_copy + (s.root_off + (s.pp - 1) + d) * (int64_t)a.Kp);
+__device__ __forceinline__ int32_t* root_link(const EngineArgs& a, int64_t root_off, int32_t pp, int32_t d) {
+    return reinterpret_cast<int32_t*>(a.root_copy + (root_off + (pp - 1) + d) * (int64_t)a.Kp);
 }
-
-template <typename T>
-__device__ __forceinline__ T ld_relaxed(const T* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ Row* list_full(const EngineArgs& a, int parity, int x) {
+    return a.rows_full + ((int64_t)parity * kXcd + x) * a.pool;
 }
-
-// ---------------------------------------------------------------- grid barrier
-// Monotone arrival counter: block arrives once per step and waits until all
-// blocks of this step arrived.  Bounded spin: on overrun the error flag is
-// raised and every block leaves the loop.
-__device__ bool grid_barrier(EngineState* st, uint32_t n_blocks, uint32_t& target,
-                             int64_t spin_limit) {
-    __threadfence();
-    __syncthreads();
-    __shared__ int s_err;
-    if (threadIdx.x == 0) {
-        target += n_blocks;
-        __hip_atomic_fetch_add(&st->barrier, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        int64_t spins = 0;
-        int err = 0;
-        while (__hip_atomic_load(&st->barrier, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            __builtin_amdgcn_s_sleep(1);
-            if (++spins > spin_limit) {
-                __hip_atomic_store(&st->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                err = 1;
-                break;
-            }
-            if ((spins & 255) == 0 &&
-                __hip_atomic_load(&st->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                err = 1;
-                break;
-            }
-        }
-        if (!err) err = __hip_atomic_load(&st->error, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        s_err = err;
-    }
-    __syncthreads();
-    return s_err == 0;
+__device__ __forceinline__ Row* list_light(const EngineArgs& a, int parity, int x) {
+    return a.rows_light + ((int64_t)parity * kXcd + x) * a.pool;
 }
 
 // ---------------------------------------------------------------- row flags
-__device__ Row make_dense_row(int32_t seq, int32_t kind, int32_t m, int32_t n, int32_t t,
-                              int32_t slot, int32_t T, int32_t pp) {
-    Row r;
-    r.seq = seq; r.kind = kind; r.m = m; r.n = n; r.t = t; r.slot = slot;
+// Row of `base`'s task at time t as a dense step.
+__device__ Row make_dense_row(const Row& base, int32_t t) {
+    Row r = base;
+    const int32_t kind = r.kind, m = r.m, n = r.n, T = r.T, pp = r.pp;
+    r.t = t;
     int32_t f = 0, aux = 0;
     if (kind == KIND_VANILLA) {
         f = F_NEED_ARG | F_PSI_TABLE;
@@ -117,10 +146,12 @@ __device__ Row make_dense_row(int32_t seq, int32_t kind, int32_t m, int32_t n, i
     return r;
 }
 
-__device__ Row make_light_row(int32_t seq, int32_t kind, int32_t m, int32_t n, int32_t t,
-                              int32_t slot, int32_t op, int32_t T, int32_t pp) {
-    Row r;
-    r.seq = seq; r.kind = kind; r.m = m; r.n = n; r.t = t; r.slot = slot; r.aux = op;
+// Row of `base`'s task at time t as a light operation.
+__device__ Row make_light_row(const Row& base, int32_t t, int32_t op) {
+    Row r = base;
+    const int32_t kind = r.kind, m = r.m, n = r.n, T = r.T, pp = r.pp;
+    r.t = t;
+    r.aux = op;
     int32_t f = 0;
     if (op == L_INIT) {
         if (kind == KIND_SUB && ((m + n) >> 1) == m) f |= F_SNAP_SUB;
@@ -129,6 +160,18 @@ __device__ Row make_light_row(int32_t seq, int32_t kind, int32_t m, int32_t n, i
     }
     r.flags = f;
     return r;
+}
+
+// First row (the start step) of a task, from the per-sequence table.
+__device__ Row row_from_task(const EngineArgs& a, const Task& tk, int32_t slot) {
+    const SeqInfo& sq = a.seqs[tk.seq];
+    Row b;
+    b.seq = tk.seq; b.kind = tk.kind; b.m = tk.m; b.n = tk.n; b.t = tk.m; b.slot = slot;
+    b.flags = 0; b.aux = 0;
+    b.T = sq.T; b.pp = sq.pp;
+    b.off = tk.kind == KIND_VANILLA ? sq.psi_off : sq.root_off;
+    b.log_b = sq.log_b; b.ld = sq.ld;
+    return make_light_row(b, tk.m, L_INIT);
 }
 
 // ---------------------------------------------------------------- dense tile
@@ -164,59 +207,87 @@ __device__ __forceinline__ void tile_partial(const float* __restrict__ Ap, int32
     }
 }
 
+// Partial results of the 16 waves of a block: [wave][column][row].
 struct TileLds {
-    float m[kWaves][kTileCols][kTileRows];
-    int32_t g[kWaves][kTileCols][kTileRows];
+    float m[kEngWaves][kTileCols][kTileRows];
+    int32_t g[kEngWaves][kTileCols][kTileRows];
 };
 
+// The block's 16 waves work on 16 / nsplit tiles at once, nsplit waves per
+// tile, each wave taking a contiguous share of the predecessor groups; all
+// waves call this together (block-wide barriers inside).  A tile group
+// without a tile passes tile < 0.  nsplit is 4, 8 or 16 and block-uniform.
 __device__ void dense_tile(const EngineArgs& a, const float* __restrict__ Ap, const Row* rows,
-                           int32_t nrows, int32_t tile, TileLds& lds) {
+                           int32_t nrows, int32_t tile, int32_t nsplit, TileLds& lds) {
+    const bool active = tile >= 0;
+    if (!active) tile = 0;
     const int32_t ncb = a.Kp / kTileCols;
     const int32_t rg = tile / ncb;
     const int32_t j0 = (tile - rg * ncb) * kTileCols;
     const int32_t lane = threadIdx.x & 63;
-    const int32_t wave = threadIdx.x >> 6;
+    const int32_t bw = threadIdx.x >> 6;              // wave in block
+    const int32_t wave = bw & (nsplit - 1);           // wave in tile group
+    const int32_t wbase = bw - wave;                  // first wave of the group
+    const int32_t cpw = kTileCols / nsplit;           // output columns per wave
     const int32_t ridx = rg * kTileRows + lane;
-    const bool valid = ridx < nrows;
-    const Row r = rows[valid ? ridx : rg * kTileRows];
-    const float* drow = slot_delta(a, r.slot, (r.t - 1) & 1);
+    const bool valid = active && ridx < nrows;
+    const Row* rp = rows + (valid ? ridx : rg * kTileRows);
+    // (t, slot), log_b and ld of the row; the rest is re-read after the loop
+    const uint64_t* rw = reinterpret_cast<const uint64_t*>(rp);
+    const uint64_t w_ts = ld_c(rw + 2);
+    const int32_t t0 = (int32_t)(uint32_t)w_ts, slot0 = clampi((int32_t)(w_ts >> 32), a.n_slots);
+    const float* log_b = reinterpret_cast<const float*>(ld_c(rw + 6));
+    const int64_t ld = (int64_t)ld_c(rw + 7);
+    const float* drow = slot_delta(a, slot0, (t0 - 1) & 1);
+    // emission scores of this thread's outputs, fetched before the max-plus loop
+    const int32_t cq = wave * cpw;
+    float bpre[4];
+    {
+        const float* bt = log_b + (int64_t)t0 * ld;
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+            const int32_t j = j0 + cq + cc;
+            bpre[cc] = (valid && cc < cpw && j < a.K) ? bt[j] : 0.0f;
+        }
+    }
 
-    const int32_t split = a.Kp / kWaves;
-    const int32_t s0 = __builtin_amdgcn_readfirstlane(wave * split);
+    // predecessor groups [g0, g1) of this wave
+    const int32_t ng = a.Kp / kGroup;
+    const int32_t g0 = __builtin_amdgcn_readfirstlane((wave * ng) / nsplit);
+    const int32_t g1 = __builtin_amdgcn_readfirstlane(((wave + 1) * ng) / nsplit);
     float m[kTileCols];
     int32_t g[kTileCols];
-    tile_partial(Ap, a.Kp, __builtin_amdgcn_readfirstlane(j0), drow, s0, s0 + split, m, g);
+    tile_partial(Ap, a.Kp, __builtin_amdgcn_readfirstlane(j0), drow, g0 * kGroup,
+                 active ? g1 * kGroup : g0 * kGroup, m, g);
 #pragma unroll
     for (int c = 0; c < kTileCols; ++c) {
-        lds.m[wave][c][lane] = m[c];
-        lds.g[wave][c][lane] = g[c];
+        lds.m[bw][c][lane] = m[c];
+        lds.g[bw][c][lane] = g[c];
     }
     __syncthreads();
 
     if (valid) {
-        const SeqInfo& sq = a.seqs[r.seq];
+        const Row r = ld_row(rp);
         const int32_t t = r.t;
-        const float* bt = sq.log_b + (int64_t)t * sq.ld;
-        float* dcur = slot_delta(a, r.slot, t & 1);
+        const int32_t slot = clampi(r.slot, a.n_slots);
+        float* dcur = slot_delta(a, slot, t & 1);
         int32_t* acur = nullptr;
         const int32_t* aprev = nullptr;
         if (a.has_anc) {
-            acur = slot_anc(a, r.slot, t & 1);
-            aprev = slot_anc(a, r.slot, (t - 1) & 1);
+            acur = slot_anc(a, slot, t & 1);
+            aprev = slot_anc(a, slot, (t - 1) & 1);
         }
         unsigned long long best_key = 0;
-        const int32_t cq = wave * 4;
 #pragma unroll
         for (int cc = 0; cc < 4; ++cc) {
             const int32_t c = cq + cc;
             const int32_t j = j0 + c;
-            if (j >= a.K) break;
-            float mv = lds.m[0][c][lane];
-            int32_t gi = lds.g[0][c][lane];
-#pragma unroll
-            for (int w = 1; w < kWaves; ++w) {
-                const float x = lds.m[w][c][lane];
-                if (x > mv) { mv = x; gi = lds.g[w][c][lane]; }
+            if (cc >= cpw || j >= a.K) break;
+            float mv = lds.m[wbase][c][lane];
+            int32_t gi = lds.g[wbase][c][lane];
+            for (int w = 1; w < nsplit; ++w) {
+                const float x = lds.m[wbase + w][c][lane];
+                if (x > mv) { mv = x; gi = lds.g[wbase + w][c][lane]; }
             }
             float val = mv;
             int32_t psi = 0;
@@ -237,25 +308,26 @@ __device__ void dense_tile(const EngineArgs& a, const float* __restrict__ Ap, co
                     if (psi < 0 && x3 == mv) { psi = src0 + k + 3; val = x3; }
                 }
                 if (psi < 0) psi = src0;  // unreachable for finite/-inf inputs
+                psi = clampi(psi, a.K);
             }
-            const float dnew = val + bt[j];
+            const float dnew = val + bpre[cc];
             dcur[j] = dnew;
             const int32_t f = r.flags;
-            if (f & F_PSI_TABLE) a.psi16[sq.psi_off + (int64_t)t * a.K + j] = (uint16_t)psi;
+            if (f & F_PSI_TABLE) a.psi16[r.off + (int64_t)t * a.K + j] = (uint16_t)psi;
             int32_t anc = 0;
             if (f & F_ANC_FIRST) { anc = psi; acur[j] = anc; }
-            else if (f & F_ANC_CHAIN) { anc = aprev[psi]; acur[j] = anc; }
-            if (f & F_SNAP_SUB) slot_snap(a, r.slot)[j] = dnew;
+            else if (f & F_ANC_CHAIN) { anc = clampi(aprev[psi], a.K); acur[j] = anc; }
+            if (f & F_SNAP_SUB) slot_snap(a, slot)[j] = dnew;
             if (f & F_SNAP_ROOT) {
-                root_dsnap(a, sq, r.aux)[j] = dnew;
-                if (r.aux >= 1) root_link(a, sq, r.aux)[j] = anc;
+                root_dsnap(a, r.off, r.aux)[j] = dnew;
+                if (r.aux >= 1) root_link(a, r.off, r.pp, r.aux)[j] = anc;
             }
             if (f & F_FINAL) {
                 const unsigned long long k = order_key(dnew, j);
                 if (k > best_key) best_key = k;
             }
         }
-        if (r.flags & F_FINAL) atomicMax(&a.keys[r.seq], best_key);
+        if (r.flags & F_FINAL) key_max(&a.keys[r.seq], best_key);
     }
     __syncthreads();
 }
@@ -270,20 +342,24 @@ __device__ __forceinline__ void wave_argmax(float& v, int32_t& idx) {
     }
 }
 
+// One wave: the O(K) operations of a task (start step, end-only step,
+// final selection and boundary resolution).
 __device__ void light_row(const EngineArgs& a, const float* __restrict__ Ap, const Row& r) {
     const int32_t lane = threadIdx.x & 63;
     SeqInfo& sq = a.seqs[r.seq];
     const int32_t K = a.K, Kp = a.Kp;
+    const int32_t slot = clampi(r.slot, a.n_slots);
     if (r.aux == L_INIT) {
         const int32_t m = r.m;
-        float* dst = slot_delta(a, r.slot, m & 1);
-        float* oth = slot_delta(a, r.slot, (m + 1) & 1);
-        const float* bm = sq.log_b + (int64_t)m * sq.ld;
+        float* dst = slot_delta(a, slot, m & 1);
+        float* oth = slot_delta(a, slot, (m + 1) & 1);
+        const float* bm = r.log_b + (int64_t)m * r.ld;
         int32_t q = -1;
         float alpha = 0.0f;
         if (m > 0) {
-            q = sq.path[m - 1];
-            alpha = a.alpha_at[sq.alpha_off + m - 1];
+            q = ld_c(sq.path + m - 1);
+            alpha = ld_cf(a.alpha_at + sq.alpha_off + m - 1);
+            if (q >= K) q = -1;
         }
         unsigned long long best_key = 0;
         for (int32_t j = lane; j < Kp; j += 64) {
@@ -291,8 +367,8 @@ __device__ void light_row(const EngineArgs& a, const float* __restrict__ Ap, con
             if (j < K) {
                 if (m == 0) v = a.log_pi ? a.log_pi[j] + bm[j] : bm[j];
                 else if (q >= 0) { const float c = alpha + Ap[(int64_t)q * Kp + j]; v = c + bm[j]; }
-                if (r.flags & F_SNAP_SUB) slot_snap(a, r.slot)[j] = v;
-                if (r.flags & F_SNAP_ROOT) root_dsnap(a, sq, 0)[j] = v;
+                if (r.flags & F_SNAP_SUB) slot_snap(a, slot)[j] = v;
+                if (r.flags & F_SNAP_ROOT) root_dsnap(a, r.off, 0)[j] = v;
                 if (r.flags & F_FINAL) {
                     const unsigned long long k = order_key(v, j);
                     if (k > best_key) best_key = k;
@@ -307,15 +383,15 @@ __device__ void light_row(const EngineArgs& a, const float* __restrict__ Ap, con
                 const unsigned long long o = __shfl_xor(best_key, off, 64);
                 if (o > best_key) best_key = o;
             }
-            if (lane == 0) atomicMax(&a.keys[r.seq], best_key);
+            if (lane == 0) key_max(&a.keys[r.seq], best_key);
         }
     } else if (r.aux == L_END) {
         // only the known end state q*_n is evaluated at a subtask's last step
-        if (ld_relaxed(&sq.status) != FV_OK) return;
+        if (ld_c(&sq.status) != FV_OK) return;
         const int32_t n = r.n, tmid = (r.m + r.n) >> 1;
-        const int32_t qn = sq.path[n];
-        if (qn < 0) return;
-        const float* dprev = slot_delta(a, r.slot, (n - 1) & 1);
+        const int32_t qn = ld_c(sq.path + n);
+        if (qn < 0 || qn >= K) return;
+        const float* dprev = slot_delta(a, slot, (n - 1) & 1);
         const float* ac = a.Acol + qn;  // column q*_n of log A
         float best = -INFINITY;
         int32_t arg = 0x7fffffff;
@@ -325,35 +401,34 @@ __device__ void light_row(const EngineArgs& a, const float* __restrict__ Ap, con
         }
         wave_argmax(best, arg);
         if (lane == 0) {
-            const int32_t qmid = (n == tmid + 1) ? arg : slot_anc(a, r.slot, (n - 1) & 1)[arg];
-            sq.path[tmid] = qmid;
-            a.alpha_at[sq.alpha_off + tmid] = slot_snap(a, r.slot)[qmid];
+            arg = clampi(arg, K);
+            const int32_t qmid = clampi((n == tmid + 1) ? arg : slot_anc(a, slot, (n - 1) & 1)[arg], K);
+            st_c(sq.path + tmid, qmid);
+            st_cf(a.alpha_at + sq.alpha_off + tmid, slot_snap(a, slot)[qmid]);
         }
     } else {  // L_FINALIZE
-        const int32_t T = sq.T;
-        const unsigned long long key = a.keys[r.seq];
-        int32_t qT = (int32_t)(0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull));
-        if (qT < 0 || qT >= K) qT = 0;  // no key arrived: cannot happen for T >= 1
-        const float sc = slot_delta(a, r.slot, (T - 1) & 1)[qT];
+        const int32_t T = r.T;
+        const unsigned long long key = ld_c(a.keys + r.seq);
+        const int32_t qT = clampi((int32_t)(0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull)), K);
+        const float sc = slot_delta(a, slot, (T - 1) & 1)[qT];
         if (sc == -INFINITY) {
-            for (int32_t t = lane; t < T; t += 64) sq.path[t] = -1;
+            for (int32_t t = lane; t < T; t += 64) st_c(sq.path + t, -1);
             if (lane == 0) {
-                *sq.score = sc;
-                __hip_atomic_store(&sq.status, (int32_t)FV_E_INFEASIBLE, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+                st_cf(sq.score, sc);
+                st_c(&sq.status, (int32_t)FV_E_INFEASIBLE);
             }
             return;
         }
         if (lane == 0) {
-            *sq.score = sc;
-            sq.path[T - 1] = qT;
-            if (r.kind == KIND_ROOT && sq.pp >= 2) {
-                int32_t q = slot_anc(a, r.slot, (T - 1) & 1)[qT];
-                for (int32_t d = sq.pp - 2; d >= 0; --d) {
-                    const int64_t e = seg_end(T, sq.pp, d);
-                    sq.path[e] = q;
-                    a.alpha_at[sq.alpha_off + e] = root_dsnap(a, sq, d)[q];
-                    if (d >= 1) q = root_link(a, sq, d)[q];
+            st_cf(sq.score, sc);
+            st_c(sq.path + T - 1, qT);
+            if (r.kind == KIND_ROOT && r.pp >= 2) {
+                int32_t q = clampi(slot_anc(a, slot, (T - 1) & 1)[qT], K);
+                for (int32_t d = r.pp - 2; d >= 0; --d) {
+                    const int64_t e = seg_end(T, r.pp, d);
+                    st_c(sq.path + e, q);
+                    st_cf(a.alpha_at + sq.alpha_off + e, root_dsnap(a, r.off, d)[q]);
+                    if (d >= 1) q = clampi(root_link(a, r.off, r.pp, d)[q], K);
                 }
             }
         }
@@ -361,35 +436,7 @@ __device__ void light_row(const EngineArgs& a, const float* __restrict__ Ap, con
 }
 
 // ---------------------------------------------------------------- scheduler
-struct SchedLds {
-    int32_t scan[4][kBlock];
-    int32_t tot[4];
-};
-
-// exclusive block scan of four counters at once
-__device__ void block_scan4(int32_t (&v)[4], int32_t (&tot)[4], SchedLds& lds) {
-    const int tid = threadIdx.x;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) lds.scan[k][tid] = v[k];
-    __syncthreads();
-    for (int off = 1; off < kBlock; off <<= 1) {
-        int32_t add[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) add[k] = tid >= off ? lds.scan[k][tid - off] : 0;
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < 4; ++k) lds.scan[k][tid] += add[k];
-        __syncthreads();
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        tot[k] = lds.scan[k][kBlock - 1];
-        v[k] = lds.scan[k][tid] - v[k];
-    }
-    __syncthreads();
-}
-
-// What a row of step s turns into at step s+1.
+// What a row of step s turns into at step s+1 (its XCD never changes).
 struct Next {
     int32_t has_full, has_light, freed, spawn;
     Row full, light;
@@ -404,26 +451,25 @@ __device__ int32_t root_segments(int32_t T, int32_t pp) {
     return c;
 }
 
-__device__ Next classify(const EngineArgs& a, const Row& r, bool from_full) {
+__device__ Next classify(const Row& r, bool from_full) {
     Next x;
     x.has_full = x.has_light = x.freed = x.spawn = 0;
-    const SeqInfo& sq = a.seqs[r.seq];
-    const int32_t T = sq.T, pp = sq.pp;
+    const int32_t T = r.T, pp = r.pp;
     if (from_full) {
         if (r.kind == KIND_SUB) {
-            if (r.t + 1 < r.n) { x.has_full = 1; x.full = make_dense_row(r.seq, r.kind, r.m, r.n, r.t + 1, r.slot, T, pp); }
-            else { x.has_light = 1; x.light = make_light_row(r.seq, r.kind, r.m, r.n, r.n, r.slot, L_END, T, pp); }
+            if (r.t + 1 < r.n) { x.has_full = 1; x.full = make_dense_row(r, r.t + 1); }
+            else { x.has_light = 1; x.light = make_light_row(r, r.n, L_END); }
         } else {
-            if (r.t + 1 < T) { x.has_full = 1; x.full = make_dense_row(r.seq, r.kind, r.m, r.n, r.t + 1, r.slot, T, pp); }
-            else { x.has_light = 1; x.light = make_light_row(r.seq, r.kind, r.m, r.n, T, r.slot, L_FINALIZE, T, pp); }
+            if (r.t + 1 < T) { x.has_full = 1; x.full = make_dense_row(r, r.t + 1); }
+            else { x.has_light = 1; x.light = make_light_row(r, T, L_FINALIZE); }
         }
     } else if (r.aux == L_INIT) {
         if (r.kind == KIND_SUB) {
-            if (r.m + 1 < r.n) { x.has_full = 1; x.full = make_dense_row(r.seq, r.kind, r.m, r.n, r.m + 1, r.slot, T, pp); }
-            else { x.has_light = 1; x.light = make_light_row(r.seq, r.kind, r.m, r.n, r.n, r.slot, L_END, T, pp); }
+            if (r.m + 1 < r.n) { x.has_full = 1; x.full = make_dense_row(r, r.m + 1); }
+            else { x.has_light = 1; x.light = make_light_row(r, r.n, L_END); }
         } else {
-            if (T > 1) { x.has_full = 1; x.full = make_dense_row(r.seq, r.kind, r.m, r.n, 1, r.slot, T, pp); }
-            else { x.has_light = 1; x.light = make_light_row(r.seq, r.kind, r.m, r.n, T, r.slot, L_FINALIZE, T, pp); }
+            if (T > 1) { x.has_full = 1; x.full = make_dense_row(r, 1); }
+            else { x.has_light = 1; x.light = make_light_row(r, T, L_FINALIZE); }
         }
     } else if (r.aux == L_END) {
         x.freed = 1;
@@ -436,6 +482,7 @@ __device__ Next classify(const EngineArgs& a, const Row& r, bool from_full) {
     return x;
 }
 
+// Children per Alg. 1 (END) or the P'-way segments of a finished root.
 __device__ void write_spawns(const EngineArgs& a, const Row& r, int64_t pos) {
     if (r.aux == L_END) {
         const int32_t tmid = (r.m + r.n) >> 1;
@@ -443,8 +490,7 @@ __device__ void write_spawns(const EngineArgs& a, const Row& r, int64_t pos) {
         if (len >= 2) a.queue[pos++] = Task{r.seq, KIND_SUB, r.m, tmid};
         if (len > 2) a.queue[pos++] = Task{r.seq, KIND_SUB, tmid + 1, r.n};
     } else {
-        const SeqInfo& sq = a.seqs[r.seq];
-        const int32_t T = sq.T, pp = sq.pp;
+        const int32_t T = r.T, pp = r.pp;
         for (int32_t d = 0; d < pp; ++d) {
             const int64_t m = d == 0 ? 0 : seg_end(T, pp, d - 1) + 1, n = seg_end(T, pp, d);
             if (n - m >= 1) a.queue[pos++] = Task{r.seq, KIND_SUB, (int32_t)m, (int32_t)n};
@@ -452,59 +498,205 @@ __device__ void write_spawns(const EngineArgs& a, const Row& r, int64_t pos) {
     }
 }
 
-__device__ void scheduler(const EngineArgs& a, int32_t s, SchedLds& lds) {
-    const int cur = s & 1, nxt = cur ^ 1;
-    EngineState* st = a.st;
-    const int32_t nf = ld_relaxed(&st->n_full[cur]);
-    const int32_t nl = ld_relaxed(&st->n_light[cur]);
-    const Row* F = a.rows_full + (int64_t)cur * a.max_rows;
-    const Row* L = a.rows_light + (int64_t)cur * a.max_rows;
-    Row* F2 = a.rows_full + (int64_t)nxt * a.max_rows;
-    Row* L2 = a.rows_light + (int64_t)nxt * a.max_rows;
-    const int32_t total = nf + nl;
-    const int32_t per = (total + kBlock - 1) / kBlock;
-    const int32_t lo = min(total, (int32_t)threadIdx.x * per), hi = min(total, lo + per);
+// The scheduler block splits into kXcd groups of 128 threads; group x
+// handles the rows of XCD x.  Its state lives in LDS.
+constexpr int kSchedGroup = kEngBlock / kXcd;
+constexpr int kSchedGroupWaves = kSchedGroup / 64;
 
-    int32_t cnt[4] = {0, 0, 0, 0};  // full, light, freed, spawned
-    for (int32_t i = lo; i < hi; ++i) {
-        const bool ff = i < nf;
-        const Next x = classify(a, ff ? F[i] : L[i - nf], ff);
-        cnt[0] += x.has_full; cnt[1] += x.has_light; cnt[2] += x.freed; cnt[3] += x.spawn;
+struct SchedLds {
+    int32_t q_head, q_tail, max_rows;
+    int32_t n_free[kXcd];
+    int32_t has_blocks[kXcd];
+    int32_t admit[kXcd];
+    int32_t spawn_total[kXcd];
+    int32_t n_full_next[kXcd];
+    int32_t n_light_next[kXcd];
+    int32_t wave_sums[kXcd][kSchedGroupWaves][4];
+};
+
+// Exclusive scan of 4 counters over the 128 threads of a scheduler group.
+__device__ void group_scan4(int32_t (&v)[4], int32_t (&tot)[4], int32_t (&ws)[kSchedGroupWaves][4]) {
+    const int lane = threadIdx.x & 63, w = (threadIdx.x >> 6) % kSchedGroupWaves;
+    int32_t inc[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        int32_t x = v[k];
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int32_t y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        inc[k] = x;
+        if (lane == 63) ws[w][k] = x;
     }
-    int32_t tot[4];
-    block_scan4(cnt, tot, lds);
-    const int32_t n_free0 = ld_relaxed(&st->n_free);
-    const int32_t q_tail0 = ld_relaxed(&st->q_tail);
-    const int32_t q_head = ld_relaxed(&st->q_head);
-    for (int32_t i = lo; i < hi; ++i) {
-        const bool ff = i < nf;
-        const Row r = ff ? F[i] : L[i - nf];
-        const Next x = classify(a, r, ff);
-        if (x.has_full) F2[cnt[0]++] = x.full;
-        if (x.has_light) L2[cnt[1]++] = x.light;
-        if (x.freed) a.free_stack[n_free0 + cnt[2]++] = r.slot;
-        if (x.spawn) { write_spawns(a, r, (int64_t)q_tail0 + cnt[3]); cnt[3] += x.spawn; }
-    }
-    __threadfence_block();
     __syncthreads();
-    const int32_t n_free = n_free0 + tot[2];
-    const int32_t q_tail = q_tail0 + tot[3];
-    const int32_t n_admit = min(n_free, q_tail - q_head);
-    for (int32_t k = threadIdx.x; k < n_admit; k += kBlock) {
-        const Task tk = a.queue[q_head + k];
-        const int32_t slot = a.free_stack[n_free - 1 - k];
-        const SeqInfo& sq = a.seqs[tk.seq];
-        L2[tot[1] + k] = make_light_row(tk.seq, tk.kind, tk.m, tk.n, tk.m, slot, L_INIT, sq.T, sq.pp);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        int32_t before = 0, all = 0;
+#pragma unroll
+        for (int u = 0; u < kSchedGroupWaves; ++u) {
+            const int32_t y = ws[u][k];
+            if (u < w) before += y;
+            all += y;
+        }
+        tot[k] = all;
+        v[k] = before + inc[k] - v[k];
+    }
+    __syncthreads();
+}
+
+// Admit queued tasks to the free slots of the XCDs that have compute
+// blocks, in proportion to their free slots, and write their start rows.
+// Called by the whole scheduler block; sl.n_light_next[x] holds the light
+// rows already written for step nxt.
+__device__ void admit(const EngineArgs& a, SchedLds& sl, int nxt) {
+    if (threadIdx.x == 0) {
+        int32_t free_total = 0;
+        for (int x = 0; x < kXcd; ++x) free_total += sl.has_blocks[x] ? sl.n_free[x] : 0;
+        const int32_t n_admit = min(free_total, sl.q_tail - sl.q_head);
+        int32_t given = 0;
+        for (int x = 0; x < kXcd; ++x) {
+            const int32_t f = sl.has_blocks[x] ? sl.n_free[x] : 0;
+            const int32_t ax = free_total ? (int32_t)((int64_t)n_admit * f / free_total) : 0;
+            sl.admit[x] = ax;
+            given += ax;
+        }
+        for (int x = 0; x < kXcd && given < n_admit; ++x) {
+            const int32_t f = sl.has_blocks[x] ? sl.n_free[x] : 0;
+            const int32_t more = min(f - sl.admit[x], n_admit - given);
+            sl.admit[x] += more;
+            given += more;
+        }
+    }
+    __syncthreads();
+    const int x = threadIdx.x / kSchedGroup, tg = threadIdx.x % kSchedGroup;
+    int32_t qbase = sl.q_head;
+    for (int y = 0; y < x; ++y) qbase += sl.admit[y];
+    const int32_t ax = sl.admit[x];
+    for (int32_t k = tg; k < ax; k += kSchedGroup) {
+        const int32_t slot = a.free_stack[(int64_t)x * a.pool + sl.n_free[x] - 1 - k];
+        st_row(list_light(a, nxt, x) + sl.n_light_next[x] + k, row_from_task(a, a.queue[qbase + k], slot));
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t tot = 0;
+        for (int y = 0; y < kXcd; ++y) {
+            sl.q_head += sl.admit[y];
+            sl.n_free[y] -= sl.admit[y];
+            sl.n_light_next[y] += sl.admit[y];
+            st_c(&a.st->cnt[nxt][y][0], sl.n_full_next[y]);
+            st_c(&a.st->cnt[nxt][y][1], sl.n_light_next[y]);
+            tot += sl.n_full_next[y] + sl.n_light_next[y];
+        }
+        st_c(&a.st->total[nxt], tot);
+        if (tot > sl.max_rows) sl.max_rows = tot;
+        st_c(&a.st->max_rows, sl.max_rows);
+    }
+    __syncthreads();
+}
+
+__device__ void scheduler(const EngineArgs& a, int32_t s, SchedLds& sl) {
+    const int cur = s & 1, nxt = cur ^ 1;
+    const int x = threadIdx.x / kSchedGroup, tg = threadIdx.x % kSchedGroup;
+    const int32_t nf = ld_c(&a.st->cnt[cur][x][0]);
+    const int32_t nl = ld_c(&a.st->cnt[cur][x][1]);
+    const int32_t total = nf + nl;
+    const int32_t per = (total + kSchedGroup - 1) / kSchedGroup;
+    const int32_t lo = min(total, tg * per), hi = min(total, lo + per);
+    const Row* F = list_full(a, cur, x);
+    const Row* L = list_light(a, cur, x);
+
+    // pass 0 counts what the group's rows turn into, pass 1 writes it
+    int32_t cnt[4] = {0, 0, 0, 0}, tot[4] = {0, 0, 0, 0};  // full, light, freed, spawned
+    for (int pass = 0; pass < 2; ++pass) {
+        if (pass == 1) {
+            group_scan4(cnt, tot, sl.wave_sums[x]);
+            if (tg == 0) sl.spawn_total[x] = tot[3];
+            __syncthreads();
+            int32_t qoff = sl.q_tail;
+            for (int y = 0; y < x; ++y) qoff += sl.spawn_total[y];
+            cnt[3] += qoff;
+        }
+        for (int32_t i = lo; i < hi; ++i) {
+            const bool ff = i < nf;
+            const Row r = ld_row(ff ? F + i : L + (i - nf));
+            const Next n = classify(r, ff);
+            if (pass == 0) {
+                cnt[0] += n.has_full; cnt[1] += n.has_light; cnt[2] += n.freed; cnt[3] += n.spawn;
+            } else {
+                if (n.has_full) st_row(list_full(a, nxt, x) + cnt[0]++, n.full);
+                if (n.has_light) st_row(list_light(a, nxt, x) + cnt[1]++, n.light);
+                if (n.freed) a.free_stack[(int64_t)x * a.pool + sl.n_free[x] + cnt[2]++] = r.slot;
+                if (n.spawn) { write_spawns(a, r, (int64_t)cnt[3]); cnt[3] += n.spawn; }
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int y = 0; y < kXcd; ++y) sl.q_tail += sl.spawn_total[y];
+    }
+    if (tg == 0) {
+        sl.n_free[x] += tot[2];
+        sl.n_full_next[x] = tot[0];
+        sl.n_light_next[x] = tot[1];
+    }
+    __syncthreads();
+    admit(a, sl, nxt);
+}
+
+// ---------------------------------------------------------------- step barrier
+// Compute blocks publish their writes (agent-scope release), store their
+// arrival flag, wait for their XCD's release flag and acquire (agent scope).
+// The scheduler block is the master: it waits for every arrival, acquires,
+// releases, then raises the 8 release flags.  One block per CU keeps the
+// per-block cache maintenance of the fences to 256 operations per step.
+// Spins are bounded; on overrun the error flag is raised and every block
+// leaves the step loop.
+__device__ bool barrier_arrive_wait(const EngineArgs& a, uint32_t epoch, uint32_t x) {
+    __shared__ int s_err;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        st_c(a.arrive + blockIdx.x, epoch);
+        int err = 0;
+        int64_t spins = 0;
+        while (ld_c(&a.st->go[x][0]) < epoch) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > a.spin_limit) { st_c(&a.st->error, 1); err = 1; break; }
+            if ((spins & 255) == 0 && ld_c(&a.st->error)) { err = 1; break; }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        s_err = err || ld_c(&a.st->error) != 0;
+    }
+    __syncthreads();
+    return s_err == 0;
+}
+
+__device__ bool barrier_master(const EngineArgs& a, uint32_t epoch) {
+    __shared__ int s_err;
+    __syncthreads();
+    int64_t spins = 0;
+    int err = 0;
+    for (;;) {
+        int ok = 1;
+        for (int32_t b = 1 + threadIdx.x; b <= a.n_compute_blocks; b += kEngBlock)
+            if (ld_c(a.arrive + b) < epoch) ok = 0;
+        if (__syncthreads_and(ok)) break;
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > a.spin_limit) { err = 1; break; }
     }
     if (threadIdx.x == 0) {
-        st->q_head = q_head + n_admit;
-        st->q_tail = q_tail;
-        st->n_free = n_free - n_admit;
-        st->n_full[nxt] = tot[0];
-        st->n_light[nxt] = tot[1] + n_admit;
-        const int32_t inflight = tot[0] + tot[1] + n_admit;
-        if (inflight > st->max_rows) st->max_rows = inflight;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     }
+    __syncthreads();
+    if (threadIdx.x < kXcd) {
+        if (err) st_c(&a.st->error, 1);
+        st_c(&a.st->go[threadIdx.x][0], epoch);
+    }
+    if (threadIdx.x == 0) s_err = err || ld_c(&a.st->error) != 0;
+    __syncthreads();
+    return s_err == 0;
 }
 
 // ---------------------------------------------------------------- engine
@@ -513,41 +705,82 @@ union EngineLds {
     SchedLds sched;
 };
 
-extern "C" __global__ __launch_bounds__(kBlock) void fv_engine_kernel(const float* __restrict__ Ap,
-                                                                      EngineArgs a) {
+extern "C" __global__ __launch_bounds__(kEngBlock) void fv_engine_kernel(const float* __restrict__ Ap,
+                                                                         EngineArgs a) {
     __shared__ EngineLds lds;
-    uint32_t target = 0;
-    const uint32_t n_blocks = gridDim.x;
-    int32_t s = 0;
-    for (;; ++s) {
-        const int cur = s & 1;
-        const int32_t nf = ld_relaxed(&a.st->n_full[cur]);
-        const int32_t nl = ld_relaxed(&a.st->n_light[cur]);
-        if (nf + nl == 0) break;
-        if (s > a.max_steps) {  // schedule longer than any valid one: report, stop
-            if (blockIdx.x == 0 && threadIdx.x == 0) a.st->error = 2;
-            break;
-        }
-        if ((int32_t)blockIdx.x == a.n_compute_blocks) {
-            scheduler(a, s, lds.sched);
-        } else {
-            const Row* F = a.rows_full + (int64_t)cur * a.max_rows;
-            const Row* L = a.rows_light + (int64_t)cur * a.max_rows;
-            const int32_t n_tiles = ((nf + kTileRows - 1) / kTileRows) * (a.Kp / kTileCols);
-            const int32_t n_light_items = (nl + kWaves - 1) / kWaves;
-            const int32_t n_items = n_tiles + n_light_items;
-            for (int32_t it = blockIdx.x; it < n_items; it += a.n_compute_blocks) {
-                if (it < n_tiles) {
-                    dense_tile(a, Ap, F, nf, it, lds.tile);
-                } else {
-                    const int32_t li = (it - n_tiles) * kWaves + (threadIdx.x >> 6);
-                    if (li < nl) light_row(a, Ap, L[li]);
-                }
+    __shared__ int32_t s_rank;
+    const bool is_sched = blockIdx.x == 0;
+    const uint32_t x = my_xcd();
+    if (!is_sched && threadIdx.x == 0)
+        s_rank = (int32_t)__hip_atomic_fetch_add(&a.st->xcd_blocks[x][0], 1u, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_SYSTEM);
+    uint32_t epoch = 1;
+    bool ok = is_sched ? barrier_master(a, epoch) : barrier_arrive_wait(a, epoch, x);
+    const int32_t rank = s_rank;
+    const int32_t nx = (int32_t)ld_c(&a.st->xcd_blocks[x][0]);
+
+    if (is_sched) {
+        SchedLds& sl = lds.sched;
+        if (threadIdx.x == 0) {
+            sl.q_head = 0;
+            sl.q_tail = ld_c(&a.st->q_tail0);
+            sl.max_rows = 0;
+            for (int y = 0; y < kXcd; ++y) {
+                sl.n_free[y] = a.pool;
+                sl.has_blocks[y] = ld_c(&a.st->xcd_blocks[y][0]) > 0;
+                sl.n_full_next[y] = 0;
+                sl.n_light_next[y] = 0;
             }
         }
-        if (!grid_barrier(a.st, n_blocks, target, a.spin_limit)) break;
+        __syncthreads();
+        if (ok) admit(a, sl, 0);
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.st->steps = s;
+    ++epoch;
+    if (ok) ok = is_sched ? barrier_master(a, epoch) : barrier_arrive_wait(a, epoch, x);
+
+    int32_t s = 0;
+    for (; ok; ++s) {
+        const int cur = s & 1;
+        if (ld_c(&a.st->total[cur]) == 0) break;
+        if (s > a.max_steps) {  // schedule longer than any valid one: report, stop
+            if (is_sched && threadIdx.x == 0) st_c(&a.st->error, 2);
+            break;
+        }
+        if (is_sched) {
+            scheduler(a, s, lds.sched);
+        } else {
+            const int32_t nf = ld_c(&a.st->cnt[cur][x][0]);
+            const int32_t nl = ld_c(&a.st->cnt[cur][x][1]);
+            const Row* F = list_full(a, cur, x);
+            const Row* L = list_light(a, cur, x);
+            const int32_t n_tiles = ((nf + kTileRows - 1) / kTileRows) * (a.Kp / kTileCols);
+            // tiles per block round (tpb) and waves per tile (16 / tpb): the
+            // block's time is about rounds x tpb tile-units; take the least,
+            // the larger tpb on ties (fewer rounds)
+            int32_t nsplit = kEngWaves;
+            while (nsplit > 4 && nsplit * kGroup > a.Kp) nsplit >>= 1;
+            int32_t tpb = kEngWaves / nsplit;
+            {
+                int32_t best = 0x7fffffff;
+                for (int32_t t = kEngWaves / nsplit; t <= 4; t <<= 1) {
+                    const int32_t cost = (n_tiles + nx * t - 1) / (nx * t) * t;
+                    if (cost <= best) { best = cost; tpb = t; }
+                }
+                nsplit = kEngWaves / tpb;
+            }
+            const int32_t group = (threadIdx.x >> 6) / nsplit;
+            for (int32_t base = rank * tpb; base < n_tiles; base += nx * tpb) {
+                const int32_t it = base + group;
+                dense_tile(a, Ap, F, nf, it < n_tiles ? it : -1, nsplit, lds.tile);
+            }
+            // light rows: one per wave
+            for (int32_t li = rank * kEngWaves + (threadIdx.x >> 6); li < nl; li += nx * kEngWaves)
+                light_row(a, Ap, ld_row(L + li));
+        }
+        ++epoch;
+        ok = is_sched ? barrier_master(a, epoch) : barrier_arrive_wait(a, epoch, x);
+    }
+    if (is_sched && threadIdx.x == 0) st_c(&a.st->steps, s);
 }
 
 // ---------------------------------------------------------------- preparation kernel
@@ -635,26 +868,17 @@ extern "C" __global__ __launch_bounds__(kBlock) void fv_setup_kernel(EngineArgs 
         n_tasks += (int32_t)scan[0][kBlock - 1];
         __syncthreads();
     }
-    for (int32_t k = tid; k < a.n_slots; k += kBlock) a.free_stack[k] = a.n_slots - 1 - k;
-    const int32_t n_admit = min(a.n_slots, n_tasks);
-    for (int32_t k = tid; k < n_admit; k += kBlock) {
-        const Task tk = a.queue[k];
-        const int32_t slot = a.free_stack[a.n_slots - 1 - k];
-        const SeqInfo& sq = a.seqs[tk.seq];
-        a.rows_light[k] = make_light_row(tk.seq, tk.kind, tk.m, tk.n, 0, slot, L_INIT, sq.T, sq.pp);
+    // slot pools: pool x holds slots x, x + kXcd, ... (free stack order is irrelevant)
+    for (int32_t k = tid; k < a.n_slots; k += kBlock) {
+        const int32_t x = k % kXcd, i = k / kXcd;
+        a.free_stack[(int64_t)x * a.pool + i] = k;
     }
-    if (tid == 0) {
-        EngineState* st = a.st;
-        st->barrier = 0;
-        st->error = 0;
-        st->n_full[0] = 0; st->n_full[1] = 0;
-        st->n_light[0] = n_admit; st->n_light[1] = 0;
-        st->q_head = n_admit;
-        st->q_tail = n_tasks;
-        st->n_free = a.n_slots - n_admit;
-        st->steps = 0;
-        st->max_rows = n_admit;
-    }
+    EngineState* st = a.st;
+    int32_t* words = reinterpret_cast<int32_t*>(st);
+    for (int32_t k = tid; k < (int32_t)(sizeof(EngineState) / 4); k += kBlock) words[k] = 0;
+    for (int32_t k = tid; k < a.n_compute_blocks + 1; k += kBlock) a.arrive[k] = 0;
+    __syncthreads();
+    if (tid == 0) st->q_tail0 = n_tasks;
 }
 
 // Vanilla backtracking through the packed table and per-sequence status.
@@ -663,7 +887,7 @@ extern "C" __global__ __launch_bounds__(kBlock) void fv_finish_kernel(EngineArgs
     if (b >= a.n_seqs) return;
     SeqInfo& sq = a.seqs[b];
     int32_t stv = sq.status;
-    if (a.st->error) stv = FV_E_DEVICE;
+    if (a.st->error) stv = FV_E_DEVICE;  // kernel boundary: plain load is coherent
     if (stv == FV_OK && a.method == FV_VANILLA && sq.T > 1) {
         int32_t q = sq.path[sq.T - 1];
         const uint16_t* tab = a.psi16 + sq.psi_off;

@@ -34,6 +34,8 @@ enum : int32_t {
 // Light (O(K)) operations.
 enum : int32_t { L_INIT = 0, L_END = 1, L_FINALIZE = 2 };
 
+// A task in flight; carries what every step needs so that tiles do not
+// look up the per-sequence table.
 struct Row {
     int32_t seq;
     int32_t kind;
@@ -42,6 +44,10 @@ struct Row {
     int32_t slot;      // buffer slot
     int32_t flags;     // F_* (dense rows)
     int32_t aux;       // L_* for light rows; division index for F_SNAP_ROOT
+    int32_t T, pp;     // sequence length and effective parallelism
+    int64_t off;       // vanilla: backpointer table offset; root: division copy offset
+    const float* log_b;
+    int64_t ld;
 };
 
 struct Task {
@@ -62,17 +68,24 @@ struct SeqInfo {
     int32_t pad_;
 };
 
+// XCD-partitioned control block.  Buffer slot s belongs to XCD s % kXcd;
+// only blocks running on that XCD touch its row buffers, so those buffers
+// are communicated through that XCD's L2.  Everything below is shared by
+// all XCDs and is accessed with coherent (sc1) loads and stores.
+constexpr int kXcd = 8;
+constexpr int kLine = 32;  // uint32 per 128-byte line
+
 struct EngineState {
-    uint32_t barrier;      // grid barrier arrivals (monotone)
-    int32_t error;
-    int32_t n_full[2];
-    int32_t n_light[2];
-    int32_t q_head;
-    int32_t q_tail;
-    int32_t n_free;
-    int32_t steps;         // global steps executed
-    int32_t max_rows;      // high-water mark of rows in flight
-    int32_t pad_[5];
+    int32_t error;              // nonzero: watchdog or step guard fired
+    int32_t steps;              // global steps executed
+    int32_t max_rows;           // high-water mark of rows in flight
+    int32_t q_tail0;            // tasks queued by the setup kernel
+    int32_t pad0[kLine - 4];
+    int32_t cnt[2][kXcd][2];    // [parity][xcd][full, light] rows of a step
+    int32_t total[2];           // rows of a step over all XCDs
+    int32_t pad1[kLine - 2];
+    uint32_t go[kXcd][kLine];   // barrier release flags, one line per XCD
+    uint32_t xcd_blocks[kXcd][kLine];  // compute blocks per XCD (counted at start)
 };
 
 // Everything the persistent engine needs (one model).
@@ -88,7 +101,7 @@ struct EngineArgs {
     // storage
     float* slot_base;           // slots * slot_floats
     int64_t slot_floats;        // floats per slot
-    int32_t n_slots;
+    int32_t n_slots;            // multiple of kXcd
     int32_t has_anc;            // slots carry anc[2] + snap
     float* alpha_at;            // sum T floats
     float* root_copy;           // division copies (delta and link), units of Kp
@@ -96,13 +109,14 @@ struct EngineArgs {
     unsigned long long* keys;   // final arg max keys [n_seqs]
     // scheduling
     EngineState* st;
-    Row* rows_full;             // [2][max_rows]
-    Row* rows_light;            // [2][max_rows]
-    int32_t max_rows;
+    uint32_t* arrive;           // [gridDim] barrier arrival flags
+    Row* rows_full;             // [2][kXcd][pool] rows of a step, per XCD
+    Row* rows_light;            // [2][kXcd][pool]
+    int32_t pool;               // slots per XCD (= n_slots / kXcd)
     Task* queue;                // linear, capacity q_cap
     int64_t q_cap;
-    int32_t* free_stack;        // [n_slots]
-    int32_t n_compute_blocks;   // the scheduler is block n_compute_blocks
+    int32_t* free_stack;        // [kXcd][pool]
+    int32_t n_compute_blocks;   // blocks 1..n_compute_blocks compute; block 0 schedules
     int64_t spin_limit;
     int64_t max_steps;          // guard against a runaway schedule
 };
