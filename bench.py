@@ -145,6 +145,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
+                    help="only run a plain device copy of GIB GiB (torch copy kernel), three times: "
+                         "the reference point for the HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported on this build "
@@ -152,11 +155,21 @@ def main():
         sys.exit(2)
 
     import torch
-    import paper_2510_19301_amd as fv
-    from workloads import hmm
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.copy_calibration > 0:
+        n = int(args.copy_calibration * (1 << 30)) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 3}))
+        return
+
+    import paper_2510_19301_amd as fv
+    from workloads import hmm
     wl = hmm.batched_flash_workload(n=args.n)
     K = wl.K
     print(f"[bench] generating workload: {wl.n} sequences, K={K}, sum T={wl.total_steps()}", file=sys.stderr, flush=True)

@@ -696,7 +696,10 @@ done:
  *   grad_log_a[i, j] = sum_b fl(g_b * c_b(i, j)).
  * accumulate != 0 adds that total to the existing value once (old + total);
  * grad_log_b is then old + g_b at the path entries.  Positions t >= T_b of
- * grad_log_b get 0 (or keep their value when accumulating). */
+ * grad_log_b get 0 (or keep their value when accumulating).  A path entry
+ * outside [0, K) (the -1 fill of an infeasible decode) contributes nothing,
+ * nor does a transition that starts or ends at one. */
+#define VALID_PAIR(i, j, K) ((i) >= 0 && (i) < (K) && (j) >= 0 && (j) < (K))
 int fvo_backward(int K, int n, int Tmax, const int32_t* lengths, const int32_t* paths,
                  const float* grad_score, float* grad_log_b, float* grad_log_a,
                  float* grad_log_pi, int accumulate)
@@ -710,7 +713,7 @@ int fvo_backward(int K, int n, int Tmax, const int32_t* lengths, const int32_t* 
                 if (!accumulate) for (int j = 0; j < K; ++j) row[j] = 0.0f;
                 if (t < lengths[b]) {
                     int q = paths[(size_t)b * Tmax + t];
-                    row[q] = accumulate ? row[q] + grad_score[b] : grad_score[b];
+                    if (q >= 0 && q < K) row[q] = accumulate ? row[q] + grad_score[b] : grad_score[b];
                 }
             }
         }
@@ -720,8 +723,10 @@ int fvo_backward(int K, int n, int Tmax, const int32_t* lengths, const int32_t* 
         int32_t* cnt = (int32_t*)calloc((size_t)K * K, sizeof(int32_t));
         for (int b = 0; b < n; ++b) {
             const int32_t* q = paths + (size_t)b * Tmax;
-            for (int t = 1; t < lengths[b]; ++t) cnt[(size_t)q[t - 1] * K + q[t]]++;
+            for (int t = 1; t < lengths[b]; ++t)
+                if (VALID_PAIR(q[t - 1], q[t], K)) cnt[(size_t)q[t - 1] * K + q[t]]++;
             for (int t = 1; t < lengths[b]; ++t) {
+                if (!VALID_PAIR(q[t - 1], q[t], K)) continue;
                 size_t c = (size_t)q[t - 1] * K + q[t];
                 if (cnt[c]) {
                     total[c] = total[c] + grad_score[b] * (float)cnt[c];
@@ -738,7 +743,7 @@ int fvo_backward(int K, int n, int Tmax, const int32_t* lengths, const int32_t* 
         for (int b = 0; b < n; ++b)
             if (lengths[b] > 0) {
                 int q = paths[(size_t)b * Tmax];
-                total[q] = total[q] + grad_score[b];
+                if (q >= 0 && q < K) total[q] = total[q] + grad_score[b];
             }
         for (int j = 0; j < K; ++j) grad_log_pi[j] = accumulate ? grad_log_pi[j] + total[j] : total[j];
         free(total);

@@ -6,6 +6,9 @@
 
 #include "../../include/flashviterbi.h"
 
+// Records the thread-local message fv_last_error() returns; returns s.
+fv_status fv_set_error(fv_status s, const char* msg, ...) __attribute__((format(printf, 2, 3)));
+
 namespace fv {
 
 constexpr int kBlock = 256;     // threads per workgroup (4 wave64)

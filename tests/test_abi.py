@@ -79,3 +79,34 @@ def test_decode_argument_errors_are_synchronous(fv):
     csr = fv._lib.FvTrans(1, 8, None, fake, fake, fake, 3)
     assert l.fv_decode_vanilla(C.byref(csr), None, fake, 8, 5, fake, fake, None, 0, fake, 1 << 20, None) == -2
     assert l.fv_last_error()
+
+
+def test_backward_workspace_size(fv):
+    # K*K float totals + K start totals + per-sequence cell lists
+    b = fv.backward_workspace_bytes(256, 512, 512)
+    assert b >= 256 * 256 * 4 + 512 * 512 * 8
+    assert fv.backward_workspace_bytes(256, 0, 0) >= 256 * 256 * 4
+    assert fv.backward_workspace_bytes(256, 512, 1024) > b
+    for args in ((0, 1, 1), (65536, 1, 1), (4, -1, 1), (4, 1, -1)):
+        with pytest.raises(fv.FvError):
+            fv.backward_workspace_bytes(*args)
+    with pytest.raises(fv.FvError):
+        fv.backward_workspace_bytes(4, 1, 16386)   # beyond the per-sequence sort capacity
+
+
+def test_backward_argument_errors_are_synchronous(fv):
+    l = fv.lib()
+    fake = C.c_void_p(256)   # never dereferenced: every call below fails on the host
+    ws = C.c_void_p(4096)
+    # K out of range
+    assert l.fv_viterbi_backward(0, 1, 4, fake, fake, fake, None, fake, None, 0, ws, 1 << 30, None) == -1
+    # missing inputs with n > 0
+    assert l.fv_viterbi_backward(8, 2, 4, None, fake, fake, None, fake, None, 0, ws, 1 << 30, None) == -1
+    assert l.fv_viterbi_backward(8, 2, 4, fake, None, fake, fake, None, None, 0, None, 0, None) == -1
+    # shared-parameter gradients need the workspace
+    assert l.fv_viterbi_backward(8, 2, 4, fake, fake, fake, None, fake, None, 0, None, 0, None) == -3
+    assert l.fv_viterbi_backward(8, 2, 4, fake, fake, fake, None, None, fake, 0, ws, 16, None) == -3
+    # misaligned workspace
+    assert l.fv_viterbi_backward(8, 2, 4, fake, fake, fake, None, fake, None, 0, C.c_void_p(4100), 1 << 30,
+                                 None) == -1
+    assert l.fv_last_error()

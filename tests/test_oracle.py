@@ -483,6 +483,26 @@ def test_backward_invariants(seed):
     assert (_bits(ga) == _bits(want)).all()
 
 
+def test_backward_skips_states_outside_range():
+    """An infeasible decode leaves -1 in its path; such entries, and the
+    transitions that touch them, carry no gradient."""
+    K = 3
+    paths = np.array([[0, -1, 1, 1, 2], [2, 2, 3, 0, 0]], np.int32)   # 3 is out of range too
+    lengths = np.array([5, 5], np.int32)
+    g = np.array([1.0, 2.0], np.float32)
+    gb, ga, gp = oracle.backward(K, lengths, paths, g)
+    want = np.zeros((K, K), np.float32)
+    want[1, 1] += 1; want[1, 2] += 1          # sequence 0: (0,-1), (-1,1) dropped
+    want[2, 2] += 2; want[0, 0] += 2          # sequence 1: (2,3), (3,0) dropped
+    assert (ga == want).all()
+    assert not gb[0, 1].any() and not gb[1, 2].any()
+    assert gb[0, 2, 1] == 1.0 and gb[1, 3, 0] == 2.0
+    assert gp.tolist() == [1.0, 0.0, 2.0]
+    bad_start = np.array([[-1, 0, 0]], np.int32)
+    _, _, gp2 = oracle.backward(K, np.array([3], np.int32), bad_start, np.ones(1, np.float32))
+    assert not gp2.any()
+
+
 def test_backward_accumulate():
     K, n, Tmax = 4, 6, 10
     lengths, paths = _random_paths(K, n, Tmax, 3)
