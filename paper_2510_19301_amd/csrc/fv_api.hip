@@ -15,6 +15,7 @@ extern "C" __global__ void fv_prep_dense_kernel(const float* __restrict__ log_a,
                                                 float* __restrict__ Ap);
 extern "C" __global__ void fv_setup_kernel(EngineArgs a, SetupArgs sa);
 extern "C" __global__ void fv_finish_kernel(EngineArgs a, int32_t* status);
+extern "C" __global__ void fv_beam_finish_kernel(EngineArgs a, const float* __restrict__ Ap, int32_t* status);
 }  // namespace fv
 
 using namespace fv;
@@ -67,8 +68,11 @@ struct DenseLayout {
     int32_t method = 0, K = 0, Kp = 0, n_seqs = 0, n_slots = 0, pool = 0;
     int64_t sum_T = 0, sum_root = 0, sum_psi = 0, n_tasks = 0, slot_floats = 0;
     int32_t has_anc = 0;
-    Region Ap, seq1, seqinfo, keys, state, arrive, rows_full, rows_light, queue, free_stack, slots,
-        alpha, root, psi;
+    int32_t B = 0, Bc = 0;       // beam width and padded length (beam decodes)
+    int64_t brec = 0;            // floats per beam record
+    int64_t q_cap = 0;
+    Region Ap, seq1, seqinfo, keys, state, arrive, rows_full, rows_light, rows_beam, queue, free_stack,
+        slots, alpha, root, psi;
     size_t total = 0;
 };
 
@@ -80,11 +84,21 @@ size_t put(size_t& cur, Region& r, size_t bytes) {
 }
 
 // Workspace layout of a dense decode.  Depends only on the arguments, so
-// fv_workspace_size and the decode calls agree.
-fv_status plan_dense(int32_t method, int32_t K, const int32_t* T_host, int32_t n_seqs, int32_t P,
+// fv_workspace_size and the decode calls agree.  method FV_BEAM means a
+// beam narrower than K (a beam of width >= K is planned as FV_FLASH).
+fv_status plan_dense(int32_t method, int32_t K, const int32_t* T_host, int32_t n_seqs, int32_t P, int32_t B,
                      bool single, DenseLayout& L) {
     L = DenseLayout{};
     L.method = method;
+    const bool beam = method == FV_BEAM;
+    if (beam) {
+        if (K > kBeamMaxK) return fail(FV_E_UNSUPPORTED, "beam decoding supports K <= %d (got %d)", kBeamMaxK, K);
+        if (B < 1 || B >= K) return fail(FV_E_INVALID_ARG, "beam width must be in [1, K)");
+        if (B > kBeamMaxB) return fail(FV_E_UNSUPPORTED, "beam width %d exceeds %d", B, kBeamMaxB);
+        L.B = B;
+        L.Bc = (int32_t)round_up(B, 64);
+        L.brec = 64 + 3 * (int64_t)L.Bc;
+    }
     L.K = K;
     L.Kp = (int32_t)round_up(K, kKAlign);
     L.n_seqs = n_seqs;
@@ -100,12 +114,17 @@ fv_status plan_dense(int32_t method, int32_t K, const int32_t* T_host, int32_t n
             L.n_tasks += 1;
         } else {
             const int32_t pp = eff_parallelism(T, P);
-            L.sum_root += 2 * (int64_t)(pp - 1);
+            L.sum_root += (beam ? 1 : 2) * (int64_t)(pp - 1);
             L.n_tasks += T - pp + 1;
         }
     }
-    L.has_anc = method == FV_FLASH;
-    L.slot_floats = (int64_t)L.Kp * (method == FV_FLASH ? 5 : 2);
+    L.has_anc = method != FV_VANILLA;
+    // dense rows: delta[2] (+ anc[2] + snapshot); beam rows: three beam
+    // records, and room for a dense row should the task need its exact re-decode
+    L.slot_floats = (int64_t)L.Kp * (method == FV_VANILLA ? 2 : 5);
+    if (beam) L.slot_floats = std::max<int64_t>(L.slot_floats, 3 * L.brec);
+    // a beam subtask may be queued twice (its exact re-decode)
+    L.q_cap = std::max<int64_t>(1, beam ? 2 * L.n_tasks : L.n_tasks);
     const int64_t slot_bytes = L.slot_floats * 4;
     int64_t slots;
     if (method == FV_VANILLA) {
@@ -131,11 +150,12 @@ fv_status plan_dense(int32_t method, int32_t K, const int32_t* T_host, int32_t n
     put(cur, L.arrive, (size_t)kMaxBlocks * 4);
     put(cur, L.rows_full, (size_t)2 * L.n_slots * sizeof(Row));
     put(cur, L.rows_light, (size_t)2 * L.n_slots * sizeof(Row));
-    put(cur, L.queue, (size_t)std::max<int64_t>(L.n_tasks, 1) * sizeof(Task));
+    put(cur, L.rows_beam, beam ? (size_t)2 * L.n_slots * sizeof(Row) : 0);
+    put(cur, L.queue, (size_t)L.q_cap * sizeof(Task));
     put(cur, L.free_stack, (size_t)L.n_slots * 4);
     put(cur, L.slots, (size_t)L.n_slots * slot_bytes);
-    put(cur, L.alpha, method == FV_FLASH ? (size_t)L.sum_T * 4 : 0);
-    put(cur, L.root, (size_t)L.sum_root * L.Kp * 4);
+    put(cur, L.alpha, method != FV_VANILLA ? (size_t)L.sum_T * 4 : 0);
+    put(cur, L.root, (size_t)L.sum_root * (beam ? L.brec : L.Kp) * 4);
     put(cur, L.psi, (size_t)L.sum_psi * 2);
     L.total = (cur + kAlign - 1) / kAlign * kAlign;
     return FV_OK;
@@ -172,12 +192,12 @@ fv_status device_info(DeviceInfo& di) {
 __global__ void write_seq_kernel(fv_seq* dst, fv_seq v) { *dst = v; }
 
 fv_status run_dense(int32_t method, const fv_trans* A, const float* log_pi, const fv_seq* seqs_dev,
-                    const int32_t* T_host, int32_t n_seqs, int32_t P, const fv_seq* single,
+                    const int32_t* T_host, int32_t n_seqs, int32_t P, int32_t B, const fv_seq* single,
                     int32_t* status, void* ws, size_t ws_bytes, hipStream_t stream) {
     fv_status rc = check_dense_model(A);
     if (rc != FV_OK) return rc;
     DenseLayout L;
-    rc = plan_dense(method, A->K, T_host, n_seqs, P, single != nullptr, L);
+    rc = plan_dense(method, A->K, T_host, n_seqs, P, B, single != nullptr, L);
     if (rc != FV_OK) return rc;
     if (!ws || ws_bytes < L.total)
         return fail(FV_E_WORKSPACE, "workspace of %zu bytes is smaller than the %zu bytes required", ws_bytes, L.total);
@@ -222,15 +242,20 @@ fv_status run_dense(int32_t method, const fv_trans* A, const float* log_pi, cons
     a.arrive = static_cast<uint32_t*>(at(L.arrive));
     a.rows_full = static_cast<Row*>(at(L.rows_full));
     a.rows_light = static_cast<Row*>(at(L.rows_light));
+    a.rows_beam = static_cast<Row*>(at(L.rows_beam));
+    a.B = L.B;
+    a.Bc = L.Bc;
+    a.brec = L.brec;
     a.pool = L.pool;
     a.queue = static_cast<Task*>(at(L.queue));
-    a.q_cap = std::max<int64_t>(L.n_tasks, 1);
+    a.q_cap = L.q_cap;
     a.free_stack = static_cast<int32_t*>(at(L.free_stack));
     // one engine block per CU: block 0 schedules, the others compute
     a.n_compute_blocks = std::min(di.cus, kMaxBlocks) - 1;
     if (a.n_compute_blocks < kXcd) return fail(FV_E_UNSUPPORTED, "device has too few compute units");
     a.spin_limit = (int64_t)1 << 24;
-    a.max_steps = 8 * (L.sum_T + L.n_tasks) + 4096;
+    // beam: exact re-decodes add at most one pass per subtask
+    a.max_steps = (method == FV_BEAM ? 16 : 8) * (L.sum_T + L.n_tasks) + 4096;
 
     SetupArgs sa{};
     sa.seqs_dev = seqs_dev;
@@ -239,7 +264,7 @@ fv_status run_dense(int32_t method, const fv_trans* A, const float* log_pi, cons
     sa.host_sum_T = L.sum_T;
     sa.host_sum_root = L.sum_root;
     sa.host_sum_psi = L.sum_psi;
-    sa.kind = method == FV_VANILLA ? KIND_VANILLA : KIND_ROOT;
+    sa.kind = method == FV_VANILLA ? KIND_VANILLA : (method == FV_BEAM ? KIND_BROOT : KIND_ROOT);
     sa.K = A->K;
     hipLaunchKernelGGL(fv_setup_kernel, dim3(1), dim3(kBlock), 0, stream, a, sa);
 
@@ -252,8 +277,12 @@ fv_status run_dense(int32_t method, const fv_trans* A, const float* log_pi, cons
             HIP_TRY(hipEventRecord(g_prof_ev[1], stream));
             g_prof_recorded = true;
         }
-        hipLaunchKernelGGL(fv_finish_kernel, dim3((n_seqs + kBlock - 1) / kBlock), dim3(kBlock), 0, stream,
-                           a, status);
+        if (method == FV_BEAM)
+            hipLaunchKernelGGL(fv_beam_finish_kernel, dim3((n_seqs + kWaves - 1) / kWaves), dim3(kBlock), 0, stream,
+                               a, Ap, status);
+        else
+            hipLaunchKernelGGL(fv_finish_kernel, dim3((n_seqs + kBlock - 1) / kBlock), dim3(kBlock), 0, stream,
+                               a, status);
     }
     HIP_TRY(hipGetLastError());
     return FV_OK;
@@ -298,20 +327,28 @@ fv_status fv_profile_engine_ms(float* ms) {
     return FV_OK;
 }
 
+// Beam widths of at least K keep every state: that is FLASH decoding.
+static int32_t effective_method(int32_t method, const fv_trans* A, int32_t B) {
+    return (method == FV_BEAM && A && B >= A->K) ? FV_FLASH : method;
+}
+
 fv_status fv_workspace_size(int32_t method, const fv_trans* models, int32_t n_models,
                             const int32_t* T_host, const int32_t* model_host, int32_t n_seqs,
                             int32_t P, int32_t B, size_t* bytes) {
     (void)model_host;
-    (void)B;
     if (!bytes) return fail(FV_E_INVALID_ARG, "null bytes");
     if (n_models != 1) return fail(FV_E_UNSUPPORTED, "exactly one model per call is supported");
     if (n_seqs < 0 || (n_seqs > 0 && !T_host)) return fail(FV_E_INVALID_ARG, "bad sequence list");
     fv_status rc = check_dense_model(models);
     if (rc != FV_OK) return rc;
-    if (method != FV_VANILLA && method != FV_FLASH) return fail(FV_E_UNSUPPORTED, "method %d", method);
+    if (method != FV_VANILLA && method != FV_FLASH && method != FV_BEAM)
+        return fail(FV_E_INVALID_ARG, "unknown method %d", method);
+    if (method == FV_BEAM && (B < 1 || P < 1)) return fail(FV_E_INVALID_ARG, "beam decoding needs B >= 1 and P >= 1");
+    if (method == FV_FLASH && P <= 0) P = 16;
+    method = effective_method(method, models, B);
     DenseLayout L;
     // single-sequence calls reserve room for their device descriptor too
-    rc = plan_dense(method, models->K, T_host, n_seqs, P, n_seqs == 1, L);
+    rc = plan_dense(method, models->K, T_host, n_seqs, P, B, n_seqs == 1, L);
     if (rc != FV_OK) return rc;
     *bytes = L.total;
     return FV_OK;
@@ -325,7 +362,7 @@ fv_status fv_decode_vanilla(const fv_trans* A, const float* log_pi, const float*
     if (!A || !log_b || !path || !score) return fail(FV_E_INVALID_ARG, "null argument");
     if (ld < A->K) return fail(FV_E_INVALID_ARG, "ld=%lld < K=%d", (long long)ld, A->K);
     fv_seq s{0, T, log_b, ld, path, score};
-    return run_dense(FV_VANILLA, A, log_pi, nullptr, &T, 1, 1, &s, status, ws, ws_bytes,
+    return run_dense(FV_VANILLA, A, log_pi, nullptr, &T, 1, 1, 0, &s, status, ws, ws_bytes,
                      reinterpret_cast<hipStream_t>(stream));
 }
 
@@ -338,8 +375,21 @@ fv_status fv_decode_flash(const fv_trans* A, const float* log_pi, const float* l
     if (ld < A->K) return fail(FV_E_INVALID_ARG, "ld=%lld < K=%d", (long long)ld, A->K);
     if (P <= 0) P = 16;
     fv_seq s{0, T, log_b, ld, path, score};
-    return run_dense(FV_FLASH, A, log_pi, nullptr, &T, 1, P, &s, status, ws, ws_bytes,
+    return run_dense(FV_FLASH, A, log_pi, nullptr, &T, 1, P, 0, &s, status, ws, ws_bytes,
                      reinterpret_cast<hipStream_t>(stream));
+}
+
+fv_status fv_decode_beam(const fv_trans* A, const float* log_pi, const float* log_b, int64_t ld, int32_t T,
+                         int32_t B, int32_t P, int32_t* path, float* score, int32_t* status, uint32_t flags,
+                         void* ws, size_t ws_bytes, fv_stream_t stream) {
+    (void)flags;
+    if (T < 1) return fail(FV_E_INVALID_ARG, "T must be >= 1 (got %d)", T);
+    if (!A || !log_b || !path || !score) return fail(FV_E_INVALID_ARG, "null argument");
+    if (ld < A->K) return fail(FV_E_INVALID_ARG, "ld=%lld < K=%d", (long long)ld, A->K);
+    if (B < 1 || P < 1) return fail(FV_E_INVALID_ARG, "beam decoding needs B >= 1 and P >= 1");
+    fv_seq s{0, T, log_b, ld, path, score};
+    return run_dense(effective_method(FV_BEAM, A, B), A, log_pi, nullptr, &T, 1, P, B, &s, status, ws,
+                     ws_bytes, reinterpret_cast<hipStream_t>(stream));
 }
 
 fv_status fv_decode_batch(const fv_trans* models, const float* const* log_pi, int32_t n_models,
@@ -347,15 +397,16 @@ fv_status fv_decode_batch(const fv_trans* models, const float* const* log_pi, in
                           int32_t n_seqs, int32_t method, int32_t P, int32_t B, int32_t* status,
                           uint32_t flags, void* ws, size_t ws_bytes, fv_stream_t stream) {
     (void)flags;
-    (void)B;
     (void)model_host;
     if (n_models != 1) return fail(FV_E_UNSUPPORTED, "exactly one model per call is supported");
     if (n_seqs < 0) return fail(FV_E_INVALID_ARG, "n_seqs < 0");
     if (n_seqs > 0 && (!seqs_dev || !T_host)) return fail(FV_E_INVALID_ARG, "null sequence list");
-    if (method != FV_VANILLA && method != FV_FLASH) return fail(FV_E_UNSUPPORTED, "method %d", method);
+    if (method != FV_VANILLA && method != FV_FLASH && method != FV_BEAM)
+        return fail(FV_E_INVALID_ARG, "unknown method %d", method);
+    if (method == FV_BEAM && (B < 1 || P < 1)) return fail(FV_E_INVALID_ARG, "beam decoding needs B >= 1 and P >= 1");
     if (method == FV_FLASH && P <= 0) P = 16;
-    return run_dense(method, models, log_pi ? log_pi[0] : nullptr, seqs_dev, T_host, n_seqs, P, nullptr,
-                     status, ws, ws_bytes, reinterpret_cast<hipStream_t>(stream));
+    return run_dense(effective_method(method, models, B), models, log_pi ? log_pi[0] : nullptr, seqs_dev,
+                     T_host, n_seqs, P, B, nullptr, status, ws, ws_bytes, reinterpret_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

@@ -113,6 +113,9 @@ __device__ __forceinline__ Row* list_full(const EngineArgs& a, int parity, int x
 __device__ __forceinline__ Row* list_light(const EngineArgs& a, int parity, int x) {
     return a.rows_light + ((int64_t)parity * kXcd + x) * a.pool;
 }
+__device__ __forceinline__ Row* list_beam(const EngineArgs& a, int parity, int x) {
+    return a.rows_beam + ((int64_t)parity * kXcd + x) * a.pool;
+}
 
 // ---------------------------------------------------------------- row flags
 // Row of `base`'s task at time t as a dense step.
@@ -154,9 +157,9 @@ __device__ Row make_light_row(const Row& base, int32_t t, int32_t op) {
     r.aux = op;
     int32_t f = 0;
     if (op == L_INIT) {
-        if (kind == KIND_SUB && ((m + n) >> 1) == m) f |= F_SNAP_SUB;
+        if (is_dense_sub(kind) && ((m + n) >> 1) == m) f |= F_SNAP_SUB;
         if (kind == KIND_ROOT && pp >= 2 && seg_end(T, pp, 0) == 0) f |= F_SNAP_ROOT;
-        if (kind != KIND_SUB && T == 1) f |= F_FINAL;
+        if ((kind == KIND_VANILLA || kind == KIND_ROOT) && T == 1) f |= F_FINAL;
     }
     r.flags = f;
     return r;
@@ -171,7 +174,20 @@ __device__ Row row_from_task(const EngineArgs& a, const Task& tk, int32_t slot) 
     b.T = sq.T; b.pp = sq.pp;
     b.off = tk.kind == KIND_VANILLA ? sq.psi_off : sq.root_off;
     b.log_b = sq.log_b; b.ld = sq.ld;
+    if (is_beam(tk.kind)) {
+        b.aux = B_INIT;
+        return b;
+    }
     return make_light_row(b, tk.m, L_INIT);
+}
+
+// Row of a beam task at time t doing operation op.
+__device__ Row make_beam_row(const Row& base, int32_t t, int32_t op) {
+    Row r = base;
+    r.t = t;
+    r.aux = op;
+    r.flags = 0;
+    return r;
 }
 
 // ---------------------------------------------------------------- dense tile
@@ -387,7 +403,7 @@ __device__ void light_row(const EngineArgs& a, const float* __restrict__ Ap, con
         }
     } else if (r.aux == L_END) {
         // only the known end state q*_n is evaluated at a subtask's last step
-        if (ld_c(&sq.status) != FV_OK) return;
+        if (ld_c(&sq.status) < 0) return;
         const int32_t n = r.n, tmid = (r.m + r.n) >> 1;
         const int32_t qn = ld_c(sq.path + n);
         if (qn < 0 || qn >= K) return;
@@ -406,6 +422,8 @@ __device__ void light_row(const EngineArgs& a, const float* __restrict__ Ap, con
             st_c(sq.path + tmid, qmid);
             st_cf(a.alpha_at + sq.alpha_off + tmid, slot_snap(a, slot)[qmid]);
         }
+    } else if (r.aux == L_BSPAWN) {
+        return;
     } else {  // L_FINALIZE
         const int32_t T = r.T;
         const unsigned long long key = ld_c(a.keys + r.seq);
@@ -435,11 +453,382 @@ __device__ void light_row(const EngineArgs& a, const float* __restrict__ Ap, con
     }
 }
 
+// ---------------------------------------------------------------- beam rows
+// FLASH-BS (Sec. V-C): every step keeps at most B states.  A beam row is
+// one task's step and takes a whole block:
+//   scores: c(j) = max over beam entries b (in state order) of
+//           v_b + log A(s_b, j), the first (lowest-state) maximum wins;
+//           score(j) = c(j) + log B_t(j)            (all K destinations, LDS)
+//   select: top B by (score desc, state asc), -inf dropped: radix select
+//           of the B-th largest score key, ties at it taken in state order
+//   store:  the kept destinations in state order (state, score, anchor)
+// A beam record is a 64-word header (word 0 = entry count) followed by the
+// state, score and anchor arrays (Bc entries each).  Slot layout of a beam
+// row: record 0 / 1 (the beams of even / odd t), record 2 (the beam at
+// t_mid); header word 1 of record 0 flags a task that needs the exact
+// re-decode.  Root division snapshots are records in the root copy area.
+struct BeamLds {
+    float sc[kBeamMaxK];
+    int32_t an[kBeamMaxK];
+    int32_t bs[kBeamMaxB];
+    float bv[kBeamMaxB];
+    int32_t ba[kBeamMaxB];
+    uint32_t hist[256];
+    int32_t wsum[kEngWaves];
+    unsigned long long wkey[kEngWaves];
+    int32_t misc[4];
+};
+
+struct BeamRec {
+    int32_t* hdr;
+    int32_t* s;
+    float* v;
+    int32_t* a;
+};
+
+__device__ __forceinline__ BeamRec beam_rec(float* base, int32_t Bc) {
+    BeamRec r;
+    r.hdr = reinterpret_cast<int32_t*>(base);
+    r.s = reinterpret_cast<int32_t*>(base + 64);
+    r.v = base + 64 + Bc;
+    r.a = reinterpret_cast<int32_t*>(base + 64 + 2 * (int64_t)Bc);
+    return r;
+}
+__device__ __forceinline__ BeamRec slot_beam(const EngineArgs& a, int32_t slot, int32_t k) {
+    return beam_rec(a.slot_base + (int64_t)slot * a.slot_floats + k * a.brec, a.Bc);
+}
+__device__ __forceinline__ BeamRec root_beam(const EngineArgs& a, int64_t root_off, int32_t d) {
+    return beam_rec(a.root_copy + (root_off + d) * a.brec, a.Bc);
+}
+__device__ __forceinline__ int32_t* beam_fallback_flag(const EngineArgs& a, int32_t slot) {
+    return slot_beam(a, slot, 0).hdr + 1;
+}
+
+// Exclusive block-wide prefix sum of one int per thread; *total = the sum.
+__device__ int32_t block_exscan(int32_t v, int32_t* total, int32_t* wsum) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int32_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    int32_t before = 0, all = 0;
+#pragma unroll
+    for (int u = 0; u < kEngWaves; ++u) {
+        const int32_t y = wsum[u];
+        if (u < w) before += y;
+        all += y;
+    }
+    __syncthreads();
+    *total = all;
+    return before + x - v;
+}
+
+// Orderable key of a score (-0 and +0 equal).
+__device__ __forceinline__ uint32_t score_key(float v) {
+    if (v == 0.0f) v = 0.0f;
+    const uint32_t b = __float_as_uint(v);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+// Index of the largest key over the block (keys from k < n; 0 = none).
+__device__ int32_t block_argmax_key(unsigned long long key, BeamLds& L) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const unsigned long long o = __shfl_xor(key, off, 64);
+        if (o > key) key = o;
+    }
+    if (lane == 0) L.wkey[w] = key;
+    __syncthreads();
+    unsigned long long best = 0;
+    for (int u = 0; u < kEngWaves; ++u) best = L.wkey[u] > best ? L.wkey[u] : best;
+    __syncthreads();
+    return (int32_t)(0xFFFFFFFFu - (uint32_t)(best & 0xFFFFFFFFull));
+}
+
+// Keep the top B of L.sc[0..K) (with anchors L.an) and write them, in state
+// order, to `out` (and `out2` when given).  Returns the number kept.
+__device__ int32_t beam_select_store(int32_t K, int32_t B, BeamLds& L, BeamRec out, const BeamRec* out2) {
+    const int tid = threadIdx.x;
+    const int32_t per = (K + kEngBlock - 1) / kEngBlock;
+    const int32_t j0 = min(K, tid * per), j1 = min(K, j0 + per);
+    int32_t nfin = 0;
+    for (int32_t j = j0; j < j1; ++j) nfin += L.sc[j] != -INFINITY;
+    int32_t n_finite;
+    block_exscan(nfin, &n_finite, L.wsum);
+    const bool all = n_finite <= B;
+    uint32_t kth = 0;
+    int32_t take_eq = 0;
+    if (!all) {
+        uint32_t prefix = 0, mask = 0;
+        int32_t rem = B;
+        for (int shift = 24; shift >= 0; shift -= 8) {
+            for (int k = tid; k < 256; k += kEngBlock) L.hist[k] = 0;
+            __syncthreads();
+            for (int32_t j = j0; j < j1; ++j) {
+                const float v = L.sc[j];
+                if (v == -INFINITY) continue;
+                const uint32_t u = score_key(v);
+                if ((u & mask) == prefix) atomicAdd(&L.hist[(u >> shift) & 255u], 1u);
+            }
+            __syncthreads();
+            if (tid < 64) {
+                // lane l owns digits 4l..4l+3; find the digit where the count
+                // from the top reaches rem
+                int32_t c[4];
+#pragma unroll
+                for (int d = 0; d < 4; ++d) c[d] = (int32_t)L.hist[4 * tid + d];
+                const int32_t own = c[0] + c[1] + c[2] + c[3];
+                int32_t incl = own;  // sum over lanes >= tid
+#pragma unroll
+                for (int off = 1; off < 64; off <<= 1) {
+                    const int32_t y = __shfl_down(incl, off, 64);
+                    if (tid + off < 64) incl += y;
+                }
+                int32_t above = incl - own;
+                for (int d = 3; d >= 0; --d) {
+                    if (above < rem && above + c[d] >= rem) {
+                        L.misc[0] = 4 * tid + d;
+                        L.misc[1] = rem - above;
+                    }
+                    above += c[d];
+                }
+            }
+            __syncthreads();
+            prefix |= (uint32_t)L.misc[0] << shift;
+            mask |= 255u << shift;
+            rem = L.misc[1];
+            __syncthreads();
+        }
+        kth = prefix;
+        take_eq = rem;
+    }
+    // ties at the B-th key go to the lowest states
+    int32_t neq = 0;
+    if (!all)
+        for (int32_t j = j0; j < j1; ++j) neq += (L.sc[j] != -INFINITY && score_key(L.sc[j]) == kth);
+    int32_t dummy;
+    const int32_t eq_before = block_exscan(neq, &dummy, L.wsum);
+    int32_t nsel = 0;
+    {
+        int32_t r = eq_before;
+        for (int32_t j = j0; j < j1; ++j) {
+            const float v = L.sc[j];
+            if (v == -INFINITY) continue;
+            const uint32_t u = score_key(v);
+            bool keep = all || u > kth;
+            if (!all && u == kth) keep = r++ < take_eq;
+            nsel += keep;
+        }
+    }
+    int32_t n_kept;
+    int32_t p = block_exscan(nsel, &n_kept, L.wsum);
+    {
+        int32_t r = eq_before;
+        for (int32_t j = j0; j < j1; ++j) {
+            const float v = L.sc[j];
+            if (v == -INFINITY) continue;
+            const uint32_t u = score_key(v);
+            bool keep = all || u > kth;
+            if (!all && u == kth) keep = r++ < take_eq;
+            if (keep) {
+                out.s[p] = j; out.v[p] = v; out.a[p] = L.an[j];
+                if (out2) { out2->s[p] = j; out2->v[p] = v; out2->a[p] = L.an[j]; }
+                ++p;
+            }
+        }
+    }
+    if (tid == 0) {
+        out.hdr[0] = n_kept;
+        if (out2) out2->hdr[0] = n_kept;
+    }
+    return n_kept;
+}
+
+// Loads a beam record into LDS; returns its entry count.  States are
+// clamped to [0, K) (they address rows of log A).
+__device__ int32_t beam_load(const BeamRec& r, int32_t B, int32_t K, BeamLds& L) {
+    if (threadIdx.x == 0) L.misc[2] = r.hdr[0];
+    __syncthreads();
+    const int32_t nb = clampi(L.misc[2], B + 1);
+    for (int32_t k = threadIdx.x; k < nb; k += kEngBlock) {
+        L.bs[k] = clampi(r.s[k], K);
+        L.bv[k] = r.v[k];
+        L.ba[k] = r.a[k];
+    }
+    __syncthreads();
+    return nb;
+}
+
+// Position of state q in a record sorted by state, or -1.
+__device__ int32_t beam_find(const BeamRec& r, int32_t n, int32_t q) {
+    int32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        const int32_t s = r.s[mid];
+        if (s == q) return mid;
+        if (s < q) lo = mid + 1; else hi = mid;
+    }
+    return -1;
+}
+
+__device__ void beam_row(const EngineArgs& a, const float* __restrict__ Ap, const Row& r, BeamLds& L) {
+    const int tid = threadIdx.x;
+    SeqInfo& sq = a.seqs[r.seq];
+    const int32_t K = a.K, Kp = a.Kp, B = a.B;
+    const int32_t slot = clampi(r.slot, a.n_slots);
+    const bool root = r.kind == KIND_BROOT;
+    const int32_t T = r.T, pp = r.pp, m = r.m, n = r.n, t = r.t;
+    const int32_t tmid = (m + n) >> 1;
+    if (r.aux == B_INIT) {
+        // start step: pi + log B_0 at m = 0, the anchored boundary otherwise
+        int32_t q = -1;
+        float alpha = 0.0f;
+        if (m > 0) {
+            if (tid == 0) {
+                L.misc[0] = ld_c(sq.path + m - 1);
+                L.misc[1] = (int32_t)__float_as_uint(ld_cf(a.alpha_at + sq.alpha_off + m - 1));
+                st_c(beam_fallback_flag(a, slot), 0);
+            }
+            __syncthreads();
+            q = L.misc[0];
+            alpha = __uint_as_float((uint32_t)L.misc[1]);
+            if (q < 0 || q >= K) q = -1;
+            __syncthreads();
+        } else if (tid == 0) {
+            st_c(beam_fallback_flag(a, slot), 0);
+        }
+        const float* bm = r.log_b + (int64_t)m * r.ld;
+        for (int32_t j = tid; j < K; j += kEngBlock) {
+            float v = -INFINITY;
+            if (m == 0) v = a.log_pi ? a.log_pi[j] + bm[j] : bm[j];
+            else if (q >= 0) { const float c = alpha + Ap[(int64_t)q * Kp + j]; v = c + bm[j]; }
+            L.sc[j] = v;
+            L.an[j] = -1;
+        }
+        __syncthreads();
+        BeamRec snap;
+        bool want_snap = false;
+        if (root && pp >= 2 && seg_end(T, pp, 0) == 0) { snap = root_beam(a, r.off, 0); want_snap = true; }
+        if (!root && tmid == m) { snap = slot_beam(a, slot, 2); want_snap = true; }
+        beam_select_store(K, B, L, slot_beam(a, slot, m & 1), want_snap ? &snap : nullptr);
+    } else if (r.aux == B_STEP) {
+        const int32_t nb = beam_load(slot_beam(a, slot, (t - 1) & 1), B, K, L);
+        int32_t mode;  // anchor: 0 none, 1 the predecessor, 2 the predecessor's anchor
+        if (root) {
+            if (pp >= 2 && div_index(T, pp, t - 1) >= 0) mode = 1;
+            else if (pp >= 2 && t > seg_end(T, pp, 0) + 1) mode = 2;
+            else mode = 0;
+        } else {
+            mode = t == tmid + 1 ? 1 : (t > tmid + 1 ? 2 : 0);
+        }
+        const float* bt = r.log_b + (int64_t)t * r.ld;
+        for (int32_t j = tid; j < K; j += kEngBlock) {
+            float c = -INFINITY;
+            int32_t w = -1;
+            for (int32_t b = 0; b < nb; ++b) {
+                const float x = L.bv[b] + Ap[(int64_t)L.bs[b] * Kp + j];
+                if (w < 0 || x > c) { c = x; w = b; }
+            }
+            L.sc[j] = w < 0 ? -INFINITY : c + bt[j];
+            L.an[j] = w < 0 ? -1 : (mode == 1 ? L.bs[w] : (mode == 2 ? L.ba[w] : -1));
+        }
+        __syncthreads();
+        BeamRec snap;
+        bool want_snap = false;
+        if (root && pp >= 2) {
+            const int32_t d = div_index(T, pp, t);
+            if (d >= 0) { snap = root_beam(a, r.off, d); want_snap = true; }
+        }
+        if (!root && t == tmid) { snap = slot_beam(a, slot, 2); want_snap = true; }
+        beam_select_store(K, B, L, slot_beam(a, slot, t & 1), want_snap ? &snap : nullptr);
+    } else if (r.aux == B_END) {
+        // only the known end state q*_n is evaluated
+        if (tid == 0) L.misc[0] = ld_c(&sq.status) < 0 ? -1 : ld_c(sq.path + n);
+        __syncthreads();
+        const int32_t qn = L.misc[0];
+        __syncthreads();
+        if (qn < 0 || qn >= K) return;
+        const int32_t nb = beam_load(slot_beam(a, slot, (n - 1) & 1), B, K, L);
+        unsigned long long key = 0;
+        for (int32_t b = tid; b < nb; b += kEngBlock) {
+            const float x = L.bv[b] + Ap[(int64_t)L.bs[b] * Kp + qn];
+            if (x != -INFINITY) {
+                const unsigned long long k = order_key(x, b);
+                if (k > key) key = k;
+            }
+        }
+        // any finite candidate gives a key above 0; block_argmax_key -> winner
+        unsigned long long kk = key;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const unsigned long long o = __shfl_xor(kk, off, 64);
+            if (o > kk) kk = o;
+        }
+        if ((tid & 63) == 0) L.wkey[tid >> 6] = kk;
+        __syncthreads();
+        unsigned long long best = 0;
+        for (int u = 0; u < kEngWaves; ++u) best = L.wkey[u] > best ? L.wkey[u] : best;
+        __syncthreads();
+        if (tid == 0) {
+            if (best == 0) {
+                // the beam lost q*_n: exact re-decode of this task
+                st_c(beam_fallback_flag(a, slot), 1);
+                if (ld_c(&sq.status) == FV_OK) st_c(&sq.status, (int32_t)FV_W_BEAM_FALLBACK);
+            } else {
+                const int32_t w = clampi((int32_t)(0xFFFFFFFFu - (uint32_t)(best & 0xFFFFFFFFull)), nb);
+                const int32_t qmid = (n == tmid + 1) ? L.bs[w] : L.ba[w];
+                const BeamRec snap = slot_beam(a, slot, 2);
+                const int32_t at = (qmid >= 0 && qmid < K) ? beam_find(snap, clampi(snap.hdr[0], B + 1), qmid) : -1;
+                st_c(sq.path + tmid, qmid);
+                st_cf(a.alpha_at + sq.alpha_off + tmid, at >= 0 ? snap.v[at] : __builtin_nanf(""));
+            }
+        }
+    } else {  // B_FINAL: the root's best end state and the division chain
+        const BeamRec fin = slot_beam(a, slot, (T - 1) & 1);
+        const int32_t nb = beam_load(fin, B, K, L);
+        if (nb == 0) {
+            for (int32_t k = tid; k < T; k += kEngBlock) st_c(sq.path + k, -1);
+            if (tid == 0) {
+                st_cf(sq.score, -INFINITY);
+                st_c(&sq.status, (int32_t)FV_E_INFEASIBLE);
+            }
+            return;
+        }
+        unsigned long long key = 0;
+        for (int32_t k = tid; k < nb; k += kEngBlock) {
+            const unsigned long long kk = order_key(L.bv[k], L.bs[k]);
+            if (kk > key) key = kk;
+        }
+        const int32_t top_state = block_argmax_key(key, L);
+        if (tid == 0) {
+            const int32_t top = beam_find(fin, nb, top_state);
+            st_c(sq.path + T - 1, top_state);
+            if (pp >= 2) {
+                int32_t q = top >= 0 ? L.ba[top] : -1;
+                for (int32_t d = pp - 2; d >= 0; --d) {
+                    const int64_t e = seg_end(T, pp, d);
+                    st_c(sq.path + e, q);
+                    const BeamRec rs = root_beam(a, r.off, d);
+                    const int32_t at = (q >= 0 && q < K) ? beam_find(rs, clampi(rs.hdr[0], B + 1), q) : -1;
+                    st_cf(a.alpha_at + sq.alpha_off + e, at >= 0 ? rs.v[at] : __builtin_nanf(""));
+                    if (d >= 1) q = at >= 0 ? rs.a[at] : -1;
+                }
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------- scheduler
 // What a row of step s turns into at step s+1 (its XCD never changes).
 struct Next {
-    int32_t has_full, has_light, freed, spawn;
-    Row full, light;
+    int32_t list;   // -1: none, else the list of the successor row (0 full, 1 light, 2 beam)
+    int32_t freed, spawn;
+    Row row;
 };
 
 __device__ int32_t root_segments(int32_t T, int32_t pp) {
@@ -451,30 +840,50 @@ __device__ int32_t root_segments(int32_t T, int32_t pp) {
     return c;
 }
 
-__device__ Next classify(const Row& r, bool from_full) {
+__device__ __forceinline__ int32_t child_count(const Row& r) {
+    const int32_t len = r.n - r.m;
+    return len > 2 ? 2 : (len == 2 ? 1 : 0);
+}
+
+// src: the list r came from (0 full, 1 light, 2 beam).
+__device__ Next classify(const EngineArgs& a, const Row& r, int src) {
     Next x;
-    x.has_full = x.has_light = x.freed = x.spawn = 0;
+    x.list = -1;
+    x.freed = x.spawn = 0;
     const int32_t T = r.T, pp = r.pp;
-    if (from_full) {
-        if (r.kind == KIND_SUB) {
-            if (r.t + 1 < r.n) { x.has_full = 1; x.full = make_dense_row(r, r.t + 1); }
-            else { x.has_light = 1; x.light = make_light_row(r, r.n, L_END); }
-        } else {
-            if (r.t + 1 < T) { x.has_full = 1; x.full = make_dense_row(r, r.t + 1); }
-            else { x.has_light = 1; x.light = make_light_row(r, T, L_FINALIZE); }
+    if (src == 2) {
+        const bool root = r.kind == KIND_BROOT;
+        if (r.aux == B_INIT || r.aux == B_STEP) {
+            const int32_t nt = r.t + 1;
+            x.list = 2;
+            if (root) x.row = nt < T ? make_beam_row(r, nt, B_STEP) : make_beam_row(r, T, B_FINAL);
+            else x.row = nt < r.n ? make_beam_row(r, nt, B_STEP) : make_beam_row(r, r.n, B_END);
+        } else if (r.aux == B_END) {
+            // its fallback flag is written while this runs: decide next step
+            x.list = 1;
+            x.row = make_light_row(r, r.n, L_BSPAWN);
+        } else {  // B_FINAL
+            x.freed = 1;
+            if (pp >= 2) x.spawn = root_segments(T, pp);
         }
-    } else if (r.aux == L_INIT) {
-        if (r.kind == KIND_SUB) {
-            if (r.m + 1 < r.n) { x.has_full = 1; x.full = make_dense_row(r, r.m + 1); }
-            else { x.has_light = 1; x.light = make_light_row(r, r.n, L_END); }
+        return x;
+    }
+    const bool sub = is_dense_sub(r.kind);
+    if (src == 0 || r.aux == L_INIT) {
+        const int32_t nt = src == 0 ? r.t + 1 : r.m + 1;
+        if (sub) {
+            if (nt < r.n) { x.list = 0; x.row = make_dense_row(r, nt); }
+            else { x.list = 1; x.row = make_light_row(r, r.n, L_END); }
         } else {
-            if (T > 1) { x.has_full = 1; x.full = make_dense_row(r, 1); }
-            else { x.has_light = 1; x.light = make_light_row(r, T, L_FINALIZE); }
+            if (nt < T) { x.list = 0; x.row = make_dense_row(r, nt); }
+            else { x.list = 1; x.row = make_light_row(r, T, L_FINALIZE); }
         }
     } else if (r.aux == L_END) {
         x.freed = 1;
-        const int32_t len = r.n - r.m;
-        x.spawn = len > 2 ? 2 : (len == 2 ? 1 : 0);
+        x.spawn = child_count(r);
+    } else if (r.aux == L_BSPAWN) {
+        x.freed = 1;
+        x.spawn = ld_c(beam_fallback_flag(a, clampi(r.slot, a.n_slots))) ? 1 : child_count(r);
     } else {  // L_FINALIZE
         x.freed = 1;
         if (r.kind == KIND_ROOT && pp >= 2) x.spawn = root_segments(T, pp);
@@ -482,18 +891,26 @@ __device__ Next classify(const Row& r, bool from_full) {
     return x;
 }
 
-// Children per Alg. 1 (END) or the P'-way segments of a finished root.
-__device__ void write_spawns(const EngineArgs& a, const Row& r, int64_t pos) {
-    if (r.aux == L_END) {
+// Children per Alg. 1 (end of a subtask), the P'-way segments of a finished
+// root, or the exact re-decode of a beam subtask that lost its end state.
+__device__ void write_spawns(const EngineArgs& a, const Row& r, int src, int64_t pos) {
+    const bool beam_end = src == 1 && r.aux == L_BSPAWN;
+    if (beam_end || (src == 1 && r.aux == L_END)) {
+        if (beam_end && ld_c(beam_fallback_flag(a, clampi(r.slot, a.n_slots)))) {
+            a.queue[pos] = Task{r.seq, KIND_FSUB, r.m, r.n};
+            return;
+        }
+        const int32_t kind = (beam_end || r.kind == KIND_FSUB) ? KIND_BSUB : KIND_SUB;
         const int32_t tmid = (r.m + r.n) >> 1;
         const int32_t len = r.n - r.m;
-        if (len >= 2) a.queue[pos++] = Task{r.seq, KIND_SUB, r.m, tmid};
-        if (len > 2) a.queue[pos++] = Task{r.seq, KIND_SUB, tmid + 1, r.n};
+        if (len >= 2) a.queue[pos++] = Task{r.seq, kind, r.m, tmid};
+        if (len > 2) a.queue[pos++] = Task{r.seq, kind, tmid + 1, r.n};
     } else {
+        const int32_t kind = src == 2 ? KIND_BSUB : KIND_SUB;
         const int32_t T = r.T, pp = r.pp;
         for (int32_t d = 0; d < pp; ++d) {
             const int64_t m = d == 0 ? 0 : seg_end(T, pp, d - 1) + 1, n = seg_end(T, pp, d);
-            if (n - m >= 1) a.queue[pos++] = Task{r.seq, KIND_SUB, (int32_t)m, (int32_t)n};
+            if (n - m >= 1) a.queue[pos++] = Task{r.seq, kind, (int32_t)m, (int32_t)n};
         }
     }
 }
@@ -509,17 +926,17 @@ struct SchedLds {
     int32_t has_blocks[kXcd];
     int32_t admit[kXcd];
     int32_t spawn_total[kXcd];
-    int32_t n_full_next[kXcd];
-    int32_t n_light_next[kXcd];
-    int32_t wave_sums[kXcd][kSchedGroupWaves][4];
+    int32_t n_next[kXcd][3];   // rows written for the next step: full, light, beam
+    int32_t wave_sums[kXcd][kSchedGroupWaves][5];
 };
 
-// Exclusive scan of 4 counters over the 128 threads of a scheduler group.
-__device__ void group_scan4(int32_t (&v)[4], int32_t (&tot)[4], int32_t (&ws)[kSchedGroupWaves][4]) {
+// Exclusive scan of N counters over the 128 threads of a scheduler group.
+template <int N>
+__device__ void group_scan(int32_t (&v)[N], int32_t (&tot)[N], int32_t (&ws)[kSchedGroupWaves][5]) {
     const int lane = threadIdx.x & 63, w = (threadIdx.x >> 6) % kSchedGroupWaves;
-    int32_t inc[4];
+    int32_t inc[N];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < N; ++k) {
         int32_t x = v[k];
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
@@ -531,7 +948,7 @@ __device__ void group_scan4(int32_t (&v)[4], int32_t (&tot)[4], int32_t (&ws)[kS
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < N; ++k) {
         int32_t before = 0, all = 0;
 #pragma unroll
         for (int u = 0; u < kSchedGroupWaves; ++u) {
@@ -546,9 +963,10 @@ __device__ void group_scan4(int32_t (&v)[4], int32_t (&tot)[4], int32_t (&ws)[kS
 }
 
 // Admit queued tasks to the free slots of the XCDs that have compute
-// blocks, in proportion to their free slots, and write their start rows.
-// Called by the whole scheduler block; sl.n_light_next[x] holds the light
-// rows already written for step nxt.
+// blocks, in proportion to their free slots, and write their start rows
+// (beam tasks to the beam list, the others to the light list).  Called by
+// the whole scheduler block; sl.n_next holds the rows already written for
+// step nxt.
 __device__ void admit(const EngineArgs& a, SchedLds& sl, int nxt) {
     if (threadIdx.x == 0) {
         int32_t free_total = 0;
@@ -573,23 +991,37 @@ __device__ void admit(const EngineArgs& a, SchedLds& sl, int nxt) {
     int32_t qbase = sl.q_head;
     for (int y = 0; y < x; ++y) qbase += sl.admit[y];
     const int32_t ax = sl.admit[x];
-    for (int32_t k = tg; k < ax; k += kSchedGroup) {
+    // this thread's tasks: a contiguous range, so list order follows the queue
+    const int32_t per = (ax + kSchedGroup - 1) / kSchedGroup;
+    const int32_t lo = min(ax, tg * per), hi = min(ax, lo + per);
+    int32_t c[2] = {0, 0}, tot[2];
+    for (int32_t k = lo; k < hi; ++k) c[is_beam(a.queue[qbase + k].kind) ? 1 : 0]++;
+    group_scan<2>(c, tot, sl.wave_sums[x]);
+    for (int32_t k = lo; k < hi; ++k) {
+        const Task tk = a.queue[qbase + k];
         const int32_t slot = a.free_stack[(int64_t)x * a.pool + sl.n_free[x] - 1 - k];
-        st_row(list_light(a, nxt, x) + sl.n_light_next[x] + k, row_from_task(a, a.queue[qbase + k], slot));
+        const Row r = row_from_task(a, tk, slot);
+        if (is_beam(tk.kind)) st_row(list_beam(a, nxt, x) + sl.n_next[x][2] + c[1]++, r);
+        else st_row(list_light(a, nxt, x) + sl.n_next[x][1] + c[0]++, r);
+    }
+    __syncthreads();
+    if (tg == 0) {
+        sl.n_next[x][1] += tot[0];
+        sl.n_next[x][2] += tot[1];
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        int32_t tot = 0;
+        int32_t all = 0;
         for (int y = 0; y < kXcd; ++y) {
             sl.q_head += sl.admit[y];
             sl.n_free[y] -= sl.admit[y];
-            sl.n_light_next[y] += sl.admit[y];
-            st_c(&a.st->cnt[nxt][y][0], sl.n_full_next[y]);
-            st_c(&a.st->cnt[nxt][y][1], sl.n_light_next[y]);
-            tot += sl.n_full_next[y] + sl.n_light_next[y];
+            for (int k = 0; k < 3; ++k) {
+                st_c(&a.st->cnt[nxt][y][k], sl.n_next[y][k]);
+                all += sl.n_next[y][k];
+            }
         }
-        st_c(&a.st->total[nxt], tot);
-        if (tot > sl.max_rows) sl.max_rows = tot;
+        st_c(&a.st->total[nxt], all);
+        if (all > sl.max_rows) sl.max_rows = all;
         st_c(&a.st->max_rows, sl.max_rows);
     }
     __syncthreads();
@@ -600,34 +1032,37 @@ __device__ void scheduler(const EngineArgs& a, int32_t s, SchedLds& sl) {
     const int x = threadIdx.x / kSchedGroup, tg = threadIdx.x % kSchedGroup;
     const int32_t nf = ld_c(&a.st->cnt[cur][x][0]);
     const int32_t nl = ld_c(&a.st->cnt[cur][x][1]);
-    const int32_t total = nf + nl;
+    const int32_t nbm = ld_c(&a.st->cnt[cur][x][2]);
+    const int32_t total = nf + nl + nbm;
     const int32_t per = (total + kSchedGroup - 1) / kSchedGroup;
     const int32_t lo = min(total, tg * per), hi = min(total, lo + per);
-    const Row* F = list_full(a, cur, x);
-    const Row* L = list_light(a, cur, x);
+    const Row* lists[3] = {list_full(a, cur, x), list_light(a, cur, x), list_beam(a, cur, x)};
+    Row* out[3] = {list_full(a, nxt, x), list_light(a, nxt, x), list_beam(a, nxt, x)};
 
     // pass 0 counts what the group's rows turn into, pass 1 writes it
-    int32_t cnt[4] = {0, 0, 0, 0}, tot[4] = {0, 0, 0, 0};  // full, light, freed, spawned
+    int32_t cnt[5] = {0, 0, 0, 0, 0}, tot[5] = {0, 0, 0, 0, 0};  // full, light, beam, freed, spawned
     for (int pass = 0; pass < 2; ++pass) {
         if (pass == 1) {
-            group_scan4(cnt, tot, sl.wave_sums[x]);
-            if (tg == 0) sl.spawn_total[x] = tot[3];
+            group_scan<5>(cnt, tot, sl.wave_sums[x]);
+            if (tg == 0) sl.spawn_total[x] = tot[4];
             __syncthreads();
             int32_t qoff = sl.q_tail;
             for (int y = 0; y < x; ++y) qoff += sl.spawn_total[y];
-            cnt[3] += qoff;
+            cnt[4] += qoff;
         }
         for (int32_t i = lo; i < hi; ++i) {
-            const bool ff = i < nf;
-            const Row r = ld_row(ff ? F + i : L + (i - nf));
-            const Next n = classify(r, ff);
+            const int src = i < nf ? 0 : (i < nf + nl ? 1 : 2);
+            const int32_t k = src == 0 ? i : (src == 1 ? i - nf : i - nf - nl);
+            const Row r = ld_row(lists[src] + k);
+            const Next n = classify(a, r, src);
             if (pass == 0) {
-                cnt[0] += n.has_full; cnt[1] += n.has_light; cnt[2] += n.freed; cnt[3] += n.spawn;
+                if (n.list >= 0) cnt[n.list]++;
+                cnt[3] += n.freed;
+                cnt[4] += n.spawn;
             } else {
-                if (n.has_full) st_row(list_full(a, nxt, x) + cnt[0]++, n.full);
-                if (n.has_light) st_row(list_light(a, nxt, x) + cnt[1]++, n.light);
-                if (n.freed) a.free_stack[(int64_t)x * a.pool + sl.n_free[x] + cnt[2]++] = r.slot;
-                if (n.spawn) { write_spawns(a, r, (int64_t)cnt[3]); cnt[3] += n.spawn; }
+                if (n.list >= 0) st_row(out[n.list] + cnt[n.list]++, n.row);
+                if (n.freed) a.free_stack[(int64_t)x * a.pool + sl.n_free[x] + cnt[3]++] = r.slot;
+                if (n.spawn) { write_spawns(a, r, src, (int64_t)cnt[4]); cnt[4] += n.spawn; }
             }
         }
     }
@@ -636,9 +1071,8 @@ __device__ void scheduler(const EngineArgs& a, int32_t s, SchedLds& sl) {
         for (int y = 0; y < kXcd; ++y) sl.q_tail += sl.spawn_total[y];
     }
     if (tg == 0) {
-        sl.n_free[x] += tot[2];
-        sl.n_full_next[x] = tot[0];
-        sl.n_light_next[x] = tot[1];
+        sl.n_free[x] += tot[3];
+        for (int k = 0; k < 3; ++k) sl.n_next[x][k] = tot[k];
     }
     __syncthreads();
     admit(a, sl, nxt);
@@ -703,6 +1137,7 @@ __device__ bool barrier_master(const EngineArgs& a, uint32_t epoch) {
 union EngineLds {
     TileLds tile;
     SchedLds sched;
+    BeamLds beam;
 };
 
 extern "C" __global__ __launch_bounds__(kEngBlock) void fv_engine_kernel(const float* __restrict__ Ap,
@@ -728,8 +1163,7 @@ extern "C" __global__ __launch_bounds__(kEngBlock) void fv_engine_kernel(const f
             for (int y = 0; y < kXcd; ++y) {
                 sl.n_free[y] = a.pool;
                 sl.has_blocks[y] = ld_c(&a.st->xcd_blocks[y][0]) > 0;
-                sl.n_full_next[y] = 0;
-                sl.n_light_next[y] = 0;
+                for (int k = 0; k < 3; ++k) sl.n_next[y][k] = 0;
             }
         }
         __syncthreads();
@@ -776,6 +1210,10 @@ extern "C" __global__ __launch_bounds__(kEngBlock) void fv_engine_kernel(const f
             // light rows: one per wave
             for (int32_t li = rank * kEngWaves + (threadIdx.x >> 6); li < nl; li += nx * kEngWaves)
                 light_row(a, Ap, ld_row(L + li));
+            // beam rows: one per block, from the last block down
+            const int32_t nbm = ld_c(&a.st->cnt[cur][x][2]);
+            const Row* Bl = list_beam(a, cur, x);
+            for (int32_t bi = nx - 1 - rank; bi < nbm; bi += nx) beam_row(a, Ap, ld_row(Bl + bi), lds.beam);
         }
         ++epoch;
         ok = is_sched ? barrier_master(a, epoch) : barrier_arrive_wait(a, epoch, x);
@@ -814,9 +1252,10 @@ extern "C" __global__ __launch_bounds__(kBlock) void fv_setup_kernel(EngineArgs 
             d = sa.seqs_dev[b];
             if (d.T < 0 || d.model != 0 || (d.T > 0 && (d.ld < sa.K || !d.log_b || !d.path)) || !d.score) s_bad = 1;
             const int32_t T = d.T < 0 ? 0 : d.T;
-            pp = sa.kind == KIND_ROOT ? eff_parallelism(T, sa.P) : 1;
+            pp = sa.kind == KIND_VANILLA ? 1 : eff_parallelism(T, sa.P);
             v[0] = T;
-            v[1] = sa.kind == KIND_ROOT ? 2 * (int64_t)(pp - 1) : 0;
+            // root division copies: delta + link per division (dense), one beam record (beam)
+            v[1] = sa.kind == KIND_ROOT ? 2 * (int64_t)(pp - 1) : (sa.kind == KIND_BROOT ? (int64_t)(pp - 1) : 0);
             v[2] = sa.kind == KIND_VANILLA ? (int64_t)T * sa.K : 0;
         }
         for (int k = 0; k < 3; ++k) scan[k][tid] = v[k];
@@ -897,6 +1336,47 @@ extern "C" __global__ __launch_bounds__(kBlock) void fv_finish_kernel(EngineArgs
         }
     }
     if (status) status[b] = stv;
+}
+
+// Beam decodes: status, and the returned score as the step-by-step float32
+// re-sum of the returned path, s_0 = log pi(q_0) + log B_0(q_0),
+// s_t = (s_{t-1} + log A(q_{t-1}, q_t)) + log B_t(q_t).  One wave per
+// sequence: the terms are gathered 64 at a time, then added in order.
+extern "C" __global__ __launch_bounds__(kBlock) void fv_beam_finish_kernel(EngineArgs a, const float* __restrict__ Ap,
+                                                                           int32_t* status) {
+    const int32_t b = blockIdx.x * kWaves + (threadIdx.x >> 6);
+    const int32_t lane = threadIdx.x & 63;
+    if (b >= a.n_seqs) return;
+    SeqInfo& sq = a.seqs[b];
+    int32_t stv = sq.status;
+    if (a.st->error) stv = FV_E_DEVICE;  // kernel boundary: plain loads are coherent
+    if (stv >= 0 && sq.T >= 1) {
+        const int32_t K = a.K, Kp = a.Kp, T = sq.T;
+        const int32_t q0 = sq.path[0];
+        bool ok = q0 >= 0 && q0 < K;
+        float s = -INFINITY;
+        if (ok) s = a.log_pi ? a.log_pi[q0] + sq.log_b[q0] : sq.log_b[q0];
+        for (int32_t t0 = 1; ok && t0 < T; t0 += 64) {
+            const int32_t t = t0 + lane;
+            float ta = 0.0f, tb = 0.0f;
+            int32_t bad = 0;
+            if (t < T) {
+                const int32_t qp = sq.path[t - 1], q = sq.path[t];
+                if (qp < 0 || qp >= K || q < 0 || q >= K) bad = 1;
+                else { ta = Ap[(int64_t)qp * Kp + q]; tb = sq.log_b[(int64_t)t * sq.ld + q]; }
+            }
+            if (__ballot(bad) != 0) { ok = false; break; }
+            const int32_t cnt = min(64, T - t0);
+            for (int32_t l = 0; l < cnt; ++l) {
+                const float x = __shfl(ta, l, 64), y = __shfl(tb, l, 64);
+                const float c = s + x;
+                s = c + y;
+            }
+        }
+        if (!ok) s = -INFINITY;
+        if (lane == 0) *sq.score = s;
+    }
+    if (lane == 0 && status) status[b] = stv;
 }
 
 }  // namespace fv

@@ -20,8 +20,14 @@ constexpr int kKAlign = 64;     // K is padded to a multiple of this
 
 inline __host__ __device__ int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
-// Kinds of rows (one row = one decoding task in flight).
-enum : int32_t { KIND_VANILLA = 0, KIND_ROOT = 1, KIND_SUB = 2 };
+// Kinds of rows (one row = one decoding task in flight).  KIND_BROOT and
+// KIND_BSUB are FLASH-BS (beam) tasks; KIND_FSUB is the exact (all-K)
+// re-decode of a beam subtask whose beam lost its known end state: it runs
+// as a dense subtask and its children are beam subtasks again.
+enum : int32_t { KIND_VANILLA = 0, KIND_ROOT = 1, KIND_SUB = 2, KIND_BROOT = 3, KIND_BSUB = 4, KIND_FSUB = 5 };
+
+inline __host__ __device__ bool is_dense_sub(int32_t kind) { return kind == KIND_SUB || kind == KIND_FSUB; }
+inline __host__ __device__ bool is_beam(int32_t kind) { return kind == KIND_BROOT || kind == KIND_BSUB; }
 
 // Per-step flags of a dense row.
 enum : int32_t {
@@ -34,8 +40,17 @@ enum : int32_t {
     F_FINAL = 1 << 6,      // t = T-1 of a full-length pass: feed the final arg max
 };
 
-// Light (O(K)) operations.
-enum : int32_t { L_INIT = 0, L_END = 1, L_FINALIZE = 2 };
+// Light (O(K)) operations.  L_BSPAWN does nothing: it holds a finished
+// beam subtask for one step so that the scheduler, which classifies a
+// step's rows while they run, reads the task's fallback flag after the
+// step that wrote it.
+enum : int32_t { L_INIT = 0, L_END = 1, L_FINALIZE = 2, L_BSPAWN = 3 };
+
+// Operations of a beam row (one block each): start step, full beam step,
+// end-only step of a subtask, final selection of a root.
+enum : int32_t { B_INIT = 0, B_STEP = 1, B_END = 2, B_FINAL = 3 };
+constexpr int32_t kBeamMaxK = 16384;   // scores of one step live in LDS
+constexpr int32_t kBeamMaxB = 2048;
 
 // A task in flight; carries what every step needs so that tiles do not
 // look up the per-sequence table.
@@ -65,7 +80,7 @@ struct SeqInfo {
     int32_t T;
     int32_t pp;          // effective parallelism P'
     int64_t alpha_off;   // into alpha_at
-    int64_t root_off;    // into root copies, in units of Kp floats
+    int64_t root_off;    // into root copies, in units (Kp floats, or one beam record)
     int64_t psi_off;     // into the vanilla table, in entries
     int32_t status;
     int32_t pad_;
@@ -84,7 +99,7 @@ struct EngineState {
     int32_t max_rows;           // high-water mark of rows in flight
     int32_t q_tail0;            // tasks queued by the setup kernel
     int32_t pad0[kLine - 4];
-    int32_t cnt[2][kXcd][2];    // [parity][xcd][full, light] rows of a step
+    int32_t cnt[2][kXcd][4];    // [parity][xcd][full, light, beam, -] rows of a step
     int32_t total[2];           // rows of a step over all XCDs
     int32_t pad1[kLine - 2];
     uint32_t go[kXcd][kLine];   // barrier release flags, one line per XCD
@@ -100,7 +115,9 @@ struct EngineArgs {
     // sequences
     SeqInfo* seqs;
     int32_t n_seqs;
-    int32_t method;             // FV_VANILLA / FV_FLASH
+    int32_t method;             // FV_VANILLA / FV_FLASH / FV_BEAM
+    int32_t B, Bc;              // beam width (<= K) and its padded array length
+    int64_t brec;               // floats per beam record (header + state, score, anchor arrays)
     // storage
     float* slot_base;           // slots * slot_floats
     int64_t slot_floats;        // floats per slot
@@ -115,6 +132,7 @@ struct EngineArgs {
     uint32_t* arrive;           // [gridDim] barrier arrival flags
     Row* rows_full;             // [2][kXcd][pool] rows of a step, per XCD
     Row* rows_light;            // [2][kXcd][pool]
+    Row* rows_beam;             // [2][kXcd][pool]
     int32_t pool;               // slots per XCD (= n_slots / kXcd)
     Task* queue;                // linear, capacity q_cap
     int64_t q_cap;
@@ -132,7 +150,7 @@ struct SetupArgs {
     int64_t host_sum_T;     // the host's totals, checked against the device's copies
     int64_t host_sum_root;
     int64_t host_sum_psi;
-    int32_t kind;           // KIND_VANILLA or KIND_ROOT
+    int32_t kind;           // KIND_VANILLA, KIND_ROOT or KIND_BROOT
     int32_t K;
 };
 

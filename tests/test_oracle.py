@@ -399,15 +399,7 @@ def test_beam_keeps_lowest_states_among_boundary_ties():
     assert pb.tolist() == [1, 2] and sb == 3.0
 
 
-def _sparse_integer_instance(seed):
-    r = np.random.default_rng(seed)
-    K = int(r.integers(3, 7)); T = int(r.integers(4, 12))
-    la = np.where(r.random((K, K)) < 0.45, r.integers(-4, 1, (K, K)).astype(np.float32),
-                  -np.inf).astype(np.float32)
-    np.fill_diagonal(la, -1.0)
-    lp = r.integers(-3, 1, K).astype(np.float32)
-    lb = r.integers(-4, 1, (T, K)).astype(np.float32)
-    return lp, la, lb
+_sparse_integer_instance = hmm.sparse_integer_instance
 
 
 def test_beam_fallback_when_end_unreachable():

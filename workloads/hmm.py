@@ -188,3 +188,18 @@ def crf_batch(n: int = 512, K: int = 256, t_lo: int = 32, t_hi: int = 512,
             em[b, :T] = lin(x).numpy()
         trans = (torch.randn(K, K, generator=g) * 0.1).numpy().astype(np.float32)
     return CRFBatch(K, lengths, em, trans)
+
+
+def sparse_integer_instance(seed: int):
+    """Tiny HMM with sparse integer transitions (about 45% of the entries
+    finite, self-loops always present), integer start and emission scores:
+    ties are common and narrow beams can lose a task's known end state."""
+    r = np.random.default_rng(seed)
+    K = int(r.integers(3, 7)); T = int(r.integers(4, 12))
+    la = np.where(r.random((K, K)) < 0.45, r.integers(-4, 1, (K, K)).astype(np.float32),
+                  -np.inf).astype(np.float32)
+    np.fill_diagonal(la, -1.0)
+    lp = r.integers(-3, 1, K).astype(np.float32)
+    lb = r.integers(-4, 1, (T, K)).astype(np.float32)
+    return lp, la, lb
+
