@@ -150,7 +150,7 @@ fv_status plan_dense(int32_t method, int32_t K, const int32_t* T_host, int32_t n
     put(cur, L.arrive, (size_t)kMaxBlocks * 4);
     put(cur, L.rows_full, (size_t)2 * L.n_slots * sizeof(Row));
     put(cur, L.rows_light, (size_t)2 * L.n_slots * sizeof(Row));
-    put(cur, L.rows_beam, beam ? (size_t)2 * L.n_slots * sizeof(Row) : 0);
+    put(cur, L.rows_beam, (size_t)2 * L.n_slots * sizeof(Row));   // block rows: beam tasks and finalizes
     put(cur, L.queue, (size_t)L.q_cap * sizeof(Task));
     put(cur, L.free_stack, (size_t)L.n_slots * 4);
     put(cur, L.slots, (size_t)L.n_slots * slot_bytes);

@@ -227,33 +227,67 @@ __device__ __forceinline__ void tile_partial(const float* __restrict__ Ap, int32
 struct TileLds {
     float m[kEngWaves][kTileCols][kTileRows];
     int32_t g[kEngWaves][kTileCols][kTileRows];
+    uint64_t stash[4][kTileRows][4];   // per tile group: row words 0, 3, 4, 5 of each lane's row
+    uint32_t gsync[4];                  // per tile group: barrier arrivals
+    int32_t gitem[4];                   // per tile group: the work item it claimed
 };
 
-// The block's 16 waves work on 16 / nsplit tiles at once, nsplit waves per
-// tile, each wave taking a contiguous share of the predecessor groups; all
-// waves call this together (block-wide barriers inside).  A tile group
-// without a tile passes tile < 0.  nsplit is 4, 8 or 16 and block-uniform.
+// Barrier of the nsplit waves of one tile group (an LDS arrival counter;
+// the groups of a block run independently of each other).  Every wave of
+// the group calls it the same number of times.
+__device__ __forceinline__ void group_sync(uint32_t* ctr, int32_t nsplit) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    if ((threadIdx.x & 63) == 0) {
+        const uint32_t old = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        const uint32_t target = old - old % (uint32_t)nsplit + (uint32_t)nsplit;
+        uint32_t spins = 0;
+        while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > (1u << 26)) break;   // bounded: the group's waves always arrive
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// One tile computed by a group of nsplit waves (4, 8 or 16), each wave
+// taking a contiguous share of the predecessor groups; the waves of the
+// group call this together (group barriers inside), other groups of the
+// block run on independently.
+//
+// After the max-plus loop the partial maxima merge through LDS and each
+// output's arg max is refined inside its winning group.  That epilogue is
+// bound by memory latency, so its loads are issued together: the row's
+// remaining fields come from an LDS copy made before the loop, the refine
+// loads of two columns go out at once, and so do the anchor gathers.
 __device__ void dense_tile(const EngineArgs& a, const float* __restrict__ Ap, const Row* rows,
                            int32_t nrows, int32_t tile, int32_t nsplit, TileLds& lds) {
-    const bool active = tile >= 0;
-    if (!active) tile = 0;
-    const int32_t ncb = a.Kp / kTileCols;
+    const bool active = true;
+    const int32_t K = a.K, Kp = a.Kp;
+    const int32_t ncb = Kp / kTileCols;
     const int32_t rg = tile / ncb;
     const int32_t j0 = (tile - rg * ncb) * kTileCols;
     const int32_t lane = threadIdx.x & 63;
     const int32_t bw = threadIdx.x >> 6;              // wave in block
     const int32_t wave = bw & (nsplit - 1);           // wave in tile group
     const int32_t wbase = bw - wave;                  // first wave of the group
+    const int32_t grp = bw / nsplit;                  // tile group in block
     const int32_t cpw = kTileCols / nsplit;           // output columns per wave
     const int32_t ridx = rg * kTileRows + lane;
     const bool valid = active && ridx < nrows;
     const Row* rp = rows + (valid ? ridx : rg * kTileRows);
-    // (t, slot), log_b and ld of the row; the rest is re-read after the loop
+    // (t, slot), log_b and ld of the row; the group's first wave also copies
+    // the fields the epilogue needs to LDS
     const uint64_t* rw = reinterpret_cast<const uint64_t*>(rp);
     const uint64_t w_ts = ld_c(rw + 2);
     const int32_t t0 = (int32_t)(uint32_t)w_ts, slot0 = clampi((int32_t)(w_ts >> 32), a.n_slots);
     const float* log_b = reinterpret_cast<const float*>(ld_c(rw + 6));
     const int64_t ld = (int64_t)ld_c(rw + 7);
+    if (wave == 0) {
+        lds.stash[grp][lane][0] = ld_c(rw + 0);
+        lds.stash[grp][lane][1] = ld_c(rw + 3);
+        lds.stash[grp][lane][2] = ld_c(rw + 4);
+        lds.stash[grp][lane][3] = ld_c(rw + 5);
+    }
     const float* drow = slot_delta(a, slot0, (t0 - 1) & 1);
     // emission scores of this thread's outputs, fetched before the max-plus loop
     const int32_t cq = wave * cpw;
@@ -263,29 +297,35 @@ __device__ void dense_tile(const EngineArgs& a, const float* __restrict__ Ap, co
 #pragma unroll
         for (int cc = 0; cc < 4; ++cc) {
             const int32_t j = j0 + cq + cc;
-            bpre[cc] = (valid && cc < cpw && j < a.K) ? bt[j] : 0.0f;
+            bpre[cc] = (valid && cc < cpw && j < K) ? bt[j] : 0.0f;
         }
     }
 
     // predecessor groups [g0, g1) of this wave
-    const int32_t ng = a.Kp / kGroup;
+    const int32_t ng = Kp / kGroup;
     const int32_t g0 = __builtin_amdgcn_readfirstlane((wave * ng) / nsplit);
     const int32_t g1 = __builtin_amdgcn_readfirstlane(((wave + 1) * ng) / nsplit);
-    float m[kTileCols];
-    int32_t g[kTileCols];
-    tile_partial(Ap, a.Kp, __builtin_amdgcn_readfirstlane(j0), drow, g0 * kGroup,
-                 active ? g1 * kGroup : g0 * kGroup, m, g);
+    {
+        float m[kTileCols];
+        int32_t g[kTileCols];
+        tile_partial(Ap, Kp, __builtin_amdgcn_readfirstlane(j0), drow, g0 * kGroup,
+                     active ? g1 * kGroup : g0 * kGroup, m, g);
 #pragma unroll
-    for (int c = 0; c < kTileCols; ++c) {
-        lds.m[bw][c][lane] = m[c];
-        lds.g[bw][c][lane] = g[c];
+        for (int c = 0; c < kTileCols; ++c) {
+            lds.m[bw][c][lane] = m[c];
+            lds.g[bw][c][lane] = g[c];
+        }
     }
-    __syncthreads();
+    group_sync(&lds.gsync[grp], nsplit);
 
     if (valid) {
-        const Row r = ld_row(rp);
-        const int32_t t = r.t;
-        const int32_t slot = clampi(r.slot, a.n_slots);
+        const uint64_t w0 = lds.stash[grp][lane][0], w3 = lds.stash[grp][lane][1];
+        const uint64_t w4 = lds.stash[grp][lane][2], w5 = lds.stash[grp][lane][3];
+        const int32_t seq = (int32_t)(uint32_t)w0;
+        const int32_t f = (int32_t)(uint32_t)w3, aux = (int32_t)(w3 >> 32);
+        const int32_t pp = (int32_t)(w4 >> 32);
+        const int64_t off = (int64_t)w5;
+        const int32_t t = t0, slot = slot0;
         float* dcur = slot_delta(a, slot, t & 1);
         int32_t* acur = nullptr;
         const int32_t* aprev = nullptr;
@@ -293,59 +333,102 @@ __device__ void dense_tile(const EngineArgs& a, const float* __restrict__ Ap, co
             acur = slot_anc(a, slot, t & 1);
             aprev = slot_anc(a, slot, (t - 1) & 1);
         }
-        unsigned long long best_key = 0;
+        // merge the partial maxima of the group's waves (earliest group keeps ties)
+        float mv[4];
+        int32_t gi[4];
+        bool live[4], need[4];
 #pragma unroll
         for (int cc = 0; cc < 4; ++cc) {
             const int32_t c = cq + cc;
-            const int32_t j = j0 + c;
-            if (cc >= cpw || j >= a.K) break;
-            float mv = lds.m[wbase][c][lane];
-            int32_t gi = lds.g[wbase][c][lane];
-            for (int w = 1; w < nsplit; ++w) {
-                const float x = lds.m[wbase + w][c][lane];
-                if (x > mv) { mv = x; gi = lds.g[wbase + w][c][lane]; }
-            }
-            float val = mv;
-            int32_t psi = 0;
-            if ((r.flags & F_NEED_ARG) || mv == 0.0f) {
-                const int32_t src0 = gi * kGroup;
-                const float* ac = a.Acol + (int64_t)src0 * a.Kp + j;   // column j, rows src0..
-                const float* dp = drow + src0;
-                psi = -1;
-#pragma unroll
-                for (int k = 0; k < kGroup; k += 4) {
-                    const float4 dv = *reinterpret_cast<const float4*>(dp + k);
-                    const float a0 = ac[(int64_t)k * a.Kp], a1 = ac[(int64_t)(k + 1) * a.Kp];
-                    const float a2 = ac[(int64_t)(k + 2) * a.Kp], a3 = ac[(int64_t)(k + 3) * a.Kp];
-                    const float x0 = dv.x + a0, x1 = dv.y + a1, x2 = dv.z + a2, x3 = dv.w + a3;
-                    if (psi < 0 && x0 == mv) { psi = src0 + k; val = x0; }
-                    if (psi < 0 && x1 == mv) { psi = src0 + k + 1; val = x1; }
-                    if (psi < 0 && x2 == mv) { psi = src0 + k + 2; val = x2; }
-                    if (psi < 0 && x3 == mv) { psi = src0 + k + 3; val = x3; }
+            live[cc] = cc < cpw && j0 + c < K;
+            mv[cc] = 0.0f;
+            gi[cc] = 0;
+            if (live[cc]) {
+                float v = lds.m[wbase][c][lane];
+                int32_t gg = lds.g[wbase][c][lane];
+                for (int w = 1; w < nsplit; ++w) {
+                    const float x = lds.m[wbase + w][c][lane];
+                    if (x > v) { v = x; gg = lds.g[wbase + w][c][lane]; }
                 }
-                if (psi < 0) psi = src0;  // unreachable for finite/-inf inputs
-                psi = clampi(psi, a.K);
+                mv[cc] = v;
+                gi[cc] = gg;
             }
-            const float dnew = val + bpre[cc];
+            need[cc] = live[cc] && ((f & F_NEED_ARG) || mv[cc] == 0.0f);
+        }
+        // refine inside the winning group: the first candidate equal to the
+        // maximum; its value is the one stored (signed zero)
+        float val[4];
+        int32_t psi[4];
+#pragma unroll
+        for (int cb = 0; cb < 4; cb += 2) {
+            float av[2][kGroup], dv[2][kGroup];
+#pragma unroll
+            for (int c2 = 0; c2 < 2; ++c2) {
+                const int cc = cb + c2;
+                if (need[cc]) {
+                    const int32_t src0 = gi[cc] * kGroup;
+                    const float* ac = a.Acol + (int64_t)src0 * Kp + (j0 + cq + cc);
+#pragma unroll
+                    for (int k = 0; k < kGroup; ++k) av[c2][k] = ac[(int64_t)k * Kp];
+#pragma unroll
+                    for (int k = 0; k < kGroup; k += 4) {
+                        const float4 d4 = *reinterpret_cast<const float4*>(drow + src0 + k);
+                        dv[c2][k] = d4.x; dv[c2][k + 1] = d4.y; dv[c2][k + 2] = d4.z; dv[c2][k + 3] = d4.w;
+                    }
+                }
+            }
+#pragma unroll
+            for (int c2 = 0; c2 < 2; ++c2) {
+                const int cc = cb + c2;
+                val[cc] = mv[cc];
+                psi[cc] = 0;
+                if (need[cc]) {
+                    const int32_t src0 = gi[cc] * kGroup;
+                    int32_t p = -1;
+#pragma unroll
+                    for (int k = 0; k < kGroup; ++k) {
+                        const float x = dv[c2][k] + av[c2][k];
+                        if (p < 0 && x == mv[cc]) { p = src0 + k; val[cc] = x; }
+                    }
+                    psi[cc] = clampi(p < 0 ? src0 : p, K);   // p < 0 is unreachable for finite/-inf inputs
+                }
+            }
+        }
+        // anchors (gathers issued together), then the stores
+        int32_t anc[4];
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+            anc[cc] = 0;
+            if (live[cc]) {
+                if (f & F_ANC_FIRST) anc[cc] = psi[cc];
+                else if (f & F_ANC_CHAIN) anc[cc] = aprev[psi[cc]];
+            }
+        }
+        unsigned long long best_key = 0;
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+            if (!live[cc]) continue;
+            const int32_t j = j0 + cq + cc;
+            const float dnew = val[cc] + bpre[cc];
             dcur[j] = dnew;
-            const int32_t f = r.flags;
-            if (f & F_PSI_TABLE) a.psi16[r.off + (int64_t)t * a.K + j] = (uint16_t)psi;
-            int32_t anc = 0;
-            if (f & F_ANC_FIRST) { anc = psi; acur[j] = anc; }
-            else if (f & F_ANC_CHAIN) { anc = clampi(aprev[psi], a.K); acur[j] = anc; }
+            if (f & F_PSI_TABLE) a.psi16[off + (int64_t)t * K + j] = (uint16_t)psi[cc];
+            if (f & (F_ANC_FIRST | F_ANC_CHAIN)) {
+                anc[cc] = clampi(anc[cc], K);
+                acur[j] = anc[cc];
+            }
             if (f & F_SNAP_SUB) slot_snap(a, slot)[j] = dnew;
             if (f & F_SNAP_ROOT) {
-                root_dsnap(a, r.off, r.aux)[j] = dnew;
-                if (r.aux >= 1) root_link(a, r.off, r.pp, r.aux)[j] = anc;
+                root_dsnap(a, off, aux)[j] = dnew;
+                if (aux >= 1) root_link(a, off, pp, aux)[j] = anc[cc];
             }
             if (f & F_FINAL) {
                 const unsigned long long k = order_key(dnew, j);
                 if (k > best_key) best_key = k;
             }
         }
-        if (r.flags & F_FINAL) key_max(&a.keys[r.seq], best_key);
+        if (f & F_FINAL) key_max(&a.keys[seq], best_key);
     }
-    __syncthreads();
+    group_sync(&lds.gsync[grp], nsplit);   // partials and stash are reused by the group's next tile
 }
 
 // ---------------------------------------------------------------- light rows
@@ -422,35 +505,8 @@ __device__ void light_row(const EngineArgs& a, const float* __restrict__ Ap, con
             st_c(sq.path + tmid, qmid);
             st_cf(a.alpha_at + sq.alpha_off + tmid, slot_snap(a, slot)[qmid]);
         }
-    } else if (r.aux == L_BSPAWN) {
-        return;
-    } else {  // L_FINALIZE
-        const int32_t T = r.T;
-        const unsigned long long key = ld_c(a.keys + r.seq);
-        const int32_t qT = clampi((int32_t)(0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull)), K);
-        const float sc = slot_delta(a, slot, (T - 1) & 1)[qT];
-        if (sc == -INFINITY) {
-            for (int32_t t = lane; t < T; t += 64) st_c(sq.path + t, -1);
-            if (lane == 0) {
-                st_cf(sq.score, sc);
-                st_c(&sq.status, (int32_t)FV_E_INFEASIBLE);
-            }
-            return;
-        }
-        if (lane == 0) {
-            st_cf(sq.score, sc);
-            st_c(sq.path + T - 1, qT);
-            if (r.kind == KIND_ROOT && r.pp >= 2) {
-                int32_t q = clampi(slot_anc(a, slot, (T - 1) & 1)[qT], K);
-                for (int32_t d = r.pp - 2; d >= 0; --d) {
-                    const int64_t e = seg_end(T, r.pp, d);
-                    st_c(sq.path + e, q);
-                    st_cf(a.alpha_at + sq.alpha_off + e, root_dsnap(a, r.off, d)[q]);
-                    if (d >= 1) q = clampi(root_link(a, r.off, r.pp, d)[q], K);
-                }
-            }
-        }
     }
+    // L_BSPAWN: nothing to do (see its definition)
 }
 
 // ---------------------------------------------------------------- beam rows
@@ -676,6 +732,8 @@ __device__ int32_t beam_find(const BeamRec& r, int32_t n, int32_t q) {
     return -1;
 }
 
+__device__ void beam_chain_walk(const EngineArgs& a, const Row& r, int32_t q, BeamLds& L);
+
 __device__ void beam_row(const EngineArgs& a, const float* __restrict__ Ap, const Row& r, BeamLds& L) {
     const int tid = threadIdx.x;
     SeqInfo& sq = a.seqs[r.seq];
@@ -806,21 +864,152 @@ __device__ void beam_row(const EngineArgs& a, const float* __restrict__ Ap, cons
         }
         const int32_t top_state = block_argmax_key(key, L);
         if (tid == 0) {
-            const int32_t top = beam_find(fin, nb, top_state);
+            int32_t top = 0;   // position of top_state in the (state-sorted) LDS copy
+            for (int32_t lo = 0, hi = nb; lo < hi;) {
+                const int32_t mid = (lo + hi) >> 1;
+                if (L.bs[mid] < top_state) lo = mid + 1; else hi = mid;
+                top = lo;
+            }
+            top = clampi(top, nb);
             st_c(sq.path + T - 1, top_state);
-            if (pp >= 2) {
-                int32_t q = top >= 0 ? L.ba[top] : -1;
-                for (int32_t d = pp - 2; d >= 0; --d) {
-                    const int64_t e = seg_end(T, pp, d);
-                    st_c(sq.path + e, q);
-                    const BeamRec rs = root_beam(a, r.off, d);
-                    const int32_t at = (q >= 0 && q < K) ? beam_find(rs, clampi(rs.hdr[0], B + 1), q) : -1;
-                    st_cf(a.alpha_at + sq.alpha_off + e, at >= 0 ? rs.v[at] : __builtin_nanf(""));
-                    if (d >= 1) q = at >= 0 ? rs.a[at] : -1;
-                }
+            L.misc[3] = L.ba[top];
+        }
+        __syncthreads();
+        if (pp >= 2) beam_chain_walk(a, r, L.misc[3], L);
+    }
+}
+
+// Division chain of a finished beam root: q*_{e_d} for d = P'-2 .. 0, each
+// found in the division's beam snapshot (state-sorted), whose score is the
+// anchor alpha and whose anchor is the next state down.  Snapshot records
+// are copied to LDS in chunks (coalesced) and walked there.
+__device__ void beam_chain_walk(const EngineArgs& a, const Row& r, int32_t q, BeamLds& L) {
+    const int tid = threadIdx.x;
+    SeqInfo& sq = a.seqs[r.seq];
+    const int32_t K = a.K, B = a.B, T = r.T, pp = r.pp;
+    int32_t* buf = reinterpret_cast<int32_t*>(L.sc);             // L.sc and L.an: 2 * kBeamMaxK ints
+    const int32_t stride = 1 + 3 * B;                             // count, states, scores, anchors
+    const int32_t per = max(1, (2 * kBeamMaxK) / stride);
+    for (int32_t dhi = pp - 2; dhi >= 0; dhi -= per) {
+        const int32_t dlo = max(0, dhi - per + 1);
+        for (int32_t d = dlo; d <= dhi; ++d) {
+            const BeamRec rs = root_beam(a, r.off, d);
+            int32_t* dst = buf + (d - dlo) * stride;
+            const int32_t n = clampi(rs.hdr[0], B + 1);
+            if (tid == 0) dst[0] = n;
+            for (int32_t k = tid; k < n; k += kEngBlock) {
+                dst[1 + k] = rs.s[k];
+                dst[1 + B + k] = __float_as_int(rs.v[k]);
+                dst[1 + 2 * B + k] = rs.a[k];
             }
         }
+        __syncthreads();
+        if (tid == 0) {
+            for (int32_t d = dhi; d >= dlo; --d) {
+                const int32_t* rec = buf + (d - dlo) * stride;
+                const int64_t e = seg_end(T, pp, d);
+                st_c(sq.path + e, q);
+                int32_t at = -1;
+                for (int32_t lo = 0, hi = rec[0]; lo < hi;) {
+                    const int32_t mid = (lo + hi) >> 1;
+                    const int32_t sm = rec[1 + mid];
+                    if (sm == q) { at = mid; break; }
+                    if (sm < q) lo = mid + 1; else hi = mid;
+                }
+                st_cf(a.alpha_at + sq.alpha_off + e, at >= 0 ? __int_as_float(rec[1 + B + at]) : __builtin_nanf(""));
+                if (d >= 1) q = (at >= 0 && q >= 0 && q < K) ? rec[1 + 2 * B + at] : -1;
+            }
+            L.misc[3] = q;
+        }
+        __syncthreads();
+        q = L.misc[3];
+        __syncthreads();
     }
+}
+
+union EngineLds {
+    TileLds tile;
+    BeamLds beam;
+};
+
+// Finalize of a vanilla pass or a FLASH root (one block): the final state,
+// the score, and for a root the division chain q*_{e_d} = Link_{d+1}(q*_{e_{d+1}})
+// with the anchors alpha = Dsnap_d(q*_{e_d}).  Link rows are copied to LDS in
+// chunks (coalesced) and the chain is walked there; the anchors are then
+// gathered in parallel.
+__device__ void dense_finalize(const EngineArgs& a, const Row& r, EngineLds& lds) {
+    const int tid = threadIdx.x;
+    SeqInfo& sq = a.seqs[r.seq];
+    const int32_t K = a.K, T = r.T, pp = r.pp;
+    const int32_t slot = clampi(r.slot, a.n_slots);
+    __shared__ int32_t sv[4];
+    int32_t* buf = reinterpret_cast<int32_t*>(&lds);
+    constexpr int32_t kBufInts = (int32_t)(sizeof(EngineLds) / 4);
+    if (tid == 0) {
+        const unsigned long long key = ld_c(a.keys + r.seq);
+        const int32_t qT = clampi((int32_t)(0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull)), K);
+        const float sc = slot_delta(a, slot, (T - 1) & 1)[qT];
+        sv[0] = qT;
+        sv[1] = __float_as_int(sc);
+        sv[2] = (r.kind == KIND_ROOT && pp >= 2) ? clampi(slot_anc(a, slot, (T - 1) & 1)[qT], K) : -1;
+    }
+    __syncthreads();
+    const int32_t qT = sv[0];
+    const float sc = __int_as_float(sv[1]);
+    int32_t q = sv[2];
+    if (sc == -INFINITY) {
+        for (int32_t t = tid; t < T; t += kEngBlock) st_c(sq.path + t, -1);
+        if (tid == 0) {
+            st_cf(sq.score, sc);
+            st_c(&sq.status, (int32_t)FV_E_INFEASIBLE);
+        }
+        __syncthreads();
+        return;
+    }
+    if (tid == 0) {
+        st_cf(sq.score, sc);
+        st_c(sq.path + T - 1, qT);
+    }
+    if (r.kind != KIND_ROOT || pp < 2) {
+        __syncthreads();
+        return;
+    }
+    if (K > kBufInts) {   // a link row does not fit in LDS: walk in global memory
+        if (tid == 0) {
+            for (int32_t d = pp - 2; d >= 0; --d) {
+                st_c(sq.path + seg_end(T, pp, d), q);
+                if (d >= 1) q = clampi(root_link(a, r.off, pp, d)[q], K);
+            }
+        }
+        __syncthreads();
+    }
+    const int32_t per = max(1, kBufInts / K);
+    for (int32_t dhi = K > kBufInts ? -1 : pp - 2; dhi >= 0; dhi -= per) {
+        const int32_t dlo = max(0, dhi - per + 1);
+        const int32_t l0 = max(dlo, 1);   // Link_0 is never followed
+        const int32_t n = (dhi - l0 + 1) * K;
+        for (int32_t idx = tid; idx < n; idx += kEngBlock) {
+            const int32_t d = l0 + idx / K, j = idx % K;
+            buf[(d - dlo) * K + j] = root_link(a, r.off, pp, d)[j];
+        }
+        __syncthreads();
+        if (tid == 0) {
+            for (int32_t d = dhi; d >= dlo; --d) {
+                st_c(sq.path + seg_end(T, pp, d), q);
+                if (d >= 1) q = clampi(buf[(d - dlo) * K + q], K);
+            }
+            sv[3] = q;
+        }
+        __syncthreads();
+        q = sv[3];
+        __syncthreads();
+    }
+    for (int32_t d = tid; d <= pp - 2; d += kEngBlock) {
+        const int64_t e = seg_end(T, pp, d);
+        const int32_t qd = clampi(ld_c(sq.path + e), K);
+        st_cf(a.alpha_at + sq.alpha_off + e, root_dsnap(a, r.off, d)[qd]);
+    }
+    __syncthreads();
 }
 
 // ---------------------------------------------------------------- scheduler
@@ -845,12 +1034,18 @@ __device__ __forceinline__ int32_t child_count(const Row& r) {
     return len > 2 ? 2 : (len == 2 ? 1 : 0);
 }
 
-// src: the list r came from (0 full, 1 light, 2 beam).
+// src: the list r came from (0 full, 1 light, 2 block rows: beam tasks and
+// the finalize of dense roots and vanilla passes).
 __device__ Next classify(const EngineArgs& a, const Row& r, int src) {
     Next x;
     x.list = -1;
     x.freed = x.spawn = 0;
     const int32_t T = r.T, pp = r.pp;
+    if (src == 2 && !is_beam(r.kind)) {  // finalize of a vanilla pass or FLASH root
+        x.freed = 1;
+        if (r.kind == KIND_ROOT && pp >= 2) x.spawn = root_segments(T, pp);
+        return x;
+    }
     if (src == 2) {
         const bool root = r.kind == KIND_BROOT;
         if (r.aux == B_INIT || r.aux == B_STEP) {
@@ -876,17 +1071,14 @@ __device__ Next classify(const EngineArgs& a, const Row& r, int src) {
             else { x.list = 1; x.row = make_light_row(r, r.n, L_END); }
         } else {
             if (nt < T) { x.list = 0; x.row = make_dense_row(r, nt); }
-            else { x.list = 1; x.row = make_light_row(r, T, L_FINALIZE); }
+            else { x.list = 2; x.row = make_light_row(r, T, L_FINALIZE); }
         }
     } else if (r.aux == L_END) {
         x.freed = 1;
         x.spawn = child_count(r);
-    } else if (r.aux == L_BSPAWN) {
+    } else {  // L_BSPAWN
         x.freed = 1;
         x.spawn = ld_c(beam_fallback_flag(a, clampi(r.slot, a.n_slots))) ? 1 : child_count(r);
-    } else {  // L_FINALIZE
-        x.freed = 1;
-        if (r.kind == KIND_ROOT && pp >= 2) x.spawn = root_segments(T, pp);
     }
     return x;
 }
@@ -906,7 +1098,7 @@ __device__ void write_spawns(const EngineArgs& a, const Row& r, int src, int64_t
         if (len >= 2) a.queue[pos++] = Task{r.seq, kind, r.m, tmid};
         if (len > 2) a.queue[pos++] = Task{r.seq, kind, tmid + 1, r.n};
     } else {
-        const int32_t kind = src == 2 ? KIND_BSUB : KIND_SUB;
+        const int32_t kind = is_beam(r.kind) ? KIND_BSUB : KIND_SUB;
         const int32_t T = r.T, pp = r.pp;
         for (int32_t d = 0; d < pp; ++d) {
             const int64_t m = d == 0 ? 0 : seg_end(T, pp, d - 1) + 1, n = seg_end(T, pp, d);
@@ -923,7 +1115,7 @@ constexpr int kSchedGroupWaves = kSchedGroup / 64;
 struct SchedLds {
     int32_t q_head, q_tail, max_rows;
     int32_t n_free[kXcd];
-    int32_t has_blocks[kXcd];
+    int32_t nblk[kXcd];        // compute blocks on each XCD
     int32_t admit[kXcd];
     int32_t spawn_total[kXcd];
     int32_t n_next[kXcd][3];   // rows written for the next step: full, light, beam
@@ -969,21 +1161,37 @@ __device__ void group_scan(int32_t (&v)[N], int32_t (&tot)[N], int32_t (&ws)[kSc
 // step nxt.
 __device__ void admit(const EngineArgs& a, SchedLds& sl, int nxt) {
     if (threadIdx.x == 0) {
-        int32_t free_total = 0;
-        for (int x = 0; x < kXcd; ++x) free_total += sl.has_blocks[x] ? sl.n_free[x] : 0;
-        const int32_t n_admit = min(free_total, sl.q_tail - sl.q_head);
-        int32_t given = 0;
-        for (int x = 0; x < kXcd; ++x) {
-            const int32_t f = sl.has_blocks[x] ? sl.n_free[x] : 0;
-            const int32_t ax = free_total ? (int32_t)((int64_t)n_admit * f / free_total) : 0;
-            sl.admit[x] = ax;
-            given += ax;
+        // water filling: XCD x gets rows up to level L * nblk[x] (its share of
+        // the compute blocks), at most its free slots; L is the lowest level
+        // (in 1/16 rows per block) that places every admissible task
+        int32_t load[kXcd], cap[kXcd], cap_total = 0;
+        for (int y = 0; y < kXcd; ++y) {
+            load[y] = sl.n_next[y][0] + sl.n_next[y][1] + sl.n_next[y][2];
+            cap[y] = sl.nblk[y] > 0 ? sl.n_free[y] : 0;
+            cap_total += cap[y];
         }
-        for (int x = 0; x < kXcd && given < n_admit; ++x) {
-            const int32_t f = sl.has_blocks[x] ? sl.n_free[x] : 0;
-            const int32_t more = min(f - sl.admit[x], n_admit - given);
-            sl.admit[x] += more;
-            given += more;
+        const int32_t n_admit = min(cap_total, sl.q_tail - sl.q_head);
+        // level in 1/16 rows per block; 32-bit arithmetic, shifts only
+        auto placed = [&](int32_t L16, int y) -> int32_t {
+            const int32_t want = ((L16 * sl.nblk[y]) >> 4) - load[y];
+            return want < 0 ? 0 : (want > cap[y] ? cap[y] : want);
+        };
+        int32_t max_load = 0;
+        for (int y = 0; y < kXcd; ++y) max_load = max(max_load, load[y]);
+        // at this level every XCD with blocks wants at least max_load + n_admit rows
+        int32_t lo = 0, hi = ((max_load + n_admit) << 4) + 16;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi) >> 1;
+            int32_t tot = 0;
+            for (int y = 0; y < kXcd; ++y) tot += placed(mid, y);
+            if (tot >= n_admit) hi = mid; else lo = mid + 1;
+        }
+        int32_t given = 0;
+        for (int y = 0; y < kXcd; ++y) { sl.admit[y] = n_admit > 0 ? placed(lo, y) : 0; given += sl.admit[y]; }
+        for (int y = kXcd - 1; y >= 0 && given > n_admit; --y) {
+            const int32_t cut = min(sl.admit[y], given - n_admit);
+            sl.admit[y] -= cut;
+            given -= cut;
         }
     }
     __syncthreads();
@@ -1019,6 +1227,8 @@ __device__ void admit(const EngineArgs& a, SchedLds& sl, int nxt) {
                 st_c(&a.st->cnt[nxt][y][k], sl.n_next[y][k]);
                 all += sl.n_next[y][k];
             }
+            st_c(&a.st->claim[nxt][y][0], 0);
+            st_c(&a.st->claim[nxt][y][16], 0);
         }
         st_c(&a.st->total[nxt], all);
         if (all > sl.max_rows) sl.max_rows = all;
@@ -1134,35 +1344,104 @@ __device__ bool barrier_master(const EngineArgs& a, uint32_t epoch) {
 }
 
 // ---------------------------------------------------------------- engine
-union EngineLds {
-    TileLds tile;
-    SchedLds sched;
-    BeamLds beam;
-};
+// Work of one XCD at one step.  Phase 1: dense tiles and light rows, taken
+// by tile groups (nsplit waves) one item at a time: a tile, or nsplit light
+// rows (one per wave).  Groups run independently, so one group's
+// latency-bound epilogue overlaps the others' max-plus loops.  Phase 2:
+// beam rows, one per block.  Each phase hands items out from a per-XCD
+// counter; every block (and the scheduler block once its own work is done)
+// takes a first item by rank, then claims until none are left.
+__device__ void run_units(const EngineArgs& a, const float* __restrict__ Ap, uint32_t x, int32_t nx, int32_t rank,
+                          int cur, EngineLds& lds) {
+    __shared__ int32_t s_unit;
+    const int32_t nf = ld_c(&a.st->cnt[cur][x][0]);
+    const int32_t nl = ld_c(&a.st->cnt[cur][x][1]);
+    const int32_t nbm = ld_c(&a.st->cnt[cur][x][2]);
+    const int32_t n_tiles = ((nf + kTileRows - 1) / kTileRows) * (a.Kp / kTileCols);
+    // waves per tile: 4 (one per SIMD) while every group gets two tiles or
+    // more, else more waves per tile (fewer, faster groups); at most one wave
+    // per 16 predecessors.  Decided from a nominal XCD of 32 blocks, so that
+    // all XCDs take the same choice for the same row count.
+    int32_t nsplit = 4;
+    {
+        constexpr int32_t kNominalBlocks = 32;
+        while (nsplit < kEngWaves && n_tiles * 2 <= kNominalBlocks * (kEngWaves / nsplit)) nsplit <<= 1;
+        while (nsplit > 4 && nsplit * kGroup > a.Kp) nsplit >>= 1;
+    }
+    const int32_t ngrp = kEngWaves / nsplit;
+    const int32_t bw = threadIdx.x >> 6, grp = bw / nsplit, wv = bw & (nsplit - 1);
+    const int32_t n_lu = (nl + nsplit - 1) / nsplit;
+    const int32_t n1 = n_tiles + n_lu;
+    const Row* F = list_full(a, cur, x);
+    const Row* L = list_light(a, cur, x);
+    if (threadIdx.x < 4) lds.tile.gsync[threadIdx.x] = 0;
+    __syncthreads();
+    if (n1 > 0) {
+        int32_t* ctr = &a.st->claim[cur][x][0];
+        int32_t item = rank >= 0 ? rank * ngrp + grp : -1;
+        for (;;) {
+            if (item < 0) {
+                if (wv == 0 && (threadIdx.x & 63) == 0)
+                    lds.tile.gitem[grp] =
+                        nx * ngrp + __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                group_sync(&lds.tile.gsync[grp], nsplit);
+                item = lds.tile.gitem[grp];
+            }
+            if (item >= n1) break;
+            if (item < n_tiles) {
+                dense_tile(a, Ap, F, nf, item, nsplit, lds.tile);
+            } else {
+                const int32_t li = (item - n_tiles) * nsplit + wv;
+                if (li < nl) light_row(a, Ap, ld_row(L + li));
+            }
+            item = -1;
+        }
+    }
+    if (nbm == 0) return;
+    __syncthreads();
+    const Row* Bl = list_beam(a, cur, x);
+    int32_t* ctr2 = &a.st->claim[cur][x][16];
+    int32_t u = rank;
+    for (;;) {
+        if (u < 0) {
+            if (threadIdx.x == 0) s_unit = nx + __hip_atomic_fetch_add(ctr2, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __syncthreads();
+            u = s_unit;
+            __syncthreads();
+        }
+        if (u >= nbm) break;
+        const Row r = ld_row(Bl + u);
+        if (is_beam(r.kind)) beam_row(a, Ap, r, lds.beam);
+        else dense_finalize(a, r, lds);
+        u = -1;
+    }
+}
 
 extern "C" __global__ __launch_bounds__(kEngBlock) void fv_engine_kernel(const float* __restrict__ Ap,
                                                                          EngineArgs a) {
     __shared__ EngineLds lds;
-    __shared__ int32_t s_rank;
+    __shared__ SchedLds sched_lds;
     const bool is_sched = blockIdx.x == 0;
     const uint32_t x = my_xcd();
-    if (!is_sched && threadIdx.x == 0)
-        s_rank = (int32_t)__hip_atomic_fetch_add(&a.st->xcd_blocks[x][0], 1u, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_SYSTEM);
+    __shared__ int32_t s_rank;
+    if (threadIdx.x == 0)   // rank among the compute blocks of this XCD (the scheduler has none)
+        s_rank = is_sched ? -1
+                          : (int32_t)__hip_atomic_fetch_add(&a.st->xcd_blocks[x][0], 1u, __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_SYSTEM);
     uint32_t epoch = 1;
     bool ok = is_sched ? barrier_master(a, epoch) : barrier_arrive_wait(a, epoch, x);
     const int32_t rank = s_rank;
     const int32_t nx = (int32_t)ld_c(&a.st->xcd_blocks[x][0]);
 
     if (is_sched) {
-        SchedLds& sl = lds.sched;
+        SchedLds& sl = sched_lds;
         if (threadIdx.x == 0) {
             sl.q_head = 0;
             sl.q_tail = ld_c(&a.st->q_tail0);
             sl.max_rows = 0;
             for (int y = 0; y < kXcd; ++y) {
                 sl.n_free[y] = a.pool;
-                sl.has_blocks[y] = ld_c(&a.st->xcd_blocks[y][0]) > 0;
+                sl.nblk[y] = (int32_t)ld_c(&a.st->xcd_blocks[y][0]);
                 for (int k = 0; k < 3; ++k) sl.n_next[y][k] = 0;
             }
         }
@@ -1180,41 +1459,8 @@ extern "C" __global__ __launch_bounds__(kEngBlock) void fv_engine_kernel(const f
             if (is_sched && threadIdx.x == 0) st_c(&a.st->error, 2);
             break;
         }
-        if (is_sched) {
-            scheduler(a, s, lds.sched);
-        } else {
-            const int32_t nf = ld_c(&a.st->cnt[cur][x][0]);
-            const int32_t nl = ld_c(&a.st->cnt[cur][x][1]);
-            const Row* F = list_full(a, cur, x);
-            const Row* L = list_light(a, cur, x);
-            const int32_t n_tiles = ((nf + kTileRows - 1) / kTileRows) * (a.Kp / kTileCols);
-            // tiles per block round (tpb) and waves per tile (16 / tpb): the
-            // block's time is about rounds x tpb tile-units; take the least,
-            // the larger tpb on ties (fewer rounds)
-            int32_t nsplit = kEngWaves;
-            while (nsplit > 4 && nsplit * kGroup > a.Kp) nsplit >>= 1;
-            int32_t tpb = kEngWaves / nsplit;
-            {
-                int32_t best = 0x7fffffff;
-                for (int32_t t = kEngWaves / nsplit; t <= 4; t <<= 1) {
-                    const int32_t cost = (n_tiles + nx * t - 1) / (nx * t) * t;
-                    if (cost <= best) { best = cost; tpb = t; }
-                }
-                nsplit = kEngWaves / tpb;
-            }
-            const int32_t group = (threadIdx.x >> 6) / nsplit;
-            for (int32_t base = rank * tpb; base < n_tiles; base += nx * tpb) {
-                const int32_t it = base + group;
-                dense_tile(a, Ap, F, nf, it < n_tiles ? it : -1, nsplit, lds.tile);
-            }
-            // light rows: one per wave
-            for (int32_t li = rank * kEngWaves + (threadIdx.x >> 6); li < nl; li += nx * kEngWaves)
-                light_row(a, Ap, ld_row(L + li));
-            // beam rows: one per block, from the last block down
-            const int32_t nbm = ld_c(&a.st->cnt[cur][x][2]);
-            const Row* Bl = list_beam(a, cur, x);
-            for (int32_t bi = nx - 1 - rank; bi < nbm; bi += nx) beam_row(a, Ap, ld_row(Bl + bi), lds.beam);
-        }
+        if (is_sched) scheduler(a, s, sched_lds);
+        run_units(a, Ap, x, nx, rank, cur, lds);
         ++epoch;
         ok = is_sched ? barrier_master(a, epoch) : barrier_arrive_wait(a, epoch, x);
     }

@@ -104,6 +104,7 @@ struct EngineState {
     int32_t pad1[kLine - 2];
     uint32_t go[kXcd][kLine];   // barrier release flags, one line per XCD
     uint32_t xcd_blocks[kXcd][kLine];  // compute blocks per XCD (counted at start)
+    int32_t claim[2][kXcd][kLine];     // [parity][xcd] next unclaimed work unit of a step
 };
 
 // Everything the persistent engine needs (one model).
