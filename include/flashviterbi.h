@@ -60,6 +60,14 @@ typedef enum {
 } fv_status;
 
 enum { FV_DENSE = 0, FV_CSR = 1 };
+
+/* Decode flags (bit set).  Placement of the rows in flight: by default the
+ * library keeps each row on one XCD and tiles rows onto lanes (many rows,
+ * log A shared through the XCD's L2), or, for large K or very few rows, uses
+ * wide rows (every compute unit takes a column slice of every row and log A
+ * streams from HBM once per step).  These flags force one placement; the
+ * results are the same either way. */
+enum { FV_FLAG_WIDE_ROWS = 1u << 0, FV_FLAG_LOCAL_ROWS = 1u << 1 };
 enum { FV_VANILLA = 0, FV_FLASH = 1, FV_BEAM = 2 };
 
 /* Transition model.  FV_DENSE: log_a[K*K] (device).  FV_CSR: out-edges of

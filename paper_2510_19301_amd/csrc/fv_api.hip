@@ -69,6 +69,7 @@ struct DenseLayout {
     int64_t sum_T = 0, sum_root = 0, sum_psi = 0, n_tasks = 0, slot_floats = 0;
     int32_t has_anc = 0;
     int32_t B = 0, Bc = 0;       // beam width and padded length (beam decodes)
+    int32_t bw = 1;              // parts of a beam task's step
     int64_t brec = 0;            // floats per beam record
     int64_t q_cap = 0;
     Region Ap, seq1, seqinfo, keys, state, arrive, rows_full, rows_light, rows_beam, queue, free_stack,
@@ -98,6 +99,15 @@ fv_status plan_dense(int32_t method, int32_t K, const int32_t* T_host, int32_t n
         L.B = B;
         L.Bc = (int32_t)round_up(B, 64);
         L.brec = 64 + 3 * (int64_t)L.Bc;
+        // parts per step: at most 4096 destinations per part, at most 8192
+        // candidates to merge, otherwise about 256 destinations per part (<= 32)
+        const int32_t Kp = (int32_t)round_up(K, kKAlign);
+        int32_t W = std::min<int32_t>(32, std::min<int32_t>(Kp / 256, 8192 / B));
+        W = std::max<int32_t>(W, (Kp + 4095) / 4096);
+        W = std::max<int32_t>(1, std::min<int32_t>(W, K));
+        if (W * B > 8192 || (K + W - 1) / W > 4096)
+            return fail(FV_E_UNSUPPORTED, "beam width %d is too large for K=%d", B, K);
+        L.bw = W;
     }
     L.K = K;
     L.Kp = (int32_t)round_up(K, kKAlign);
@@ -122,7 +132,7 @@ fv_status plan_dense(int32_t method, int32_t K, const int32_t* T_host, int32_t n
     // dense rows: delta[2] (+ anc[2] + snapshot); beam rows: three beam
     // records, and room for a dense row should the task need its exact re-decode
     L.slot_floats = (int64_t)L.Kp * (method == FV_VANILLA ? 2 : 5);
-    if (beam) L.slot_floats = std::max<int64_t>(L.slot_floats, 3 * L.brec);
+    if (beam) L.slot_floats = std::max<int64_t>(L.slot_floats, (2 * (int64_t)L.bw + 1) * L.brec);
     // a beam subtask may be queued twice (its exact re-decode)
     L.q_cap = std::max<int64_t>(1, beam ? 2 * L.n_tasks : L.n_tasks);
     const int64_t slot_bytes = L.slot_floats * 4;
@@ -191,9 +201,21 @@ fv_status device_info(DeviceInfo& di) {
 
 __global__ void write_seq_kernel(fv_seq* dst, fv_seq v) { *dst = v; }
 
+// Row placement (see FV_FLAG_WIDE_ROWS): wide rows when log A cannot be
+// shared through L2 (large K) or when too few rows exist to fill lane tiles.
+bool use_wide_rows(uint32_t flags, int32_t K, int32_t n_seqs) {
+    if (flags & FV_FLAG_WIDE_ROWS) return true;
+    if (flags & FV_FLAG_LOCAL_ROWS) return false;
+    return K >= 4096 || (K >= 1024 && n_seqs <= 4);
+}
+
 fv_status run_dense(int32_t method, const fv_trans* A, const float* log_pi, const fv_seq* seqs_dev,
                     const int32_t* T_host, int32_t n_seqs, int32_t P, int32_t B, const fv_seq* single,
-                    int32_t* status, void* ws, size_t ws_bytes, hipStream_t stream) {
+                    int32_t* status, uint32_t flags, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if ((flags & FV_FLAG_WIDE_ROWS) && (flags & FV_FLAG_LOCAL_ROWS))
+        return fail(FV_E_INVALID_ARG, "FV_FLAG_WIDE_ROWS and FV_FLAG_LOCAL_ROWS exclude each other");
+    if (flags & ~(uint32_t)(FV_FLAG_WIDE_ROWS | FV_FLAG_LOCAL_ROWS))
+        return fail(FV_E_INVALID_ARG, "unknown flags 0x%x", flags);
     fv_status rc = check_dense_model(A);
     if (rc != FV_OK) return rc;
     DenseLayout L;
@@ -234,6 +256,7 @@ fv_status run_dense(int32_t method, const fv_trans* A, const float* log_pi, cons
     a.slot_floats = L.slot_floats;
     a.n_slots = L.n_slots;
     a.has_anc = L.has_anc;
+    a.wide = use_wide_rows(flags, A->K, n_seqs) ? 1 : 0;
     a.alpha_at = static_cast<float*>(at(L.alpha));
     a.root_copy = static_cast<float*>(at(L.root));
     a.psi16 = static_cast<uint16_t*>(at(L.psi));
@@ -246,6 +269,7 @@ fv_status run_dense(int32_t method, const fv_trans* A, const float* log_pi, cons
     a.B = L.B;
     a.Bc = L.Bc;
     a.brec = L.brec;
+    a.bw = L.bw;
     a.pool = L.pool;
     a.queue = static_cast<Task*>(at(L.queue));
     a.q_cap = L.q_cap;
@@ -357,38 +381,35 @@ fv_status fv_workspace_size(int32_t method, const fv_trans* models, int32_t n_mo
 fv_status fv_decode_vanilla(const fv_trans* A, const float* log_pi, const float* log_b, int64_t ld,
                             int32_t T, int32_t* path, float* score, int32_t* status, uint32_t flags,
                             void* ws, size_t ws_bytes, fv_stream_t stream) {
-    (void)flags;
     if (T < 1) return fail(FV_E_INVALID_ARG, "T must be >= 1 (got %d)", T);
     if (!A || !log_b || !path || !score) return fail(FV_E_INVALID_ARG, "null argument");
     if (ld < A->K) return fail(FV_E_INVALID_ARG, "ld=%lld < K=%d", (long long)ld, A->K);
     fv_seq s{0, T, log_b, ld, path, score};
-    return run_dense(FV_VANILLA, A, log_pi, nullptr, &T, 1, 1, 0, &s, status, ws, ws_bytes,
+    return run_dense(FV_VANILLA, A, log_pi, nullptr, &T, 1, 1, 0, &s, status, flags, ws, ws_bytes,
                      reinterpret_cast<hipStream_t>(stream));
 }
 
 fv_status fv_decode_flash(const fv_trans* A, const float* log_pi, const float* log_b, int64_t ld,
                           int32_t T, int32_t P, int32_t* path, float* score, int32_t* status,
                           uint32_t flags, void* ws, size_t ws_bytes, fv_stream_t stream) {
-    (void)flags;
     if (T < 1) return fail(FV_E_INVALID_ARG, "T must be >= 1 (got %d)", T);
     if (!A || !log_b || !path || !score) return fail(FV_E_INVALID_ARG, "null argument");
     if (ld < A->K) return fail(FV_E_INVALID_ARG, "ld=%lld < K=%d", (long long)ld, A->K);
     if (P <= 0) P = 16;
     fv_seq s{0, T, log_b, ld, path, score};
-    return run_dense(FV_FLASH, A, log_pi, nullptr, &T, 1, P, 0, &s, status, ws, ws_bytes,
+    return run_dense(FV_FLASH, A, log_pi, nullptr, &T, 1, P, 0, &s, status, flags, ws, ws_bytes,
                      reinterpret_cast<hipStream_t>(stream));
 }
 
 fv_status fv_decode_beam(const fv_trans* A, const float* log_pi, const float* log_b, int64_t ld, int32_t T,
                          int32_t B, int32_t P, int32_t* path, float* score, int32_t* status, uint32_t flags,
                          void* ws, size_t ws_bytes, fv_stream_t stream) {
-    (void)flags;
     if (T < 1) return fail(FV_E_INVALID_ARG, "T must be >= 1 (got %d)", T);
     if (!A || !log_b || !path || !score) return fail(FV_E_INVALID_ARG, "null argument");
     if (ld < A->K) return fail(FV_E_INVALID_ARG, "ld=%lld < K=%d", (long long)ld, A->K);
     if (B < 1 || P < 1) return fail(FV_E_INVALID_ARG, "beam decoding needs B >= 1 and P >= 1");
     fv_seq s{0, T, log_b, ld, path, score};
-    return run_dense(effective_method(FV_BEAM, A, B), A, log_pi, nullptr, &T, 1, P, B, &s, status, ws,
+    return run_dense(effective_method(FV_BEAM, A, B), A, log_pi, nullptr, &T, 1, P, B, &s, status, flags, ws,
                      ws_bytes, reinterpret_cast<hipStream_t>(stream));
 }
 
@@ -396,7 +417,6 @@ fv_status fv_decode_batch(const fv_trans* models, const float* const* log_pi, in
                           const fv_seq* seqs_dev, const int32_t* T_host, const int32_t* model_host,
                           int32_t n_seqs, int32_t method, int32_t P, int32_t B, int32_t* status,
                           uint32_t flags, void* ws, size_t ws_bytes, fv_stream_t stream) {
-    (void)flags;
     (void)model_host;
     if (n_models != 1) return fail(FV_E_UNSUPPORTED, "exactly one model per call is supported");
     if (n_seqs < 0) return fail(FV_E_INVALID_ARG, "n_seqs < 0");
@@ -406,7 +426,7 @@ fv_status fv_decode_batch(const fv_trans* models, const float* const* log_pi, in
     if (method == FV_BEAM && (B < 1 || P < 1)) return fail(FV_E_INVALID_ARG, "beam decoding needs B >= 1 and P >= 1");
     if (method == FV_FLASH && P <= 0) P = 16;
     return run_dense(effective_method(method, models, B), models, log_pi ? log_pi[0] : nullptr, seqs_dev,
-                     T_host, n_seqs, P, B, nullptr, status, ws, ws_bytes, reinterpret_cast<hipStream_t>(stream));
+                     T_host, n_seqs, P, B, nullptr, status, flags, ws, ws_bytes, reinterpret_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

@@ -73,6 +73,28 @@ __device__ __forceinline__ void st_row(Row* p, const Row& r) {
 }
 __device__ __forceinline__ int32_t clampi(int32_t v, int32_t hi) { return v < 0 ? 0 : (v >= hi ? hi - 1 : v); }
 
+// Explicit address spaces for the hot loops, which live in non-inlined
+// functions (where pointers are generic): log A is never written during a
+// decode, so a wave-uniform pointer to it may be read through the constant
+// address space (scalar loads); per-lane data goes through the global one.
+typedef __attribute__((address_space(4))) const float cfloat_t;
+typedef __attribute__((address_space(1))) const float gfloat_t;
+__device__ __forceinline__ cfloat_t* uniform_const(const float* p) {
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return reinterpret_cast<cfloat_t*>(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ gfloat_t* as_global(const float* p) {
+    return reinterpret_cast<gfloat_t*>(reinterpret_cast<uint64_t>(p));
+}
+// coherent (agent-scope) load through the global address space
+__device__ __forceinline__ float ld_cg(const float* p) {
+    typedef __attribute__((address_space(1))) const uint32_t gu32_t;
+    gu32_t* q = reinterpret_cast<gu32_t*>(reinterpret_cast<uint64_t>(p));
+    return __uint_as_float(__hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
 // Final arg-max keys are combined by tiles and read by the finalize step
 // with coherent loads, so the max is performed at the memory side (sc1).
 __device__ __forceinline__ void key_max(unsigned long long* p, unsigned long long v) {
@@ -116,6 +138,68 @@ __device__ __forceinline__ Row* list_light(const EngineArgs& a, int parity, int 
 __device__ __forceinline__ Row* list_beam(const EngineArgs& a, int parity, int x) {
     return a.rows_beam + ((int64_t)parity * kXcd + x) * a.pool;
 }
+
+// ---------------------------------------------------------------- LDS
+// The engine's shared memory, at file scope so that every function of the
+// engine addresses it as LDS (a reference passed to a non-inlined function
+// would become a generic pointer).
+struct TileLds {
+    float m[kEngWaves][kTileCols][kTileRows];
+    int32_t g[kEngWaves][kTileCols][kTileRows];
+    uint64_t stash[4][kTileRows][4];   // per tile group: row words 0, 3, 4, 5 of each lane's row
+    uint32_t gsync[4];                  // per tile group: barrier arrivals
+    int32_t gitem[4];                   // per tile group: the work item it claimed
+};
+
+constexpr int32_t kWideRows = 16;
+constexpr int32_t kWideCols = 64;
+constexpr int32_t kWideStage = 64;   // predecessors staged per LDS refill (4 groups)
+
+struct WideLds {
+    float area[kEngWaves][2 * kWideRows * kWideCols];   // per wave: staged scores, later (max, group)
+    Row rows[kWideRows];
+};
+
+constexpr int32_t kBeamPartMax = 4096;   // destinations per part
+constexpr int32_t kBeamCandMax = 8192;   // W * B: candidates of a rebuild
+
+struct BeamLds {
+    int32_t cs[kBeamCandMax];   // candidates of a rebuild: states, scores, anchors
+    float cv[kBeamCandMax];
+    int32_t ca[kBeamCandMax];
+    float sc[kBeamPartMax];     // scores and anchors of a part's destinations
+    int32_t an[kBeamPartMax];
+    int32_t bs[kBeamMaxB];      // the rebuilt beam, in state order
+    float bv[kBeamMaxB];
+    int32_t ba[kBeamMaxB];
+    uint32_t hist[256];
+    int32_t wsum[kEngWaves];
+    unsigned long long wkey[kEngWaves];
+    int32_t pofs[33];
+    int32_t misc[8];
+};
+
+union EngineLds {
+    TileLds tile;
+    WideLds wide;
+    BeamLds beam;
+};
+
+constexpr int kSchedGroup = kEngBlock / kXcd;
+constexpr int kSchedGroupWaves = kSchedGroup / 64;
+
+struct SchedLds {
+    int32_t q_head, q_tail, max_rows;
+    int32_t n_free[kXcd];
+    int32_t nblk[kXcd];        // compute blocks on each XCD
+    int32_t admit[kXcd];
+    int32_t spawn_total[kXcd];
+    int32_t n_next[kXcd][3];   // rows written for the next step: full, light, beam
+    int32_t wave_sums[kXcd][kSchedGroupWaves][5];
+};
+
+static __shared__ EngineLds g_lds;
+static __shared__ SchedLds g_sched;
 
 // ---------------------------------------------------------------- row flags
 // Row of `base`'s task at time t as a dense step.
@@ -193,8 +277,8 @@ __device__ Row make_beam_row(const Row& base, int32_t t, int32_t op) {
 // ---------------------------------------------------------------- dense tile
 // Partial (max, group) of 16 columns over predecessors [s0, s1) for the
 // lane's row; drow = the row's delta_{t-1}, Ap = padded row-major log A.
-__device__ __forceinline__ void tile_partial(const float* __restrict__ Ap, int32_t Kp, int32_t j0,
-                                             const float* drow, int32_t s0, int32_t s1,
+__device__ __forceinline__ void tile_partial(cfloat_t* __restrict__ Ap, int32_t Kp, int32_t j0,
+                                             gfloat_t* drow, int32_t s0, int32_t s1,
                                              float (&m)[kTileCols], int32_t (&g)[kTileCols]) {
 #pragma unroll
     for (int c = 0; c < kTileCols; ++c) { m[c] = -INFINITY; g[c] = s0 / kGroup; }
@@ -204,8 +288,9 @@ __device__ __forceinline__ void tile_partial(const float* __restrict__ Ap, int32
         for (int c = 0; c < kTileCols; ++c) gm[c] = -INFINITY;
 #pragma unroll
         for (int k = 0; k < kGroup; k += 4) {
-            const float4 d = *reinterpret_cast<const float4*>(drow + i0 + k);
-            const float* a0 = Ap + (int64_t)(i0 + k) * Kp + j0;
+            typedef float v4f_t __attribute__((ext_vector_type(4)));
+            const v4f_t d = *reinterpret_cast<__attribute__((address_space(1))) const v4f_t*>(drow + i0 + k);
+            cfloat_t* a0 = Ap + (int64_t)(i0 + k) * Kp + j0;
 #pragma unroll
             for (int c = 0; c < kTileCols; ++c) {
                 const float x0 = d.x + a0[c];
@@ -224,13 +309,6 @@ __device__ __forceinline__ void tile_partial(const float* __restrict__ Ap, int32
 }
 
 // Partial results of the 16 waves of a block: [wave][column][row].
-struct TileLds {
-    float m[kEngWaves][kTileCols][kTileRows];
-    int32_t g[kEngWaves][kTileCols][kTileRows];
-    uint64_t stash[4][kTileRows][4];   // per tile group: row words 0, 3, 4, 5 of each lane's row
-    uint32_t gsync[4];                  // per tile group: barrier arrivals
-    int32_t gitem[4];                   // per tile group: the work item it claimed
-};
 
 // Barrier of the nsplit waves of one tile group (an LDS arrival counter;
 // the groups of a block run independently of each other).  Every wave of
@@ -259,8 +337,9 @@ __device__ __forceinline__ void group_sync(uint32_t* ctr, int32_t nsplit) {
 // bound by memory latency, so its loads are issued together: the row's
 // remaining fields come from an LDS copy made before the loop, the refine
 // loads of two columns go out at once, and so do the anchor gathers.
-__device__ void dense_tile(const EngineArgs& a, const float* __restrict__ Ap, const Row* rows,
-                           int32_t nrows, int32_t tile, int32_t nsplit, TileLds& lds) {
+__device__ __noinline__ void dense_tile(const EngineArgs& a, const float* __restrict__ Ap, const Row* rows,
+                           int32_t nrows, int32_t tile, int32_t nsplit) {
+    TileLds& lds = g_lds.tile;
     const bool active = true;
     const int32_t K = a.K, Kp = a.Kp;
     const int32_t ncb = Kp / kTileCols;
@@ -308,8 +387,8 @@ __device__ void dense_tile(const EngineArgs& a, const float* __restrict__ Ap, co
     {
         float m[kTileCols];
         int32_t g[kTileCols];
-        tile_partial(Ap, Kp, __builtin_amdgcn_readfirstlane(j0), drow, g0 * kGroup,
-                     active ? g1 * kGroup : g0 * kGroup, m, g);
+        tile_partial(uniform_const(Ap), __builtin_amdgcn_readfirstlane(Kp), __builtin_amdgcn_readfirstlane(j0),
+                     as_global(drow), g0 * kGroup, active ? g1 * kGroup : g0 * kGroup, m, g);
 #pragma unroll
         for (int c = 0; c < kTileCols; ++c) {
             lds.m[bw][c][lane] = m[c];
@@ -431,6 +510,133 @@ __device__ void dense_tile(const EngineArgs& a, const float* __restrict__ Ap, co
     group_sync(&lds.gsync[grp], nsplit);   // partials and stash are reused by the group's next tile
 }
 
+// ---------------------------------------------------------------- wide rows
+// Wide rows: each item is one chunk of 64 destination columns (one per lane)
+// for up to 16 rows at once, computed by a whole block: the 16 waves split
+// the predecessors, each streams its share of log A(i, chunk) from memory
+// once for all the item's rows and keeps, per row and column, the maximum
+// and the winning group of 16 predecessors; the previous step's scores are
+// staged through LDS.  After a block barrier the partial maxima merge in
+// wave order (the earliest group keeps ties), the winning group is refined
+// and the outputs are written.  Row data crosses XCDs here, so it is read
+// with coherent loads; the step barrier's release makes the stores visible.
+
+
+__device__ __noinline__ void wide_item(const EngineArgs& a, const float* __restrict__ Ap, const Row* list, int32_t nlist,
+                          int32_t rg, int32_t chunk) {
+    WideLds& L = g_lds.wide;
+    const int32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int32_t K = a.K, Kp = __builtin_amdgcn_readfirstlane(a.Kp);
+    gfloat_t* Ag = as_global(Ap);
+    const int32_t r0 = rg * kWideRows;
+    const int32_t R = min(kWideRows, nlist - r0);
+    const int32_t j = chunk * kWideCols + lane;
+    if (tid < R) L.rows[tid] = ld_row(list + r0 + tid);
+    __syncthreads();
+    // this wave's output row (w < R): its emission score, fetched early
+    float bpre = 0.0f;
+    if (w < R && j < K) {
+        const Row& rr = L.rows[w];
+        bpre = rr.log_b[(int64_t)rr.t * rr.ld + j];
+    }
+    // predecessors [i_lo, i_hi) of this wave, whole groups of 16
+    const int32_t ng = Kp / kGroup;
+    const int32_t i_lo = ((w * ng) / kEngWaves) * kGroup, i_hi = (((w + 1) * ng) / kEngWaves) * kGroup;
+    float m[kWideRows];
+    int32_t g[kWideRows];
+#pragma unroll
+    for (int r = 0; r < kWideRows; ++r) { m[r] = -INFINITY; g[r] = i_lo / kGroup; }
+    float* stage = L.area[w];
+    for (int32_t i0 = i_lo; i0 < i_hi; i0 += kWideStage) {
+        const int32_t n = min(kWideStage, i_hi - i0);   // a multiple of 16
+#pragma unroll
+        for (int r = 0; r < kWideRows; ++r) {
+            if (r < R && lane < n) {
+                const Row& rr = L.rows[r];
+                const float* dp = slot_delta(a, clampi(rr.slot, a.n_slots), (rr.t - 1) & 1);
+                stage[r * kWideStage + lane] = ld_cg(dp + i0 + lane);
+            }
+        }
+        for (int32_t k0 = 0; k0 < n; k0 += kGroup) {
+            float av[kGroup];
+#pragma unroll
+            for (int k = 0; k < kGroup; ++k) av[k] = Ag[(int64_t)(i0 + k0 + k) * Kp + j];
+            const int32_t gi = (i0 + k0) / kGroup;
+#pragma unroll
+            for (int r = 0; r < kWideRows; ++r) {
+                if (r < R) {
+                    const float* sd = stage + r * kWideStage + k0;
+                    float gm = -INFINITY;
+#pragma unroll
+                    for (int k = 0; k < kGroup; k += 2) gm = fmaxf(fmaxf(gm, sd[k] + av[k]), sd[k + 1] + av[k + 1]);
+                    if (gm > m[r]) { m[r] = gm; g[r] = gi; }
+                }
+            }
+        }
+    }
+    // partials to this wave's area (its staging is done)
+#pragma unroll
+    for (int r = 0; r < kWideRows; ++r) {
+        if (r < R) {
+            stage[r * kWideCols + lane] = m[r];
+            reinterpret_cast<int32_t*>(stage)[kWideRows * kWideCols + r * kWideCols + lane] = g[r];
+        }
+    }
+    __syncthreads();
+    unsigned long long key = 0;
+    if (w < R && j < K) {
+        const Row& rr = L.rows[w];
+        const int32_t t = rr.t, f = rr.flags, slot = clampi(rr.slot, a.n_slots);
+        float mv = L.area[0][w * kWideCols + lane];
+        int32_t gi = reinterpret_cast<const int32_t*>(L.area[0])[kWideRows * kWideCols + w * kWideCols + lane];
+        for (int v = 1; v < kEngWaves; ++v) {
+            const float x = L.area[v][w * kWideCols + lane];
+            if (x > mv) { mv = x; gi = reinterpret_cast<const int32_t*>(L.area[v])[kWideRows * kWideCols + w * kWideCols + lane]; }
+        }
+        const float* dprev = slot_delta(a, slot, (t - 1) & 1);
+        float val = mv;
+        int32_t psi = 0;
+        if ((f & F_NEED_ARG) || mv == 0.0f) {
+            const int32_t src0 = gi * kGroup;
+            float av[kGroup], dv[kGroup];
+#pragma unroll
+            for (int k = 0; k < kGroup; ++k) {
+                av[k] = Ag[(int64_t)(src0 + k) * Kp + j];
+                dv[k] = ld_cg(dprev + src0 + k);
+            }
+            int32_t p = -1;
+#pragma unroll
+            for (int k = 0; k < kGroup; ++k) {
+                const float x = dv[k] + av[k];
+                if (p < 0 && x == mv) { p = src0 + k; val = x; }
+            }
+            psi = clampi(p < 0 ? src0 : p, K);   // p < 0 is unreachable for finite/-inf inputs
+        }
+        int32_t anc = 0;
+        if (f & F_ANC_FIRST) anc = psi;
+        else if (f & F_ANC_CHAIN) anc = clampi(ld_c(slot_anc(a, slot, (t - 1) & 1) + psi), K);
+        const float dnew = val + bpre;
+        slot_delta(a, slot, t & 1)[j] = dnew;
+        if (f & F_PSI_TABLE) a.psi16[rr.off + (int64_t)t * K + j] = (uint16_t)psi;
+        if (f & (F_ANC_FIRST | F_ANC_CHAIN)) slot_anc(a, slot, t & 1)[j] = anc;
+        if (f & F_SNAP_SUB) slot_snap(a, slot)[j] = dnew;
+        if (f & F_SNAP_ROOT) {
+            root_dsnap(a, rr.off, rr.aux)[j] = dnew;
+            if (rr.aux >= 1) root_link(a, rr.off, rr.pp, rr.aux)[j] = anc;
+        }
+        if (f & F_FINAL) key = order_key(dnew, j);
+    }
+    if (w < R && (L.rows[w].flags & F_FINAL)) {   // wave-uniform: the whole wave reduces
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const unsigned long long o = __shfl_xor(key, off, 64);
+            if (o > key) key = o;
+        }
+        if (lane == 0) key_max(&a.keys[L.rows[w].seq], key);
+    }
+    __syncthreads();
+}
+
 // ---------------------------------------------------------------- light rows
 __device__ __forceinline__ void wave_argmax(float& v, int32_t& idx) {
 #pragma unroll
@@ -443,7 +649,7 @@ __device__ __forceinline__ void wave_argmax(float& v, int32_t& idx) {
 
 // One wave: the O(K) operations of a task (start step, end-only step,
 // final selection and boundary resolution).
-__device__ void light_row(const EngineArgs& a, const float* __restrict__ Ap, const Row& r) {
+__device__ __noinline__ void light_row(const EngineArgs& a, const float* __restrict__ Ap, const Row& r) {
     const int32_t lane = threadIdx.x & 63;
     SeqInfo& sq = a.seqs[r.seq];
     const int32_t K = a.K, Kp = a.Kp;
@@ -495,45 +701,44 @@ __device__ void light_row(const EngineArgs& a, const float* __restrict__ Ap, con
         float best = -INFINITY;
         int32_t arg = 0x7fffffff;
         for (int32_t i = lane; i < K; i += 64) {
-            const float x = dprev[i] + ac[(int64_t)i * Kp];
+            const float x = (a.wide ? ld_cf(dprev + i) : dprev[i]) + ac[(int64_t)i * Kp];
             if (arg == 0x7fffffff || x > best) { best = x; arg = i; }
         }
         wave_argmax(best, arg);
         if (lane == 0) {
             arg = clampi(arg, K);
-            const int32_t qmid = clampi((n == tmid + 1) ? arg : slot_anc(a, slot, (n - 1) & 1)[arg], K);
+            const int32_t* ap = slot_anc(a, slot, (n - 1) & 1);
+            const int32_t qmid = clampi((n == tmid + 1) ? arg : (a.wide ? ld_c(ap + arg) : ap[arg]), K);
+            const float* sn = slot_snap(a, slot);
             st_c(sq.path + tmid, qmid);
-            st_cf(a.alpha_at + sq.alpha_off + tmid, slot_snap(a, slot)[qmid]);
+            st_cf(a.alpha_at + sq.alpha_off + tmid, a.wide ? ld_cf(sn + qmid) : sn[qmid]);
         }
     }
     // L_BSPAWN: nothing to do (see its definition)
 }
 
 // ---------------------------------------------------------------- beam rows
-// FLASH-BS (Sec. V-C): every step keeps at most B states.  A beam row is
-// one task's step and takes a whole block:
-//   scores: c(j) = max over beam entries b (in state order) of
-//           v_b + log A(s_b, j), the first (lowest-state) maximum wins;
-//           score(j) = c(j) + log B_t(j)            (all K destinations, LDS)
-//   select: top B by (score desc, state asc), -inf dropped: radix select
-//           of the B-th largest score key, ties at it taken in state order
-//   store:  the kept destinations in state order (state, score, anchor)
-// A beam record is a 64-word header (word 0 = entry count) followed by the
-// state, score and anchor arrays (Bc entries each).  Slot layout of a beam
-// row: record 0 / 1 (the beams of even / odd t), record 2 (the beam at
-// t_mid); header word 1 of record 0 flags a task that needs the exact
-// re-decode.  Root division snapshots are records in the root copy area.
-struct BeamLds {
-    float sc[kBeamMaxK];
-    int32_t an[kBeamMaxK];
-    int32_t bs[kBeamMaxB];
-    float bv[kBeamMaxB];
-    int32_t ba[kBeamMaxB];
-    uint32_t hist[256];
-    int32_t wsum[kEngWaves];
-    unsigned long long wkey[kEngWaves];
-    int32_t misc[4];
-};
+// FLASH-BS (Sec. V-C): every step keeps at most B states, ranked by
+// (score desc, state asc), -inf dropped.  A beam task's step is split into
+// W parts, column ranges of about K/W destinations in state order, each
+// computed by one block:
+//   rebuild: the previous step's beam = the top B of the union of the
+//            parts' kept lists (each in state order, so their concatenation
+//            is too), by a radix select of the B-th largest score key with
+//            ties at it going to the lowest states;
+//   scores:  for each destination j of the part, c(j) = max over the beam
+//            (in state order) of v_b + log A(s_b, j), the first maximum
+//            wins; score(j) = c(j) + log B_t(j);
+//   keep:    the part's own top B by the same rule, stored in state order.
+// The union of the parts' top-B lists holds the global top B, so the
+// rebuild is exact; W = 1 is the single-block case.  A beam record is a
+// 64-word header (word 0 = entry count) followed by the state, score and
+// anchor arrays (Bc entries each).  Slot of a beam task: records [0, W) are
+// the parts of even t, [W, 2W) of odd t, record 2W the beam at t_mid (its
+// header word 1 flags a task that needs the exact re-decode).  Root
+// division beams are records in the root copy area.  Division and t_mid
+// beams are written by the block that rebuilds that step's beam.
+
 
 struct BeamRec {
     int32_t* hdr;
@@ -553,12 +758,20 @@ __device__ __forceinline__ BeamRec beam_rec(float* base, int32_t Bc) {
 __device__ __forceinline__ BeamRec slot_beam(const EngineArgs& a, int32_t slot, int32_t k) {
     return beam_rec(a.slot_base + (int64_t)slot * a.slot_floats + k * a.brec, a.Bc);
 }
+__device__ __forceinline__ BeamRec slot_part(const EngineArgs& a, int32_t slot, int32_t parity, int32_t part) {
+    return slot_beam(a, slot, parity * a.bw + part);
+}
+__device__ __forceinline__ BeamRec slot_snap_beam(const EngineArgs& a, int32_t slot) {
+    return slot_beam(a, slot, 2 * a.bw);
+}
 __device__ __forceinline__ BeamRec root_beam(const EngineArgs& a, int64_t root_off, int32_t d) {
     return beam_rec(a.root_copy + (root_off + d) * a.brec, a.Bc);
 }
 __device__ __forceinline__ int32_t* beam_fallback_flag(const EngineArgs& a, int32_t slot) {
-    return slot_beam(a, slot, 0).hdr + 1;
+    return slot_snap_beam(a, slot).hdr + 1;
 }
+// destinations [lo, hi) of part p of W
+__device__ __forceinline__ int32_t part_lo(int32_t K, int32_t W, int32_t p) { return (int32_t)(((int64_t)p * K) / W); }
 
 // Exclusive block-wide prefix sum of one int per thread; *total = the sum.
 __device__ int32_t block_exscan(int32_t v, int32_t* total, int32_t* wsum) {
@@ -590,8 +803,9 @@ __device__ __forceinline__ uint32_t score_key(float v) {
     return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
 }
 
-// Index of the largest key over the block (keys from k < n; 0 = none).
-__device__ int32_t block_argmax_key(unsigned long long key, BeamLds& L) {
+// The index held in the largest key over the block (keys: 0 = none).
+__device__ int32_t block_argmax_key(unsigned long long key) {
+    BeamLds& L = g_lds.beam;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
@@ -606,14 +820,19 @@ __device__ int32_t block_argmax_key(unsigned long long key, BeamLds& L) {
     return (int32_t)(0xFFFFFFFFu - (uint32_t)(best & 0xFFFFFFFFull));
 }
 
-// Keep the top B of L.sc[0..K) (with anchors L.an) and write them, in state
-// order, to `out` (and `out2` when given).  Returns the number kept.
-__device__ int32_t beam_select_store(int32_t K, int32_t B, BeamLds& L, BeamRec out, const BeamRec* out2) {
+// Top B of n entries given in state order (score v[k], state s ? s[k] :
+// s0 + k, anchor an[k]) by (score desc, state asc), -inf dropped.  out(p,
+// state, score, anchor) receives the kept entries in state order; returns
+// how many were kept.
+template <typename Out>
+__device__ int32_t beam_select(int32_t n, int32_t B, const float* v, const int32_t* s, int32_t s0,
+                               const int32_t* an, Out out) {
+    BeamLds& L = g_lds.beam;
     const int tid = threadIdx.x;
-    const int32_t per = (K + kEngBlock - 1) / kEngBlock;
-    const int32_t j0 = min(K, tid * per), j1 = min(K, j0 + per);
+    const int32_t per = (n + kEngBlock - 1) / kEngBlock;
+    const int32_t k0 = min(n, tid * per), k1 = min(n, k0 + per);
     int32_t nfin = 0;
-    for (int32_t j = j0; j < j1; ++j) nfin += L.sc[j] != -INFINITY;
+    for (int32_t k = k0; k < k1; ++k) nfin += v[k] != -INFINITY;
     int32_t n_finite;
     block_exscan(nfin, &n_finite, L.wsum);
     const bool all = n_finite <= B;
@@ -625,10 +844,10 @@ __device__ int32_t beam_select_store(int32_t K, int32_t B, BeamLds& L, BeamRec o
         for (int shift = 24; shift >= 0; shift -= 8) {
             for (int k = tid; k < 256; k += kEngBlock) L.hist[k] = 0;
             __syncthreads();
-            for (int32_t j = j0; j < j1; ++j) {
-                const float v = L.sc[j];
-                if (v == -INFINITY) continue;
-                const uint32_t u = score_key(v);
+            for (int32_t k = k0; k < k1; ++k) {
+                const float x = v[k];
+                if (x == -INFINITY) continue;
+                const uint32_t u = score_key(x);
                 if ((u & mask) == prefix) atomicAdd(&L.hist[(u >> shift) & 255u], 1u);
             }
             __syncthreads();
@@ -663,19 +882,18 @@ __device__ int32_t beam_select_store(int32_t K, int32_t B, BeamLds& L, BeamRec o
         kth = prefix;
         take_eq = rem;
     }
-    // ties at the B-th key go to the lowest states
     int32_t neq = 0;
     if (!all)
-        for (int32_t j = j0; j < j1; ++j) neq += (L.sc[j] != -INFINITY && score_key(L.sc[j]) == kth);
+        for (int32_t k = k0; k < k1; ++k) neq += (v[k] != -INFINITY && score_key(v[k]) == kth);
     int32_t dummy;
     const int32_t eq_before = block_exscan(neq, &dummy, L.wsum);
     int32_t nsel = 0;
     {
         int32_t r = eq_before;
-        for (int32_t j = j0; j < j1; ++j) {
-            const float v = L.sc[j];
-            if (v == -INFINITY) continue;
-            const uint32_t u = score_key(v);
+        for (int32_t k = k0; k < k1; ++k) {
+            const float x = v[k];
+            if (x == -INFINITY) continue;
+            const uint32_t u = score_key(x);
             bool keep = all || u > kth;
             if (!all && u == kth) keep = r++ < take_eq;
             nsel += keep;
@@ -685,97 +903,119 @@ __device__ int32_t beam_select_store(int32_t K, int32_t B, BeamLds& L, BeamRec o
     int32_t p = block_exscan(nsel, &n_kept, L.wsum);
     {
         int32_t r = eq_before;
-        for (int32_t j = j0; j < j1; ++j) {
-            const float v = L.sc[j];
-            if (v == -INFINITY) continue;
-            const uint32_t u = score_key(v);
+        for (int32_t k = k0; k < k1; ++k) {
+            const float x = v[k];
+            if (x == -INFINITY) continue;
+            const uint32_t u = score_key(x);
             bool keep = all || u > kth;
             if (!all && u == kth) keep = r++ < take_eq;
-            if (keep) {
-                out.s[p] = j; out.v[p] = v; out.a[p] = L.an[j];
-                if (out2) { out2->s[p] = j; out2->v[p] = v; out2->a[p] = L.an[j]; }
-                ++p;
-            }
+            if (keep) { out(p, s ? s[k] : s0 + k, x, an[k]); ++p; }
         }
     }
-    if (tid == 0) {
-        out.hdr[0] = n_kept;
-        if (out2) out2->hdr[0] = n_kept;
-    }
+    __syncthreads();
     return n_kept;
 }
 
-// Loads a beam record into LDS; returns its entry count.  States are
-// clamped to [0, K) (they address rows of log A).
-__device__ int32_t beam_load(const BeamRec& r, int32_t B, int32_t K, BeamLds& L) {
-    if (threadIdx.x == 0) L.misc[2] = r.hdr[0];
+// The beam of the step whose parts are stored at `parity`, into L.bs/bv/ba.
+// States are clamped to [0, K) (they address rows of log A).
+__device__ int32_t beam_rebuild(const EngineArgs& a, int32_t slot, int32_t parity) {
+    BeamLds& L = g_lds.beam;
+    const int tid = threadIdx.x;
+    const int32_t W = a.bw, B = a.B, K = a.K;
+    if (tid < W) L.pofs[tid + 1] = clampi(slot_part(a, slot, parity, tid).hdr[0], B + 1);
+    if (tid == 0) L.pofs[0] = 0;
     __syncthreads();
-    const int32_t nb = clampi(L.misc[2], B + 1);
-    for (int32_t k = threadIdx.x; k < nb; k += kEngBlock) {
-        L.bs[k] = clampi(r.s[k], K);
-        L.bv[k] = r.v[k];
-        L.ba[k] = r.a[k];
+    if (tid == 0)
+        for (int32_t p = 1; p <= W; ++p) L.pofs[p] += L.pofs[p - 1];
+    __syncthreads();
+    for (int32_t p = 0; p < W; ++p) {
+        const BeamRec rp = slot_part(a, slot, parity, p);
+        const int32_t o = L.pofs[p], np = L.pofs[p + 1] - o;
+        for (int32_t k = tid; k < np; k += kEngBlock) {
+            L.cs[o + k] = clampi(rp.s[k], K);
+            L.cv[o + k] = rp.v[k];
+            L.ca[o + k] = rp.a[k];
+        }
     }
     __syncthreads();
-    return nb;
+    return beam_select(L.pofs[W], B, L.cv, L.cs, 0, L.ca, [&](int32_t p, int32_t st, float sv, int32_t av) {
+        L.bs[p] = st; L.bv[p] = sv; L.ba[p] = av;
+    });
 }
 
-// Position of state q in a record sorted by state, or -1.
-__device__ int32_t beam_find(const BeamRec& r, int32_t n, int32_t q) {
-    int32_t lo = 0, hi = n;
+// Copies the rebuilt beam (L.bs/bv/ba, nb entries) to a record.
+__device__ void beam_store(const BeamRec& rec, int32_t nb) {
+    const BeamLds& L = g_lds.beam;
+    for (int32_t k = threadIdx.x; k < nb; k += kEngBlock) {
+        rec.s[k] = L.bs[k];
+        rec.v[k] = L.bv[k];
+        rec.a[k] = L.ba[k];
+    }
+    if (threadIdx.x == 0) rec.hdr[0] = nb;
+}
+
+// Position of state q in an LDS beam of nb entries sorted by state, or -1.
+__device__ __forceinline__ int32_t beam_find_lds(const int32_t* bs, int32_t nb, int32_t q) {
+    int32_t lo = 0, hi = nb;
     while (lo < hi) {
         const int32_t mid = (lo + hi) >> 1;
-        const int32_t s = r.s[mid];
-        if (s == q) return mid;
-        if (s < q) lo = mid + 1; else hi = mid;
+        if (bs[mid] == q) return mid;
+        if (bs[mid] < q) lo = mid + 1; else hi = mid;
     }
     return -1;
 }
 
-__device__ void beam_chain_walk(const EngineArgs& a, const Row& r, int32_t q, BeamLds& L);
+__device__ __noinline__ void beam_chain_walk(const EngineArgs& a, const Row& r, int32_t q);
 
-__device__ void beam_row(const EngineArgs& a, const float* __restrict__ Ap, const Row& r, BeamLds& L) {
+// One part of one beam task's step (parts beyond the first return at once
+// for the single-block operations END and FINAL).
+__device__ __noinline__ void beam_row(const EngineArgs& a, const float* __restrict__ Ap, const Row& r, int32_t part) {
+    BeamLds& L = g_lds.beam;
     const int tid = threadIdx.x;
     SeqInfo& sq = a.seqs[r.seq];
-    const int32_t K = a.K, Kp = a.Kp, B = a.B;
+    const int32_t K = a.K, Kp = a.Kp, B = a.B, W = a.bw;
+    gfloat_t* Ag = as_global(Ap);
     const int32_t slot = clampi(r.slot, a.n_slots);
     const bool root = r.kind == KIND_BROOT;
     const int32_t T = r.T, pp = r.pp, m = r.m, n = r.n, t = r.t;
     const int32_t tmid = (m + n) >> 1;
+    const int32_t jlo = part_lo(K, W, part), jhi = part_lo(K, W, part + 1), nj = jhi - jlo;
     if (r.aux == B_INIT) {
         // start step: pi + log B_0 at m = 0, the anchored boundary otherwise
-        int32_t q = -1;
-        float alpha = 0.0f;
-        if (m > 0) {
-            if (tid == 0) {
-                L.misc[0] = ld_c(sq.path + m - 1);
-                L.misc[1] = (int32_t)__float_as_uint(ld_cf(a.alpha_at + sq.alpha_off + m - 1));
-                st_c(beam_fallback_flag(a, slot), 0);
-            }
-            __syncthreads();
-            q = L.misc[0];
-            alpha = __uint_as_float((uint32_t)L.misc[1]);
-            if (q < 0 || q >= K) q = -1;
-            __syncthreads();
-        } else if (tid == 0) {
-            st_c(beam_fallback_flag(a, slot), 0);
+        if (tid == 0) {
+            L.misc[2] = m > 0 ? ld_c(sq.path + m - 1) : -1;
+            L.misc[3] = m > 0 ? (int32_t)__float_as_uint(ld_cf(a.alpha_at + sq.alpha_off + m - 1)) : 0;
+            if (part == 0) st_c(beam_fallback_flag(a, slot), 0);
         }
+        __syncthreads();
+        int32_t q = L.misc[2];
+        const float alpha = __uint_as_float((uint32_t)L.misc[3]);
+        if (q < 0 || q >= K) q = -1;
         const float* bm = r.log_b + (int64_t)m * r.ld;
-        for (int32_t j = tid; j < K; j += kEngBlock) {
+        for (int32_t k = tid; k < nj; k += kEngBlock) {
+            const int32_t j = jlo + k;
             float v = -INFINITY;
             if (m == 0) v = a.log_pi ? a.log_pi[j] + bm[j] : bm[j];
             else if (q >= 0) { const float c = alpha + Ap[(int64_t)q * Kp + j]; v = c + bm[j]; }
-            L.sc[j] = v;
-            L.an[j] = -1;
+            L.sc[k] = v;
+            L.an[k] = -1;
         }
         __syncthreads();
-        BeamRec snap;
-        bool want_snap = false;
-        if (root && pp >= 2 && seg_end(T, pp, 0) == 0) { snap = root_beam(a, r.off, 0); want_snap = true; }
-        if (!root && tmid == m) { snap = slot_beam(a, slot, 2); want_snap = true; }
-        beam_select_store(K, B, L, slot_beam(a, slot, m & 1), want_snap ? &snap : nullptr);
+        const BeamRec out = slot_part(a, slot, m & 1, part);
+        const int32_t nk = beam_select(nj, B, L.sc, nullptr, jlo, L.an, [&](int32_t p, int32_t st, float sv, int32_t av) {
+            out.s[p] = st; out.v[p] = sv; out.a[p] = av;
+        });
+        if (tid == 0) out.hdr[0] = nk;
     } else if (r.aux == B_STEP) {
-        const int32_t nb = beam_load(slot_beam(a, slot, (t - 1) & 1), B, K, L);
+        const int32_t nb = beam_rebuild(a, slot, (t - 1) & 1);
+        if (part == 0) {
+            // division / t_mid beams are taken from the rebuilt step t - 1
+            if (root && pp >= 2) {
+                const int32_t d = div_index(T, pp, t - 1);
+                if (d >= 0) beam_store(root_beam(a, r.off, d), nb);
+            }
+            if (!root && t - 1 == tmid) beam_store(slot_snap_beam(a, slot), nb);
+        }
         int32_t mode;  // anchor: 0 none, 1 the predecessor, 2 the predecessor's anchor
         if (root) {
             if (pp >= 2 && div_index(T, pp, t - 1) >= 0) mode = 1;
@@ -785,33 +1025,32 @@ __device__ void beam_row(const EngineArgs& a, const float* __restrict__ Ap, cons
             mode = t == tmid + 1 ? 1 : (t > tmid + 1 ? 2 : 0);
         }
         const float* bt = r.log_b + (int64_t)t * r.ld;
-        for (int32_t j = tid; j < K; j += kEngBlock) {
+        for (int32_t k = tid; k < nj; k += kEngBlock) {
+            const int32_t j = jlo + k;
             float c = -INFINITY;
             int32_t w = -1;
             for (int32_t b = 0; b < nb; ++b) {
-                const float x = L.bv[b] + Ap[(int64_t)L.bs[b] * Kp + j];
+                const float x = L.bv[b] + Ag[(int64_t)L.bs[b] * Kp + j];
                 if (w < 0 || x > c) { c = x; w = b; }
             }
-            L.sc[j] = w < 0 ? -INFINITY : c + bt[j];
-            L.an[j] = w < 0 ? -1 : (mode == 1 ? L.bs[w] : (mode == 2 ? L.ba[w] : -1));
+            L.sc[k] = w < 0 ? -INFINITY : c + bt[j];
+            L.an[k] = w < 0 ? -1 : (mode == 1 ? L.bs[w] : (mode == 2 ? L.ba[w] : -1));
         }
         __syncthreads();
-        BeamRec snap;
-        bool want_snap = false;
-        if (root && pp >= 2) {
-            const int32_t d = div_index(T, pp, t);
-            if (d >= 0) { snap = root_beam(a, r.off, d); want_snap = true; }
-        }
-        if (!root && t == tmid) { snap = slot_beam(a, slot, 2); want_snap = true; }
-        beam_select_store(K, B, L, slot_beam(a, slot, t & 1), want_snap ? &snap : nullptr);
+        const BeamRec out = slot_part(a, slot, t & 1, part);
+        const int32_t nk = beam_select(nj, B, L.sc, nullptr, jlo, L.an, [&](int32_t p, int32_t st, float sv, int32_t av) {
+            out.s[p] = st; out.v[p] = sv; out.a[p] = av;
+        });
+        if (tid == 0) out.hdr[0] = nk;
     } else if (r.aux == B_END) {
+        if (part != 0) return;
         // only the known end state q*_n is evaluated
-        if (tid == 0) L.misc[0] = ld_c(&sq.status) < 0 ? -1 : ld_c(sq.path + n);
+        if (tid == 0) L.misc[4] = ld_c(&sq.status) < 0 ? -1 : ld_c(sq.path + n);
         __syncthreads();
-        const int32_t qn = L.misc[0];
+        const int32_t qn = L.misc[4];
         __syncthreads();
         if (qn < 0 || qn >= K) return;
-        const int32_t nb = beam_load(slot_beam(a, slot, (n - 1) & 1), B, K, L);
+        const int32_t nb = beam_rebuild(a, slot, (n - 1) & 1);
         unsigned long long key = 0;
         for (int32_t b = tid; b < nb; b += kEngBlock) {
             const float x = L.bv[b] + Ap[(int64_t)L.bs[b] * Kp + qn];
@@ -820,7 +1059,6 @@ __device__ void beam_row(const EngineArgs& a, const float* __restrict__ Ap, cons
                 if (k > key) key = k;
             }
         }
-        // any finite candidate gives a key above 0; block_argmax_key -> winner
         unsigned long long kk = key;
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) {
@@ -840,15 +1078,30 @@ __device__ void beam_row(const EngineArgs& a, const float* __restrict__ Ap, cons
             } else {
                 const int32_t w = clampi((int32_t)(0xFFFFFFFFu - (uint32_t)(best & 0xFFFFFFFFull)), nb);
                 const int32_t qmid = (n == tmid + 1) ? L.bs[w] : L.ba[w];
-                const BeamRec snap = slot_beam(a, slot, 2);
-                const int32_t at = (qmid >= 0 && qmid < K) ? beam_find(snap, clampi(snap.hdr[0], B + 1), qmid) : -1;
+                float amid = __builtin_nanf("");
+                if (qmid >= 0 && qmid < K) {
+                    if (n - 1 == tmid) {   // the t_mid beam is the one just rebuilt
+                        const int32_t at = beam_find_lds(L.bs, nb, qmid);
+                        if (at >= 0) amid = L.bv[at];
+                    } else {
+                        const BeamRec snap = slot_snap_beam(a, slot);
+                        const int32_t ns = clampi(snap.hdr[0], B + 1);
+                        int32_t lo = 0, hi = ns;
+                        while (lo < hi) {
+                            const int32_t mid = (lo + hi) >> 1;
+                            const int32_t sm = snap.s[mid];
+                            if (sm == qmid) { amid = snap.v[mid]; break; }
+                            if (sm < qmid) lo = mid + 1; else hi = mid;
+                        }
+                    }
+                }
                 st_c(sq.path + tmid, qmid);
-                st_cf(a.alpha_at + sq.alpha_off + tmid, at >= 0 ? snap.v[at] : __builtin_nanf(""));
+                st_cf(a.alpha_at + sq.alpha_off + tmid, amid);
             }
         }
     } else {  // B_FINAL: the root's best end state and the division chain
-        const BeamRec fin = slot_beam(a, slot, (T - 1) & 1);
-        const int32_t nb = beam_load(fin, B, K, L);
+        if (part != 0) return;
+        const int32_t nb = beam_rebuild(a, slot, (T - 1) & 1);
         if (nb == 0) {
             for (int32_t k = tid; k < T; k += kEngBlock) st_c(sq.path + k, -1);
             if (tid == 0) {
@@ -862,34 +1115,29 @@ __device__ void beam_row(const EngineArgs& a, const float* __restrict__ Ap, cons
             const unsigned long long kk = order_key(L.bv[k], L.bs[k]);
             if (kk > key) key = kk;
         }
-        const int32_t top_state = block_argmax_key(key, L);
+        const int32_t top_state = block_argmax_key(key);
         if (tid == 0) {
-            int32_t top = 0;   // position of top_state in the (state-sorted) LDS copy
-            for (int32_t lo = 0, hi = nb; lo < hi;) {
-                const int32_t mid = (lo + hi) >> 1;
-                if (L.bs[mid] < top_state) lo = mid + 1; else hi = mid;
-                top = lo;
-            }
-            top = clampi(top, nb);
+            const int32_t top = clampi(beam_find_lds(L.bs, nb, top_state), nb);
             st_c(sq.path + T - 1, top_state);
-            L.misc[3] = L.ba[top];
+            L.misc[5] = L.ba[top];
         }
         __syncthreads();
-        if (pp >= 2) beam_chain_walk(a, r, L.misc[3], L);
+        if (pp >= 2) beam_chain_walk(a, r, L.misc[5]);
     }
 }
 
 // Division chain of a finished beam root: q*_{e_d} for d = P'-2 .. 0, each
-// found in the division's beam snapshot (state-sorted), whose score is the
-// anchor alpha and whose anchor is the next state down.  Snapshot records
-// are copied to LDS in chunks (coalesced) and walked there.
-__device__ void beam_chain_walk(const EngineArgs& a, const Row& r, int32_t q, BeamLds& L) {
+// found in the division's beam (state-sorted), whose score is the anchor
+// alpha and whose anchor is the next state down.  Division records are
+// copied to LDS in chunks (coalesced) and walked there.
+__device__ __noinline__ void beam_chain_walk(const EngineArgs& a, const Row& r, int32_t q) {
+    BeamLds& L = g_lds.beam;
     const int tid = threadIdx.x;
     SeqInfo& sq = a.seqs[r.seq];
     const int32_t K = a.K, B = a.B, T = r.T, pp = r.pp;
-    int32_t* buf = reinterpret_cast<int32_t*>(L.sc);             // L.sc and L.an: 2 * kBeamMaxK ints
-    const int32_t stride = 1 + 3 * B;                             // count, states, scores, anchors
-    const int32_t per = max(1, (2 * kBeamMaxK) / stride);
+    int32_t* buf = L.cs;                        // L.cs, L.cv, L.ca: 3 * kBeamCandMax ints
+    const int32_t stride = 1 + 3 * B;           // count, states, scores, anchors
+    const int32_t per = max(1, (3 * kBeamCandMax) / stride);
     for (int32_t dhi = pp - 2; dhi >= 0; dhi -= per) {
         const int32_t dlo = max(0, dhi - per + 1);
         for (int32_t d = dlo; d <= dhi; ++d) {
@@ -919,25 +1167,22 @@ __device__ void beam_chain_walk(const EngineArgs& a, const Row& r, int32_t q, Be
                 st_cf(a.alpha_at + sq.alpha_off + e, at >= 0 ? __int_as_float(rec[1 + B + at]) : __builtin_nanf(""));
                 if (d >= 1) q = (at >= 0 && q >= 0 && q < K) ? rec[1 + 2 * B + at] : -1;
             }
-            L.misc[3] = q;
+            L.misc[6] = q;
         }
         __syncthreads();
-        q = L.misc[3];
+        q = L.misc[6];
         __syncthreads();
     }
 }
 
-union EngineLds {
-    TileLds tile;
-    BeamLds beam;
-};
 
 // Finalize of a vanilla pass or a FLASH root (one block): the final state,
 // the score, and for a root the division chain q*_{e_d} = Link_{d+1}(q*_{e_{d+1}})
 // with the anchors alpha = Dsnap_d(q*_{e_d}).  Link rows are copied to LDS in
 // chunks (coalesced) and the chain is walked there; the anchors are then
 // gathered in parallel.
-__device__ void dense_finalize(const EngineArgs& a, const Row& r, EngineLds& lds) {
+__device__ __noinline__ void dense_finalize(const EngineArgs& a, const Row& r) {
+    EngineLds& lds = g_lds;
     const int tid = threadIdx.x;
     SeqInfo& sq = a.seqs[r.seq];
     const int32_t K = a.K, T = r.T, pp = r.pp;
@@ -948,10 +1193,11 @@ __device__ void dense_finalize(const EngineArgs& a, const Row& r, EngineLds& lds
     if (tid == 0) {
         const unsigned long long key = ld_c(a.keys + r.seq);
         const int32_t qT = clampi((int32_t)(0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull)), K);
-        const float sc = slot_delta(a, slot, (T - 1) & 1)[qT];
+        // coherent reads: with wide rows these were written on other XCDs
+        const float sc = ld_cf(slot_delta(a, slot, (T - 1) & 1) + qT);
         sv[0] = qT;
         sv[1] = __float_as_int(sc);
-        sv[2] = (r.kind == KIND_ROOT && pp >= 2) ? clampi(slot_anc(a, slot, (T - 1) & 1)[qT], K) : -1;
+        sv[2] = (r.kind == KIND_ROOT && pp >= 2) ? clampi(ld_c(slot_anc(a, slot, (T - 1) & 1) + qT), K) : -1;
     }
     __syncthreads();
     const int32_t qT = sv[0];
@@ -978,7 +1224,7 @@ __device__ void dense_finalize(const EngineArgs& a, const Row& r, EngineLds& lds
         if (tid == 0) {
             for (int32_t d = pp - 2; d >= 0; --d) {
                 st_c(sq.path + seg_end(T, pp, d), q);
-                if (d >= 1) q = clampi(root_link(a, r.off, pp, d)[q], K);
+                if (d >= 1) q = clampi(ld_c(root_link(a, r.off, pp, d) + q), K);
             }
         }
         __syncthreads();
@@ -990,7 +1236,7 @@ __device__ void dense_finalize(const EngineArgs& a, const Row& r, EngineLds& lds
         const int32_t n = (dhi - l0 + 1) * K;
         for (int32_t idx = tid; idx < n; idx += kEngBlock) {
             const int32_t d = l0 + idx / K, j = idx % K;
-            buf[(d - dlo) * K + j] = root_link(a, r.off, pp, d)[j];
+            buf[(d - dlo) * K + j] = ld_c(root_link(a, r.off, pp, d) + j);
         }
         __syncthreads();
         if (tid == 0) {
@@ -1007,7 +1253,7 @@ __device__ void dense_finalize(const EngineArgs& a, const Row& r, EngineLds& lds
     for (int32_t d = tid; d <= pp - 2; d += kEngBlock) {
         const int64_t e = seg_end(T, pp, d);
         const int32_t qd = clampi(ld_c(sq.path + e), K);
-        st_cf(a.alpha_at + sq.alpha_off + e, root_dsnap(a, r.off, d)[qd]);
+        st_cf(a.alpha_at + sq.alpha_off + e, ld_cf(root_dsnap(a, r.off, d) + qd));
     }
     __syncthreads();
 }
@@ -1109,18 +1355,7 @@ __device__ void write_spawns(const EngineArgs& a, const Row& r, int src, int64_t
 
 // The scheduler block splits into kXcd groups of 128 threads; group x
 // handles the rows of XCD x.  Its state lives in LDS.
-constexpr int kSchedGroup = kEngBlock / kXcd;
-constexpr int kSchedGroupWaves = kSchedGroup / 64;
 
-struct SchedLds {
-    int32_t q_head, q_tail, max_rows;
-    int32_t n_free[kXcd];
-    int32_t nblk[kXcd];        // compute blocks on each XCD
-    int32_t admit[kXcd];
-    int32_t spawn_total[kXcd];
-    int32_t n_next[kXcd][3];   // rows written for the next step: full, light, beam
-    int32_t wave_sums[kXcd][kSchedGroupWaves][5];
-};
 
 // Exclusive scan of N counters over the 128 threads of a scheduler group.
 template <int N>
@@ -1159,7 +1394,8 @@ __device__ void group_scan(int32_t (&v)[N], int32_t (&tot)[N], int32_t (&ws)[kSc
 // (beam tasks to the beam list, the others to the light list).  Called by
 // the whole scheduler block; sl.n_next holds the rows already written for
 // step nxt.
-__device__ void admit(const EngineArgs& a, SchedLds& sl, int nxt) {
+__device__ __noinline__ void admit(const EngineArgs& a, int nxt) {
+    SchedLds& sl = g_sched;
     if (threadIdx.x == 0) {
         // water filling: XCD x gets rows up to level L * nblk[x] (its share of
         // the compute blocks), at most its free slots; L is the lowest level
@@ -1230,6 +1466,7 @@ __device__ void admit(const EngineArgs& a, SchedLds& sl, int nxt) {
             st_c(&a.st->claim[nxt][y][0], 0);
             st_c(&a.st->claim[nxt][y][16], 0);
         }
+        st_c(&a.st->wclaim[nxt][0], 0);
         st_c(&a.st->total[nxt], all);
         if (all > sl.max_rows) sl.max_rows = all;
         st_c(&a.st->max_rows, sl.max_rows);
@@ -1237,7 +1474,8 @@ __device__ void admit(const EngineArgs& a, SchedLds& sl, int nxt) {
     __syncthreads();
 }
 
-__device__ void scheduler(const EngineArgs& a, int32_t s, SchedLds& sl) {
+__device__ __noinline__ void scheduler(const EngineArgs& a, int32_t s) {
+    SchedLds& sl = g_sched;
     const int cur = s & 1, nxt = cur ^ 1;
     const int x = threadIdx.x / kSchedGroup, tg = threadIdx.x % kSchedGroup;
     const int32_t nf = ld_c(&a.st->cnt[cur][x][0]);
@@ -1285,7 +1523,7 @@ __device__ void scheduler(const EngineArgs& a, int32_t s, SchedLds& sl) {
         for (int k = 0; k < 3; ++k) sl.n_next[x][k] = tot[k];
     }
     __syncthreads();
-    admit(a, sl, nxt);
+    admit(a, nxt);
 }
 
 // ---------------------------------------------------------------- step barrier
@@ -1344,6 +1582,38 @@ __device__ bool barrier_master(const EngineArgs& a, uint32_t epoch) {
 }
 
 // ---------------------------------------------------------------- engine
+// Wide-row phase of a step: items (XCD list, group of 16 rows, 64-column
+// chunk) over the dense rows of every XCD, taken by all blocks of the chip:
+// first by global rank, then claimed from one counter.
+__device__ void run_wide(const EngineArgs& a, const float* __restrict__ Ap, int cur) {
+    __shared__ int32_t s_item;
+    const int32_t nch = a.Kp / kWideCols;
+    int32_t nf[kXcd], base[kXcd + 1];
+    base[0] = 0;
+    for (int y = 0; y < kXcd; ++y) {
+        nf[y] = ld_c(&a.st->cnt[cur][y][0]);
+        base[y + 1] = base[y] + ((nf[y] + kWideRows - 1) / kWideRows) * nch;
+    }
+    const int32_t total = base[kXcd];
+    int32_t item = blockIdx.x >= 1 ? (int32_t)blockIdx.x - 1 : -1;
+    for (;;) {
+        if (item < 0) {
+            if (threadIdx.x == 0)
+                s_item = a.n_compute_blocks +
+                         __hip_atomic_fetch_add(&a.st->wclaim[cur][0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __syncthreads();
+            item = s_item;
+            __syncthreads();
+        }
+        if (item >= total) break;
+        int y = 0;
+        while (item >= base[y + 1]) ++y;
+        const int32_t rem = item - base[y];
+        wide_item(a, Ap, list_full(a, cur, y), nf[y], rem / nch, rem % nch);
+        item = -1;
+    }
+}
+
 // Work of one XCD at one step.  Phase 1: dense tiles and light rows, taken
 // by tile groups (nsplit waves) one item at a time: a tile, or nsplit light
 // rows (one per wave).  Groups run independently, so one group's
@@ -1352,12 +1622,14 @@ __device__ bool barrier_master(const EngineArgs& a, uint32_t epoch) {
 // counter; every block (and the scheduler block once its own work is done)
 // takes a first item by rank, then claims until none are left.
 __device__ void run_units(const EngineArgs& a, const float* __restrict__ Ap, uint32_t x, int32_t nx, int32_t rank,
-                          int cur, EngineLds& lds) {
+                          int cur) {
+    EngineLds& lds = g_lds;
     __shared__ int32_t s_unit;
     const int32_t nf = ld_c(&a.st->cnt[cur][x][0]);
     const int32_t nl = ld_c(&a.st->cnt[cur][x][1]);
     const int32_t nbm = ld_c(&a.st->cnt[cur][x][2]);
-    const int32_t n_tiles = ((nf + kTileRows - 1) / kTileRows) * (a.Kp / kTileCols);
+    const int32_t n_tiles = a.wide ? 0 : ((nf + kTileRows - 1) / kTileRows) * (a.Kp / kTileCols);
+    if (a.wide) run_wide(a, Ap, cur);
     // waves per tile: 4 (one per SIMD) while every group gets two tiles or
     // more, else more waves per tile (fewer, faster groups); at most one wave
     // per 16 predecessors.  Decided from a nominal XCD of 32 blocks, so that
@@ -1389,7 +1661,7 @@ __device__ void run_units(const EngineArgs& a, const float* __restrict__ Ap, uin
             }
             if (item >= n1) break;
             if (item < n_tiles) {
-                dense_tile(a, Ap, F, nf, item, nsplit, lds.tile);
+                dense_tile(a, Ap, F, nf, item, nsplit);
             } else {
                 const int32_t li = (item - n_tiles) * nsplit + wv;
                 if (li < nl) light_row(a, Ap, ld_row(L + li));
@@ -1409,18 +1681,17 @@ __device__ void run_units(const EngineArgs& a, const float* __restrict__ Ap, uin
             u = s_unit;
             __syncthreads();
         }
-        if (u >= nbm) break;
-        const Row r = ld_row(Bl + u);
-        if (is_beam(r.kind)) beam_row(a, Ap, r, lds.beam);
-        else dense_finalize(a, r, lds);
+        if (u >= nbm * a.bw) break;   // item = (row, part); finalizes use part 0
+        const int32_t part = u % a.bw;
+        const Row r = ld_row(Bl + u / a.bw);
+        if (is_beam(r.kind)) beam_row(a, Ap, r, part);
+        else if (part == 0) dense_finalize(a, r);
         u = -1;
     }
 }
 
 extern "C" __global__ __launch_bounds__(kEngBlock) void fv_engine_kernel(const float* __restrict__ Ap,
                                                                          EngineArgs a) {
-    __shared__ EngineLds lds;
-    __shared__ SchedLds sched_lds;
     const bool is_sched = blockIdx.x == 0;
     const uint32_t x = my_xcd();
     __shared__ int32_t s_rank;
@@ -1434,7 +1705,7 @@ extern "C" __global__ __launch_bounds__(kEngBlock) void fv_engine_kernel(const f
     const int32_t nx = (int32_t)ld_c(&a.st->xcd_blocks[x][0]);
 
     if (is_sched) {
-        SchedLds& sl = sched_lds;
+        SchedLds& sl = g_sched;
         if (threadIdx.x == 0) {
             sl.q_head = 0;
             sl.q_tail = ld_c(&a.st->q_tail0);
@@ -1446,7 +1717,7 @@ extern "C" __global__ __launch_bounds__(kEngBlock) void fv_engine_kernel(const f
             }
         }
         __syncthreads();
-        if (ok) admit(a, sl, 0);
+        if (ok) admit(a, 0);
     }
     ++epoch;
     if (ok) ok = is_sched ? barrier_master(a, epoch) : barrier_arrive_wait(a, epoch, x);
@@ -1459,8 +1730,8 @@ extern "C" __global__ __launch_bounds__(kEngBlock) void fv_engine_kernel(const f
             if (is_sched && threadIdx.x == 0) st_c(&a.st->error, 2);
             break;
         }
-        if (is_sched) scheduler(a, s, sched_lds);
-        run_units(a, Ap, x, nx, rank, cur, lds);
+        if (is_sched) scheduler(a, s);
+        run_units(a, Ap, x, nx, rank, cur);
         ++epoch;
         ok = is_sched ? barrier_master(a, epoch) : barrier_arrive_wait(a, epoch, x);
     }

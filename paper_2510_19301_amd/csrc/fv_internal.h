@@ -105,6 +105,7 @@ struct EngineState {
     uint32_t go[kXcd][kLine];   // barrier release flags, one line per XCD
     uint32_t xcd_blocks[kXcd][kLine];  // compute blocks per XCD (counted at start)
     int32_t claim[2][kXcd][kLine];     // [parity][xcd] next unclaimed work unit of a step
+    int32_t wclaim[2][kLine];          // [parity] next unclaimed wide item of a step
 };
 
 // Everything the persistent engine needs (one model).
@@ -118,12 +119,14 @@ struct EngineArgs {
     int32_t n_seqs;
     int32_t method;             // FV_VANILLA / FV_FLASH / FV_BEAM
     int32_t B, Bc;              // beam width (<= K) and its padded array length
+    int32_t bw;                 // parts of a beam task's step (1 for other methods)
     int64_t brec;               // floats per beam record (header + state, score, anchor arrays)
     // storage
     float* slot_base;           // slots * slot_floats
     int64_t slot_floats;        // floats per slot
     int32_t n_slots;            // multiple of kXcd
     int32_t has_anc;            // slots carry anc[2] + snap
+    int32_t wide;               // wide rows: every block takes a column slice of every dense row
     float* alpha_at;            // sum T floats
     float* root_copy;           // division copies (delta and link), units of Kp
     uint16_t* psi16;            // vanilla backpointers

@@ -50,11 +50,16 @@ def _workspace(n: int, dev) -> torch.Tensor:
     return torch.empty(max(n, 256), dtype=torch.uint8, device=dev)
 
 
+ROWS = {"auto": 0, "wide": L.FV_FLAG_WIDE_ROWS, "local": L.FV_FLAG_LOCAL_ROWS}
+
+
 def decode(log_a: torch.Tensor, log_b: torch.Tensor, log_pi: torch.Tensor | None = None,
-           method: str = "vanilla", P: int = 16, B: int = 0, check_status: bool = True):
+           method: str = "vanilla", P: int = 16, B: int = 0, check_status: bool = True,
+           rows: str = "auto"):
     """Decode one sequence.  log_a [K, K], log_b [T, >=K] (row stride = ld),
-    log_pi [K] or None; all float32 CUDA tensors.  Returns
-    (path int32 [T], score float32 [1], status int32 [1]) on the device."""
+    log_pi [K] or None; all float32 CUDA tensors.  rows: "auto", "wide" or
+    "local" row placement (same results).  Returns (path int32 [T],
+    score float32 [1], status int32 [1]) on the device."""
     model = dense_model(log_a)
     _need(log_b, "log_b")
     if log_b.dim() != 2 or log_b.stride(1) != 1:
@@ -74,15 +79,15 @@ def decode(log_a: torch.Tensor, log_b: torch.Tensor, log_pi: torch.Tensor | None
     lib = L.lib()
     if method == "vanilla":
         rc = lib.fv_decode_vanilla(C.byref(model), pi, log_b.data_ptr(), ld, T, path.data_ptr(),
-                                   score.data_ptr(), status.data_ptr(), 0, ws.data_ptr(), ws.numel(),
+                                   score.data_ptr(), status.data_ptr(), ROWS[rows], ws.data_ptr(), ws.numel(),
                                    _stream(dev))
     elif method == "flash":
         rc = lib.fv_decode_flash(C.byref(model), pi, log_b.data_ptr(), ld, T, int(P), path.data_ptr(),
-                                 score.data_ptr(), status.data_ptr(), 0, ws.data_ptr(), ws.numel(),
+                                 score.data_ptr(), status.data_ptr(), ROWS[rows], ws.data_ptr(), ws.numel(),
                                  _stream(dev))
     elif method == "beam":
         rc = lib.fv_decode_beam(C.byref(model), pi, log_b.data_ptr(), ld, T, int(B), int(P),
-                                path.data_ptr(), score.data_ptr(), status.data_ptr(), 0, ws.data_ptr(),
+                                path.data_ptr(), score.data_ptr(), status.data_ptr(), ROWS[rows], ws.data_ptr(),
                                 ws.numel(), _stream(dev))
     else:
         raise ValueError(method)
@@ -138,7 +143,8 @@ class Batch:
 
 
 def decode_batch(log_a: torch.Tensor, batch: Batch, log_pi: torch.Tensor | None = None,
-                 method: str = "flash", P: int = 16, B: int = 0, ws: torch.Tensor | None = None):
+                 method: str = "flash", P: int = 16, B: int = 0, ws: torch.Tensor | None = None,
+                 rows: str = "auto"):
     """Decode all sequences of `batch` in one persistent launch; results land
     in batch.paths / batch.scores / batch.status.  Returns the workspace
     tensor so callers can reuse it."""
@@ -151,7 +157,7 @@ def decode_batch(log_a: torch.Tensor, batch: Batch, log_pi: torch.Tensor | None 
     lengths = np.ascontiguousarray(batch.lengths, np.int32)
     rc = L.lib().fv_decode_batch(C.byref(model), C.cast(pis, C.c_void_p), 1, batch.desc.data_ptr(),
                                  lengths.ctypes.data, None, batch.n, L.METHODS[method], int(P),
-                                 int(B or 0), batch.status.data_ptr(), 0, ws.data_ptr(), ws.numel(),
+                                 int(B or 0), batch.status.data_ptr(), ROWS[rows], ws.data_ptr(), ws.numel(),
                                  _stream(dev))
     L.check(rc, "fv_decode_batch")
     return ws
