@@ -10,7 +10,7 @@
 #include "fv_internal.h"
 
 namespace fv {
-extern "C" __global__ void fv_engine_kernel(const float* __restrict__ Ap, EngineArgs a);
+extern "C" __global__ void fv_engine_kernel(const float* __restrict__ Ap, const EngineArgs* __restrict__ args);
 extern "C" __global__ void fv_prep_dense_kernel(const float* __restrict__ log_a, int32_t K, int32_t Kp,
                                                 float* __restrict__ Ap);
 extern "C" __global__ void fv_setup_kernel(EngineArgs a, SetupArgs sa);
@@ -72,7 +72,7 @@ struct DenseLayout {
     int32_t bw = 1;              // parts of a beam task's step
     int64_t brec = 0;            // floats per beam record
     int64_t q_cap = 0;
-    Region Ap, seq1, seqinfo, keys, state, arrive, rows_full, rows_light, rows_beam, queue, free_stack,
+    Region Ap, seq1, seqinfo, keys, args, state, arrive, rows_full, rows_light, rows_beam, queue, free_stack,
         slots, alpha, root, psi;
     size_t total = 0;
 };
@@ -156,6 +156,7 @@ fv_status plan_dense(int32_t method, int32_t K, const int32_t* T_host, int32_t n
     put(cur, L.seq1, single ? sizeof(fv_seq) : 0);
     put(cur, L.seqinfo, (size_t)std::max(n_seqs, 1) * sizeof(SeqInfo));
     put(cur, L.keys, (size_t)std::max(n_seqs, 1) * 8);
+    put(cur, L.args, sizeof(EngineArgs));
     put(cur, L.state, sizeof(EngineState));
     put(cur, L.arrive, (size_t)kMaxBlocks * 4);
     put(cur, L.rows_full, (size_t)2 * L.n_slots * sizeof(Row));
@@ -290,10 +291,12 @@ fv_status run_dense(int32_t method, const fv_trans* A, const float* log_pi, cons
     sa.host_sum_psi = L.sum_psi;
     sa.kind = method == FV_VANILLA ? KIND_VANILLA : (method == FV_BEAM ? KIND_BROOT : KIND_ROOT);
     sa.K = A->K;
+    sa.args_out = static_cast<EngineArgs*>(at(L.args));
     hipLaunchKernelGGL(fv_setup_kernel, dim3(1), dim3(kBlock), 0, stream, a, sa);
 
     if (n_seqs > 0) {
-        void* args[] = {&Ap, &a};
+        const EngineArgs* args_dev = sa.args_out;
+        void* args[] = {&Ap, &args_dev};
         if (g_prof_on) HIP_TRY(hipEventRecord(g_prof_ev[0], stream));
         HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(fv_engine_kernel),
                                            dim3(a.n_compute_blocks + 1), dim3(kEngineBlock), args, 0, stream));

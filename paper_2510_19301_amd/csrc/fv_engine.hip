@@ -34,6 +34,17 @@ namespace fv {
 
 static_assert(sizeof(Row) == 64, "Row is moved as 8 coherent 64-bit words");
 
+// The engine reads its arguments from a copy in the workspace through the
+// constant address space: field loads are scalar loads in every function.
+typedef __attribute__((address_space(4))) const EngineArgs cargs_t;
+// the argument block is the same for every lane: keep its address scalar
+__device__ __forceinline__ cargs_t& uniform_args(cargs_t& a) {
+    const uint64_t v = reinterpret_cast<uint64_t>(&a);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return *reinterpret_cast<cargs_t*>(((uint64_t)hi << 32) | lo);
+}
+
 // The engine runs one 1024-thread block per CU: 16 waves = 4 tile groups of
 // 4 waves (one wave per SIMD each), which keeps 4 waves per SIMD for latency
 // hiding while the step barrier has one participant per CU.
@@ -113,29 +124,29 @@ __device__ __forceinline__ unsigned long long order_key(float v, int32_t j) {
     return ((unsigned long long)o << 32) | (unsigned long long)(0xFFFFFFFFu - (uint32_t)j);
 }
 
-__device__ __forceinline__ float* slot_delta(const EngineArgs& a, int32_t slot, int32_t parity) {
+__device__ __forceinline__ float* slot_delta(cargs_t& a, int32_t slot, int32_t parity) {
     return a.slot_base + (int64_t)slot * a.slot_floats + (int64_t)parity * a.Kp;
 }
-__device__ __forceinline__ int32_t* slot_anc(const EngineArgs& a, int32_t slot, int32_t parity) {
+__device__ __forceinline__ int32_t* slot_anc(cargs_t& a, int32_t slot, int32_t parity) {
     return reinterpret_cast<int32_t*>(a.slot_base + (int64_t)slot * a.slot_floats +
                                       (int64_t)(2 + parity) * a.Kp);
 }
-__device__ __forceinline__ float* slot_snap(const EngineArgs& a, int32_t slot) {
+__device__ __forceinline__ float* slot_snap(cargs_t& a, int32_t slot) {
     return a.slot_base + (int64_t)slot * a.slot_floats + (int64_t)4 * a.Kp;
 }
-__device__ __forceinline__ float* root_dsnap(const EngineArgs& a, int64_t root_off, int32_t d) {
+__device__ __forceinline__ float* root_dsnap(cargs_t& a, int64_t root_off, int32_t d) {
     return a.root_copy + (root_off + d) * (int64_t)a.Kp;
 }
-__device__ __forceinline__ int32_t* root_link(const EngineArgs& a, int64_t root_off, int32_t pp, int32_t d) {
+__device__ __forceinline__ int32_t* root_link(cargs_t& a, int64_t root_off, int32_t pp, int32_t d) {
     return reinterpret_cast<int32_t*>(a.root_copy + (root_off + (pp - 1) + d) * (int64_t)a.Kp);
 }
-__device__ __forceinline__ Row* list_full(const EngineArgs& a, int parity, int x) {
+__device__ __forceinline__ Row* list_full(cargs_t& a, int parity, int x) {
     return a.rows_full + ((int64_t)parity * kXcd + x) * a.pool;
 }
-__device__ __forceinline__ Row* list_light(const EngineArgs& a, int parity, int x) {
+__device__ __forceinline__ Row* list_light(cargs_t& a, int parity, int x) {
     return a.rows_light + ((int64_t)parity * kXcd + x) * a.pool;
 }
-__device__ __forceinline__ Row* list_beam(const EngineArgs& a, int parity, int x) {
+__device__ __forceinline__ Row* list_beam(cargs_t& a, int parity, int x) {
     return a.rows_beam + ((int64_t)parity * kXcd + x) * a.pool;
 }
 
@@ -250,7 +261,7 @@ __device__ Row make_light_row(const Row& base, int32_t t, int32_t op) {
 }
 
 // First row (the start step) of a task, from the per-sequence table.
-__device__ Row row_from_task(const EngineArgs& a, const Task& tk, int32_t slot) {
+__device__ Row row_from_task(cargs_t& a, const Task& tk, int32_t slot) {
     const SeqInfo& sq = a.seqs[tk.seq];
     Row b;
     b.seq = tk.seq; b.kind = tk.kind; b.m = tk.m; b.n = tk.n; b.t = tk.m; b.slot = slot;
@@ -337,8 +348,9 @@ __device__ __forceinline__ void group_sync(uint32_t* ctr, int32_t nsplit) {
 // bound by memory latency, so its loads are issued together: the row's
 // remaining fields come from an LDS copy made before the loop, the refine
 // loads of two columns go out at once, and so do the anchor gathers.
-__device__ __noinline__ void dense_tile(const EngineArgs& a, const float* __restrict__ Ap, const Row* rows,
+__device__ __noinline__ void dense_tile(cargs_t& a_in, const float* __restrict__ Ap, const Row* rows,
                            int32_t nrows, int32_t tile, int32_t nsplit) {
+    cargs_t& a = uniform_args(a_in);
     TileLds& lds = g_lds.tile;
     const bool active = true;
     const int32_t K = a.K, Kp = a.Kp;
@@ -522,8 +534,9 @@ __device__ __noinline__ void dense_tile(const EngineArgs& a, const float* __rest
 // with coherent loads; the step barrier's release makes the stores visible.
 
 
-__device__ __noinline__ void wide_item(const EngineArgs& a, const float* __restrict__ Ap, const Row* list, int32_t nlist,
+__device__ __noinline__ void wide_item(cargs_t& a_in, const float* __restrict__ Ap, const Row* list, int32_t nlist,
                           int32_t rg, int32_t chunk) {
+    cargs_t& a = uniform_args(a_in);
     WideLds& L = g_lds.wide;
     const int32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int32_t K = a.K, Kp = __builtin_amdgcn_readfirstlane(a.Kp);
@@ -649,7 +662,8 @@ __device__ __forceinline__ void wave_argmax(float& v, int32_t& idx) {
 
 // One wave: the O(K) operations of a task (start step, end-only step,
 // final selection and boundary resolution).
-__device__ __noinline__ void light_row(const EngineArgs& a, const float* __restrict__ Ap, const Row& r) {
+__device__ __noinline__ void light_row(cargs_t& a_in, const float* __restrict__ Ap, const Row& r) {
+    cargs_t& a = uniform_args(a_in);
     const int32_t lane = threadIdx.x & 63;
     SeqInfo& sq = a.seqs[r.seq];
     const int32_t K = a.K, Kp = a.Kp;
@@ -755,19 +769,19 @@ __device__ __forceinline__ BeamRec beam_rec(float* base, int32_t Bc) {
     r.a = reinterpret_cast<int32_t*>(base + 64 + 2 * (int64_t)Bc);
     return r;
 }
-__device__ __forceinline__ BeamRec slot_beam(const EngineArgs& a, int32_t slot, int32_t k) {
+__device__ __forceinline__ BeamRec slot_beam(cargs_t& a, int32_t slot, int32_t k) {
     return beam_rec(a.slot_base + (int64_t)slot * a.slot_floats + k * a.brec, a.Bc);
 }
-__device__ __forceinline__ BeamRec slot_part(const EngineArgs& a, int32_t slot, int32_t parity, int32_t part) {
+__device__ __forceinline__ BeamRec slot_part(cargs_t& a, int32_t slot, int32_t parity, int32_t part) {
     return slot_beam(a, slot, parity * a.bw + part);
 }
-__device__ __forceinline__ BeamRec slot_snap_beam(const EngineArgs& a, int32_t slot) {
+__device__ __forceinline__ BeamRec slot_snap_beam(cargs_t& a, int32_t slot) {
     return slot_beam(a, slot, 2 * a.bw);
 }
-__device__ __forceinline__ BeamRec root_beam(const EngineArgs& a, int64_t root_off, int32_t d) {
+__device__ __forceinline__ BeamRec root_beam(cargs_t& a, int64_t root_off, int32_t d) {
     return beam_rec(a.root_copy + (root_off + d) * a.brec, a.Bc);
 }
-__device__ __forceinline__ int32_t* beam_fallback_flag(const EngineArgs& a, int32_t slot) {
+__device__ __forceinline__ int32_t* beam_fallback_flag(cargs_t& a, int32_t slot) {
     return slot_snap_beam(a, slot).hdr + 1;
 }
 // destinations [lo, hi) of part p of W
@@ -918,7 +932,7 @@ __device__ int32_t beam_select(int32_t n, int32_t B, const float* v, const int32
 
 // The beam of the step whose parts are stored at `parity`, into L.bs/bv/ba.
 // States are clamped to [0, K) (they address rows of log A).
-__device__ int32_t beam_rebuild(const EngineArgs& a, int32_t slot, int32_t parity) {
+__device__ int32_t beam_rebuild(cargs_t& a, int32_t slot, int32_t parity) {
     BeamLds& L = g_lds.beam;
     const int tid = threadIdx.x;
     const int32_t W = a.bw, B = a.B, K = a.K;
@@ -965,11 +979,12 @@ __device__ __forceinline__ int32_t beam_find_lds(const int32_t* bs, int32_t nb, 
     return -1;
 }
 
-__device__ __noinline__ void beam_chain_walk(const EngineArgs& a, const Row& r, int32_t q);
+__device__ __noinline__ void beam_chain_walk(cargs_t& a, const Row& r, int32_t q);
 
 // One part of one beam task's step (parts beyond the first return at once
 // for the single-block operations END and FINAL).
-__device__ __noinline__ void beam_row(const EngineArgs& a, const float* __restrict__ Ap, const Row& r, int32_t part) {
+__device__ __noinline__ void beam_row(cargs_t& a_in, const float* __restrict__ Ap, const Row& r, int32_t part) {
+    cargs_t& a = uniform_args(a_in);
     BeamLds& L = g_lds.beam;
     const int tid = threadIdx.x;
     SeqInfo& sq = a.seqs[r.seq];
@@ -1130,7 +1145,8 @@ __device__ __noinline__ void beam_row(const EngineArgs& a, const float* __restri
 // found in the division's beam (state-sorted), whose score is the anchor
 // alpha and whose anchor is the next state down.  Division records are
 // copied to LDS in chunks (coalesced) and walked there.
-__device__ __noinline__ void beam_chain_walk(const EngineArgs& a, const Row& r, int32_t q) {
+__device__ __noinline__ void beam_chain_walk(cargs_t& a_in, const Row& r, int32_t q) {
+    cargs_t& a = uniform_args(a_in);
     BeamLds& L = g_lds.beam;
     const int tid = threadIdx.x;
     SeqInfo& sq = a.seqs[r.seq];
@@ -1181,7 +1197,8 @@ __device__ __noinline__ void beam_chain_walk(const EngineArgs& a, const Row& r, 
 // with the anchors alpha = Dsnap_d(q*_{e_d}).  Link rows are copied to LDS in
 // chunks (coalesced) and the chain is walked there; the anchors are then
 // gathered in parallel.
-__device__ __noinline__ void dense_finalize(const EngineArgs& a, const Row& r) {
+__device__ __noinline__ void dense_finalize(cargs_t& a_in, const Row& r) {
+    cargs_t& a = uniform_args(a_in);
     EngineLds& lds = g_lds;
     const int tid = threadIdx.x;
     SeqInfo& sq = a.seqs[r.seq];
@@ -1282,7 +1299,7 @@ __device__ __forceinline__ int32_t child_count(const Row& r) {
 
 // src: the list r came from (0 full, 1 light, 2 block rows: beam tasks and
 // the finalize of dense roots and vanilla passes).
-__device__ Next classify(const EngineArgs& a, const Row& r, int src) {
+__device__ Next classify(cargs_t& a, const Row& r, int src) {
     Next x;
     x.list = -1;
     x.freed = x.spawn = 0;
@@ -1331,7 +1348,7 @@ __device__ Next classify(const EngineArgs& a, const Row& r, int src) {
 
 // Children per Alg. 1 (end of a subtask), the P'-way segments of a finished
 // root, or the exact re-decode of a beam subtask that lost its end state.
-__device__ void write_spawns(const EngineArgs& a, const Row& r, int src, int64_t pos) {
+__device__ void write_spawns(cargs_t& a, const Row& r, int src, int64_t pos) {
     const bool beam_end = src == 1 && r.aux == L_BSPAWN;
     if (beam_end || (src == 1 && r.aux == L_END)) {
         if (beam_end && ld_c(beam_fallback_flag(a, clampi(r.slot, a.n_slots)))) {
@@ -1394,7 +1411,8 @@ __device__ void group_scan(int32_t (&v)[N], int32_t (&tot)[N], int32_t (&ws)[kSc
 // (beam tasks to the beam list, the others to the light list).  Called by
 // the whole scheduler block; sl.n_next holds the rows already written for
 // step nxt.
-__device__ __noinline__ void admit(const EngineArgs& a, int nxt) {
+__device__ __noinline__ void admit(cargs_t& a_in, int nxt) {
+    cargs_t& a = uniform_args(a_in);
     SchedLds& sl = g_sched;
     if (threadIdx.x == 0) {
         // water filling: XCD x gets rows up to level L * nblk[x] (its share of
@@ -1474,7 +1492,8 @@ __device__ __noinline__ void admit(const EngineArgs& a, int nxt) {
     __syncthreads();
 }
 
-__device__ __noinline__ void scheduler(const EngineArgs& a, int32_t s) {
+__device__ __noinline__ void scheduler(cargs_t& a_in, int32_t s) {
+    cargs_t& a = uniform_args(a_in);
     SchedLds& sl = g_sched;
     const int cur = s & 1, nxt = cur ^ 1;
     const int x = threadIdx.x / kSchedGroup, tg = threadIdx.x % kSchedGroup;
@@ -1534,7 +1553,7 @@ __device__ __noinline__ void scheduler(const EngineArgs& a, int32_t s) {
 // per-block cache maintenance of the fences to 256 operations per step.
 // Spins are bounded; on overrun the error flag is raised and every block
 // leaves the step loop.
-__device__ bool barrier_arrive_wait(const EngineArgs& a, uint32_t epoch, uint32_t x) {
+__device__ bool barrier_arrive_wait(cargs_t& a, uint32_t epoch, uint32_t x) {
     __shared__ int s_err;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1554,7 +1573,7 @@ __device__ bool barrier_arrive_wait(const EngineArgs& a, uint32_t epoch, uint32_
     return s_err == 0;
 }
 
-__device__ bool barrier_master(const EngineArgs& a, uint32_t epoch) {
+__device__ bool barrier_master(cargs_t& a, uint32_t epoch) {
     __shared__ int s_err;
     __syncthreads();
     int64_t spins = 0;
@@ -1585,7 +1604,7 @@ __device__ bool barrier_master(const EngineArgs& a, uint32_t epoch) {
 // Wide-row phase of a step: items (XCD list, group of 16 rows, 64-column
 // chunk) over the dense rows of every XCD, taken by all blocks of the chip:
 // first by global rank, then claimed from one counter.
-__device__ void run_wide(const EngineArgs& a, const float* __restrict__ Ap, int cur) {
+__device__ void run_wide(cargs_t& a, const float* __restrict__ Ap, int cur) {
     __shared__ int32_t s_item;
     const int32_t nch = a.Kp / kWideCols;
     int32_t nf[kXcd], base[kXcd + 1];
@@ -1621,7 +1640,7 @@ __device__ void run_wide(const EngineArgs& a, const float* __restrict__ Ap, int 
 // beam rows, one per block.  Each phase hands items out from a per-XCD
 // counter; every block (and the scheduler block once its own work is done)
 // takes a first item by rank, then claims until none are left.
-__device__ void run_units(const EngineArgs& a, const float* __restrict__ Ap, uint32_t x, int32_t nx, int32_t rank,
+__device__ void run_units(cargs_t& a, const float* __restrict__ Ap, uint32_t x, int32_t nx, int32_t rank,
                           int cur) {
     EngineLds& lds = g_lds;
     __shared__ int32_t s_unit;
@@ -1691,7 +1710,8 @@ __device__ void run_units(const EngineArgs& a, const float* __restrict__ Ap, uin
 }
 
 extern "C" __global__ __launch_bounds__(kEngBlock) void fv_engine_kernel(const float* __restrict__ Ap,
-                                                                         EngineArgs a) {
+                                                                         const EngineArgs* __restrict__ args) {
+    cargs_t& a = *reinterpret_cast<cargs_t*>(reinterpret_cast<uint64_t>(args));
     const bool is_sched = blockIdx.x == 0;
     const uint32_t x = my_xcd();
     __shared__ int32_t s_rank;
@@ -1753,6 +1773,7 @@ extern "C" __global__ __launch_bounds__(kBlock) void fv_prep_dense_kernel(const 
 // Per-sequence setup and the first step's row list (one block).
 
 extern "C" __global__ __launch_bounds__(kBlock) void fv_setup_kernel(EngineArgs a, SetupArgs sa) {
+    if (threadIdx.x == 0) *sa.args_out = a;
     __shared__ int64_t scan[3][kBlock];
     __shared__ int32_t s_bad;
     const int tid = threadIdx.x;

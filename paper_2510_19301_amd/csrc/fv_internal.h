@@ -156,6 +156,7 @@ struct SetupArgs {
     int64_t host_sum_psi;
     int32_t kind;           // KIND_VANILLA, KIND_ROOT or KIND_BROOT
     int32_t K;
+    EngineArgs* args_out;   // the engine's copy of its arguments (workspace)
 };
 
 // Division points of the first P'-way split: e_d = floor(((d+1) T - 1) / P').
