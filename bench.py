@@ -104,6 +104,40 @@ def _time_method(fv, torch, la, lp, batch, method, P, B, steps, warmup, ws=None)
     return start.elapsed_time(stop) / steps, float(ms.value), ws, int((st != 0).sum())
 
 
+def large_runs(fv, torch, hmm, dev):
+    """One sequence on a large dense HMM: K = 16384 (log A rows
+    Dirichlet(0.05), 1 GiB), T = 10000, log B ~ N(0, 3^2).  Vanilla and FLASH
+    stream all of log A from HBM every step (wide rows); FLASH-BS reads only
+    the B beam rows of log A per step."""
+    wl = hmm.large_dense_workload()
+    K, T = wl.K, int(wl.lengths[0])
+    print(f"[bench] large: K={K} T={T}", file=sys.stderr, flush=True)
+    la = torch.from_numpy(wl.log_a).to(dev)
+    lb = torch.from_numpy(wl.log_b(0)).to(dev)
+    lp = torch.from_numpy(wl.log_pi).to(dev)
+    del wl
+    res = {"workload": f"one sequence, dense K={K} (log A rows Dirichlet(0.05)), T={T}, log B ~ N(0,3^2)"}
+    for method, P, B in (("vanilla", 1, 0), ("flash", 16, 0), ("beam", 16, 16), ("beam", 16, 64), ("beam", 16, 256)):
+        fv.decode(la, lb, lp, method, P=P, B=B)   # warm-up (also sizes the workspace)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        path, score, status = fv.decode(la, lb, lp, method, P=P, B=B)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        key = {"flash": f"flash_P{P}", "vanilla": "vanilla", "beam": f"beam_P{P}_B{B}"}[method]
+        entry = {"ms": round(ms, 1), "state_steps_per_s": T * K / (ms / 1e3), "status": int(status.item()),
+                 "workspace_bytes": fv.workspace_bytes(method, K, [T], P, B)}
+        if method == "vanilla":   # HBM bound: log A (K*K*4 bytes) every step
+            gbs = (T - 1) * K * K * 4 / (ms / 1e3) / 1e9
+            entry["hbm_roofline"] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
+                                     "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 3)}
+        res[key] = entry
+        print(f"[bench] large {key}: {ms:.1f} ms", file=sys.stderr, flush=True)
+    return res
+
+
 def cpu_baseline(wl, budget_s: float):
     """The oracle's vanilla decode on a prefix of the workload's sequences,
     all host cores in parallel (one sequence per thread at a time)."""
@@ -140,8 +174,10 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--P", type=int, default=64, help="FLASH parallelism of the headline run")
-    ap.add_argument("--sweep", default="vanilla,flash:1,flash:4,flash:16",
-                    help="extra methods timed once each (method[:P])")
+    ap.add_argument("--sweep", default="vanilla,flash:1,flash:4,flash:16,beam:16:64,beam:16:256",
+                    help="extra methods timed once each (method[:P[:B]])")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the K=16384, T=10000 single-sequence runs")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--n", type=int, default=256)
@@ -182,26 +218,27 @@ def main():
 
     results = {}
     ws = None
-    runs = [("flash", args.P, args.steps, args.warmup)]
+    runs = [("flash", args.P, 0, args.steps, args.warmup)]
     for item in [s for s in args.sweep.split(",") if s]:
-        name, _, p = item.partition(":")
-        runs.append((name, int(p or 1), 1, 1))
-    for method, P, steps, warmup in runs:
-        print(f"[bench] {method} P={P}: warmup {warmup}, timed {steps}", file=sys.stderr, flush=True)
-        ms, eng_ms, ws_new, bad = _time_method(fv, torch, la, lp, batch, method, P, 0, steps, warmup)
+        parts = item.split(":")
+        runs.append((parts[0], int(parts[1]) if len(parts) > 1 else 1,
+                     int(parts[2]) if len(parts) > 2 else 0, 1, 1))
+    for method, P, B, steps, warmup in runs:
+        print(f"[bench] {method} P={P} B={B}: warmup {warmup}, timed {steps}", file=sys.stderr, flush=True)
+        ms, eng_ms, ws_new, bad = _time_method(fv, torch, la, lp, batch, method, P, B, steps, warmup)
         if ws is None or ws_new.numel() > ws.numel():
             ws = ws_new
-        if method == "flash":
-            cand = sum(flash_candidates(int(T), P, K) for T in wl.lengths)
-        else:
-            cand = sum(vanilla_candidates(int(T), K) for T in wl.lengths)
-        results[f"{method}_P{P}" if method == "flash" else method] = {
-            "ms_per_step": round(ms, 3), "engine_ms": round(eng_ms, 3),
-            "state_steps_per_s": state_steps / (ms / 1e3),
-            "candidates": cand, "candidates_per_s": cand / (eng_ms / 1e3),
-            "workspace_bytes": fv.workspace_bytes(method, K, wl.lengths, P),
-            "bad_status": bad}
-        print(f"[bench] {method} P={P}: {ms:.2f} ms/step, engine {eng_ms:.2f} ms", file=sys.stderr, flush=True)
+        entry = {"ms_per_step": round(ms, 3), "engine_ms": round(eng_ms, 3),
+                 "state_steps_per_s": state_steps / (ms / 1e3),
+                 "workspace_bytes": fv.workspace_bytes(method, K, wl.lengths, P, B),
+                 "bad_status": bad}
+        if method in ("flash", "vanilla"):
+            cand = (sum(flash_candidates(int(T), P, K) for T in wl.lengths) if method == "flash"
+                    else sum(vanilla_candidates(int(T), K) for T in wl.lengths))
+            entry.update({"candidates": cand, "candidates_per_s": cand / (eng_ms / 1e3)})
+        key = {"flash": f"flash_P{P}", "vanilla": "vanilla", "beam": f"beam_P{P}_B{B}"}[method]
+        results[key] = entry
+        print(f"[bench] {method} P={P} B={B}: {ms:.2f} ms/step, engine {eng_ms:.2f} ms", file=sys.stderr, flush=True)
 
     head = results[f"flash_P{args.P}"]
     ach_tflops = head["candidates"] * 2 / (head["engine_ms"] / 1e3) / 1e12
@@ -224,6 +261,10 @@ def main():
                      "frac_of_fp32_vector_peak": round(ach_tflops / PEAK_FP32_VECTOR_TFLOPS, 4)},
         "methods": results,
     }
+    if not args.no_large:
+        del lbs, batch, ws
+        torch.cuda.empty_cache()
+        out["large"] = large_runs(fv, torch, hmm, dev)
     if not args.no_cpu:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)

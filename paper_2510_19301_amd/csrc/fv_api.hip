@@ -100,9 +100,11 @@ fv_status plan_dense(int32_t method, int32_t K, const int32_t* T_host, int32_t n
         L.Bc = (int32_t)round_up(B, 64);
         L.brec = 64 + 3 * (int64_t)L.Bc;
         // parts per step: at most 4096 destinations per part, at most 8192
-        // candidates to merge, otherwise about 256 destinations per part (<= 32)
+        // candidates to merge; a batch that fills the device by itself keeps
+        // one part per task, a small one spreads each task over up to 32
+        // blocks (about 256 destinations per part)
         const int32_t Kp = (int32_t)round_up(K, kKAlign);
-        int32_t W = std::min<int32_t>(32, std::min<int32_t>(Kp / 256, 8192 / B));
+        int32_t W = n_seqs >= 64 ? 1 : std::min<int32_t>(32, std::min<int32_t>(Kp / 256, 8192 / B));
         W = std::max<int32_t>(W, (Kp + 4095) / 4096);
         W = std::max<int32_t>(1, std::min<int32_t>(W, K));
         if (W * B > 8192 || (K + W - 1) / W > 4096)

@@ -1044,9 +1044,23 @@ __device__ __noinline__ void beam_row(cargs_t& a_in, const float* __restrict__ A
             const int32_t j = jlo + k;
             float c = -INFINITY;
             int32_t w = -1;
-            for (int32_t b = 0; b < nb; ++b) {
-                const float x = L.bv[b] + Ag[(int64_t)L.bs[b] * Kp + j];
-                if (w < 0 || x > c) { c = x; w = b; }
+            // 16 loads in flight, then the candidates in beam order; a beam
+            // entry's state and score are the same for every lane (scalars)
+            for (int32_t b0 = 0; b0 < nb; b0 += 16) {
+                float av[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    const int32_t sb = __builtin_amdgcn_readfirstlane(L.bs[min(b0 + u, nb - 1)]);
+                    av[u] = Ag[(int64_t)sb * Kp + j];
+                }
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    if (b0 + u < nb) {
+                        const float x = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
+                                            __builtin_bit_cast(int32_t, L.bv[b0 + u]))) + av[u];
+                        if (w < 0 || x > c) { c = x; w = b0 + u; }
+                    }
+                }
             }
             L.sc[k] = w < 0 ? -INFINITY : c + bt[j];
             L.an[k] = w < 0 ? -1 : (mode == 1 ? L.bs[w] : (mode == 2 ? L.ba[w] : -1));
