@@ -165,6 +165,7 @@ struct TileLds {
 constexpr int32_t kWideRows = 16;
 constexpr int32_t kWideCols = 64;
 constexpr int32_t kWideStage = 64;   // predecessors staged per LDS refill (4 groups)
+constexpr int32_t kLocalColRows = 40;  // an XCD with at most this many dense rows uses column items
 
 struct WideLds {
     float area[kEngWaves][2 * kWideRows * kWideCols];   // per wave: staged scores, later (max, group)
@@ -535,7 +536,7 @@ __device__ __noinline__ void dense_tile(cargs_t& a_in, const float* __restrict__
 
 
 __device__ __noinline__ void wide_item(cargs_t& a_in, const float* __restrict__ Ap, const Row* list, int32_t nlist,
-                          int32_t rg, int32_t chunk) {
+                          int32_t rg, int32_t chunk, int32_t coh) {
     cargs_t& a = uniform_args(a_in);
     WideLds& L = g_lds.wide;
     const int32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -567,7 +568,7 @@ __device__ __noinline__ void wide_item(cargs_t& a_in, const float* __restrict__ 
             if (r < R && lane < n) {
                 const Row& rr = L.rows[r];
                 const float* dp = slot_delta(a, clampi(rr.slot, a.n_slots), (rr.t - 1) & 1);
-                stage[r * kWideStage + lane] = ld_cg(dp + i0 + lane);
+                stage[r * kWideStage + lane] = coh ? ld_cg(dp + i0 + lane) : as_global(dp)[i0 + lane];
             }
         }
         for (int32_t k0 = 0; k0 < n; k0 += kGroup) {
@@ -615,7 +616,7 @@ __device__ __noinline__ void wide_item(cargs_t& a_in, const float* __restrict__ 
 #pragma unroll
             for (int k = 0; k < kGroup; ++k) {
                 av[k] = Ag[(int64_t)(src0 + k) * Kp + j];
-                dv[k] = ld_cg(dprev + src0 + k);
+                dv[k] = coh ? ld_cg(dprev + src0 + k) : as_global(dprev)[src0 + k];
             }
             int32_t p = -1;
 #pragma unroll
@@ -627,7 +628,10 @@ __device__ __noinline__ void wide_item(cargs_t& a_in, const float* __restrict__ 
         }
         int32_t anc = 0;
         if (f & F_ANC_FIRST) anc = psi;
-        else if (f & F_ANC_CHAIN) anc = clampi(ld_c(slot_anc(a, slot, (t - 1) & 1) + psi), K);
+        else if (f & F_ANC_CHAIN) {
+            const int32_t* ap = slot_anc(a, slot, (t - 1) & 1) + psi;
+            anc = clampi(coh ? ld_c(ap) : *ap, K);
+        }
         const float dnew = val + bpre;
         slot_delta(a, slot, t & 1)[j] = dnew;
         if (f & F_PSI_TABLE) a.psi16[rr.off + (int64_t)t * K + j] = (uint16_t)psi;
@@ -1496,6 +1500,7 @@ __device__ __noinline__ void admit(cargs_t& a_in, int nxt) {
                 all += sl.n_next[y][k];
             }
             st_c(&a.st->claim[nxt][y][0], 0);
+            st_c(&a.st->claim[nxt][y][8], 0);
             st_c(&a.st->claim[nxt][y][16], 0);
         }
         st_c(&a.st->wclaim[nxt][0], 0);
@@ -1642,7 +1647,7 @@ __device__ void run_wide(cargs_t& a, const float* __restrict__ Ap, int cur) {
         int y = 0;
         while (item >= base[y + 1]) ++y;
         const int32_t rem = item - base[y];
-        wide_item(a, Ap, list_full(a, cur, y), nf[y], rem / nch, rem % nch);
+        wide_item(a, Ap, list_full(a, cur, y), nf[y], rem / nch, rem % nch, 1);
         item = -1;
     }
 }
@@ -1661,8 +1666,31 @@ __device__ void run_units(cargs_t& a, const float* __restrict__ Ap, uint32_t x, 
     const int32_t nf = ld_c(&a.st->cnt[cur][x][0]);
     const int32_t nl = ld_c(&a.st->cnt[cur][x][1]);
     const int32_t nbm = ld_c(&a.st->cnt[cur][x][2]);
-    const int32_t n_tiles = a.wide ? 0 : ((nf + kTileRows - 1) / kTileRows) * (a.Kp / kTileCols);
+    // few rows on this XCD: lane tiles would run mostly empty, so its rows are
+    // computed as column items (lanes = destinations) by its own blocks
+    const bool local_cols = !a.wide && nf > 0 && nf <= kLocalColRows;
+    const int32_t n_tiles = (a.wide || local_cols) ? 0 : ((nf + kTileRows - 1) / kTileRows) * (a.Kp / kTileCols);
     if (a.wide) run_wide(a, Ap, cur);
+    if (local_cols) {
+        __shared__ int32_t s_citem;
+        const int32_t nch = a.Kp / kWideCols;
+        const int32_t total = ((nf + kWideRows - 1) / kWideRows) * nch;
+        const Row* Fl = list_full(a, cur, x);
+        int32_t item = rank;
+        for (;;) {
+            if (item < 0) {
+                if (threadIdx.x == 0)
+                    s_citem = nx + __hip_atomic_fetch_add(&a.st->claim[cur][x][8], 1, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT);
+                __syncthreads();
+                item = s_citem;
+                __syncthreads();
+            }
+            if (item >= total) break;
+            wide_item(a, Ap, Fl, nf, item / nch, item % nch, 0);
+            item = -1;
+        }
+    }
     // waves per tile: 4 (one per SIMD) while every group gets two tiles or
     // more, else more waves per tile (fewer, faster groups); at most one wave
     // per 16 predecessors.  Decided from a nominal XCD of 32 blocks, so that
