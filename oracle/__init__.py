@@ -59,9 +59,11 @@ def _load():
         lib.fvo_flash.argtypes = [i32, i32, i32, vp, vp, vp, i64, vp, vp, u64, C.POINTER(Stats), vp]
         lib.fvo_beam.argtypes = [i32, i32, i32, i32, vp, vp, vp, i64, vp, vp, vp, u64,
                                  C.POINTER(Stats), vp]
+        lib.fvo_beam_csr.argtypes = [i32, i32, i32, i32, vp, vp, vp, vp, vp, i64, vp, vp, vp, u64,
+                                     C.POINTER(Stats), vp]
         lib.fvo_backward.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp, vp, i32]
         for fn in (lib.fvo_vanilla, lib.fvo_vanilla_f64, lib.fvo_vanilla_csr, lib.fvo_flash,
-                   lib.fvo_beam, lib.fvo_backward, lib.fvo_gather_emissions):
+                   lib.fvo_beam, lib.fvo_beam_csr, lib.fvo_backward, lib.fvo_gather_emissions):
             fn.restype = C.c_int
         _lib = lib
         return lib
@@ -171,6 +173,30 @@ def beam(log_pi, log_a, log_b, B, P, shuffle_seed=0):
     st = Stats()
     rc = lib.fvo_beam(K, T, int(B), int(P), _p(log_pi), _p(log_a), _p(log_b), ld, _p(path),
                       _p(score), _p(root), int(shuffle_seed), C.byref(st), _p(nfb))
+    d = {k: getattr(st, k) for k, _ in Stats._fields_}
+    d["root_score"] = root[0]
+    d["fallbacks"] = int(nfb[0])
+    return path, score[0], rc, d
+
+
+def beam_csr(log_pi, row_ptr, col, val, log_b, B, P, shuffle_seed=0):
+    """FLASH-BS on a CSR model (out-edges; missing edges are -inf).  Returns
+    (path, score, status, stats dict) like beam()."""
+    lib = _load()
+    row_ptr = np.ascontiguousarray(row_ptr, np.int32)
+    col = np.ascontiguousarray(col, np.int32)
+    val = _f32(val)
+    log_b = np.ascontiguousarray(log_b, np.float32)
+    log_pi = _f32(log_pi)
+    K, T = row_ptr.shape[0] - 1, log_b.shape[0]
+    path = np.empty(T, np.int32)
+    score = np.zeros(1, np.float32)
+    root = np.zeros(1, np.float32)
+    nfb = np.zeros(1, np.int32)
+    st = Stats()
+    rc = lib.fvo_beam_csr(K, T, int(B), int(P), _p(log_pi), _p(row_ptr), _p(col), _p(val), _p(log_b),
+                          log_b.shape[1], _p(path), _p(score), _p(root), int(shuffle_seed), C.byref(st),
+                          _p(nfb))
     d = {k: getattr(st, k) for k, _ in Stats._fields_}
     d["root_score"] = root[0]
     d["fallbacks"] = int(nfb[0])

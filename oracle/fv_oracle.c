@@ -18,6 +18,7 @@
  *   fvo_rescore      re-sum of one path's log score         (Sec. III-A)
  *   fvo_flash        non-recursive D&C with pruning         (Alg. 1, Alg. 2, Sec. V-A/V-B)
  *   fvo_beam         FLASH-BS dynamic beam                  (Sec. V-C)
+ *   fvo_beam_csr     same, transitions as CSR out-edges     (Sec. V-C)
  *   fvo_backward     subgradient of the Viterbi score       (score is a sum of
  *                    the decoded path's log-scores, Sec. III-A)
  *   fvo_gather_emissions  log B_t[j] = log e[j, x_t]        (Sec. III, the HMM triplet)
@@ -248,6 +249,75 @@ static void dense_step(int K, const float* in, const float* log_a, const float* 
         }
     }
     for (int j = 0; j < K; ++j) out[j] = best[j] + b_t[j];
+}
+
+/* Transition model seen by FLASH-BS: dense log A, or CSR out-edges whose
+ * missing entries are -inf (Sec. III-A's A with zero probabilities).  With
+ * several edges i -> j, log A(i, j) is the largest of them. */
+typedef struct {
+    int K;
+    const float* log_a;       /* dense [K*K], NULL for CSR */
+    const int32_t* row_ptr;   /* CSR: out-edges of source i are [row_ptr[i], row_ptr[i+1]) */
+    const int32_t* col;
+    const float* val;
+} fvo_model;
+
+static float model_a(const fvo_model* M, int i, int j)
+{
+    if (M->log_a) return M->log_a[(size_t)i * M->K + j];
+    float a = -INFINITY;
+    for (int e = M->row_ptr[i]; e < M->row_ptr[i + 1]; ++e)
+        if (M->col[e] == j && M->val[e] > a) a = M->val[e];
+    return a;
+}
+
+/* sc[j] = (alpha + log A(q, j)) + b_m[j] for every j: the anchored start
+ * of a segment (Def. 3).  CSR: -inf except at q's out-neighbours. */
+static void model_anchor_row(const fvo_model* M, int q, float alpha, const float* b_m, float* sc)
+{
+    if (!M->log_a) {   /* only q's out-neighbours are finite */
+        for (int j = 0; j < M->K; ++j) sc[j] = -INFINITY;
+        for (int e = M->row_ptr[q]; e < M->row_ptr[q + 1]; ++e) {
+            int j = M->col[e];
+            float c = alpha + model_a(M, q, j);
+            sc[j] = c + b_m[j];
+        }
+        return;
+    }
+    for (int j = 0; j < M->K; ++j) {
+        float c = alpha + model_a(M, q, j);
+        sc[j] = c + b_m[j];
+    }
+}
+
+/* Exact step (the fallback re-decode): dense_step, or for CSR the scan of
+ * vanilla_csr: sources upward, each source's edges in order, the first
+ * edge giving a destination's initial value; pre[j] = 0 without in-edge. */
+static void model_exact_step(const fvo_model* M, const float* in, const float* b_t, float* out,
+                             int32_t* pre, float* best, uint8_t* seen)
+{
+    const int K = M->K;
+    if (M->log_a) { dense_step(K, in, M->log_a, b_t, out, pre, best); return; }
+    for (int j = 0; j < K; ++j) { best[j] = -INFINITY; pre[j] = 0; seen[j] = 0; }
+    for (int i = 0; i < K; ++i) {
+        for (int e = M->row_ptr[i]; e < M->row_ptr[i + 1]; ++e) {
+            int j = M->col[e];
+            float c = in[i] + M->val[e];
+            if (!seen[j] || c > best[j]) { best[j] = c; pre[j] = i; seen[j] = 1; }
+        }
+    }
+    for (int j = 0; j < K; ++j) out[j] = best[j] + b_t[j];
+}
+
+static float model_rescore(const fvo_model* M, int T, const float* log_pi, const float* log_b,
+                           int64_t ld, const int32_t* path)
+{
+    float s = log_pi ? log_pi[path[0]] + log_b[path[0]] : log_b[path[0]];
+    for (int t = 1; t < T; ++t) {
+        float c = s + model_a(M, path[t - 1], path[t]);
+        s = c + log_b[(size_t)t * ld + path[t]];
+    }
+    return s;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -483,11 +553,38 @@ static void beam_from_scores(int K, int B, const float* sc, const int32_t* anc,
 }
 
 /* one beam step over all destinations.  anc_mode: 0 none, 1 anc = predecessor
- * state, 2 anc = predecessor's anc. */
-static void beam_step(int K, int B, const fvo_beam_t* in, const float* log_a,
-                      const float* b_t, int anc_mode, fvo_beam_t* out, int64_t* cand)
+ * state, 2 anc = predecessor's anc.  A CSR model pushes the beam entries'
+ * out-edges instead (entries in state order, each entry's edges in order,
+ * a strictly larger candidate replacing a destination's current one): the
+ * same maxima and predecessors as the dense scan with -inf for missing
+ * edges, whose destinations never enter the beam.  c, w, seen: K-entry
+ * scratch. */
+static void beam_step(const fvo_model* M, int B, const fvo_beam_t* in, const float* b_t, int anc_mode,
+                      fvo_beam_t* out, int64_t* cand, float* c, int32_t* w, uint8_t* seen)
 {
+    const int K = M->K;
+    const float* log_a = M->log_a;
     out->n = 0;
+    if (!log_a) {
+        for (int j = 0; j < K; ++j) seen[j] = 0;
+        for (int b = 0; b < in->n; ++b) {
+            int s = in->e[b].s;
+            for (int e = M->row_ptr[s]; e < M->row_ptr[s + 1]; ++e) {
+                int j = M->col[e];
+                float x = in->e[b].v + M->val[e];
+                if (!seen[j] || x > c[j]) { c[j] = x; w[j] = b; seen[j] = 1; }
+                ++*cand;
+            }
+        }
+        for (int j = 0; j < K; ++j) {
+            if (!seen[j]) continue;
+            int b = w[j];
+            fvo_ent y = {j, c[j] + b_t[j], anc_mode == 1 ? in->e[b].s : (anc_mode == 2 ? in->e[b].a : -1)};
+            topb_insert(out->e, &out->n, B, y);
+        }
+        qsort(out->e, (size_t)out->n, sizeof(fvo_ent), ent_by_state);
+        return;
+    }
     for (int j = 0; j < K; ++j) {
         if (in->n == 0) break;
         float c = in->e[0].v + log_a[(size_t)in->e[0].s * K + j];
@@ -509,11 +606,12 @@ static const fvo_ent* beam_find(const fvo_beam_t* b, int s)
     return NULL;
 }
 
-int fvo_beam(int K, int T, int B, int P, const float* log_pi, const float* log_a,
-             const float* log_b, int64_t ld, int32_t* path, float* score,
-             float* root_score, uint64_t shuffle_seed, fvo_stats* st, int32_t* n_fallback)
+static int beam_impl(const fvo_model* M, int T, int B, int P, const float* log_pi,
+                     const float* log_b, int64_t ld, int32_t* path, float* score,
+                     float* root_score, uint64_t shuffle_seed, fvo_stats* st, int32_t* n_fallback)
 {
-    if (K < 1 || T < 1 || B < 1 || ld < K || !log_a || !log_b || !path || !score)
+    const int K = M->K;
+    if (K < 1 || T < 1 || B < 1 || ld < K || !log_b || !path || !score)
         return FVO_INVALID;
     if (B > K) B = K;
     fvo_stats local;
@@ -530,6 +628,9 @@ int fvo_beam(int K, int T, int B, int P, const float* log_pi, const float* log_a
     fvo_beam_t* rsnap = (fvo_beam_t*)malloc(sizeof(fvo_beam_t) * (pp > 1 ? pp - 1 : 1));
     for (int d = 0; d < pp - 1; ++d) { rsnap[d].e = (fvo_ent*)malloc(sizeof(fvo_ent) * B); rsnap[d].n = 0; }
     float* sc = (float*)malloc(sizeof(float) * K);
+    float* cbuf = (float*)malloc(sizeof(float) * K);
+    int32_t* wbuf = (int32_t*)malloc(sizeof(int32_t) * K);
+    uint8_t* seen = (uint8_t*)malloc((size_t)K);
     uint8_t* written = (uint8_t*)calloc((size_t)T, 1);
     int rc = FVO_OK;
 
@@ -545,7 +646,7 @@ int fvo_beam(int K, int T, int B, int P, const float* log_pi, const float* log_a
         int after_div = 0;
         for (int d = 0; d < pp - 1; ++d) if (e[d] == t - 1) after_div = 1;
         int mode = after_div ? 1 : ((pp > 1 && t > e[0] + 1) ? 2 : 0);
-        beam_step(K, B, &cur, log_a, log_b + (size_t)t * ld, mode, &nxt, &st->candidates);
+        beam_step(M, B, &cur, log_b + (size_t)t * ld, mode, &nxt, &st->candidates, cbuf, wbuf, seen);
         fvo_beam_t tb = cur; cur = nxt; nxt = tb;
         if (d_next < pp - 1 && e[d_next] == t) {
             memcpy(rsnap[d_next].e, cur.e, sizeof(fvo_ent) * cur.n); rsnap[d_next].n = cur.n;
@@ -600,16 +701,14 @@ int fvo_beam(int K, int T, int B, int P, const float* log_pi, const float* log_a
             if (m == 0) {
                 for (int i = 0; i < K; ++i) sc[i] = log_pi ? log_pi[i] + log_b[i] : log_b[i];
             } else {
-                const float* row = log_a + (size_t)tk.q_prev * K;
-                const float* b_m = log_b + (size_t)m * ld;
-                for (int i = 0; i < K; ++i) { float c = tk.alpha + row[i]; sc[i] = c + b_m[i]; }
+                model_anchor_row(M, tk.q_prev, tk.alpha, log_b + (size_t)m * ld, sc);
                 st->candidates += K;
             }
             beam_from_scores(K, B, sc, NULL, &cur);
             if (tmid == m) { memcpy(snap.e, cur.e, sizeof(fvo_ent) * cur.n); snap.n = cur.n; }
             for (int t = m + 1; t < n; ++t) {
                 int mode = t == tmid + 1 ? 1 : (t > tmid + 1 ? 2 : 0);
-                beam_step(K, B, &cur, log_a, log_b + (size_t)t * ld, mode, &nxt, &st->candidates);
+                beam_step(M, B, &cur, log_b + (size_t)t * ld, mode, &nxt, &st->candidates, cbuf, wbuf, seen);
                 fvo_beam_t tb = cur; cur = nxt; nxt = tb;
                 if (t == tmid) { memcpy(snap.e, cur.e, sizeof(fvo_ent) * cur.n); snap.n = cur.n; }
             }
@@ -618,10 +717,10 @@ int fvo_beam(int K, int T, int B, int P, const float* log_pi, const float* log_a
             float amid = NAN;
             int ok = 0;
             if (cur.n > 0) {
-                float c = cur.e[0].v + log_a[(size_t)cur.e[0].s * K + qn];
+                float c = cur.e[0].v + model_a(M, cur.e[0].s, qn);
                 int w = 0;
                 for (int b = 1; b < cur.n; ++b) {
-                    float x = cur.e[b].v + log_a[(size_t)cur.e[b].s * K + qn];
+                    float x = cur.e[b].v + model_a(M, cur.e[b].s, qn);
                     if (x > c) { c = x; w = b; }
                 }
                 st->candidates += cur.n;
@@ -639,14 +738,12 @@ int fvo_beam(int K, int T, int B, int P, const float* log_pi, const float* log_a
                 if (m == 0) {
                     for (int i = 0; i < K; ++i) opt[i] = log_pi ? log_pi[i] + log_b[i] : log_b[i];
                 } else {
-                    const float* row = log_a + (size_t)tk.q_prev * K;
-                    const float* b_m = log_b + (size_t)m * ld;
-                    for (int i = 0; i < K; ++i) { float c = tk.alpha + row[i]; opt[i] = c + b_m[i]; }
+                    model_anchor_row(M, tk.q_prev, tk.alpha, log_b + (size_t)m * ld, opt);
                 }
                 float* exsnap = sc;
                 if (tmid == m) memcpy(exsnap, opt, sizeof(float) * K);
                 for (int t = m + 1; t <= n; ++t) {
-                    dense_step(K, opt, log_a, log_b + (size_t)t * ld, opt2, pre, best);
+                    model_exact_step(M, opt, log_b + (size_t)t * ld, opt2, pre, best, seen);
                     st->candidates += (int64_t)K * K;
                     if (t == tmid + 1) for (int j = 0; j < K; ++j) mid2[j] = pre[j];
                     else if (t > tmid + 1) for (int j = 0; j < K; ++j) mid2[j] = mid[pre[j]];
@@ -674,13 +771,34 @@ int fvo_beam(int K, int T, int B, int P, const float* log_pi, const float* log_a
         free(opt); free(opt2); free(best); free(pre); free(mid); free(mid2);
         free(queue.v);
         for (int t = 0; t < T; ++t) if (!written[t]) st->resolved_twice += 1000000;
-        *score = fvo_rescore(K, T, log_pi, log_a, log_b, ld, path);
+        *score = model_rescore(M, T, log_pi, log_b, ld, path);
     }
 done:
     free(cur.e); free(nxt.e); free(snap.e);
     for (int d = 0; d < pp - 1; ++d) free(rsnap[d].e);
-    free(rsnap); free(sc); free(written); free(e);
+    free(rsnap); free(sc); free(cbuf); free(wbuf); free(seen); free(written); free(e);
     return rc;
+}
+
+int fvo_beam(int K, int T, int B, int P, const float* log_pi, const float* log_a,
+             const float* log_b, int64_t ld, int32_t* path, float* score,
+             float* root_score, uint64_t shuffle_seed, fvo_stats* st, int32_t* n_fallback)
+{
+    if (!log_a) return FVO_INVALID;
+    fvo_model M = {K, log_a, NULL, NULL, NULL};
+    return beam_impl(&M, T, B, P, log_pi, log_b, ld, path, score, root_score, shuffle_seed, st, n_fallback);
+}
+
+/* FLASH-BS on a CSR model (out-edges row_ptr[K+1], col, val; missing edges
+ * -inf): the same procedure, each step pushing the beam's out-edges. */
+int fvo_beam_csr(int K, int T, int B, int P, const float* log_pi, const int32_t* row_ptr,
+                 const int32_t* col, const float* val, const float* log_b, int64_t ld,
+                 int32_t* path, float* score, float* root_score, uint64_t shuffle_seed,
+                 fvo_stats* st, int32_t* n_fallback)
+{
+    if (!row_ptr) return FVO_INVALID;
+    fvo_model M = {K, NULL, row_ptr, col, val};
+    return beam_impl(&M, T, B, P, log_pi, log_b, ld, path, score, root_score, shuffle_seed, st, n_fallback);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -564,3 +564,55 @@ def test_discrete_hmm_is_deterministic():
     b = hmm.discrete_hmm(K=16, V=8, T=50, seed=9)
     assert (a.obs == b.obs).all() and (a.log_a == b.log_a).all()
     assert a.obs.min() >= 0 and a.obs.max() < 8
+
+
+def _dense_from_csr(K, row_ptr, col, val):
+    """log A with -inf for missing edges; duplicates keep their largest value."""
+    la = np.full((K, K), -np.inf, np.float32)
+    for i in range(K):
+        for e in range(row_ptr[i], row_ptr[i + 1]):
+            la[i, col[e]] = max(la[i, col[e]], val[e])
+    return la
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_beam_csr_matches_dense_beam(seed):
+    """FLASH-BS on CSR out-edges (push) equals the dense procedure on the
+    same matrix with -inf entries, for every B and P, duplicates included."""
+    K, T = 15, 37
+    lp, rp, col, val, lb = hmm.random_csr(K, T, seed, deg_lo=0, deg_hi=4, integer=seed % 2 == 0,
+                                          dup_frac=0.2 if seed % 3 == 0 else 0.0)
+    la = _dense_from_csr(K, rp, col, val)
+    for B in (1, 2, 4, 14, 15):
+        for P in (1, 3, 8):
+            a = oracle.beam(lp, la, lb, B, P)
+            b = oracle.beam_csr(lp, rp, col, val, lb, B, P)
+            assert a[2] == b[2] and (a[0] == b[0]).all() and _bits(a[1]) == _bits(b[1]), (B, P)
+            assert a[3]["fallbacks"] == b[3]["fallbacks"]
+
+
+def test_beam_csr_full_width_is_vanilla_csr():
+    lp, rp, col, val, lb = hmm.random_csr(30, 50, 3, deg_lo=1, deg_hi=5)
+    po, so, rc = oracle.vanilla_csr(lp, rp, col, val, lb)
+    for P in (1, 4, 50):
+        p, s, r, _ = oracle.beam_csr(lp, rp, col, val, lb, 30, P)
+        assert r == rc and (p == po).all() and _bits(s) == _bits(so)
+
+
+def test_vanilla_csr_duplicates_take_the_largest_edge():
+    """Parallel edges i -> j act as one edge with the largest score (the
+    dense form's entry), on an instance where brute force is feasible."""
+    from itertools import product
+    K, T = 4, 5
+    lp, rp, col, val, lb = hmm.random_csr(K, T, 9, deg_lo=1, deg_hi=3, dup_frac=0.5)
+    la = _dense_from_csr(K, rp, col, val).astype(np.float64)
+    best, arg = -np.inf, None
+    for q in product(range(K), repeat=T):   # first maximum in lexicographic order
+        s = lp[q[0]] + lb[0, q[0]] + sum(la[q[t - 1], q[t]] + lb[t, q[t]] for t in range(1, T))
+        if s > best:
+            best, arg = s, q
+    p, s, rc = oracle.vanilla_csr(lp, rp, col, val, lb)
+    assert rc == oracle.OK and abs(s - best) < 1e-4
+    # the same path as the dense oracle (ties broken identically)
+    pd, sd, _ = oracle.vanilla(lp, la.astype(np.float32), lb)
+    assert (p == pd).all() and _bits(s) == _bits(sd)

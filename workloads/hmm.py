@@ -203,3 +203,118 @@ def sparse_integer_instance(seed: int):
     lb = r.integers(-4, 1, (T, K)).astype(np.float32)
     return lp, la, lb
 
+
+
+def random_csr(K: int, T: int, seed: int, deg_lo: int = 0, deg_hi: int = 6, integer: bool = False,
+               dup_frac: float = 0.0, self_loops: bool = True, with_pi: bool = True,
+               lo: int = -4, hi: int = 0):
+    """Small random sparse instance (log_pi, row_ptr, col, val, log_b) for
+    tests.  Source i gets a degree in [deg_lo, deg_hi] and random
+    destinations in random order within its row; dup_frac of the edges repeat
+    an earlier destination of the same row (with their own value); with
+    self_loops every row also holds i -> i.  integer=True draws small
+    integers (frequent exact ties, exact sums)."""
+    r = _rng(seed, 11, K, T)
+    rows = []
+    for i in range(K):
+        d = int(r.integers(deg_lo, deg_hi + 1))
+        js = list(r.choice(K, size=min(d, K), replace=False)) if d > 0 else []
+        if self_loops and i not in js:
+            js.insert(int(r.integers(0, len(js) + 1)), i)
+        n_dup = int(round(dup_frac * len(js)))
+        for _ in range(n_dup):
+            js.insert(int(r.integers(0, len(js) + 1)), js[int(r.integers(0, len(js)))])
+        rows.append(js)
+    row_ptr = np.zeros(K + 1, np.int32)
+    row_ptr[1:] = np.cumsum([len(x) for x in rows])
+    col = np.array([j for x in rows for j in x], np.int32)
+    nnz = int(col.shape[0])
+    if integer:
+        val = r.integers(lo, hi + 1, size=nnz).astype(np.float32)
+        log_b = r.integers(lo, hi + 1, size=(T, K)).astype(np.float32)
+        log_pi = r.integers(lo, hi + 1, size=K).astype(np.float32)
+    else:
+        val = (r.standard_normal(nnz) * 1.5 - 2.0).astype(np.float32)
+        log_b = (r.standard_normal((T, K)) * 2.0).astype(np.float32)
+        log_pi = (r.standard_normal(K) - 3.0).astype(np.float32)
+    return (log_pi if with_pi else None), row_ptr, col, val, log_b
+
+
+@dataclass
+class MapMatching:
+    """Map-matching-shaped sparse HMM.  K states uniform in the unit square;
+    state i's out-edges go to its 8 nearest neighbours and itself with
+    log-probability -d/sigma_a log-normalised over the 9 (float64, then
+    float32); trajectories are random walks on the graph (each step to a
+    uniformly chosen neighbour other than the state itself) observed through
+    GPS points = position + N(0, sigma_gps^2) per axis; the emission score of
+    state j at time t is log N(dist(state j, gps_t); 0, sigma_gps^2)."""
+    K: int
+    xy: np.ndarray            # [K, 2] float64
+    row_ptr: np.ndarray       # [K+1] int32, columns sorted within a row
+    col: np.ndarray           # [9K] int32
+    val: np.ndarray           # [9K] float32
+    log_pi: np.ndarray        # [K] uniform
+    lengths: np.ndarray       # [n] int32
+    seed: int
+    sigma_gps: float
+
+    @property
+    def n(self) -> int:
+        return int(self.lengths.shape[0])
+
+    def total_steps(self) -> int:
+        return int(self.lengths.astype(np.int64).sum())
+
+    def gps(self, b: int) -> np.ndarray:
+        """float64 [T_b, 2] observations of trajectory b (its own stream)."""
+        r = _rng(self.seed, 20, b)
+        T = int(self.lengths[b])
+        s = int(r.integers(0, self.K))
+        pts = np.empty((T, 2), np.float64)
+        for t in range(T):
+            pts[t] = self.xy[s]
+            nb = [j for j in self.col[self.row_ptr[s]:self.row_ptr[s + 1]] if j != s]
+            s = int(nb[int(r.integers(0, len(nb)))])
+        return pts + r.standard_normal((T, 2)) * self.sigma_gps
+
+    def log_b(self, b: int, device="cpu", t0: int = 0, t1: int | None = None):
+        """float32 [t1 - t0, K] torch tensor of emission scores on `device`
+        (float64 arithmetic, one rounding per elementwise op, then float32)."""
+        import torch
+        g = self.gps(b)[t0:t1]
+        xy = torch.from_numpy(self.xy).to(device)
+        out = torch.empty((g.shape[0], self.K), dtype=torch.float32, device=device)
+        s2 = self.sigma_gps * self.sigma_gps
+        scale = -1.0 / (2.0 * s2)
+        norm = math.log(self.sigma_gps * math.sqrt(2.0 * math.pi))
+        for c0 in range(0, g.shape[0], 128):
+            gp = torch.from_numpy(g[c0:c0 + 128]).to(device)
+            dx = xy[None, :, 0] - gp[:, 0, None]
+            dy = xy[None, :, 1] - gp[:, 1, None]
+            d2 = dx * dx + dy * dy
+            out[c0:c0 + gp.shape[0]] = (d2 * scale - norm).to(torch.float32)
+        return out
+
+
+def map_matching_workload(seed: int = 4, K: int = 100000, n: int = 64, t_lo: int = 200,
+                          t_hi: int = 2000, sigma_a: float = 0.01,
+                          sigma_gps: float = 0.005) -> MapMatching:
+    """K=100000 states, 9 out-edges each, 64 trajectories of length uniform in
+    [200, 2000]."""
+    from scipy.spatial import cKDTree
+    xy = _rng(seed, 0).random((K, 2))
+    dist, idx = cKDTree(xy).query(xy, k=9)
+    # per row: the 9 nearest by (distance, index), then listed by column
+    order = np.lexsort((idx, dist), axis=1)
+    idx = np.take_along_axis(idx, order, 1)
+    dist = np.take_along_axis(dist, order, 1)
+    lg = -dist / sigma_a
+    mx = lg.max(axis=1, keepdims=True)
+    lg = lg - (mx + np.log(np.exp(lg - mx).sum(axis=1, keepdims=True)))
+    by_col = np.argsort(idx, axis=1, kind="stable")
+    col = np.take_along_axis(idx, by_col, 1).astype(np.int32).reshape(-1)
+    val = np.take_along_axis(lg, by_col, 1).astype(np.float32).reshape(-1)
+    row_ptr = (np.arange(K + 1, dtype=np.int64) * 9).astype(np.int32)
+    lengths = _rng(seed, 1).integers(t_lo, t_hi + 1, size=n).astype(np.int32)
+    return MapMatching(K, xy, row_ptr, col, val, uniform_log_pi(K), lengths, seed, sigma_gps)
