@@ -16,6 +16,20 @@ extern "C" __global__ void fv_prep_dense_kernel(const float* __restrict__ log_a,
 extern "C" __global__ void fv_setup_kernel(EngineArgs a, SetupArgs sa);
 extern "C" __global__ void fv_finish_kernel(EngineArgs a, int32_t* status);
 extern "C" __global__ void fv_beam_finish_kernel(EngineArgs a, const float* __restrict__ Ap, int32_t* status);
+extern "C" __global__ void fv_csr_zero_kernel(int32_t* __restrict__ p, int64_t n);
+extern "C" __global__ void fv_csr_check_kernel(int32_t K, int64_t nnz, const int32_t* __restrict__ row_ptr,
+                                               int32_t* __restrict__ flag);
+extern "C" __global__ void fv_csr_count_kernel(int32_t K, int64_t nnz, const int32_t* __restrict__ col,
+                                               int32_t* __restrict__ deg);
+extern "C" __global__ void fv_csr_scan_kernel(int32_t K, const int32_t* __restrict__ deg, int32_t* __restrict__ in_ptr,
+                                              int32_t* __restrict__ flag);
+extern "C" __global__ void fv_csr_scatter_kernel(int32_t K, int64_t nnz, const int32_t* __restrict__ col,
+                                                 const int32_t* __restrict__ in_ptr, int32_t* __restrict__ cursor,
+                                                 int32_t* __restrict__ eid);
+extern "C" __global__ void fv_csr_place_kernel(int32_t K, const int32_t* __restrict__ row_ptr,
+                                               const int32_t* __restrict__ col, const float* __restrict__ val,
+                                               const int32_t* __restrict__ in_ptr, const int32_t* __restrict__ eid,
+                                               int32_t* __restrict__ in_src, float* __restrict__ in_val);
 }  // namespace fv
 
 using namespace fv;
@@ -57,6 +71,8 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int32_t kMaxDenseK = 65535;   // packed uint16 backpointers
+constexpr int32_t kMaxSparseK = 1 << 30;
+constexpr int64_t kMaxNnz = 0x7fffffffLL;
 constexpr int32_t kMaxBlocks = 4096;    // engine grid size limit (arrival flags)
 constexpr int kEngineBlock = 1024;      // engine threads per block (one block per CU)
 
@@ -72,8 +88,10 @@ struct DenseLayout {
     int32_t bw = 1;              // parts of a beam task's step
     int64_t brec = 0;            // floats per beam record
     int64_t q_cap = 0;
+    int32_t sparse = 0;
+    int64_t nnz = 0;
     Region Ap, seq1, seqinfo, keys, args, state, arrive, rows_full, rows_light, rows_beam, queue, free_stack,
-        slots, alpha, root, psi;
+        slots, alpha, root, psi, csr_flag, csr_ptr, csr_deg, csr_eid, csr_src, csr_val;
     size_t total = 0;
 };
 
@@ -87,12 +105,24 @@ size_t put(size_t& cur, Region& r, size_t bytes) {
 // Workspace layout of a dense decode.  Depends only on the arguments, so
 // fv_workspace_size and the decode calls agree.  method FV_BEAM means a
 // beam narrower than K (a beam of width >= K is planned as FV_FLASH).
-fv_status plan_dense(int32_t method, int32_t K, const int32_t* T_host, int32_t n_seqs, int32_t P, int32_t B,
+fv_status plan_dense(int32_t method, const fv_trans* A, const int32_t* T_host, int32_t n_seqs, int32_t P, int32_t B,
                      bool single, DenseLayout& L) {
     L = DenseLayout{};
     L.method = method;
+    const int32_t K = A->K;
+    const bool sparse = A->kind == FV_CSR;
+    L.sparse = sparse ? 1 : 0;
+    L.nnz = sparse ? A->nnz : 0;
     const bool beam = method == FV_BEAM;
-    if (beam) {
+    if (beam && sparse) {
+        // one block per task step: the beam states' out-edges are pushed
+        if (B < 1 || B >= K) return fail(FV_E_INVALID_ARG, "beam width must be in [1, K)");
+        if (B > kBeamMaxB) return fail(FV_E_UNSUPPORTED, "beam width %d exceeds %d", B, kBeamMaxB);
+        L.B = B;
+        L.Bc = (int32_t)round_up(B, 64);
+        L.brec = 64 + 3 * (int64_t)L.Bc;
+        L.bw = 1;
+    } else if (beam) {
         if (K > kBeamMaxK) return fail(FV_E_UNSUPPORTED, "beam decoding supports K <= %d (got %d)", kBeamMaxK, K);
         if (B < 1 || B >= K) return fail(FV_E_INVALID_ARG, "beam width must be in [1, K)");
         if (B > kBeamMaxB) return fail(FV_E_UNSUPPORTED, "beam width %d exceeds %d", B, kBeamMaxB);
@@ -170,17 +200,57 @@ fv_status plan_dense(int32_t method, int32_t K, const int32_t* T_host, int32_t n
     put(cur, L.alpha, method != FV_VANILLA ? (size_t)L.sum_T * 4 : 0);
     put(cur, L.root, (size_t)L.sum_root * (beam ? L.brec : L.Kp) * 4);
     put(cur, L.psi, (size_t)L.sum_psi * 2);
+    // sparse models: the in-edge transpose (pointers, sources, scores) and its scratch
+    const size_t nn = sparse ? (size_t)std::max<int64_t>(L.nnz, 1) : 0;
+    put(cur, L.csr_flag, sparse ? 4 : 0);
+    put(cur, L.csr_ptr, sparse ? ((size_t)K + 1) * 4 : 0);
+    put(cur, L.csr_deg, sparse ? (size_t)K * 4 : 0);
+    put(cur, L.csr_eid, nn * 4);
+    put(cur, L.csr_src, nn * 4);
+    put(cur, L.csr_val, nn * 4);
     L.total = (cur + kAlign - 1) / kAlign * kAlign;
     return FV_OK;
 }
 
-fv_status check_dense_model(const fv_trans* A) {
+fv_status check_model(const fv_trans* A) {
     if (!A) return fail(FV_E_INVALID_ARG, "null transition model");
-    if (A->kind != FV_DENSE) return fail(FV_E_UNSUPPORTED, "only dense transition models are supported by this entry point");
     if (A->K < 1) return fail(FV_E_INVALID_ARG, "K must be >= 1 (got %d)", A->K);
-    if (A->K > kMaxDenseK) return fail(FV_E_UNSUPPORTED, "K=%d exceeds %d", A->K, kMaxDenseK);
-    if (!A->log_a) return fail(FV_E_INVALID_ARG, "null log_a");
+    if (A->kind == FV_DENSE) {
+        if (A->K > kMaxDenseK) return fail(FV_E_UNSUPPORTED, "K=%d exceeds %d", A->K, kMaxDenseK);
+        if (!A->log_a) return fail(FV_E_INVALID_ARG, "null log_a");
+        return FV_OK;
+    }
+    if (A->kind != FV_CSR) return fail(FV_E_INVALID_ARG, "unknown transition model kind %d", A->kind);
+    if (A->K > kMaxSparseK) return fail(FV_E_UNSUPPORTED, "K=%d exceeds %d", A->K, kMaxSparseK);
+    if (A->nnz < 0) return fail(FV_E_INVALID_ARG, "nnz < 0");
+    if (A->nnz > kMaxNnz) return fail(FV_E_UNSUPPORTED, "nnz=%lld exceeds %lld", (long long)A->nnz, (long long)kMaxNnz);
+    if (!A->row_ptr || (A->nnz > 0 && (!A->col || !A->val))) return fail(FV_E_INVALID_ARG, "null CSR array");
     return FV_OK;
+}
+
+unsigned grid_for(int64_t n) {
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, 8192));
+}
+
+// In-edge transpose of a CSR model into the workspace (see fv_sparse.hip).
+void launch_transpose(const fv_trans* A, const DenseLayout& L, char* w, hipStream_t stream) {
+    auto at = [&](const Region& r) { return reinterpret_cast<int32_t*>(w + r.off); };
+    const int32_t K = A->K;
+    const int64_t nnz = A->nnz;
+    int32_t* flag = at(L.csr_flag);
+    int32_t* deg = at(L.csr_deg);
+    int32_t* in_ptr = at(L.csr_ptr);
+    hipLaunchKernelGGL(fv_csr_zero_kernel, dim3(1), dim3(kBlock), 0, stream, flag, (int64_t)1);
+    hipLaunchKernelGGL(fv_csr_zero_kernel, dim3(grid_for(K)), dim3(kBlock), 0, stream, deg, (int64_t)K);
+    hipLaunchKernelGGL(fv_csr_check_kernel, dim3(grid_for((int64_t)K + 1)), dim3(kBlock), 0, stream, K, nnz,
+                       A->row_ptr, flag);
+    hipLaunchKernelGGL(fv_csr_count_kernel, dim3(grid_for(nnz)), dim3(kBlock), 0, stream, K, nnz, A->col, deg);
+    hipLaunchKernelGGL(fv_csr_scan_kernel, dim3(1), dim3(1024), 0, stream, K, deg, in_ptr, flag);
+    hipLaunchKernelGGL(fv_csr_zero_kernel, dim3(grid_for(K)), dim3(kBlock), 0, stream, deg, (int64_t)K);
+    hipLaunchKernelGGL(fv_csr_scatter_kernel, dim3(grid_for(nnz)), dim3(kBlock), 0, stream, K, nnz, A->col,
+                       in_ptr, deg, at(L.csr_eid));
+    hipLaunchKernelGGL(fv_csr_place_kernel, dim3(grid_for(nnz)), dim3(kBlock), 0, stream, K, A->row_ptr, A->col,
+                       A->val, in_ptr, at(L.csr_eid), at(L.csr_src), reinterpret_cast<float*>(at(L.csr_val)));
 }
 
 struct DeviceInfo {
@@ -206,7 +276,8 @@ __global__ void write_seq_kernel(fv_seq* dst, fv_seq v) { *dst = v; }
 
 // Row placement (see FV_FLAG_WIDE_ROWS): wide rows when log A cannot be
 // shared through L2 (large K) or when too few rows exist to fill lane tiles.
-bool use_wide_rows(uint32_t flags, int32_t K, int32_t n_seqs) {
+bool use_wide_rows(uint32_t flags, int32_t K, int32_t n_seqs, bool sparse) {
+    if (sparse) return false;
     if (flags & FV_FLAG_WIDE_ROWS) return true;
     if (flags & FV_FLAG_LOCAL_ROWS) return false;
     return K >= 4096 || (K >= 1024 && n_seqs <= 4);
@@ -219,10 +290,13 @@ fv_status run_dense(int32_t method, const fv_trans* A, const float* log_pi, cons
         return fail(FV_E_INVALID_ARG, "FV_FLAG_WIDE_ROWS and FV_FLAG_LOCAL_ROWS exclude each other");
     if (flags & ~(uint32_t)(FV_FLAG_WIDE_ROWS | FV_FLAG_LOCAL_ROWS))
         return fail(FV_E_INVALID_ARG, "unknown flags 0x%x", flags);
-    fv_status rc = check_dense_model(A);
+    fv_status rc = check_model(A);
     if (rc != FV_OK) return rc;
+    const bool sparse = A->kind == FV_CSR;
+    if (sparse && (flags & FV_FLAG_WIDE_ROWS))
+        return fail(FV_E_INVALID_ARG, "FV_FLAG_WIDE_ROWS applies to dense models only");
     DenseLayout L;
-    rc = plan_dense(method, A->K, T_host, n_seqs, P, B, single != nullptr, L);
+    rc = plan_dense(method, A, T_host, n_seqs, P, B, single != nullptr, L);
     if (rc != FV_OK) return rc;
     if (!ws || ws_bytes < L.total)
         return fail(FV_E_WORKSPACE, "workspace of %zu bytes is smaller than the %zu bytes required", ws_bytes, L.total);
@@ -238,8 +312,9 @@ fv_status run_dense(int32_t method, const fv_trans* A, const float* log_pi, cons
         hipLaunchKernelGGL(write_seq_kernel, dim3(1), dim3(1), 0, stream, static_cast<fv_seq*>(at(L.seq1)), *single);
         seqs_dev = static_cast<const fv_seq*>(at(L.seq1));
     }
-    const float* Ap = A->log_a;
-    if (L.Kp != A->K) {
+    const float* Ap = sparse ? nullptr : A->log_a;
+    if (sparse) launch_transpose(A, L, w, stream);
+    if (!sparse && L.Kp != A->K) {
         float* pad = static_cast<float*>(at(L.Ap));
         const int64_t cells = (int64_t)L.Kp * L.Kp;
         hipLaunchKernelGGL(fv_prep_dense_kernel, dim3((unsigned)((cells + kBlock - 1) / kBlock)), dim3(kBlock), 0,
@@ -259,7 +334,18 @@ fv_status run_dense(int32_t method, const fv_trans* A, const float* log_pi, cons
     a.slot_floats = L.slot_floats;
     a.n_slots = L.n_slots;
     a.has_anc = L.has_anc;
-    a.wide = use_wide_rows(flags, A->K, n_seqs) ? 1 : 0;
+    a.wide = use_wide_rows(flags, A->K, n_seqs, sparse) ? 1 : 0;
+    if (sparse) {
+        a.sparse = 1;
+        a.nnz = A->nnz;
+        a.row_ptr = A->row_ptr;
+        a.col = A->col;
+        a.val = A->val;
+        a.in_ptr = static_cast<const int32_t*>(at(L.csr_ptr));
+        a.in_src = static_cast<const int32_t*>(at(L.csr_src));
+        a.in_val = static_cast<const float*>(at(L.csr_val));
+        a.csr_flag = static_cast<int32_t*>(at(L.csr_flag));
+    }
     a.alpha_at = static_cast<float*>(at(L.alpha));
     a.root_copy = static_cast<float*>(at(L.root));
     a.psi16 = static_cast<uint16_t*>(at(L.psi));
@@ -368,7 +454,7 @@ fv_status fv_workspace_size(int32_t method, const fv_trans* models, int32_t n_mo
     if (!bytes) return fail(FV_E_INVALID_ARG, "null bytes");
     if (n_models != 1) return fail(FV_E_UNSUPPORTED, "exactly one model per call is supported");
     if (n_seqs < 0 || (n_seqs > 0 && !T_host)) return fail(FV_E_INVALID_ARG, "bad sequence list");
-    fv_status rc = check_dense_model(models);
+    fv_status rc = check_model(models);
     if (rc != FV_OK) return rc;
     if (method != FV_VANILLA && method != FV_FLASH && method != FV_BEAM)
         return fail(FV_E_INVALID_ARG, "unknown method %d", method);
@@ -377,7 +463,7 @@ fv_status fv_workspace_size(int32_t method, const fv_trans* models, int32_t n_mo
     method = effective_method(method, models, B);
     DenseLayout L;
     // single-sequence calls reserve room for their device descriptor too
-    rc = plan_dense(method, models->K, T_host, n_seqs, P, B, n_seqs == 1, L);
+    rc = plan_dense(method, models, T_host, n_seqs, P, B, n_seqs == 1, L);
     if (rc != FV_OK) return rc;
     *bytes = L.total;
     return FV_OK;

@@ -191,11 +191,25 @@ struct BeamLds {
     int32_t misc[8];
 };
 
+// A sparse beam step (push over the beam states' out-edges) works in the
+// candidate area of BeamLds; the rebuilt beam (bs/bv/ba) stays in place.
+struct SpBeamLds {
+    uint64_t key[kSpCandMax];    // (destination << 32) | candidate position, sorted
+    float cval[kSpCandMax];      // candidate score by position
+    int32_t ds[kSpCandMax];      // distinct destinations (state order), their
+    float dv[kSpCandMax];        // scores and anchors
+    int32_t da[kSpCandMax];
+    int32_t offs[kBeamMaxB + 1]; // first candidate position of each beam entry
+    int32_t estart[kBeamMaxB];   // first out-edge of each beam entry
+};
+
 union EngineLds {
     TileLds tile;
     WideLds wide;
     BeamLds beam;
+    SpBeamLds spbeam;
 };
+static_assert(sizeof(SpBeamLds) <= offsetof(BeamLds, bs), "sparse beam scratch overlaps the beam");
 
 constexpr int kSchedGroup = kEngBlock / kXcd;
 constexpr int kSchedGroupWaves = kSchedGroup / 64;
@@ -274,7 +288,17 @@ __device__ Row row_from_task(cargs_t& a, const Task& tk, int32_t slot) {
         b.aux = B_INIT;
         return b;
     }
-    return make_light_row(b, tk.m, L_INIT);
+    Row r = make_light_row(b, tk.m, L_INIT);
+    if (a.sparse) {   // a sparse start step is a row of the full list (see sparse_unit)
+        r.flags |= F_START;
+        r.aux = 0;    // division 0 for F_SNAP_ROOT
+    }
+    return r;
+}
+
+// List a task's first row goes to: 0 full (sparse start), 1 light, 2 beam.
+__device__ __forceinline__ int32_t start_list(cargs_t& a, int32_t kind) {
+    return is_beam(kind) ? 2 : (a.sparse ? 0 : 1);
 }
 
 // Row of a beam task at time t doing operation op.
@@ -654,6 +678,105 @@ __device__ __noinline__ void wide_item(cargs_t& a_in, const float* __restrict__ 
     __syncthreads();
 }
 
+// ---------------------------------------------------------------- sparse rows
+// Sparse model (CSR): one wave computes 64 destinations j (one per lane) of
+// one row by pulling over j's in-edges, which are in (source, edge) order:
+//     c(j) = max over in-edges (i -> j) of delta_{t-1}(i) + log A(i, j)
+// with the first maximum winning, so psi(j) is the lowest source on ties and
+// the stored value is that candidate's.  A destination without in-edges gets
+// -inf (and psi 0).  Vanilla backpointers hold the winning in-edge's slot
+// within j's list.  F_START rows compute the task's start vector instead:
+// log pi + log B_0 at m = 0, else the anchored boundary
+// (alpha + log A(q*_{m-1}, j)) + log B_m(j), the edge found by binary search
+// among j's in-edges (sources are sorted).  Rows and their buffers belong to
+// this XCD, so plain loads see the previous step's stores.
+__device__ __noinline__ void sparse_unit(cargs_t& a_in, const Row* list, int32_t ridx, int32_t c64) {
+    cargs_t& a = uniform_args(a_in);
+    const int32_t lane = threadIdx.x & 63;
+    const int32_t K = a.K;
+    const Row r = ld_row(list + ridx);
+    const int32_t j = c64 * 64 + lane;
+    const int32_t t = r.t, f = r.flags, slot = clampi(r.slot, a.n_slots);
+    const int32_t* __restrict__ in_ptr = a.in_ptr;
+    const int32_t* __restrict__ in_src = a.in_src;
+    const float* __restrict__ in_val = a.in_val;
+    unsigned long long key = 0;
+    if (j < K) {
+        const float bt = r.log_b[(int64_t)t * r.ld + j];
+        const int32_t e0 = in_ptr[j], e1 = in_ptr[j + 1];
+        float dnew;
+        int32_t psi = 0, pslot = 0;
+        if (f & F_START) {
+            if (t == 0) {
+                dnew = a.log_pi ? a.log_pi[j] + bt : bt;
+            } else {
+                const SeqInfo& sq = a.seqs[r.seq];
+                const int32_t q = ld_c(sq.path + t - 1);
+                const float alpha = ld_cf(a.alpha_at + sq.alpha_off + t - 1);
+                int32_t lo = e0, hi = e1;   // first in-edge with source >= q
+                while (lo < hi) {
+                    const int32_t mid = (lo + hi) >> 1;
+                    if (in_src[mid] < q) lo = mid + 1; else hi = mid;
+                }
+                float c = -INFINITY;
+                bool found = false;
+                for (int32_t p = lo; p < e1 && in_src[p] == q; ++p) {
+                    const float x = alpha + in_val[p];
+                    if (!found || x > c) { c = x; found = true; }
+                }
+                dnew = found ? c + bt : -INFINITY;
+            }
+        } else {
+            const float* dprev = slot_delta(a, slot, (t - 1) & 1);
+            float best = -INFINITY;
+            int32_t bp = -1;
+            // four in-edges per round: their gathers are issued together
+            for (int32_t p0 = e0; p0 < e1; p0 += 4) {
+                int32_t sidx[4];
+                float av[4], dv[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int32_t p = min(p0 + k, e1 - 1);
+                    sidx[k] = in_src[p];
+                    av[k] = in_val[p];
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) dv[k] = dprev[sidx[k]];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const float x = dv[k] + av[k];
+                    if (p0 + k < e1 && (bp < 0 || x > best)) { best = x; bp = p0 + k; }
+                }
+            }
+            if (bp >= 0) {
+                psi = in_src[bp];
+                pslot = bp - e0;
+            }
+            dnew = best + bt;
+        }
+        int32_t anc = 0;
+        if (f & F_ANC_FIRST) anc = psi;
+        else if (f & F_ANC_CHAIN) anc = clampi(slot_anc(a, slot, (t - 1) & 1)[psi], K);
+        slot_delta(a, slot, t & 1)[j] = dnew;
+        if (f & F_PSI_TABLE) a.psi16[r.off + (int64_t)t * K + j] = (uint16_t)pslot;
+        if (f & (F_ANC_FIRST | F_ANC_CHAIN)) slot_anc(a, slot, t & 1)[j] = anc;
+        if (f & F_SNAP_SUB) slot_snap(a, slot)[j] = dnew;
+        if (f & F_SNAP_ROOT) {
+            root_dsnap(a, r.off, r.aux)[j] = dnew;
+            if (r.aux >= 1) root_link(a, r.off, r.pp, r.aux)[j] = anc;
+        }
+        if (f & F_FINAL) key = order_key(dnew, j);
+    }
+    if (f & F_FINAL) {   // wave-uniform
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const unsigned long long o = __shfl_xor(key, off, 64);
+            if (o > key) key = o;
+        }
+        if (lane == 0) key_max(&a.keys[r.seq], key);
+    }
+}
+
 // ---------------------------------------------------------------- light rows
 __device__ __forceinline__ void wave_argmax(float& v, int32_t& idx) {
 #pragma unroll
@@ -715,14 +838,25 @@ __device__ __noinline__ void light_row(cargs_t& a_in, const float* __restrict__ 
         const int32_t qn = ld_c(sq.path + n);
         if (qn < 0 || qn >= K) return;
         const float* dprev = slot_delta(a, slot, (n - 1) & 1);
-        const float* ac = a.Acol + qn;  // column q*_n of log A
         float best = -INFINITY;
         int32_t arg = 0x7fffffff;
-        for (int32_t i = lane; i < K; i += 64) {
-            const float x = (a.wide ? ld_cf(dprev + i) : dprev[i]) + ac[(int64_t)i * Kp];
-            if (arg == 0x7fffffff || x > best) { best = x; arg = i; }
+        if (a.sparse) {
+            // q*_n's in-edges in order; the lowest position wins ties
+            const int32_t e0 = a.in_ptr[qn], e1 = a.in_ptr[qn + 1];
+            for (int32_t p = e0 + lane; p < e1; p += 64) {
+                const float x = dprev[a.in_src[p]] + a.in_val[p];
+                if (arg == 0x7fffffff || x > best) { best = x; arg = p; }
+            }
+            wave_argmax(best, arg);
+            arg = arg == 0x7fffffff ? 0 : a.in_src[arg];
+        } else {
+            const float* ac = a.Acol + qn;  // column q*_n of log A
+            for (int32_t i = lane; i < K; i += 64) {
+                const float x = (a.wide ? ld_cf(dprev + i) : dprev[i]) + ac[(int64_t)i * Kp];
+                if (arg == 0x7fffffff || x > best) { best = x; arg = i; }
+            }
+            wave_argmax(best, arg);
         }
-        wave_argmax(best, arg);
         if (lane == 0) {
             arg = clampi(arg, K);
             const int32_t* ap = slot_anc(a, slot, (n - 1) & 1);
@@ -983,6 +1117,129 @@ __device__ __forceinline__ int32_t beam_find_lds(const int32_t* bs, int32_t nb, 
     return -1;
 }
 
+// Ascending bitonic sort of n2 (a power of two) keys in LDS by the block.
+__device__ void lds_bitonic_sort(uint64_t* key, int32_t n2) {
+    for (int32_t k = 2; k <= n2; k <<= 1) {
+        for (int32_t h = k >> 1; h > 0; h >>= 1) {
+            for (int32_t i = threadIdx.x; i < n2; i += kEngBlock) {
+                const int32_t l = i ^ h;
+                if (l > i) {
+                    const uint64_t x = key[i], y = key[l];
+                    if ((x > y) == ((i & k) == 0)) { key[i] = y; key[l] = x; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Beam entry owning candidate position p: the b with offs[b] <= p < offs[b+1].
+__device__ __forceinline__ int32_t sp_owner(const int32_t* offs, int32_t nb, int32_t p) {
+    int32_t lo = 0, hi = nb;
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (offs[mid] <= p) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Clamped out-edge range [e0, e1) of source s.
+__device__ __forceinline__ void sp_out_range(const int32_t* row_ptr, int64_t nnz, int32_t s, int32_t& e0,
+                                             int32_t& e1) {
+    int64_t x0 = row_ptr[s], x1 = row_ptr[s + 1];
+    x0 = x0 < 0 ? 0 : (x0 > nnz ? nnz : x0);
+    x1 = x1 < x0 ? x0 : (x1 > nnz ? nnz : x1);
+    e0 = (int32_t)x0;
+    e1 = (int32_t)x1;
+}
+
+// Sparse beam step (push): the candidates are the out-edges of the beam's
+// states (L.bs/bv/ba, nb entries in state order), at positions in (beam
+// entry, edge) order.  Sorting the keys (destination << 32 | position) puts
+// each destination's candidates together in that order, so the first
+// maximum of a run is the one the dense scan over the beam would keep.
+// Writes the distinct destinations in state order to S.ds/dv/da with
+// dv = c + log B_t(j) and the anchor chosen by mode (0 none, 1 the
+// predecessor, 2 its anchor); returns their count.  More than kSpCandMax
+// candidates: the sequence fails with FV_E_UNSUPPORTED (the first
+// kSpCandMax are used, so every access stays in range).
+__device__ int32_t sparse_push(cargs_t& a, SeqInfo& sq, int32_t nb, int32_t mode, const float* bt) {
+    BeamLds& L = g_lds.beam;
+    SpBeamLds& S = g_lds.spbeam;
+    const int tid = threadIdx.x;
+    const int32_t K = a.K;
+    const int32_t per = (nb + kEngBlock - 1) / kEngBlock;
+    const int32_t b0 = min(nb, tid * per), b1 = min(nb, b0 + per);
+    int32_t sum = 0;
+    for (int32_t b = b0; b < b1; ++b) {
+        int32_t e0, e1;
+        sp_out_range(a.row_ptr, a.nnz, clampi(L.bs[b], K), e0, e1);
+        S.estart[b] = e0;
+        S.offs[b] = e1 - e0;   // degree for now
+        sum += e1 - e0;
+    }
+    int32_t total;
+    int32_t pos = block_exscan(sum, &total, L.wsum);
+    for (int32_t b = b0; b < b1; ++b) {
+        const int32_t d = S.offs[b];
+        S.offs[b] = pos;
+        pos += d;
+    }
+    if (tid == 0) S.offs[nb] = total;
+    int32_t nc = total;
+    if (nc > kSpCandMax) {
+        if (tid == 0) {
+            atomicOr(a.csr_flag, kCsrBeamCands);
+            st_c(&sq.status, (int32_t)FV_E_UNSUPPORTED);
+        }
+        nc = kSpCandMax;
+    }
+    __syncthreads();
+    int32_t n2 = 1;
+    while (n2 < nc) n2 <<= 1;
+    for (int32_t p = tid; p < n2; p += kEngBlock) {
+        uint64_t k = ~0ull;
+        if (p < nc) {
+            const int32_t b = sp_owner(S.offs, nb, p);
+            const int32_t e = S.estart[b] + (p - S.offs[b]);
+            const int32_t j = a.col[e];
+            S.cval[p] = L.bv[b] + a.val[e];
+            if (j >= 0 && j < K) k = ((uint64_t)(uint32_t)j << 32) | (uint32_t)p;
+        }
+        S.key[p] = k;
+    }
+    __syncthreads();
+    lds_bitonic_sort(S.key, n2);
+    const int32_t per2 = (n2 + kEngBlock - 1) / kEngBlock;
+    const int32_t k0 = min(n2, tid * per2), k1 = min(n2, k0 + per2);
+    int32_t nh = 0;
+    for (int32_t k = k0; k < k1; ++k) {
+        const uint64_t x = S.key[k];
+        nh += x != ~0ull && (k == 0 || (S.key[k - 1] >> 32) != (x >> 32));
+    }
+    int32_t nd;
+    int32_t o = block_exscan(nh, &nd, L.wsum);
+    for (int32_t k = k0; k < k1; ++k) {
+        const uint64_t x = S.key[k];
+        if (x == ~0ull || (k > 0 && (S.key[k - 1] >> 32) == (x >> 32))) continue;
+        const uint32_t j = (uint32_t)(x >> 32);
+        int32_t w = (int32_t)(uint32_t)x;
+        float c = S.cval[w];
+        for (int32_t u = k + 1; u < n2 && (uint32_t)(S.key[u] >> 32) == j; ++u) {
+            const int32_t p = (int32_t)(uint32_t)S.key[u];
+            const float y = S.cval[p];
+            if (y > c) { c = y; w = p; }
+        }
+        const int32_t b = sp_owner(S.offs, nb, w);
+        S.ds[o] = (int32_t)j;
+        S.dv[o] = c + bt[j];
+        S.da[o] = mode == 1 ? L.bs[b] : (mode == 2 ? L.ba[b] : -1);
+        ++o;
+    }
+    __syncthreads();
+    return nd;
+}
+
 __device__ __noinline__ void beam_chain_walk(cargs_t& a, const Row& r, int32_t q);
 
 // One part of one beam task's step (parts beyond the first return at once
@@ -1011,6 +1268,41 @@ __device__ __noinline__ void beam_row(cargs_t& a_in, const float* __restrict__ A
         const float alpha = __uint_as_float((uint32_t)L.misc[3]);
         if (q < 0 || q >= K) q = -1;
         const float* bm = r.log_b + (int64_t)m * r.ld;
+        if (a.sparse) {   // one part
+            const BeamRec out = slot_part(a, slot, m & 1, 0);
+            int32_t nk = 0;
+            if (m == 0) {
+                // every state: chunks merged into a running top B (L.bs/bv/ba)
+                for (int32_t c0 = 0; c0 < K; c0 += kBeamPartMax) {
+                    const int32_t nc = min(kBeamPartMax, K - c0);
+                    for (int32_t k = tid; k < nk; k += kEngBlock) {
+                        L.cs[k] = L.bs[k]; L.cv[k] = L.bv[k]; L.ca[k] = L.ba[k];
+                    }
+                    for (int32_t k = tid; k < nc; k += kEngBlock) {
+                        const int32_t j = c0 + k;
+                        L.cs[nk + k] = j;
+                        L.cv[nk + k] = a.log_pi ? a.log_pi[j] + bm[j] : bm[j];
+                        L.ca[nk + k] = -1;
+                    }
+                    __syncthreads();
+                    nk = beam_select(nk + nc, B, L.cv, L.cs, 0, L.ca, [&](int32_t p, int32_t st, float sv, int32_t av) {
+                        L.bs[p] = st; L.bv[p] = sv; L.ba[p] = av;
+                    });
+                }
+                beam_store(out, nk);
+            } else {
+                // the boundary state alone, with its anchor score, pushed
+                if (tid == 0) { L.bs[0] = q; L.bv[0] = alpha; L.ba[0] = -1; }
+                __syncthreads();
+                const SpBeamLds& S = g_lds.spbeam;
+                const int32_t nd = q >= 0 ? sparse_push(a, sq, 1, 0, bm) : 0;
+                nk = beam_select(nd, B, S.dv, S.ds, 0, S.da, [&](int32_t p, int32_t st, float sv, int32_t av) {
+                    out.s[p] = st; out.v[p] = sv; out.a[p] = av;
+                });
+                if (tid == 0) out.hdr[0] = nk;
+            }
+            return;
+        }
         for (int32_t k = tid; k < nj; k += kEngBlock) {
             const int32_t j = jlo + k;
             float v = -INFINITY;
@@ -1044,6 +1336,16 @@ __device__ __noinline__ void beam_row(cargs_t& a_in, const float* __restrict__ A
             mode = t == tmid + 1 ? 1 : (t > tmid + 1 ? 2 : 0);
         }
         const float* bt = r.log_b + (int64_t)t * r.ld;
+        if (a.sparse) {
+            const SpBeamLds& S = g_lds.spbeam;
+            const int32_t nd = sparse_push(a, sq, nb, mode, bt);
+            const BeamRec out = slot_part(a, slot, t & 1, 0);
+            const int32_t nk = beam_select(nd, B, S.dv, S.ds, 0, S.da, [&](int32_t p, int32_t st, float sv, int32_t av) {
+                out.s[p] = st; out.v[p] = sv; out.a[p] = av;
+            });
+            if (tid == 0) out.hdr[0] = nk;
+            return;
+        }
         for (int32_t k = tid; k < nj; k += kEngBlock) {
             const int32_t j = jlo + k;
             float c = -INFINITY;
@@ -1086,7 +1388,19 @@ __device__ __noinline__ void beam_row(cargs_t& a_in, const float* __restrict__ A
         const int32_t nb = beam_rebuild(a, slot, (n - 1) & 1);
         unsigned long long key = 0;
         for (int32_t b = tid; b < nb; b += kEngBlock) {
-            const float x = L.bv[b] + Ap[(int64_t)L.bs[b] * Kp + qn];
+            float x = -INFINITY;
+            if (a.sparse) {   // the edges s_b -> q*_n (the first maximum among duplicates)
+                int32_t e0, e1;
+                sp_out_range(a.row_ptr, a.nnz, L.bs[b], e0, e1);
+                bool found = false;
+                for (int32_t e = e0; e < e1; ++e) {
+                    if (a.col[e] != qn) continue;
+                    const float y = L.bv[b] + a.val[e];
+                    if (!found || y > x) { x = y; found = true; }
+                }
+            } else {
+                x = L.bv[b] + Ap[(int64_t)L.bs[b] * Kp + qn];
+            }
             if (x != -INFINITY) {
                 const unsigned long long k = order_key(x, b);
                 if (k > key) key = k;
@@ -1474,20 +1788,20 @@ __device__ __noinline__ void admit(cargs_t& a_in, int nxt) {
     // this thread's tasks: a contiguous range, so list order follows the queue
     const int32_t per = (ax + kSchedGroup - 1) / kSchedGroup;
     const int32_t lo = min(ax, tg * per), hi = min(ax, lo + per);
-    int32_t c[2] = {0, 0}, tot[2];
-    for (int32_t k = lo; k < hi; ++k) c[is_beam(a.queue[qbase + k].kind) ? 1 : 0]++;
-    group_scan<2>(c, tot, sl.wave_sums[x]);
+    int32_t c[3] = {0, 0, 0}, tot[3];
+    for (int32_t k = lo; k < hi; ++k) c[start_list(a, a.queue[qbase + k].kind)]++;
+    group_scan<3>(c, tot, sl.wave_sums[x]);
+    Row* out[3] = {list_full(a, nxt, x), list_light(a, nxt, x), list_beam(a, nxt, x)};
     for (int32_t k = lo; k < hi; ++k) {
         const Task tk = a.queue[qbase + k];
         const int32_t slot = a.free_stack[(int64_t)x * a.pool + sl.n_free[x] - 1 - k];
         const Row r = row_from_task(a, tk, slot);
-        if (is_beam(tk.kind)) st_row(list_beam(a, nxt, x) + sl.n_next[x][2] + c[1]++, r);
-        else st_row(list_light(a, nxt, x) + sl.n_next[x][1] + c[0]++, r);
+        const int32_t li = start_list(a, tk.kind);
+        st_row(out[li] + sl.n_next[x][li] + c[li]++, r);
     }
     __syncthreads();
     if (tg == 0) {
-        sl.n_next[x][1] += tot[0];
-        sl.n_next[x][2] += tot[1];
+        for (int k = 0; k < 3; ++k) sl.n_next[x][k] += tot[k];
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1668,9 +1982,33 @@ __device__ void run_units(cargs_t& a, const float* __restrict__ Ap, uint32_t x, 
     const int32_t nbm = ld_c(&a.st->cnt[cur][x][2]);
     // few rows on this XCD: lane tiles would run mostly empty, so its rows are
     // computed as column items (lanes = destinations) by its own blocks
-    const bool local_cols = !a.wide && nf > 0 && nf <= kLocalColRows;
-    const int32_t n_tiles = (a.wide || local_cols) ? 0 : ((nf + kTileRows - 1) / kTileRows) * (a.Kp / kTileCols);
+    const bool local_cols = !a.wide && !a.sparse && nf > 0 && nf <= kLocalColRows;
+    const int32_t n_tiles =
+        (a.wide || local_cols || a.sparse) ? 0 : ((nf + kTileRows - 1) / kTileRows) * (a.Kp / kTileCols);
     if (a.wide) run_wide(a, Ap, cur);
+    if (a.sparse && nf > 0) {
+        // sparse rows: units of (row, 64 destinations), one per wave, 16 per block item
+        __shared__ int32_t s_sitem;
+        const int32_t nch = a.Kp / 64;
+        const int32_t n_units = nf * nch;
+        const int32_t n_items = (n_units + kEngWaves - 1) / kEngWaves;
+        const Row* Fl = list_full(a, cur, x);
+        int32_t item = rank;
+        for (;;) {
+            if (item < 0) {
+                if (threadIdx.x == 0)
+                    s_sitem = nx + __hip_atomic_fetch_add(&a.st->claim[cur][x][8], 1, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT);
+                __syncthreads();
+                item = s_sitem;
+                __syncthreads();
+            }
+            if (item >= n_items) break;
+            const int32_t u = item * kEngWaves + (threadIdx.x >> 6);
+            if (u < n_units) sparse_unit(a, Fl, u / nch, u % nch);
+            item = -1;
+        }
+    }
     if (local_cols) {
         __shared__ int32_t s_citem;
         const int32_t nch = a.Kp / kWideCols;
@@ -1907,11 +2245,22 @@ extern "C" __global__ __launch_bounds__(kBlock) void fv_finish_kernel(EngineArgs
     SeqInfo& sq = a.seqs[b];
     int32_t stv = sq.status;
     if (a.st->error) stv = FV_E_DEVICE;  // kernel boundary: plain load is coherent
+    if (a.sparse && stv != FV_E_DEVICE && sq.T > 0) {   // malformed CSR input outranks what it caused
+        const int32_t fl = *a.csr_flag;
+        if (fl & kCsrInvalid) stv = FV_E_INVALID_ARG;
+        else if ((fl & kCsrWideIn) && a.method == FV_VANILLA) stv = FV_E_UNSUPPORTED;
+    }
     if (stv == FV_OK && a.method == FV_VANILLA && sq.T > 1) {
         int32_t q = sq.path[sq.T - 1];
         const uint16_t* tab = a.psi16 + sq.psi_off;
         for (int32_t t = sq.T - 1; t > 0; --t) {
-            q = tab[(int64_t)t * a.K + q];
+            const int32_t v = tab[(int64_t)t * a.K + q];
+            if (a.sparse) {   // v is the slot of q's winning in-edge
+                const int32_t e0 = a.in_ptr[q], e1 = a.in_ptr[q + 1];
+                q = e1 > e0 ? a.in_src[min(e0 + v, e1 - 1)] : 0;
+            } else {
+                q = v;
+            }
             sq.path[t - 1] = q;
         }
     }
@@ -1930,6 +2279,7 @@ extern "C" __global__ __launch_bounds__(kBlock) void fv_beam_finish_kernel(Engin
     SeqInfo& sq = a.seqs[b];
     int32_t stv = sq.status;
     if (a.st->error) stv = FV_E_DEVICE;  // kernel boundary: plain loads are coherent
+    if (a.sparse && stv != FV_E_DEVICE && sq.T > 0 && (*a.csr_flag & kCsrInvalid)) stv = FV_E_INVALID_ARG;
     if (stv >= 0 && sq.T >= 1) {
         const int32_t K = a.K, Kp = a.Kp, T = sq.T;
         const int32_t q0 = sq.path[0];
@@ -1942,8 +2292,23 @@ extern "C" __global__ __launch_bounds__(kBlock) void fv_beam_finish_kernel(Engin
             int32_t bad = 0;
             if (t < T) {
                 const int32_t qp = sq.path[t - 1], q = sq.path[t];
-                if (qp < 0 || qp >= K || q < 0 || q >= K) bad = 1;
-                else { ta = Ap[(int64_t)qp * Kp + q]; tb = sq.log_b[(int64_t)t * sq.ld + q]; }
+                if (qp < 0 || qp >= K || q < 0 || q >= K) {
+                    bad = 1;
+                } else {
+                    if (a.sparse) {   // largest of the edges qp -> q, -inf without one
+                        int32_t e0, e1;
+                        sp_out_range(a.row_ptr, a.nnz, qp, e0, e1);
+                        ta = -INFINITY;
+                        bool found = false;
+                        for (int32_t e = e0; e < e1; ++e) {
+                            if (a.col[e] != q) continue;
+                            if (!found || a.val[e] > ta) { ta = a.val[e]; found = true; }
+                        }
+                    } else {
+                        ta = Ap[(int64_t)qp * Kp + q];
+                    }
+                    tb = sq.log_b[(int64_t)t * sq.ld + q];
+                }
             }
             if (__ballot(bad) != 0) { ok = false; break; }
             const int32_t cnt = min(64, T - t0);

@@ -38,6 +38,7 @@ enum : int32_t {
     F_SNAP_SUB = 1 << 4,   // copy delta_t to the row's snapshot (t = t_mid)
     F_SNAP_ROOT = 1 << 5,  // copy delta_t (and anc_t) to the root's division copy aux
     F_FINAL = 1 << 6,      // t = T-1 of a full-length pass: feed the final arg max
+    F_START = 1 << 7,      // sparse rows: this step computes the task's start vector
 };
 
 // Light (O(K)) operations.  L_BSPAWN does nothing: it holds a finished
@@ -51,6 +52,14 @@ enum : int32_t { L_INIT = 0, L_END = 1, L_FINALIZE = 2, L_BSPAWN = 3 };
 enum : int32_t { B_INIT = 0, B_STEP = 1, B_END = 2, B_FINAL = 3 };
 constexpr int32_t kBeamMaxK = 16384;   // scores of one step live in LDS
 constexpr int32_t kBeamMaxB = 2048;
+
+// Sparse models.  Vanilla backpointers of a sparse model hold the winning
+// in-edge's slot within its destination's list (uint16), so a destination
+// may have at most kMaxInSlot + 1 in-edges there.  A sparse beam step
+// pushes the out-edges of its beam states: at most kSpCandMax candidates.
+constexpr int32_t kMaxInSlot = 65535;
+constexpr int32_t kSpCandMax = 4096;
+enum : int32_t { kCsrInvalid = 1, kCsrWideIn = 2, kCsrBeamCands = 4 };
 
 // A task in flight; carries what every step needs so that tiles do not
 // look up the per-sequence table.
@@ -127,6 +136,17 @@ struct EngineArgs {
     int32_t n_slots;            // multiple of kXcd
     int32_t has_anc;            // slots carry anc[2] + snap
     int32_t wide;               // wide rows: every block takes a column slice of every dense row
+    // sparse transitions (CSR out-edges and their in-edge transpose in edge
+    // order); null for dense models
+    int32_t sparse;
+    int64_t nnz;
+    const int32_t* row_ptr;     // [K+1] out-edges of each source
+    const int32_t* col;         // [nnz] destination
+    const float* val;           // [nnz] log A
+    const int32_t* in_ptr;      // [K+1] in-edges of each destination
+    const int32_t* in_src;      // [in_ptr[K]] source, non-decreasing within a destination
+    const float* in_val;        // [in_ptr[K]]
+    int32_t* csr_flag;          // kCsr* bits found by the transpose and the engine
     float* alpha_at;            // sum T floats
     float* root_copy;           // division copies (delta and link), units of Kp
     uint16_t* psi16;            // vanilla backpointers

@@ -31,6 +31,38 @@ def dense_model(log_a: torch.Tensor) -> L.FvTrans:
     return L.FvTrans(L.FV_DENSE, log_a.shape[0], log_a.data_ptr(), None, None, None, 0)
 
 
+class CsrModel:
+    """Sparse transition model: CSR out-edges of each source state, as device
+    tensors row_ptr int32 [K+1], col int32 [nnz] (destination), val float32
+    [nnz] (log A); missing edges are -inf.  The library builds the in-edge
+    transpose in each decode's workspace."""
+
+    def __init__(self, row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor):
+        _need(row_ptr, "row_ptr", torch.int32)
+        _need(col, "col", torch.int32)
+        _need(val, "val")
+        for name, t in (("row_ptr", row_ptr), ("col", col), ("val", val)):
+            if t.dim() != 1 or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous 1-D tensor")
+        if col.numel() != val.numel():
+            raise ValueError("col and val must have the same length")
+        if row_ptr.numel() < 2:
+            raise ValueError("row_ptr must have K+1 >= 2 entries")
+        self.K = row_ptr.numel() - 1
+        self.nnz = col.numel()
+        self.device = row_ptr.device
+        self.keep = (row_ptr, col, val)
+        self.trans = L.FvTrans(L.FV_CSR, self.K, None, row_ptr.data_ptr(), col.data_ptr() if self.nnz else None,
+                               val.data_ptr() if self.nnz else None, self.nnz)
+
+
+def _model(log_a):
+    """(FvTrans, K, device) of a dense [K, K] tensor or a CsrModel."""
+    if isinstance(log_a, CsrModel):
+        return log_a.trans, log_a.K, log_a.device
+    return dense_model(log_a), log_a.shape[0], log_a.device
+
+
 def workspace_bytes(method: str, K_or_model, lengths, P: int = 16, B: int = 0) -> int:
     """Workspace bytes for a decode of sequences with the given lengths.
     K_or_model: an FvTrans, or K (sizing never dereferences the model)."""
@@ -53,22 +85,22 @@ def _workspace(n: int, dev) -> torch.Tensor:
 ROWS = {"auto": 0, "wide": L.FV_FLAG_WIDE_ROWS, "local": L.FV_FLAG_LOCAL_ROWS}
 
 
-def decode(log_a: torch.Tensor, log_b: torch.Tensor, log_pi: torch.Tensor | None = None,
+def decode(log_a, log_b: torch.Tensor, log_pi: torch.Tensor | None = None,
            method: str = "vanilla", P: int = 16, B: int = 0, check_status: bool = True,
            rows: str = "auto"):
-    """Decode one sequence.  log_a [K, K], log_b [T, >=K] (row stride = ld),
-    log_pi [K] or None; all float32 CUDA tensors.  rows: "auto", "wide" or
-    "local" row placement (same results).  Returns (path int32 [T],
-    score float32 [1], status int32 [1]) on the device."""
-    model = dense_model(log_a)
+    """Decode one sequence.  log_a: dense [K, K] tensor or a CsrModel;
+    log_b [T, >=K] (row stride = ld), log_pi [K] or None; all float32 CUDA
+    tensors.  rows: "auto", "wide" or "local" row placement of dense models
+    (same results).  Returns (path int32 [T], score float32 [1], status
+    int32 [1]) on the device."""
+    model, K, dev = _model(log_a)
     _need(log_b, "log_b")
     if log_b.dim() != 2 or log_b.stride(1) != 1:
         raise ValueError("log_b must be [T, ld] with unit column stride")
     if log_pi is not None:
         _need(log_pi, "log_pi")
-        if not log_pi.is_contiguous() or log_pi.numel() != log_a.shape[0]:
+        if not log_pi.is_contiguous() or log_pi.numel() != K:
             raise ValueError("log_pi must be a contiguous [K] tensor")
-    dev = log_a.device
     T, ld = log_b.shape[0], log_b.stride(0)
     path = torch.empty(T, dtype=torch.int32, device=dev)
     score = torch.empty(1, dtype=torch.float32, device=dev)
@@ -142,14 +174,14 @@ class Batch:
         self.desc = host.to(dev)
 
 
-def decode_batch(log_a: torch.Tensor, batch: Batch, log_pi: torch.Tensor | None = None,
+def decode_batch(log_a, batch: Batch, log_pi: torch.Tensor | None = None,
                  method: str = "flash", P: int = 16, B: int = 0, ws: torch.Tensor | None = None,
                  rows: str = "auto"):
-    """Decode all sequences of `batch` in one persistent launch; results land
-    in batch.paths / batch.scores / batch.status.  Returns the workspace
-    tensor so callers can reuse it."""
-    model = dense_model(log_a)
-    dev = log_a.device
+    """Decode all sequences of `batch` in one persistent launch (log_a: dense
+    [K, K] tensor or a CsrModel); results land in batch.paths /
+    batch.scores / batch.status.  Returns the workspace tensor so callers
+    can reuse it."""
+    model, _, dev = _model(log_a)
     n = workspace_bytes(method, model, batch.lengths, P, B)
     if ws is None or ws.numel() < n:
         ws = _workspace(n, dev)

@@ -76,9 +76,38 @@ def test_decode_argument_errors_are_synchronous(fv):
     assert l.fv_decode_flash(C.byref(m), None, fake, 8, 0, 4, fake, fake, None, 0, fake, 1 << 20, None) == -1
     # workspace too small is caught on the host
     assert l.fv_decode_vanilla(C.byref(m), None, fake, 8, 5, fake, fake, None, 0, fake, 16, None) == -3
+    # malformed CSR descriptors and flags that do not apply to them
+    for bad in (fv._lib.FvTrans(1, 8, None, fake, fake, fake, -1),     # nnz < 0
+                fv._lib.FvTrans(1, 8, None, None, fake, fake, 3),      # no row_ptr
+                fv._lib.FvTrans(1, 8, None, fake, None, fake, 3),      # no col
+                fv._lib.FvTrans(7, 8, None, fake, fake, fake, 3)):     # unknown kind
+        assert l.fv_decode_vanilla(C.byref(bad), None, fake, 8, 5, fake, fake, None, 0, fake, 1 << 20, None) == -1
     csr = fv._lib.FvTrans(1, 8, None, fake, fake, fake, 3)
-    assert l.fv_decode_vanilla(C.byref(csr), None, fake, 8, 5, fake, fake, None, 0, fake, 1 << 20, None) == -2
+    assert l.fv_decode_flash(C.byref(csr), None, fake, 8, 5, 4, fake, fake, None, fv._lib.FV_FLAG_WIDE_ROWS,
+                             fake, 1 << 20, None) == -1
+    assert l.fv_decode_vanilla(C.byref(csr), None, fake, 8, 5, fake, fake, None, 0, fake, 16, None) == -3
     assert l.fv_last_error()
+
+
+def test_sparse_workspace_size(fv):
+    d = fv
+    fake = 4096
+    K, nnz = 100000, 900000
+    m = fv._lib.FvTrans(1, K, None, fake, fake, fake, nnz)
+    lens = [2000] * 4
+    v = d.workspace_bytes("vanilla", m, lens)
+    f = d.workspace_bytes("flash", m, lens, P=16)
+    b = d.workspace_bytes("beam", m, lens, P=16, B=128)
+    # the in-edge transpose (pointers + sources + scores + scratch) is part of every sparse plan
+    assert f >= (K + 1) * 4 + 3 * nnz * 4
+    # vanilla keeps a uint16 in-edge slot per state and step
+    assert v >= sum(lens) * K * 2
+    assert f < v and b < v
+    # no dense beam limit on K for sparse models; B is bounded
+    assert d.workspace_bytes("beam", fv._lib.FvTrans(1, 1 << 20, None, fake, fake, fake, 9 << 20), [50],
+                             P=4, B=64) > 0
+    with pytest.raises(fv.FvError):
+        d.workspace_bytes("beam", fv._lib.FvTrans(1, 10000, None, fake, fake, fake, 30), [50], P=4, B=4096)
 
 
 def test_backward_workspace_size(fv):
