@@ -184,7 +184,7 @@ fv_status plan_dense(int32_t method, const fv_trans* A, const int32_t* T_host, i
     L.n_slots = (int32_t)slots;
     L.pool = L.n_slots / kXcd;
     size_t cur = 0;
-    put(cur, L.Ap, L.Kp != K ? (size_t)L.Kp * L.Kp * 4 : 0);  // padded copy only when needed
+    put(cur, L.Ap, (!sparse && L.Kp != K) ? (size_t)L.Kp * L.Kp * 4 : 0);  // padded dense copy only when needed
     put(cur, L.seq1, single ? sizeof(fv_seq) : 0);
     put(cur, L.seqinfo, (size_t)std::max(n_seqs, 1) * sizeof(SeqInfo));
     put(cur, L.keys, (size_t)std::max(n_seqs, 1) * 8);
