@@ -137,12 +137,17 @@ fv_status fv_decode_beam(const fv_trans* A, const float* log_pi, const float* lo
                          size_t ws_bytes, fv_stream_t stream);
 
 /* Many sequences, uneven lengths, one persistent launch.  models: host
- * array [n_models]; log_pi: host array of n_models device pointers (entries
- * may be NULL); seqs_dev: device array [n_seqs]; T_host / model_host: host
- * copies of each sequence's T and model (used to lay out the workspace; the
- * device copies must agree, otherwise every status is FV_E_INVALID_ARG).
- * method FV_VANILLA / FV_FLASH / FV_BEAM with P, B as above.  Each
- * sequence's result equals the single-sequence call's. */
+ * array [n_models] (dense and CSR models may be mixed, K may differ);
+ * log_pi: host array of n_models device pointers (entries may be NULL);
+ * seqs_dev: device array [n_seqs]; T_host / model_host: host copies of each
+ * sequence's T and model index (they lay out the workspace; model_host may
+ * be NULL only when n_models == 1).  The device copies must agree: a model
+ * index outside [0, n_models) or counts that differ from the host's make
+ * the affected statuses FV_E_INVALID_ARG.  The launch decodes the models'
+ * sequence sets one after the other, each with its own rows and buffers.
+ * method FV_VANILLA / FV_FLASH / FV_BEAM with P, B as above (B >= K_m makes
+ * model m's decode FLASH).  Each sequence's result equals the
+ * single-sequence call's. */
 fv_status fv_decode_batch(const fv_trans* models, const float* const* log_pi, int32_t n_models,
                           const fv_seq* seqs_dev, const int32_t* T_host,
                           const int32_t* model_host, int32_t n_seqs, int32_t method,

@@ -10,7 +10,9 @@
 #include "fv_internal.h"
 
 namespace fv {
-extern "C" __global__ void fv_engine_kernel(const float* __restrict__ Ap, const EngineArgs* __restrict__ args);
+extern "C" __global__ void fv_engine_kernel(const EngineArgs* __restrict__ table, int32_t n_models);
+extern "C" __global__ void fv_model_check_kernel(const fv_seq* seqs_dev, int32_t n_seqs, int32_t n_models,
+                                                 int32_t* status);
 extern "C" __global__ void fv_prep_dense_kernel(const float* __restrict__ log_a, int32_t K, int32_t Kp,
                                                 float* __restrict__ Ap);
 extern "C" __global__ void fv_setup_kernel(EngineArgs a, SetupArgs sa);
@@ -283,121 +285,204 @@ bool use_wide_rows(uint32_t flags, int32_t K, int32_t n_seqs, bool sparse) {
     return K >= 4096 || (K >= 1024 && n_seqs <= 4);
 }
 
-fv_status run_dense(int32_t method, const fv_trans* A, const float* log_pi, const fv_seq* seqs_dev,
-                    const int32_t* T_host, int32_t n_seqs, int32_t P, int32_t B, const fv_seq* single,
-                    int32_t* status, uint32_t flags, void* ws, size_t ws_bytes, hipStream_t stream) {
+// Beam widths of at least K keep every state: that is FLASH decoding.
+int32_t effective_method(int32_t method, const fv_trans* A, int32_t B) {
+    return (method == FV_BEAM && A && B >= A->K) ? FV_FLASH : method;
+}
+
+// Workspace of a batch: the engine's table of per-model argument blocks,
+// then one region per model that has sequences (its own plan).
+struct BatchPlan {
+    Region table;
+    std::vector<int32_t> model;     // model index of each planned decode
+    std::vector<int32_t> method;    // its effective method
+    std::vector<DenseLayout> L;
+    std::vector<size_t> base;       // byte offset of its region
+    size_t total = 0;
+};
+
+fv_status plan_batch(int32_t method, const fv_trans* models, int32_t n_models, const int32_t* T_host,
+                     const int32_t* model_host, int32_t n_seqs, int32_t P, int32_t B, bool single, BatchPlan& bp) {
+    bp = BatchPlan{};
+    if (!models || n_models < 1) return fail(FV_E_INVALID_ARG, "need at least one transition model");
+    if (n_models > 1 && n_seqs > 0 && !model_host)
+        return fail(FV_E_INVALID_ARG, "model_host is required when n_models > 1");
+    for (int32_t m = 0; m < n_models; ++m) {
+        fv_status rc = check_model(&models[m]);
+        if (rc != FV_OK) return fail(rc, "model %d: %s", m, g_last_error.c_str());
+    }
+    std::vector<std::vector<int32_t>> lens(n_models);
+    for (int32_t b = 0; b < n_seqs; ++b) {
+        const int32_t mi = model_host ? model_host[b] : 0;
+        if (mi < 0 || mi >= n_models) return fail(FV_E_INVALID_ARG, "sequence %d has model %d", b, mi);
+        lens[mi].push_back(T_host[b]);
+    }
+    int32_t n_plans = 0;
+    for (int32_t m = 0; m < n_models; ++m) n_plans += !lens[m].empty();
+    size_t cur = 0;
+    put(cur, bp.table, (size_t)std::max(n_plans, 1) * sizeof(EngineArgs));
+    for (int32_t m = 0; m < n_models; ++m) {
+        if (lens[m].empty()) continue;
+        const int32_t eff = effective_method(method, &models[m], B);
+        DenseLayout L;
+        fv_status rc = plan_dense(eff, &models[m], lens[m].data(), (int32_t)lens[m].size(), P, B, single, L);
+        if (rc != FV_OK) return n_models > 1 ? fail(rc, "model %d: %s", m, g_last_error.c_str()) : rc;
+        const size_t base = (cur + kAlign - 1) / kAlign * kAlign;
+        bp.model.push_back(m);
+        bp.method.push_back(eff);
+        bp.L.push_back(L);
+        bp.base.push_back(base);
+        cur = base + L.total;
+    }
+    bp.total = (cur + kAlign - 1) / kAlign * kAlign;
+    return FV_OK;
+}
+
+fv_status check_flags(uint32_t flags, const fv_trans* models, int32_t n_models) {
     if ((flags & FV_FLAG_WIDE_ROWS) && (flags & FV_FLAG_LOCAL_ROWS))
         return fail(FV_E_INVALID_ARG, "FV_FLAG_WIDE_ROWS and FV_FLAG_LOCAL_ROWS exclude each other");
     if (flags & ~(uint32_t)(FV_FLAG_WIDE_ROWS | FV_FLAG_LOCAL_ROWS))
         return fail(FV_E_INVALID_ARG, "unknown flags 0x%x", flags);
-    fv_status rc = check_model(A);
+    if (flags & FV_FLAG_WIDE_ROWS)
+        for (int32_t m = 0; models && m < n_models; ++m)
+            if (models[m].kind == FV_CSR) return fail(FV_E_INVALID_ARG, "FV_FLAG_WIDE_ROWS applies to dense models only");
+    return FV_OK;
+}
+
+// Decodes every sequence of seqs_dev (or the one sequence `single`) with
+// its model: per model, the preparation kernels and the setup kernel, then
+// one persistent engine launch for all models, then the finish kernels.
+fv_status run_batch(int32_t method, const fv_trans* models, const float* const* log_pi, int32_t n_models,
+                    const fv_seq* seqs_dev, const int32_t* T_host, const int32_t* model_host, int32_t n_seqs,
+                    int32_t P, int32_t B, const fv_seq* single, int32_t* status, uint32_t flags, void* ws,
+                    size_t ws_bytes, hipStream_t stream) {
+    fv_status rc = check_flags(flags, models, n_models);
     if (rc != FV_OK) return rc;
-    const bool sparse = A->kind == FV_CSR;
-    if (sparse && (flags & FV_FLAG_WIDE_ROWS))
-        return fail(FV_E_INVALID_ARG, "FV_FLAG_WIDE_ROWS applies to dense models only");
-    DenseLayout L;
-    rc = plan_dense(method, A, T_host, n_seqs, P, B, single != nullptr, L);
+    BatchPlan bp;
+    rc = plan_batch(method, models, n_models, T_host, model_host, n_seqs, P, B, single != nullptr, bp);
     if (rc != FV_OK) return rc;
-    if (!ws || ws_bytes < L.total)
-        return fail(FV_E_WORKSPACE, "workspace of %zu bytes is smaller than the %zu bytes required", ws_bytes, L.total);
+    if (!ws || ws_bytes < bp.total)
+        return fail(FV_E_WORKSPACE, "workspace of %zu bytes is smaller than the %zu bytes required", ws_bytes, bp.total);
     if (reinterpret_cast<uintptr_t>(ws) % kAlign)
         return fail(FV_E_INVALID_ARG, "workspace must be %zu-byte aligned", kAlign);
+    if (bp.L.empty()) return FV_OK;   // no sequences
     DeviceInfo di;
     rc = device_info(di);
     if (rc != FV_OK) return rc;
+    const int32_t n_compute = std::min(di.cus, kMaxBlocks) - 1;
+    if (n_compute < kXcd) return fail(FV_E_UNSUPPORTED, "device has too few compute units");
 
-    char* w = static_cast<char*>(ws);
-    auto at = [&](const Region& r) { return static_cast<void*>(w + r.off); };
-    if (single) {
-        hipLaunchKernelGGL(write_seq_kernel, dim3(1), dim3(1), 0, stream, static_cast<fv_seq*>(at(L.seq1)), *single);
-        seqs_dev = static_cast<const fv_seq*>(at(L.seq1));
-    }
-    const float* Ap = sparse ? nullptr : A->log_a;
-    if (sparse) launch_transpose(A, L, w, stream);
-    if (!sparse && L.Kp != A->K) {
-        float* pad = static_cast<float*>(at(L.Ap));
-        const int64_t cells = (int64_t)L.Kp * L.Kp;
-        hipLaunchKernelGGL(fv_prep_dense_kernel, dim3((unsigned)((cells + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                           stream, A->log_a, A->K, L.Kp, pad);
-        Ap = pad;
-    }
-
-    EngineArgs a{};
-    a.K = A->K;
-    a.Kp = L.Kp;
-    a.log_pi = log_pi;
-    a.Acol = Ap;
-    a.seqs = static_cast<SeqInfo*>(at(L.seqinfo));
-    a.n_seqs = n_seqs;
-    a.method = method;
-    a.slot_base = static_cast<float*>(at(L.slots));
-    a.slot_floats = L.slot_floats;
-    a.n_slots = L.n_slots;
-    a.has_anc = L.has_anc;
-    a.wide = use_wide_rows(flags, A->K, n_seqs, sparse) ? 1 : 0;
-    if (sparse) {
-        a.sparse = 1;
-        a.nnz = A->nnz;
-        a.row_ptr = A->row_ptr;
-        a.col = A->col;
-        a.val = A->val;
-        a.in_ptr = static_cast<const int32_t*>(at(L.csr_ptr));
-        a.in_src = static_cast<const int32_t*>(at(L.csr_src));
-        a.in_val = static_cast<const float*>(at(L.csr_val));
-        a.csr_flag = static_cast<int32_t*>(at(L.csr_flag));
-    }
-    a.alpha_at = static_cast<float*>(at(L.alpha));
-    a.root_copy = static_cast<float*>(at(L.root));
-    a.psi16 = static_cast<uint16_t*>(at(L.psi));
-    a.keys = static_cast<unsigned long long*>(at(L.keys));
-    a.st = static_cast<EngineState*>(at(L.state));
-    a.arrive = static_cast<uint32_t*>(at(L.arrive));
-    a.rows_full = static_cast<Row*>(at(L.rows_full));
-    a.rows_light = static_cast<Row*>(at(L.rows_light));
-    a.rows_beam = static_cast<Row*>(at(L.rows_beam));
-    a.B = L.B;
-    a.Bc = L.Bc;
-    a.brec = L.brec;
-    a.bw = L.bw;
-    a.pool = L.pool;
-    a.queue = static_cast<Task*>(at(L.queue));
-    a.q_cap = L.q_cap;
-    a.free_stack = static_cast<int32_t*>(at(L.free_stack));
-    // one engine block per CU: block 0 schedules, the others compute
-    a.n_compute_blocks = std::min(di.cus, kMaxBlocks) - 1;
-    if (a.n_compute_blocks < kXcd) return fail(FV_E_UNSUPPORTED, "device has too few compute units");
-    a.spin_limit = (int64_t)1 << 24;
-    // beam: exact re-decodes add at most one pass per subtask
-    a.max_steps = (method == FV_BEAM ? 16 : 8) * (L.sum_T + L.n_tasks) + 4096;
-
-    SetupArgs sa{};
-    sa.seqs_dev = seqs_dev;
-    sa.n_seqs = n_seqs;
-    sa.P = P;
-    sa.host_sum_T = L.sum_T;
-    sa.host_sum_root = L.sum_root;
-    sa.host_sum_psi = L.sum_psi;
-    sa.kind = method == FV_VANILLA ? KIND_VANILLA : (method == FV_BEAM ? KIND_BROOT : KIND_ROOT);
-    sa.K = A->K;
-    sa.args_out = static_cast<EngineArgs*>(at(L.args));
-    hipLaunchKernelGGL(fv_setup_kernel, dim3(1), dim3(kBlock), 0, stream, a, sa);
-
-    if (n_seqs > 0) {
-        const EngineArgs* args_dev = sa.args_out;
-        void* args[] = {&Ap, &args_dev};
-        if (g_prof_on) HIP_TRY(hipEventRecord(g_prof_ev[0], stream));
-        HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(fv_engine_kernel),
-                                           dim3(a.n_compute_blocks + 1), dim3(kEngineBlock), args, 0, stream));
-        if (g_prof_on) {
-            HIP_TRY(hipEventRecord(g_prof_ev[1], stream));
-            g_prof_recorded = true;
+    char* const w0 = static_cast<char*>(ws);
+    EngineArgs* table = reinterpret_cast<EngineArgs*>(w0 + bp.table.off);
+    std::vector<EngineArgs> args(bp.L.size());
+    std::vector<const float*> aps(bp.L.size());
+    for (size_t p = 0; p < bp.L.size(); ++p) {
+        const DenseLayout& L = bp.L[p];
+        const fv_trans* A = &models[bp.model[p]];
+        const int32_t meth = bp.method[p];
+        const int32_t n_local = L.n_seqs;
+        const bool sparse = A->kind == FV_CSR;
+        char* w = w0 + bp.base[p];
+        auto at = [&](const Region& r) { return static_cast<void*>(w + r.off); };
+        const fv_seq* sd = seqs_dev;
+        if (single) {
+            hipLaunchKernelGGL(write_seq_kernel, dim3(1), dim3(1), 0, stream, static_cast<fv_seq*>(at(L.seq1)), *single);
+            sd = static_cast<const fv_seq*>(at(L.seq1));
         }
-        if (method == FV_BEAM)
-            hipLaunchKernelGGL(fv_beam_finish_kernel, dim3((n_seqs + kWaves - 1) / kWaves), dim3(kBlock), 0, stream,
-                               a, Ap, status);
+        const float* Ap = sparse ? nullptr : A->log_a;
+        if (sparse) launch_transpose(A, L, w, stream);
+        if (!sparse && L.Kp != A->K) {
+            float* pad = static_cast<float*>(at(L.Ap));
+            const int64_t cells = (int64_t)L.Kp * L.Kp;
+            hipLaunchKernelGGL(fv_prep_dense_kernel, dim3((unsigned)((cells + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                               stream, A->log_a, A->K, L.Kp, pad);
+            Ap = pad;
+        }
+        aps[p] = Ap;
+        EngineArgs& a = args[p];
+        a = EngineArgs{};
+        a.K = A->K;
+        a.Kp = L.Kp;
+        a.log_pi = log_pi ? log_pi[bp.model[p]] : nullptr;
+        a.Acol = Ap;
+        a.seqs = static_cast<SeqInfo*>(at(L.seqinfo));
+        a.n_seqs = n_local;
+        a.method = meth;
+        a.slot_base = static_cast<float*>(at(L.slots));
+        a.slot_floats = L.slot_floats;
+        a.n_slots = L.n_slots;
+        a.has_anc = L.has_anc;
+        a.wide = use_wide_rows(flags, A->K, n_local, sparse) ? 1 : 0;
+        if (sparse) {
+            a.sparse = 1;
+            a.nnz = A->nnz;
+            a.row_ptr = A->row_ptr;
+            a.col = A->col;
+            a.val = A->val;
+            a.in_ptr = static_cast<const int32_t*>(at(L.csr_ptr));
+            a.in_src = static_cast<const int32_t*>(at(L.csr_src));
+            a.in_val = static_cast<const float*>(at(L.csr_val));
+            a.csr_flag = static_cast<int32_t*>(at(L.csr_flag));
+        }
+        a.alpha_at = static_cast<float*>(at(L.alpha));
+        a.root_copy = static_cast<float*>(at(L.root));
+        a.psi16 = static_cast<uint16_t*>(at(L.psi));
+        a.keys = static_cast<unsigned long long*>(at(L.keys));
+        a.st = static_cast<EngineState*>(at(L.state));
+        a.arrive = static_cast<uint32_t*>(at(L.arrive));
+        a.rows_full = static_cast<Row*>(at(L.rows_full));
+        a.rows_light = static_cast<Row*>(at(L.rows_light));
+        a.rows_beam = static_cast<Row*>(at(L.rows_beam));
+        a.B = L.B;
+        a.Bc = L.Bc;
+        a.brec = L.brec;
+        a.bw = L.bw;
+        a.pool = L.pool;
+        a.queue = static_cast<Task*>(at(L.queue));
+        a.q_cap = L.q_cap;
+        a.free_stack = static_cast<int32_t*>(at(L.free_stack));
+        // one engine block per CU: block 0 schedules, the others compute
+        a.n_compute_blocks = n_compute;
+        a.spin_limit = (int64_t)1 << 24;
+        // beam: exact re-decodes add at most one pass per subtask
+        a.max_steps = (meth == FV_BEAM ? 16 : 8) * (L.sum_T + L.n_tasks) + 4096;
+
+        SetupArgs sa{};
+        sa.seqs_dev = sd;
+        sa.n_seqs = single ? 1 : n_seqs;
+        sa.P = P;
+        sa.host_sum_T = L.sum_T;
+        sa.host_sum_root = L.sum_root;
+        sa.host_sum_psi = L.sum_psi;
+        sa.kind = meth == FV_VANILLA ? KIND_VANILLA : (meth == FV_BEAM ? KIND_BROOT : KIND_ROOT);
+        sa.K = A->K;
+        sa.model = single ? 0 : bp.model[p];
+        sa.n_local = n_local;
+        sa.args_out = table + p;
+        hipLaunchKernelGGL(fv_setup_kernel, dim3(1), dim3(kBlock), 0, stream, a, sa);
+    }
+    if (status && !single && n_models > 1)
+        hipLaunchKernelGGL(fv_model_check_kernel, dim3((n_seqs + kBlock - 1) / kBlock), dim3(kBlock), 0, stream,
+                           seqs_dev, n_seqs, n_models, status);
+
+    const EngineArgs* table_dev = table;
+    int32_t n_tab = (int32_t)bp.L.size();
+    void* kargs[] = {&table_dev, &n_tab};
+    if (g_prof_on) HIP_TRY(hipEventRecord(g_prof_ev[0], stream));
+    HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(fv_engine_kernel), dim3(n_compute + 1),
+                                       dim3(kEngineBlock), kargs, 0, stream));
+    if (g_prof_on) {
+        HIP_TRY(hipEventRecord(g_prof_ev[1], stream));
+        g_prof_recorded = true;
+    }
+    for (size_t p = 0; p < bp.L.size(); ++p) {
+        const int32_t n_local = bp.L[p].n_seqs;
+        if (bp.method[p] == FV_BEAM)
+            hipLaunchKernelGGL(fv_beam_finish_kernel, dim3((n_local + kWaves - 1) / kWaves), dim3(kBlock), 0, stream,
+                               args[p], aps[p], status);
         else
-            hipLaunchKernelGGL(fv_finish_kernel, dim3((n_seqs + kBlock - 1) / kBlock), dim3(kBlock), 0, stream,
-                               a, status);
+            hipLaunchKernelGGL(fv_finish_kernel, dim3((n_local + kBlock - 1) / kBlock), dim3(kBlock), 0, stream,
+                               args[p], status);
     }
     HIP_TRY(hipGetLastError());
     return FV_OK;
@@ -442,82 +527,68 @@ fv_status fv_profile_engine_ms(float* ms) {
     return FV_OK;
 }
 
-// Beam widths of at least K keep every state: that is FLASH decoding.
-static int32_t effective_method(int32_t method, const fv_trans* A, int32_t B) {
-    return (method == FV_BEAM && A && B >= A->K) ? FV_FLASH : method;
-}
 
 fv_status fv_workspace_size(int32_t method, const fv_trans* models, int32_t n_models,
                             const int32_t* T_host, const int32_t* model_host, int32_t n_seqs,
                             int32_t P, int32_t B, size_t* bytes) {
-    (void)model_host;
     if (!bytes) return fail(FV_E_INVALID_ARG, "null bytes");
-    if (n_models != 1) return fail(FV_E_UNSUPPORTED, "exactly one model per call is supported");
     if (n_seqs < 0 || (n_seqs > 0 && !T_host)) return fail(FV_E_INVALID_ARG, "bad sequence list");
-    fv_status rc = check_model(models);
-    if (rc != FV_OK) return rc;
     if (method != FV_VANILLA && method != FV_FLASH && method != FV_BEAM)
         return fail(FV_E_INVALID_ARG, "unknown method %d", method);
     if (method == FV_BEAM && (B < 1 || P < 1)) return fail(FV_E_INVALID_ARG, "beam decoding needs B >= 1 and P >= 1");
     if (method == FV_FLASH && P <= 0) P = 16;
-    method = effective_method(method, models, B);
-    DenseLayout L;
+    BatchPlan bp;
     // single-sequence calls reserve room for their device descriptor too
-    rc = plan_dense(method, models, T_host, n_seqs, P, B, n_seqs == 1, L);
+    fv_status rc = plan_batch(method, models, n_models, T_host, model_host, n_seqs, P, B, n_seqs == 1, bp);
     if (rc != FV_OK) return rc;
-    *bytes = L.total;
+    *bytes = bp.total;
     return FV_OK;
+}
+
+static fv_status decode_one(int32_t method, const fv_trans* A, const float* log_pi, const float* log_b, int64_t ld,
+                            int32_t T, int32_t P, int32_t B, int32_t* path, float* score, int32_t* status,
+                            uint32_t flags, void* ws, size_t ws_bytes, fv_stream_t stream) {
+    if (T < 1) return fail(FV_E_INVALID_ARG, "T must be >= 1 (got %d)", T);
+    if (!A || !log_b || !path || !score) return fail(FV_E_INVALID_ARG, "null argument");
+    if (ld < A->K) return fail(FV_E_INVALID_ARG, "ld=%lld < K=%d", (long long)ld, A->K);
+    fv_seq s{0, T, log_b, ld, path, score};
+    const float* pis[1] = {log_pi};
+    return run_batch(method, A, pis, 1, nullptr, &T, nullptr, 1, P, B, &s, status, flags, ws, ws_bytes,
+                     reinterpret_cast<hipStream_t>(stream));
 }
 
 fv_status fv_decode_vanilla(const fv_trans* A, const float* log_pi, const float* log_b, int64_t ld,
                             int32_t T, int32_t* path, float* score, int32_t* status, uint32_t flags,
                             void* ws, size_t ws_bytes, fv_stream_t stream) {
-    if (T < 1) return fail(FV_E_INVALID_ARG, "T must be >= 1 (got %d)", T);
-    if (!A || !log_b || !path || !score) return fail(FV_E_INVALID_ARG, "null argument");
-    if (ld < A->K) return fail(FV_E_INVALID_ARG, "ld=%lld < K=%d", (long long)ld, A->K);
-    fv_seq s{0, T, log_b, ld, path, score};
-    return run_dense(FV_VANILLA, A, log_pi, nullptr, &T, 1, 1, 0, &s, status, flags, ws, ws_bytes,
-                     reinterpret_cast<hipStream_t>(stream));
+    return decode_one(FV_VANILLA, A, log_pi, log_b, ld, T, 1, 0, path, score, status, flags, ws, ws_bytes, stream);
 }
 
 fv_status fv_decode_flash(const fv_trans* A, const float* log_pi, const float* log_b, int64_t ld,
                           int32_t T, int32_t P, int32_t* path, float* score, int32_t* status,
                           uint32_t flags, void* ws, size_t ws_bytes, fv_stream_t stream) {
-    if (T < 1) return fail(FV_E_INVALID_ARG, "T must be >= 1 (got %d)", T);
-    if (!A || !log_b || !path || !score) return fail(FV_E_INVALID_ARG, "null argument");
-    if (ld < A->K) return fail(FV_E_INVALID_ARG, "ld=%lld < K=%d", (long long)ld, A->K);
-    if (P <= 0) P = 16;
-    fv_seq s{0, T, log_b, ld, path, score};
-    return run_dense(FV_FLASH, A, log_pi, nullptr, &T, 1, P, 0, &s, status, flags, ws, ws_bytes,
-                     reinterpret_cast<hipStream_t>(stream));
+    return decode_one(FV_FLASH, A, log_pi, log_b, ld, T, P <= 0 ? 16 : P, 0, path, score, status, flags, ws,
+                      ws_bytes, stream);
 }
 
 fv_status fv_decode_beam(const fv_trans* A, const float* log_pi, const float* log_b, int64_t ld, int32_t T,
                          int32_t B, int32_t P, int32_t* path, float* score, int32_t* status, uint32_t flags,
                          void* ws, size_t ws_bytes, fv_stream_t stream) {
-    if (T < 1) return fail(FV_E_INVALID_ARG, "T must be >= 1 (got %d)", T);
-    if (!A || !log_b || !path || !score) return fail(FV_E_INVALID_ARG, "null argument");
-    if (ld < A->K) return fail(FV_E_INVALID_ARG, "ld=%lld < K=%d", (long long)ld, A->K);
     if (B < 1 || P < 1) return fail(FV_E_INVALID_ARG, "beam decoding needs B >= 1 and P >= 1");
-    fv_seq s{0, T, log_b, ld, path, score};
-    return run_dense(effective_method(FV_BEAM, A, B), A, log_pi, nullptr, &T, 1, P, B, &s, status, flags, ws,
-                     ws_bytes, reinterpret_cast<hipStream_t>(stream));
+    return decode_one(FV_BEAM, A, log_pi, log_b, ld, T, P, B, path, score, status, flags, ws, ws_bytes, stream);
 }
 
 fv_status fv_decode_batch(const fv_trans* models, const float* const* log_pi, int32_t n_models,
                           const fv_seq* seqs_dev, const int32_t* T_host, const int32_t* model_host,
                           int32_t n_seqs, int32_t method, int32_t P, int32_t B, int32_t* status,
                           uint32_t flags, void* ws, size_t ws_bytes, fv_stream_t stream) {
-    (void)model_host;
-    if (n_models != 1) return fail(FV_E_UNSUPPORTED, "exactly one model per call is supported");
     if (n_seqs < 0) return fail(FV_E_INVALID_ARG, "n_seqs < 0");
     if (n_seqs > 0 && (!seqs_dev || !T_host)) return fail(FV_E_INVALID_ARG, "null sequence list");
     if (method != FV_VANILLA && method != FV_FLASH && method != FV_BEAM)
         return fail(FV_E_INVALID_ARG, "unknown method %d", method);
     if (method == FV_BEAM && (B < 1 || P < 1)) return fail(FV_E_INVALID_ARG, "beam decoding needs B >= 1 and P >= 1");
     if (method == FV_FLASH && P <= 0) P = 16;
-    return run_dense(effective_method(method, models, B), models, log_pi ? log_pi[0] : nullptr, seqs_dev,
-                     T_host, n_seqs, P, B, nullptr, status, flags, ws, ws_bytes, reinterpret_cast<hipStream_t>(stream));
+    return run_batch(method, models, log_pi, n_models, seqs_dev, T_host, model_host, n_seqs, P, B, nullptr, status,
+                     flags, ws, ws_bytes, reinterpret_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

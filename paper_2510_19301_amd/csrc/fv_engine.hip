@@ -808,21 +808,41 @@ __device__ __noinline__ void light_row(cargs_t& a_in, const float* __restrict__ 
             if (q >= K) q = -1;
         }
         unsigned long long best_key = 0;
-        for (int32_t j = lane; j < Kp; j += 64) {
-            float v = -INFINITY;
-            if (j < K) {
-                if (m == 0) v = a.log_pi ? a.log_pi[j] + bm[j] : bm[j];
-                else if (q >= 0) { const float c = alpha + Ap[(int64_t)q * Kp + j]; v = c + bm[j]; }
-                if (r.flags & F_SNAP_SUB) slot_snap(a, slot)[j] = v;
-                if (r.flags & F_SNAP_ROOT) root_dsnap(a, r.off, 0)[j] = v;
-                if (r.flags & F_FINAL) {
-                    const unsigned long long k = order_key(v, j);
-                    if (k > best_key) best_key = k;
+        const float* arow = Ap + (int64_t)(q < 0 ? 0 : q) * Kp;
+        // 8 destinations per lane per round: every load of a round is issued
+        // before its stores (which might alias them)
+        for (int32_t j0 = lane; j0 < Kp; j0 += 64 * 8) {
+            float bv[8], xv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int32_t j = j0 + 64 * u;
+                bv[u] = 0.0f;
+                xv[u] = 0.0f;
+                if (j < K) {
+                    bv[u] = bm[j];
+                    if (m == 0) xv[u] = a.log_pi ? a.log_pi[j] : 0.0f;
+                    else if (q >= 0) xv[u] = arow[j];
                 }
-            } else {
-                oth[j] = -INFINITY;
             }
-            dst[j] = v;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int32_t j = j0 + 64 * u;
+                if (j >= Kp) break;
+                float v = -INFINITY;
+                if (j < K) {
+                    if (m == 0) v = a.log_pi ? xv[u] + bv[u] : bv[u];
+                    else if (q >= 0) { const float c = alpha + xv[u]; v = c + bv[u]; }
+                    if (r.flags & F_SNAP_SUB) slot_snap(a, slot)[j] = v;
+                    if (r.flags & F_SNAP_ROOT) root_dsnap(a, r.off, 0)[j] = v;
+                    if (r.flags & F_FINAL) {
+                        const unsigned long long k = order_key(v, j);
+                        if (k > best_key) best_key = k;
+                    }
+                } else {
+                    oth[j] = -INFINITY;
+                }
+                dst[j] = v;
+            }
         }
         if (r.flags & F_FINAL) {
             for (int off = 32; off >= 1; off >>= 1) {
@@ -851,9 +871,20 @@ __device__ __noinline__ void light_row(cargs_t& a_in, const float* __restrict__ 
             arg = arg == 0x7fffffff ? 0 : a.in_src[arg];
         } else {
             const float* ac = a.Acol + qn;  // column q*_n of log A
-            for (int32_t i = lane; i < K; i += 64) {
-                const float x = (a.wide ? ld_cf(dprev + i) : dprev[i]) + ac[(int64_t)i * Kp];
-                if (arg == 0x7fffffff || x > best) { best = x; arg = i; }
+            const bool coh = a.wide;
+            for (int32_t i0 = lane; i0 < K; i0 += 64 * 8) {   // 8 candidates per lane in flight
+                float dv[8], av[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int32_t i = min(i0 + 64 * u, K - 1);
+                    dv[u] = coh ? ld_cf(dprev + i) : dprev[i];
+                    av[u] = ac[(int64_t)i * Kp];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const float x = dv[u] + av[u];
+                    if (i0 + 64 * u < K && (arg == 0x7fffffff || x > best)) { best = x; arg = i0 + 64 * u; }
+                }
             }
             wave_argmax(best, arg);
         }
@@ -2089,9 +2120,8 @@ __device__ void run_units(cargs_t& a, const float* __restrict__ Ap, uint32_t x, 
     }
 }
 
-extern "C" __global__ __launch_bounds__(kEngBlock) void fv_engine_kernel(const float* __restrict__ Ap,
-                                                                         const EngineArgs* __restrict__ args) {
-    cargs_t& a = *reinterpret_cast<cargs_t*>(reinterpret_cast<uint64_t>(args));
+// Every step of one model's decode (its own state, lists and buffers).
+__device__ void engine_model(cargs_t& a, const float* __restrict__ Ap) {
     const bool is_sched = blockIdx.x == 0;
     const uint32_t x = my_xcd();
     __shared__ int32_t s_rank;
@@ -2138,6 +2168,17 @@ extern "C" __global__ __launch_bounds__(kEngBlock) void fv_engine_kernel(const f
     if (is_sched && threadIdx.x == 0) st_c(&a.st->steps, s);
 }
 
+// One cooperative launch decodes the batches of n_models models in turn
+// (table: their argument blocks, in the workspace).
+extern "C" __global__ __launch_bounds__(kEngBlock) void fv_engine_kernel(const EngineArgs* __restrict__ table,
+                                                                         int32_t n_models) {
+    for (int32_t mi = 0; mi < n_models; ++mi) {
+        __syncthreads();
+        cargs_t& a = *reinterpret_cast<cargs_t*>(reinterpret_cast<uint64_t>(table + mi));
+        engine_model(a, a.Acol);
+    }
+}
+
 // ---------------------------------------------------------------- preparation kernel
 // Ap[i][j] = log A(i, j) on a Kp x Kp grid, -inf outside K x K (only used
 // when K is not a multiple of the padding granularity).
@@ -2150,42 +2191,44 @@ extern "C" __global__ __launch_bounds__(kBlock) void fv_prep_dense_kernel(const 
     Ap[idx] = (i < K && j < K) ? log_a[(int64_t)i * K + j] : -INFINITY;
 }
 
-// Per-sequence setup and the first step's row list (one block).
-
+// Per-sequence setup and the first step's row list (one block).  The
+// decode covers the sequences of the caller's array whose model index is
+// sa.model, in their order; their local index is their rank among them.
 extern "C" __global__ __launch_bounds__(kBlock) void fv_setup_kernel(EngineArgs a, SetupArgs sa) {
     if (threadIdx.x == 0) *sa.args_out = a;
-    __shared__ int64_t scan[3][kBlock];
+    __shared__ int64_t scan[4][kBlock];
     __shared__ int32_t s_bad;
     const int tid = threadIdx.x;
     if (tid == 0) s_bad = 0;
     __syncthreads();
-    int64_t base[3] = {0, 0, 0};
-    int32_t n_tasks = 0;
+    int64_t base[4] = {0, 0, 0, 0};
     for (int32_t b0 = 0; b0 < sa.n_seqs; b0 += kBlock) {
         const int32_t b = b0 + tid;
-        int64_t v[3] = {0, 0, 0};
+        int64_t v[4] = {0, 0, 0, 0};
         fv_seq d{};
         int32_t pp = 1;
-        if (b < sa.n_seqs) {
-            d = sa.seqs_dev[b];
-            if (d.T < 0 || d.model != 0 || (d.T > 0 && (d.ld < sa.K || !d.log_b || !d.path)) || !d.score) s_bad = 1;
+        const bool member = b < sa.n_seqs && (d = sa.seqs_dev[b]).model == sa.model;
+        if (member) {
+            if (d.T < 0 || (d.T > 0 && (d.ld < sa.K || !d.log_b || !d.path)) || !d.score) s_bad = 1;
             const int32_t T = d.T < 0 ? 0 : d.T;
             pp = sa.kind == KIND_VANILLA ? 1 : eff_parallelism(T, sa.P);
             v[0] = T;
             // root division copies: delta + link per division (dense), one beam record (beam)
             v[1] = sa.kind == KIND_ROOT ? 2 * (int64_t)(pp - 1) : (sa.kind == KIND_BROOT ? (int64_t)(pp - 1) : 0);
             v[2] = sa.kind == KIND_VANILLA ? (int64_t)T * sa.K : 0;
+            v[3] = 1;
         }
-        for (int k = 0; k < 3; ++k) scan[k][tid] = v[k];
+        for (int k = 0; k < 4; ++k) scan[k][tid] = v[k];
         __syncthreads();
         for (int off = 1; off < kBlock; off <<= 1) {
-            int64_t add[3];
-            for (int k = 0; k < 3; ++k) add[k] = tid >= off ? scan[k][tid - off] : 0;
+            int64_t add[4];
+            for (int k = 0; k < 4; ++k) add[k] = tid >= off ? scan[k][tid - off] : 0;
             __syncthreads();
-            for (int k = 0; k < 3; ++k) scan[k][tid] += add[k];
+            for (int k = 0; k < 4; ++k) scan[k][tid] += add[k];
             __syncthreads();
         }
-        if (b < sa.n_seqs) {
+        const int64_t li = base[3] + scan[3][tid] - v[3];
+        if (member && li < sa.n_local) {   // more members than the host counted: reported below
             SeqInfo si;
             si.log_b = d.log_b; si.ld = d.ld; si.path = d.path; si.score = d.score;
             si.T = d.T < 0 ? 0 : d.T;
@@ -2194,22 +2237,26 @@ extern "C" __global__ __launch_bounds__(kBlock) void fv_setup_kernel(EngineArgs 
             si.root_off = base[1] + scan[1][tid] - v[1];
             si.psi_off = base[2] + scan[2][tid] - v[2];
             si.status = FV_OK;
-            si.pad_ = 0;
-            a.seqs[b] = si;
-            a.keys[b] = 0ull;
+            si.orig = b;
+            a.seqs[li] = si;
+            a.keys[li] = 0ull;
             if (si.T == 0 && d.score) *d.score = 0.0f;
         }
-        for (int k = 0; k < 3; ++k) base[k] += scan[k][kBlock - 1];
+        for (int k = 0; k < 4; ++k) base[k] += scan[k][kBlock - 1];
         __syncthreads();
     }
-    if (base[0] != sa.host_sum_T || base[1] != sa.host_sum_root || base[2] != sa.host_sum_psi) s_bad = 1;
+    if (base[0] != sa.host_sum_T || base[1] != sa.host_sum_root || base[2] != sa.host_sum_psi ||
+        base[3] != sa.n_local)
+        s_bad = 1;
     __syncthreads();
     const bool bad = s_bad != 0;
+    const int32_t n_local = (int32_t)(base[3] < sa.n_local ? base[3] : sa.n_local);
     // task queue: every non-empty sequence's full-length pass
-    for (int32_t b0 = 0; b0 < sa.n_seqs; b0 += kBlock) {
+    int32_t n_tasks = 0;
+    for (int32_t b0 = 0; b0 < n_local; b0 += kBlock) {
         const int32_t b = b0 + tid;
         int32_t has = 0;
-        if (b < sa.n_seqs) {
+        if (b < n_local) {
             if (bad) a.seqs[b].status = FV_E_INVALID_ARG;
             has = (!bad && a.seqs[b].T > 0) ? 1 : 0;
         }
@@ -2225,6 +2272,13 @@ extern "C" __global__ __launch_bounds__(kBlock) void fv_setup_kernel(EngineArgs 
         n_tasks += (int32_t)scan[0][kBlock - 1];
         __syncthreads();
     }
+    // local sequences the setup never reached (fewer members than the host counted)
+    for (int32_t b = n_local + tid; b < sa.n_local; b += kBlock) {
+        SeqInfo si{};
+        si.status = FV_E_INVALID_ARG;
+        si.orig = -1;
+        a.seqs[b] = si;
+    }
     // slot pools: pool x holds slots x, x + kXcd, ... (free stack order is irrelevant)
     for (int32_t k = tid; k < a.n_slots; k += kBlock) {
         const int32_t x = k % kXcd, i = k / kXcd;
@@ -2236,6 +2290,15 @@ extern "C" __global__ __launch_bounds__(kBlock) void fv_setup_kernel(EngineArgs 
     for (int32_t k = tid; k < a.n_compute_blocks + 1; k += kBlock) a.arrive[k] = 0;
     __syncthreads();
     if (tid == 0) st->q_tail0 = n_tasks;
+}
+
+// Sequences whose model index is outside [0, n_models) belong to no decode.
+extern "C" __global__ __launch_bounds__(kBlock) void fv_model_check_kernel(const fv_seq* seqs_dev, int32_t n_seqs,
+                                                                           int32_t n_models, int32_t* status) {
+    const int32_t b = blockIdx.x * kBlock + threadIdx.x;
+    if (b >= n_seqs) return;
+    const int32_t m = seqs_dev[b].model;
+    if (m < 0 || m >= n_models) status[b] = FV_E_INVALID_ARG;
 }
 
 // Vanilla backtracking through the packed table and per-sequence status.
@@ -2264,7 +2327,7 @@ extern "C" __global__ __launch_bounds__(kBlock) void fv_finish_kernel(EngineArgs
             sq.path[t - 1] = q;
         }
     }
-    if (status) status[b] = stv;
+    if (status && sq.orig >= 0) status[sq.orig] = stv;
 }
 
 // Beam decodes: status, and the returned score as the step-by-step float32
@@ -2321,7 +2384,7 @@ extern "C" __global__ __launch_bounds__(kBlock) void fv_beam_finish_kernel(Engin
         if (!ok) s = -INFINITY;
         if (lane == 0) *sq.score = s;
     }
-    if (lane == 0 && status) status[b] = stv;
+    if (lane == 0 && status && sq.orig >= 0) status[sq.orig] = stv;
 }
 
 }  // namespace fv

@@ -92,7 +92,7 @@ struct SeqInfo {
     int64_t root_off;    // into root copies, in units (Kp floats, or one beam record)
     int64_t psi_off;     // into the vanilla table, in entries
     int32_t status;
-    int32_t pad_;
+    int32_t orig;        // index of the sequence in the caller's array
 };
 
 // XCD-partitioned control block.  Buffer slot s belongs to XCD s % kXcd;
@@ -176,6 +176,8 @@ struct SetupArgs {
     int64_t host_sum_psi;
     int32_t kind;           // KIND_VANILLA, KIND_ROOT or KIND_BROOT
     int32_t K;
+    int32_t model;          // this decode takes the sequences whose model index equals this
+    int32_t n_local;        // the host's count of them
     EngineArgs* args_out;   // the engine's copy of its arguments (workspace)
 };
 

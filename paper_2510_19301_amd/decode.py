@@ -128,14 +128,16 @@ def decode(log_a, log_b: torch.Tensor, log_pi: torch.Tensor | None = None,
 
 
 class Batch:
-    """Device descriptors of a batch of sequences sharing one dense model.
+    """Device descriptors of a batch of sequences.
 
-    Either a list of [T_b, K] tensors or a padded [n, Tmax, K] tensor plus
-    lengths.  Outputs are a padded int32 [n, Tmax] path tensor (entries past
-    each length untouched) and float32 [n] scores.
+    Either a list of [T_b, K_b] tensors or a padded [n, Tmax, K] tensor plus
+    lengths.  models: per-sequence model index (host ints) for batches over
+    several transition models (default: all 0).  Outputs are a padded int32
+    [n, Tmax] path tensor (entries past each length untouched) and float32
+    [n] scores.
     """
 
-    def __init__(self, log_b, lengths=None):
+    def __init__(self, log_b, lengths=None, models=None):
         if isinstance(log_b, torch.Tensor):
             _need(log_b, "log_b")
             if log_b.dim() != 3 or log_b.stride(2) != 1:
@@ -162,34 +164,67 @@ class Batch:
             self.keep = seqs
             dev = seqs[0].device if n else torch.device("cuda")
         self.n, self.tmax, self.lengths, self.device = n, tmax, lengths, dev
+        self.models = np.ascontiguousarray(np.zeros(n, np.int32) if models is None else np.asarray(models, np.int32))
+        if self.models.shape != (n,):
+            raise ValueError("models must give one model index per sequence")
         self.paths = torch.full((n, max(tmax, 1)), -1, dtype=torch.int32, device=dev)
         self.scores = torch.empty(n, dtype=torch.float32, device=dev)
         self.status = torch.empty(n, dtype=torch.int32, device=dev)
         arr = (L.FvSeq * max(n, 1))()
         for b in range(n):
-            arr[b] = L.FvSeq(0, int(lengths[b]), ptrs[b], int(ld[b]),
+            arr[b] = L.FvSeq(int(self.models[b]), int(lengths[b]), ptrs[b], int(ld[b]),
                              self.paths.data_ptr() + b * self.paths.stride(0) * 4,
                              self.scores.data_ptr() + b * 4)
         host = torch.frombuffer(bytearray(bytes(arr)), dtype=torch.uint8)
         self.desc = host.to(dev)
 
 
-def decode_batch(log_a, batch: Batch, log_pi: torch.Tensor | None = None,
-                 method: str = "flash", P: int = 16, B: int = 0, ws: torch.Tensor | None = None,
-                 rows: str = "auto"):
-    """Decode all sequences of `batch` in one persistent launch (log_a: dense
-    [K, K] tensor or a CsrModel); results land in batch.paths /
-    batch.scores / batch.status.  Returns the workspace tensor so callers
+def decode_batch(log_a, batch: Batch, log_pi=None, method: str = "flash", P: int = 16, B: int = 0,
+                 ws: torch.Tensor | None = None, rows: str = "auto"):
+    """Decode all sequences of `batch` in one persistent launch.  log_a: a
+    dense [K, K] tensor or a CsrModel, or a list of them when the batch's
+    sequences use several models (batch.models indexes it); log_pi: a [K]
+    tensor or None, or a list matching log_a.  Results land in batch.paths
+    / batch.scores / batch.status.  Returns the workspace tensor so callers
     can reuse it."""
-    model, _, dev = _model(log_a)
-    n = workspace_bytes(method, model, batch.lengths, P, B)
+    many = isinstance(log_a, (list, tuple))
+    mods = list(log_a) if many else [log_a]
+    pis = list(log_pi) if isinstance(log_pi, (list, tuple)) else [log_pi] * len(mods)
+    if len(pis) != len(mods):
+        raise ValueError("log_pi must match the list of models")
+    if not many and (batch.models != 0).any():
+        raise ValueError("batch.models refers to several models: pass a list of models")
+    trans = (L.FvTrans * len(mods))()
+    dev = None
+    for m, x in enumerate(mods):
+        t, _, d = _model(x)
+        trans[m] = t
+        dev = dev or d
+    n = workspace_bytes_models(method, trans, len(mods), batch.lengths, batch.models, P, B)
     if ws is None or ws.numel() < n:
         ws = _workspace(n, dev)
-    pis = (C.c_void_p * 1)(log_pi.data_ptr() if log_pi is not None else None)
+    pa = (C.c_void_p * len(mods))(*[p.data_ptr() if p is not None else None for p in pis])
     lengths = np.ascontiguousarray(batch.lengths, np.int32)
-    rc = L.lib().fv_decode_batch(C.byref(model), C.cast(pis, C.c_void_p), 1, batch.desc.data_ptr(),
-                                 lengths.ctypes.data, None, batch.n, L.METHODS[method], int(P),
-                                 int(B or 0), batch.status.data_ptr(), ROWS[rows], ws.data_ptr(), ws.numel(),
-                                 _stream(dev))
+    rc = L.lib().fv_decode_batch(trans, C.cast(pa, C.c_void_p), len(mods), batch.desc.data_ptr(),
+                                 lengths.ctypes.data, batch.models.ctypes.data, batch.n, L.METHODS[method],
+                                 int(P), int(B or 0), batch.status.data_ptr(), ROWS[rows], ws.data_ptr(),
+                                 ws.numel(), _stream(dev))
     L.check(rc, "fv_decode_batch")
     return ws
+
+
+def model_descriptor(log_a) -> L.FvTrans:
+    """The C descriptor of a dense [K, K] tensor or a CsrModel."""
+    return _model(log_a)[0]
+
+
+def workspace_bytes_models(method, trans, n_models, lengths, models, P, B) -> int:
+    """Workspace bytes of a batch over n_models models (trans: an FvTrans
+    array); models gives each sequence's model index."""
+    lengths = np.ascontiguousarray(np.asarray(lengths, dtype=np.int32).reshape(-1))
+    models = np.ascontiguousarray(np.asarray(models, dtype=np.int32).reshape(-1))
+    out = C.c_size_t(0)
+    L.check(L.lib().fv_workspace_size(L.METHODS[method], trans, n_models, lengths.ctypes.data,
+                                      models.ctypes.data, lengths.shape[0], int(P), int(B or 0),
+                                      C.byref(out)), "fv_workspace_size")
+    return int(out.value)

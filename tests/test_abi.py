@@ -139,3 +139,28 @@ def test_backward_argument_errors_are_synchronous(fv):
     assert l.fv_viterbi_backward(8, 2, 4, fake, fake, fake, None, fake, None, 0, C.c_void_p(4100), 1 << 30,
                                  None) == -1
     assert l.fv_last_error()
+
+
+def test_multimodel_workspace_size(fv):
+    d = fv
+    fake = 4096
+    models = (fv._lib.FvTrans * 3)(fv._lib.FvTrans(0, 64, fake, None, None, None, 0),
+                                    fv._lib.FvTrans(0, 1024, fake, None, None, None, 0),
+                                    fv._lib.FvTrans(1, 5000, None, fake, fake, fake, 45000))
+    lens = np.array([100, 2000, 300, 50], np.int32)
+    mh = np.array([0, 1, 2, 1], np.int32)
+    both = d.workspace_bytes_models("flash", models, 3, lens, mh, 16, 0)
+    parts = [d.workspace_bytes_models("flash", (fv._lib.FvTrans * 1)(models[m]), 1, lens[mh == m],
+                                              np.zeros((mh == m).sum(), np.int32), 16, 0) for m in range(3)]
+    # one region per model (plus the engine's argument table and alignment)
+    assert sum(parts) - 3 * 4096 <= both <= sum(parts) + 4096
+    # a model without sequences costs nothing
+    mh2 = np.array([0, 1, 1, 1], np.int32)
+    assert d.workspace_bytes_models("flash", models, 3, lens, mh2, 16, 0) < both
+    l = fv.lib()
+    out = C.c_size_t(0)
+    # several models need the per-sequence model indices, and they must be in range
+    assert l.fv_workspace_size(1, models, 3, lens.ctypes.data, None, 4, 16, 0, C.byref(out)) == -1
+    bad = np.array([0, 3, 0, 0], np.int32)
+    assert l.fv_workspace_size(1, models, 3, lens.ctypes.data, bad.ctypes.data, 4, 16, 0, C.byref(out)) == -1
+    assert l.fv_workspace_size(1, models, 0, lens.ctypes.data, mh.ctypes.data, 4, 16, 0, C.byref(out)) == -1
