@@ -15,7 +15,8 @@
 // "my stores are done" and reading it only an L1 invalidate.  The small
 // state shared across XCDs (row lists, counts, path entries, anchors, status)
 // is read and written with coherent (sc1) accesses.  No L2 write-back or
-// invalidate is issued per step, and log A stays resident in every L2.
+// invalidate is issued per step (except with wide rows, whose row data does
+// cross XCDs), and log A stays resident in every L2.
 //
 // Dense step of a row at time t (Sec. III-A recurrence, log domain):
 //     c(j)   = max_i delta_{t-1}(i) + log A(i, j)     (one float32 add per candidate)
@@ -1570,14 +1571,16 @@ __device__ __noinline__ void dense_finalize(cargs_t& a_in, const Row& r) {
     __shared__ int32_t sv[4];
     int32_t* buf = reinterpret_cast<int32_t*>(&lds);
     constexpr int32_t kBufInts = (int32_t)(sizeof(EngineLds) / 4);
+    const bool coh = a.wide != 0;   // with wide rows the row data was written on other XCDs
     if (tid == 0) {
         const unsigned long long key = ld_c(a.keys + r.seq);
         const int32_t qT = clampi((int32_t)(0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull)), K);
-        // coherent reads: with wide rows these were written on other XCDs
-        const float sc = ld_cf(slot_delta(a, slot, (T - 1) & 1) + qT);
+        const float* dp = slot_delta(a, slot, (T - 1) & 1) + qT;
+        const int32_t* ap = slot_anc(a, slot, (T - 1) & 1) + qT;
+        const float sc = coh ? ld_cf(dp) : *dp;
         sv[0] = qT;
         sv[1] = __float_as_int(sc);
-        sv[2] = (r.kind == KIND_ROOT && pp >= 2) ? clampi(ld_c(slot_anc(a, slot, (T - 1) & 1) + qT), K) : -1;
+        sv[2] = (r.kind == KIND_ROOT && pp >= 2) ? clampi(coh ? ld_c(ap) : *ap, K) : -1;
     }
     __syncthreads();
     const int32_t qT = sv[0];
@@ -1604,7 +1607,8 @@ __device__ __noinline__ void dense_finalize(cargs_t& a_in, const Row& r) {
         if (tid == 0) {
             for (int32_t d = pp - 2; d >= 0; --d) {
                 st_c(sq.path + seg_end(T, pp, d), q);
-                if (d >= 1) q = clampi(ld_c(root_link(a, r.off, pp, d) + q), K);
+                const int32_t* lp = root_link(a, r.off, pp, d) + q;
+                if (d >= 1) q = clampi(coh ? ld_c(lp) : *lp, K);
             }
         }
         __syncthreads();
@@ -1616,7 +1620,8 @@ __device__ __noinline__ void dense_finalize(cargs_t& a_in, const Row& r) {
         const int32_t n = (dhi - l0 + 1) * K;
         for (int32_t idx = tid; idx < n; idx += kEngBlock) {
             const int32_t d = l0 + idx / K, j = idx % K;
-            buf[(d - dlo) * K + j] = ld_c(root_link(a, r.off, pp, d) + j);
+            const int32_t* lp = root_link(a, r.off, pp, d) + j;
+            buf[(d - dlo) * K + j] = coh ? ld_c(lp) : *lp;
         }
         __syncthreads();
         if (tid == 0) {
@@ -1633,7 +1638,8 @@ __device__ __noinline__ void dense_finalize(cargs_t& a_in, const Row& r) {
     for (int32_t d = tid; d <= pp - 2; d += kEngBlock) {
         const int64_t e = seg_end(T, pp, d);
         const int32_t qd = clampi(ld_c(sq.path + e), K);
-        st_cf(a.alpha_at + sq.alpha_off + e, ld_cf(root_dsnap(a, r.off, d) + qd));
+        const float* dp = root_dsnap(a, r.off, d) + qd;
+        st_cf(a.alpha_at + sq.alpha_off + e, coh ? ld_cf(dp) : *dp);
     }
     __syncthreads();
 }
@@ -1917,11 +1923,26 @@ __device__ __noinline__ void scheduler(cargs_t& a_in, int32_t s) {
 // per-block cache maintenance of the fences to 256 operations per step.
 // Spins are bounded; on overrun the error flag is raised and every block
 // leaves the step loop.
+// Step-barrier memory ordering.  With wide rows, plain stores of one XCD
+// are read by others: the agent-scope fences write back and invalidate the
+// L2.  Otherwise every plain store is read on its own XCD (through its L2)
+// and all data crossing XCDs moves by coherent atomics, so a block only
+// waits for its stores to complete and invalidates its L1.
+__device__ __forceinline__ void step_release(bool wide) {
+    if (wide) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+__device__ __forceinline__ void step_acquire(bool wide) {
+    if (wide) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    else l1_invalidate();
+}
+
 __device__ bool barrier_arrive_wait(cargs_t& a, uint32_t epoch, uint32_t x) {
     __shared__ int s_err;
     __syncthreads();
     if (threadIdx.x == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const bool wide = a.wide != 0;
+        step_release(wide);
         st_c(a.arrive + blockIdx.x, epoch);
         int err = 0;
         int64_t spins = 0;
@@ -1930,7 +1951,7 @@ __device__ bool barrier_arrive_wait(cargs_t& a, uint32_t epoch, uint32_t x) {
             if (++spins > a.spin_limit) { st_c(&a.st->error, 1); err = 1; break; }
             if ((spins & 255) == 0 && ld_c(&a.st->error)) { err = 1; break; }
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        step_acquire(wide);
         s_err = err || ld_c(&a.st->error) != 0;
     }
     __syncthreads();
@@ -1951,8 +1972,9 @@ __device__ bool barrier_master(cargs_t& a, uint32_t epoch) {
         if (++spins > a.spin_limit) { err = 1; break; }
     }
     if (threadIdx.x == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const bool wide = a.wide != 0;
+        step_acquire(wide);
+        step_release(wide);
     }
     __syncthreads();
     if (threadIdx.x < kXcd) {
