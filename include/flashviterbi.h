@@ -68,6 +68,13 @@ enum { FV_DENSE = 0, FV_CSR = 1 };
  * streams from HBM once per step).  These flags force one placement; the
  * results are the same either way. */
 enum { FV_FLAG_WIDE_ROWS = 1u << 0, FV_FLAG_LOCAL_ROWS = 1u << 1 };
+/* Input validation.  Scores must be finite or -inf (NaN and +inf are outside
+ * the contract and give unspecified paths, though never an out-of-range
+ * access).  With FV_FLAG_VALIDATE the call first scans log A (or the CSR
+ * scores), log pi and every sequence's log B; a sequence whose model or
+ * emissions hold NaN or +inf gets status FV_E_INVALID_ARG (written
+ * asynchronously, like every status). */
+enum { FV_FLAG_VALIDATE = 1u << 2 };
 enum { FV_VANILLA = 0, FV_FLASH = 1, FV_BEAM = 2 };
 
 /* Transition model.  FV_DENSE: log_a[K*K] (device).  FV_CSR: out-edges of
@@ -118,7 +125,11 @@ fv_status fv_decode_vanilla(const fv_trans* A, const float* log_pi, const float*
  * segments, each started from its single known boundary state.  The
  * boundary state's float32 score is carried into the segment (retained
  * pruning, Def. 3), so the result equals fv_decode_vanilla bit for bit for
- * every P.  P <= 0 selects P automatically. */
+ * every P.  P <= 0 selects P automatically: the largest power of two in
+ * [2, 512] with P <= T/16 for the median length T, which bounds the
+ * division copies to a quarter of a vanilla backpointer table (a larger P
+ * means shorter subtask trees, hence fewer engine steps and less
+ * recomputation). */
 fv_status fv_decode_flash(const fv_trans* A, const float* log_pi, const float* log_b,
                           int64_t ld, int32_t T, int32_t P, int32_t* path, float* score,
                           int32_t* status, uint32_t flags, void* ws, size_t ws_bytes,

@@ -11,6 +11,10 @@
 
 namespace fv {
 extern "C" __global__ void fv_engine_kernel(const EngineArgs* __restrict__ table, int32_t n_models);
+extern "C" __global__ void fv_fill_i32_kernel(int32_t* __restrict__ p, int64_t n, int32_t v);
+extern "C" __global__ void fv_validate_array_kernel(const float* __restrict__ p, int64_t n, int32_t* __restrict__ flag);
+extern "C" __global__ void fv_validate_seqs_kernel(const fv_seq* __restrict__ seqs, int32_t n_seqs, int32_t model,
+                                                   int32_t K, int32_t* __restrict__ bad_seq);
 extern "C" __global__ void fv_model_check_kernel(const fv_seq* seqs_dev, int32_t n_seqs, int32_t n_models,
                                                  int32_t* status);
 extern "C" __global__ void fv_prep_dense_kernel(const float* __restrict__ log_a, int32_t K, int32_t Kp,
@@ -285,6 +289,25 @@ bool use_wide_rows(uint32_t flags, int32_t K, int32_t n_seqs, bool sparse) {
     return K >= 4096 || (K >= 1024 && n_seqs <= 4);
 }
 
+// FLASH parallelism when the caller passes P <= 0.  The engine's time is
+// about (number of global steps) x (fixed cost per step) + work / rate:
+// a larger P shortens the subtask trees (fewer steps after the root pass,
+// less recomputation), and costs (P'-1) division copies of 2K values per
+// sequence.  The choice keeps those copies at most a quarter of what a
+// vanilla backpointer table would need (2 bytes per state and step), i.e.
+// P' <= T/16 for the median length, as a power of two in [2, 512].
+int32_t auto_parallelism(const int32_t* T_host, int32_t n_seqs) {
+    std::vector<int32_t> t;
+    for (int32_t b = 0; b < n_seqs; ++b)
+        if (T_host[b] > 0) t.push_back(T_host[b]);
+    if (t.empty()) return 2;
+    std::nth_element(t.begin(), t.begin() + t.size() / 2, t.end());
+    const int32_t med = t[t.size() / 2];
+    int32_t P = 2;
+    while (P < 512 && 2 * P * 16 <= med) P *= 2;
+    return P;
+}
+
 // Beam widths of at least K keep every state: that is FLASH decoding.
 int32_t effective_method(int32_t method, const fv_trans* A, int32_t B) {
     return (method == FV_BEAM && A && B >= A->K) ? FV_FLASH : method;
@@ -294,6 +317,7 @@ int32_t effective_method(int32_t method, const fv_trans* A, int32_t B) {
 // then one region per model that has sequences (its own plan).
 struct BatchPlan {
     Region table;
+    Region valid;                   // validation flags: [n_seqs] per sequence, then one per planned decode
     std::vector<int32_t> model;     // model index of each planned decode
     std::vector<int32_t> method;    // its effective method
     std::vector<DenseLayout> L;
@@ -321,6 +345,7 @@ fv_status plan_batch(int32_t method, const fv_trans* models, int32_t n_models, c
     for (int32_t m = 0; m < n_models; ++m) n_plans += !lens[m].empty();
     size_t cur = 0;
     put(cur, bp.table, (size_t)std::max(n_plans, 1) * sizeof(EngineArgs));
+    put(cur, bp.valid, ((size_t)std::max(n_seqs, 0) + std::max(n_plans, 1)) * 4);
     for (int32_t m = 0; m < n_models; ++m) {
         if (lens[m].empty()) continue;
         const int32_t eff = effective_method(method, &models[m], B);
@@ -341,7 +366,7 @@ fv_status plan_batch(int32_t method, const fv_trans* models, int32_t n_models, c
 fv_status check_flags(uint32_t flags, const fv_trans* models, int32_t n_models) {
     if ((flags & FV_FLAG_WIDE_ROWS) && (flags & FV_FLAG_LOCAL_ROWS))
         return fail(FV_E_INVALID_ARG, "FV_FLAG_WIDE_ROWS and FV_FLAG_LOCAL_ROWS exclude each other");
-    if (flags & ~(uint32_t)(FV_FLAG_WIDE_ROWS | FV_FLAG_LOCAL_ROWS))
+    if (flags & ~(uint32_t)(FV_FLAG_WIDE_ROWS | FV_FLAG_LOCAL_ROWS | FV_FLAG_VALIDATE))
         return fail(FV_E_INVALID_ARG, "unknown flags 0x%x", flags);
     if (flags & FV_FLAG_WIDE_ROWS)
         for (int32_t m = 0; models && m < n_models; ++m)
@@ -374,6 +399,14 @@ fv_status run_batch(int32_t method, const fv_trans* models, const float* const* 
 
     char* const w0 = static_cast<char*>(ws);
     EngineArgs* table = reinterpret_cast<EngineArgs*>(w0 + bp.table.off);
+    const bool validate = (flags & FV_FLAG_VALIDATE) != 0;
+    const int32_t n_desc = single ? 1 : n_seqs;   // descriptors the sequence flags index
+    int32_t* bad_seq = reinterpret_cast<int32_t*>(w0 + bp.valid.off);
+    int32_t* bad_model = bad_seq + n_desc;
+    if (validate) {
+        const int64_t n_flags = (int64_t)n_desc + (int64_t)bp.L.size();
+        hipLaunchKernelGGL(fv_fill_i32_kernel, dim3(grid_for(n_flags)), dim3(kBlock), 0, stream, bad_seq, n_flags, 0);
+    }
     std::vector<EngineArgs> args(bp.L.size());
     std::vector<const float*> aps(bp.L.size());
     for (size_t p = 0; p < bp.L.size(); ++p) {
@@ -399,6 +432,23 @@ fv_status run_batch(int32_t method, const fv_trans* models, const float* const* 
             Ap = pad;
         }
         aps[p] = Ap;
+        if (validate) {
+            const int64_t kk = (int64_t)A->K;
+            if (sparse) {
+                if (A->nnz > 0)
+                    hipLaunchKernelGGL(fv_validate_array_kernel, dim3(grid_for(A->nnz)), dim3(kBlock), 0, stream,
+                                       A->val, A->nnz, bad_model + p);
+            } else {
+                hipLaunchKernelGGL(fv_validate_array_kernel, dim3(grid_for(kk * kk)), dim3(kBlock), 0, stream,
+                                   A->log_a, kk * kk, bad_model + p);
+            }
+            const float* pi = log_pi ? log_pi[bp.model[p]] : nullptr;
+            if (pi)
+                hipLaunchKernelGGL(fv_validate_array_kernel, dim3(grid_for(kk)), dim3(kBlock), 0, stream, pi, kk,
+                                   bad_model + p);
+            hipLaunchKernelGGL(fv_validate_seqs_kernel, dim3((unsigned)std::min(n_desc, 4096)), dim3(kBlock), 0,
+                               stream, sd, n_desc, single ? 0 : bp.model[p], A->K, bad_seq);
+        }
         EngineArgs& a = args[p];
         a = EngineArgs{};
         a.K = A->K;
@@ -446,6 +496,10 @@ fv_status run_batch(int32_t method, const fv_trans* models, const float* const* 
         a.spin_limit = (int64_t)1 << 24;
         // beam: exact re-decodes add at most one pass per subtask
         a.max_steps = (meth == FV_BEAM ? 16 : 8) * (L.sum_T + L.n_tasks) + 4096;
+        if (validate) {
+            a.bad_seq = bad_seq;
+            a.bad_model = bad_model + p;
+        }
 
         SetupArgs sa{};
         sa.seqs_dev = sd;
@@ -536,7 +590,7 @@ fv_status fv_workspace_size(int32_t method, const fv_trans* models, int32_t n_mo
     if (method != FV_VANILLA && method != FV_FLASH && method != FV_BEAM)
         return fail(FV_E_INVALID_ARG, "unknown method %d", method);
     if (method == FV_BEAM && (B < 1 || P < 1)) return fail(FV_E_INVALID_ARG, "beam decoding needs B >= 1 and P >= 1");
-    if (method == FV_FLASH && P <= 0) P = 16;
+    if (method == FV_FLASH && P <= 0) P = auto_parallelism(T_host, n_seqs);
     BatchPlan bp;
     // single-sequence calls reserve room for their device descriptor too
     fv_status rc = plan_batch(method, models, n_models, T_host, model_host, n_seqs, P, B, n_seqs == 1, bp);
@@ -566,8 +620,8 @@ fv_status fv_decode_vanilla(const fv_trans* A, const float* log_pi, const float*
 fv_status fv_decode_flash(const fv_trans* A, const float* log_pi, const float* log_b, int64_t ld,
                           int32_t T, int32_t P, int32_t* path, float* score, int32_t* status,
                           uint32_t flags, void* ws, size_t ws_bytes, fv_stream_t stream) {
-    return decode_one(FV_FLASH, A, log_pi, log_b, ld, T, P <= 0 ? 16 : P, 0, path, score, status, flags, ws,
-                      ws_bytes, stream);
+    if (P <= 0 && T >= 1) P = auto_parallelism(&T, 1);
+    return decode_one(FV_FLASH, A, log_pi, log_b, ld, T, P, 0, path, score, status, flags, ws, ws_bytes, stream);
 }
 
 fv_status fv_decode_beam(const fv_trans* A, const float* log_pi, const float* log_b, int64_t ld, int32_t T,
@@ -586,7 +640,7 @@ fv_status fv_decode_batch(const fv_trans* models, const float* const* log_pi, in
     if (method != FV_VANILLA && method != FV_FLASH && method != FV_BEAM)
         return fail(FV_E_INVALID_ARG, "unknown method %d", method);
     if (method == FV_BEAM && (B < 1 || P < 1)) return fail(FV_E_INVALID_ARG, "beam decoding needs B >= 1 and P >= 1");
-    if (method == FV_FLASH && P <= 0) P = 16;
+    if (method == FV_FLASH && P <= 0) P = auto_parallelism(T_host, n_seqs);
     return run_batch(method, models, log_pi, n_models, seqs_dev, T_host, model_host, n_seqs, P, B, nullptr, status,
                      flags, ws, ws_bytes, reinterpret_cast<hipStream_t>(stream));
 }

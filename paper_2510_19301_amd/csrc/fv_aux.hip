@@ -41,6 +41,44 @@ extern "C" __global__ __launch_bounds__(kBlock) void fv_rescore_kernel(const flo
     out[b] = v;
 }
 
+// ---- input validation (FV_FLAG_VALIDATE): every score must be finite or -inf
+
+extern "C" __global__ __launch_bounds__(kBlock) void fv_fill_i32_kernel(int32_t* __restrict__ p, int64_t n,
+                                                                        int32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) p[i] = v;
+}
+
+// NaN and +inf fail "x < +inf"; -inf and finite values pass.
+__device__ __forceinline__ bool bad_score(float x) { return !(x < INFINITY); }
+
+// *flag = 1 if any of p[0..n) is NaN or +inf (p may be null: nothing to check).
+extern "C" __global__ __launch_bounds__(kBlock) void fv_validate_array_kernel(const float* __restrict__ p, int64_t n,
+                                                                              int32_t* __restrict__ flag) {
+    if (!p) return;
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        bad |= bad_score(p[i]);
+    if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(flag, 1);
+}
+
+// bad_seq[b] = 1 if sequence b (of model `model`) has a NaN or +inf among its
+// emission scores log_b[t*ld + j], t < T, j < K.  Blocks take sequences.
+extern "C" __global__ __launch_bounds__(kBlock) void fv_validate_seqs_kernel(const fv_seq* __restrict__ seqs,
+                                                                             int32_t n_seqs, int32_t model,
+                                                                             int32_t K, int32_t* __restrict__ bad_seq) {
+    for (int32_t b = blockIdx.x; b < n_seqs; b += gridDim.x) {
+        const fv_seq d = seqs[b];
+        if (d.model != model || d.T <= 0 || !d.log_b || d.ld < K) continue;
+        bool bad = false;
+        const int64_t n = (int64_t)d.T * K;
+        for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+            const int64_t t = i / K, j = i - t * K;
+            bad |= bad_score(d.log_b[t * d.ld + j]);
+        }
+        if (__syncthreads_or(bad) && threadIdx.x == 0) bad_seq[b] = 1;
+    }
+}
+
 }  // namespace fv
 
 using namespace fv;

@@ -2335,6 +2335,8 @@ extern "C" __global__ __launch_bounds__(kBlock) void fv_finish_kernel(EngineArgs
         if (fl & kCsrInvalid) stv = FV_E_INVALID_ARG;
         else if ((fl & kCsrWideIn) && a.method == FV_VANILLA) stv = FV_E_UNSUPPORTED;
     }
+    if (a.bad_model && stv != FV_E_DEVICE && sq.T > 0 && sq.orig >= 0 && (*a.bad_model || a.bad_seq[sq.orig]))
+        stv = FV_E_INVALID_ARG;
     if (stv == FV_OK && a.method == FV_VANILLA && sq.T > 1) {
         int32_t q = sq.path[sq.T - 1];
         const uint16_t* tab = a.psi16 + sq.psi_off;
@@ -2365,6 +2367,8 @@ extern "C" __global__ __launch_bounds__(kBlock) void fv_beam_finish_kernel(Engin
     int32_t stv = sq.status;
     if (a.st->error) stv = FV_E_DEVICE;  // kernel boundary: plain loads are coherent
     if (a.sparse && stv != FV_E_DEVICE && sq.T > 0 && (*a.csr_flag & kCsrInvalid)) stv = FV_E_INVALID_ARG;
+    if (a.bad_model && stv != FV_E_DEVICE && sq.T > 0 && sq.orig >= 0 && (*a.bad_model || a.bad_seq[sq.orig]))
+        stv = FV_E_INVALID_ARG;
     if (stv >= 0 && sq.T >= 1) {
         const int32_t K = a.K, Kp = a.Kp, T = sq.T;
         const int32_t q0 = sq.path[0];

@@ -164,6 +164,9 @@ struct EngineArgs {
     int32_t n_compute_blocks;   // blocks 1..n_compute_blocks compute; block 0 schedules
     int64_t spin_limit;
     int64_t max_steps;          // guard against a runaway schedule
+    // input validation (FV_FLAG_VALIDATE): null when not requested
+    const int32_t* bad_seq;     // [caller's n_seqs] nonzero: NaN or +inf in that sequence's log B
+    const int32_t* bad_model;   // nonzero: NaN or +inf in this model's log A or log pi
 };
 
 // Arguments of the per-call setup kernel (per-sequence layout, first row list).

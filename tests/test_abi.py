@@ -164,3 +164,12 @@ def test_multimodel_workspace_size(fv):
     bad = np.array([0, 3, 0, 0], np.int32)
     assert l.fv_workspace_size(1, models, 3, lens.ctypes.data, bad.ctypes.data, 4, 16, 0, C.byref(out)) == -1
     assert l.fv_workspace_size(1, models, 0, lens.ctypes.data, mh.ctypes.data, 4, 16, 0, C.byref(out)) == -1
+
+
+def test_auto_parallelism_rule(fv):
+    """P <= 0 picks the largest power of two in [2, 512] with P <= T/16 for
+    the median length: the plan equals the explicit P's plan."""
+    d = fv
+    for lens, P in (([4000] * 3, 128), ([4250, 100, 9000], 256), ([20], 2), ([31, 64, 64], 4),
+                    ([10 ** 6], 512), ([0, 0, 700], 32)):
+        assert d.workspace_bytes("flash", 1024, lens, 0) == d.workspace_bytes("flash", 1024, lens, P), (lens, P)
