@@ -116,7 +116,6 @@ __device__ __forceinline__ void key_max(unsigned long long* p, unsigned long lon
 __device__ __forceinline__ uint32_t my_xcd() {
     return __builtin_amdgcn_s_getreg((15 << 11) | (0 << 6) | 20) & (kXcd - 1);  // HW_REG_XCC_ID
 }
-__device__ __forceinline__ void l1_invalidate() { asm volatile("buffer_inv sc0" ::: "memory"); }
 
 __device__ __forceinline__ unsigned long long order_key(float v, int32_t j) {
     if (v == 0.0f) v = 0.0f;  // -0 and +0 compare equal; the lower index must win
@@ -1924,18 +1923,17 @@ __device__ __noinline__ void scheduler(cargs_t& a_in, int32_t s) {
 // Spins are bounded; on overrun the error flag is raised and every block
 // leaves the step loop.
 // Step-barrier memory ordering.  With wide rows, plain stores of one XCD
-// are read by others: the agent-scope fences write back and invalidate the
-// L2.  Otherwise every plain store is read on its own XCD (through its L2)
-// and all data crossing XCDs moves by coherent atomics, so a block only
-// waits for its stores to complete and invalidates its L1.
+// are read by others: the agent-scope release writes the L2 back.
+// Otherwise every plain store is read on its own XCD (through its L2) and
+// all data crossing XCDs moves by coherent atomics, so a block only waits
+// for its stores to complete.  The acquire side is the agent-scope fence in
+// both cases: it invalidates the vector L1 (an L1-only invalidate does not
+// on this device) and leaves the XCD's L2 lines of device memory in place.
 __device__ __forceinline__ void step_release(bool wide) {
     if (wide) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
-__device__ __forceinline__ void step_acquire(bool wide) {
-    if (wide) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    else l1_invalidate();
-}
+__device__ __forceinline__ void step_acquire(bool) { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 
 __device__ bool barrier_arrive_wait(cargs_t& a, uint32_t epoch, uint32_t x) {
     __shared__ int s_err;
