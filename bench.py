@@ -37,24 +37,29 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3
 
 
 # ------------------------------------------------------------------ work model
-def _sub_candidates(m: int, n: int, K: int, memo: dict) -> int:
+LEAF_LEN = 64   # subtasks of at most this many steps are leaves (the library's default schedule)
+
+
+def _sub_candidates(m: int, n: int, K: int, memo: dict, leaf_len: int) -> int:
     """Candidates the GPU evaluates for subtask (m, n) and its descendants:
     anchored start (K, none at m = 0), full steps m+1..n-1 (K^2 each), the
-    end-only last step (K)."""
+    end-only last step (K).  A leaf (at most leaf_len steps) has no children."""
     key = (n - m, m == 0)
     if key in memo:
         return memo[key]
     c = (K if m > 0 else 0) + (n - m - 1) * K * K + K
     tmid = (m + n) // 2
-    if n - m > 2:
-        c += _sub_candidates(m, tmid, K, memo) + _sub_candidates(tmid + 1, n, K, memo)
+    if n - m + 1 <= leaf_len:
+        pass
+    elif n - m > 2:
+        c += _sub_candidates(m, tmid, K, memo, leaf_len) + _sub_candidates(tmid + 1, n, K, memo, leaf_len)
     elif n - m == 2:
-        c += _sub_candidates(m, tmid, K, memo)
+        c += _sub_candidates(m, tmid, K, memo, leaf_len)
     memo[key] = c
     return c
 
 
-def flash_candidates(T: int, P: int, K: int) -> int:
+def flash_candidates(T: int, P: int, K: int, leaf_len: int = 0) -> int:
     """Candidates of one FLASH decode: root pass + every subtask."""
     if T <= 1:
         return 0
@@ -65,7 +70,7 @@ def flash_candidates(T: int, P: int, K: int) -> int:
         m = 0 if d == 0 else ((d * T - 1) // pp) + 1
         n = ((d + 1) * T - 1) // pp
         if n - m >= 1:
-            total += _sub_candidates(m, n, K, memo)
+            total += _sub_candidates(m, n, K, memo, leaf_len)
     return total
 
 
@@ -114,7 +119,7 @@ def _make_inputs(wl, torch, dev):
     return [torch.from_numpy(x).to(dev) for x in host]
 
 
-def _time_method(fv, torch, la, lp, batch, method, P, B, steps, warmup, ws=None):
+def _time_method(fv, torch, la, lp, batch, method, P, B, steps, warmup, ws=None, leaves=True):
     """Mean ms per decode over `steps` timed decodes (torch events on the
     current stream, which is the stream the library launches on) and the
     engine kernel's own duration in the last timed decode (HIP events the
@@ -122,13 +127,13 @@ def _time_method(fv, torch, la, lp, batch, method, P, B, steps, warmup, ws=None)
     import ctypes as C
     lib = fv.lib()
     for _ in range(warmup):
-        ws = fv.decode_batch(la, batch, lp, method=method, P=P, B=B, ws=ws)
+        ws = fv.decode_batch(la, batch, lp, method=method, P=P, B=B, ws=ws, leaves=leaves)
     torch.cuda.synchronize()
     fv._lib.check(lib.fv_profile_engine(1), "fv_profile_engine")
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     start.record()
     for _ in range(steps):
-        ws = fv.decode_batch(la, batch, lp, method=method, P=P, B=B, ws=ws)
+        ws = fv.decode_batch(la, batch, lp, method=method, P=P, B=B, ws=ws, leaves=leaves)
     stop.record()
     torch.cuda.synchronize()
     ms = C.c_float(0)
@@ -270,9 +275,11 @@ def main():
         parts = item.split(":")
         runs.append((parts[0], int(parts[1]) if len(parts) > 1 else 1,
                      int(parts[2]) if len(parts) > 2 else 0, 1, 1))
-    for method, P, B, steps, warmup in runs:
-        print(f"[bench] {method} P={P} B={B}: warmup {warmup}, timed {steps}", file=sys.stderr, flush=True)
-        ms, eng_ms, ws_new, bad = _time_method(fv, torch, la, lp, batch, method, P, B, steps, warmup)
+    for name, P, B, steps, warmup in runs:
+        # "flash-bisect": FLASH with every subtask bisected (no leaf tables)
+        method, leaves = ("flash", False) if name == "flash-bisect" else (name, True)
+        print(f"[bench] {name} P={P} B={B}: warmup {warmup}, timed {steps}", file=sys.stderr, flush=True)
+        ms, eng_ms, ws_new, bad = _time_method(fv, torch, la, lp, batch, method, P, B, steps, warmup, leaves=leaves)
         if ws is None or ws_new.numel() > ws.numel():
             ws = ws_new
         entry = {"ms_per_step": round(ms, 3), "engine_ms": round(eng_ms, 3),
@@ -280,12 +287,14 @@ def main():
                  "workspace_bytes": fv.workspace_bytes(method, K, wl.lengths, P, B),
                  "bad_status": bad}
         if method in ("flash", "vanilla"):
-            cand = (sum(flash_candidates(int(T), P, K) for T in wl.lengths) if method == "flash"
+            leaf = LEAF_LEN if (leaves and K <= 2048) else 0
+            cand = (sum(flash_candidates(int(T), P, K, leaf) for T in wl.lengths) if method == "flash"
                     else sum(vanilla_candidates(int(T), K) for T in wl.lengths))
             entry.update({"candidates": cand, "candidates_per_s": cand / (eng_ms / 1e3)})
-        key = {"flash": f"flash_P{P}", "vanilla": "vanilla", "beam": f"beam_P{P}_B{B}"}[method]
+        key = {"flash": f"flash_P{P}", "flash-bisect": f"flash_bisect_P{P}", "vanilla": "vanilla",
+               "beam": f"beam_P{P}_B{B}"}[name]
         results[key] = entry
-        print(f"[bench] {method} P={P} B={B}: {ms:.2f} ms/step, engine {eng_ms:.2f} ms", file=sys.stderr, flush=True)
+        print(f"[bench] {name} P={P} B={B}: {ms:.2f} ms/step, engine {eng_ms:.2f} ms", file=sys.stderr, flush=True)
 
     head = results[f"flash_P{args.P}"]
     ach_tflops = head["candidates"] * 2 / (head["engine_ms"] / 1e3) / 1e12

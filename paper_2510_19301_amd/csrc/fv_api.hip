@@ -96,6 +96,8 @@ struct DenseLayout {
     int64_t q_cap = 0;
     int32_t sparse = 0;
     int64_t nnz = 0;
+    int32_t leaves = 0;          // slots carry a leaf backpointer table
+    int64_t leaf_off = 0;        // its offset in a slot, in floats
     Region Ap, seq1, seqinfo, keys, args, state, arrive, rows_full, rows_light, rows_beam, queue, free_stack,
         slots, alpha, root, psi, csr_flag, csr_ptr, csr_deg, csr_eid, csr_src, csr_val;
     size_t total = 0;
@@ -170,6 +172,10 @@ fv_status plan_dense(int32_t method, const fv_trans* A, const int32_t* T_host, i
     // dense rows: delta[2] (+ anc[2] + snapshot); beam rows: three beam
     // records, and room for a dense row should the task need its exact re-decode
     L.slot_floats = (int64_t)L.Kp * (method == FV_VANILLA ? 2 : 5);
+    // FLASH on a dense model of moderate K: room for a leaf subtask's table
+    L.leaves = method == FV_FLASH && !sparse && L.Kp <= kLeafMaxKp;
+    L.leaf_off = 5 * (int64_t)L.Kp;
+    if (L.leaves) L.slot_floats += (int64_t)kLeafLen * L.Kp / 2;
     if (beam) L.slot_floats = std::max<int64_t>(L.slot_floats, (2 * (int64_t)L.bw + 1) * L.brec);
     // a beam subtask may be queued twice (its exact re-decode)
     L.q_cap = std::max<int64_t>(1, beam ? 2 * L.n_tasks : L.n_tasks);
@@ -180,7 +186,7 @@ fv_status plan_dense(int32_t method, const fv_trans* A, const int32_t* T_host, i
     } else {
         // rows in flight: every root at once, then as many subtasks as a
         // bounded budget of row buffers allows (parallelism vs memory)
-        const int64_t budget = (int64_t)128 << 20;
+        const int64_t budget = (int64_t)(L.leaves ? 512 : 128) << 20;
         const int64_t cap = std::max<int64_t>(256, std::min<int64_t>(4096, budget / slot_bytes));
         slots = std::min<int64_t>(L.n_tasks, std::max<int64_t>(std::min<int64_t>(nonempty, 1 << 16), cap));
     }
@@ -366,7 +372,7 @@ fv_status plan_batch(int32_t method, const fv_trans* models, int32_t n_models, c
 fv_status check_flags(uint32_t flags, const fv_trans* models, int32_t n_models) {
     if ((flags & FV_FLAG_WIDE_ROWS) && (flags & FV_FLAG_LOCAL_ROWS))
         return fail(FV_E_INVALID_ARG, "FV_FLAG_WIDE_ROWS and FV_FLAG_LOCAL_ROWS exclude each other");
-    if (flags & ~(uint32_t)(FV_FLAG_WIDE_ROWS | FV_FLAG_LOCAL_ROWS | FV_FLAG_VALIDATE))
+    if (flags & ~(uint32_t)(FV_FLAG_WIDE_ROWS | FV_FLAG_LOCAL_ROWS | FV_FLAG_VALIDATE | FV_FLAG_NO_LEAVES))
         return fail(FV_E_INVALID_ARG, "unknown flags 0x%x", flags);
     if (flags & FV_FLAG_WIDE_ROWS)
         for (int32_t m = 0; models && m < n_models; ++m)
@@ -463,6 +469,8 @@ fv_status run_batch(int32_t method, const fv_trans* models, const float* const* 
         a.n_slots = L.n_slots;
         a.has_anc = L.has_anc;
         a.wide = use_wide_rows(flags, A->K, n_local, sparse) ? 1 : 0;
+        a.leaf_len = (L.leaves && !a.wide && !(flags & FV_FLAG_NO_LEAVES)) ? kLeafLen : 0;
+        a.leaf_off = L.leaf_off;
         if (sparse) {
             a.sparse = 1;
             a.nnz = A->nnz;

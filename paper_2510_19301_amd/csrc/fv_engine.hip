@@ -134,6 +134,14 @@ __device__ __forceinline__ int32_t* slot_anc(cargs_t& a, int32_t slot, int32_t p
 __device__ __forceinline__ float* slot_snap(cargs_t& a, int32_t slot) {
     return a.slot_base + (int64_t)slot * a.slot_floats + (int64_t)4 * a.Kp;
 }
+__device__ __forceinline__ uint16_t* slot_leaf(cargs_t& a, int32_t slot) {
+    return reinterpret_cast<uint16_t*>(a.slot_base + (int64_t)slot * a.slot_floats + a.leaf_off);
+}
+// A dense subtask short enough to be a leaf (never an exact re-decode of a
+// beam subtask: those keep the beam procedure's structure).
+__device__ __forceinline__ bool is_leaf(cargs_t& a, int32_t kind, int32_t m, int32_t n) {
+    return kind == KIND_SUB && a.leaf_len > 0 && n - m + 1 <= a.leaf_len;
+}
 __device__ __forceinline__ float* root_dsnap(cargs_t& a, int64_t root_off, int32_t d) {
     return a.root_copy + (root_off + d) * (int64_t)a.Kp;
 }
@@ -224,12 +232,12 @@ struct SchedLds {
     int32_t wave_sums[kXcd][kSchedGroupWaves][5];
 };
 
-static __shared__ EngineLds g_lds;
+static __shared__ __align__(16) EngineLds g_lds;
 static __shared__ SchedLds g_sched;
 
 // ---------------------------------------------------------------- row flags
-// Row of `base`'s task at time t as a dense step.
-__device__ Row make_dense_row(const Row& base, int32_t t) {
+// Row of `base`'s task at time t as a dense step (leaf: a leaf subtask).
+__device__ Row make_dense_row(const Row& base, int32_t t, bool leaf) {
     Row r = base;
     const int32_t kind = r.kind, m = r.m, n = r.n, T = r.T, pp = r.pp;
     r.t = t;
@@ -247,6 +255,9 @@ __device__ Row make_dense_row(const Row& base, int32_t t) {
             if (d >= 0) { f |= F_SNAP_ROOT; aux = d; }
         }
         if (t == T - 1) f |= F_FINAL;
+    } else if (leaf) {
+        f = F_NEED_ARG | F_LEAF_TABLE;
+        aux = t - m;
     } else {
         int32_t tmid = (m + n) >> 1;
         if (t > tmid) f |= F_NEED_ARG;
@@ -259,15 +270,15 @@ __device__ Row make_dense_row(const Row& base, int32_t t) {
     return r;
 }
 
-// Row of `base`'s task at time t as a light operation.
-__device__ Row make_light_row(const Row& base, int32_t t, int32_t op) {
+// Row of `base`'s task at time t as a light operation (leaf: a leaf subtask).
+__device__ Row make_light_row(const Row& base, int32_t t, int32_t op, bool leaf = false) {
     Row r = base;
     const int32_t kind = r.kind, m = r.m, n = r.n, T = r.T, pp = r.pp;
     r.t = t;
     r.aux = op;
     int32_t f = 0;
     if (op == L_INIT) {
-        if (is_dense_sub(kind) && ((m + n) >> 1) == m) f |= F_SNAP_SUB;
+        if (is_dense_sub(kind) && !leaf && ((m + n) >> 1) == m) f |= F_SNAP_SUB;
         if (kind == KIND_ROOT && pp >= 2 && seg_end(T, pp, 0) == 0) f |= F_SNAP_ROOT;
         if ((kind == KIND_VANILLA || kind == KIND_ROOT) && T == 1) f |= F_FINAL;
     }
@@ -288,7 +299,7 @@ __device__ Row row_from_task(cargs_t& a, const Task& tk, int32_t slot) {
         b.aux = B_INIT;
         return b;
     }
-    Row r = make_light_row(b, tk.m, L_INIT);
+    Row r = make_light_row(b, tk.m, L_INIT, is_leaf(a, tk.kind, tk.m, tk.n));
     if (a.sparse) {   // a sparse start step is a row of the full list (see sparse_unit)
         r.flags |= F_START;
         r.aux = 0;    // division 0 for F_SNAP_ROOT
@@ -528,6 +539,7 @@ __device__ __noinline__ void dense_tile(cargs_t& a_in, const float* __restrict__
             const float dnew = val[cc] + bpre[cc];
             dcur[j] = dnew;
             if (f & F_PSI_TABLE) a.psi16[off + (int64_t)t * K + j] = (uint16_t)psi[cc];
+            if (f & F_LEAF_TABLE) slot_leaf(a, slot)[(int64_t)aux * Kp + j] = (uint16_t)psi[cc];
             if (f & (F_ANC_FIRST | F_ANC_CHAIN)) {
                 anc[cc] = clampi(anc[cc], K);
                 acur[j] = anc[cc];
@@ -659,6 +671,7 @@ __device__ __noinline__ void wide_item(cargs_t& a_in, const float* __restrict__ 
         const float dnew = val + bpre;
         slot_delta(a, slot, t & 1)[j] = dnew;
         if (f & F_PSI_TABLE) a.psi16[rr.off + (int64_t)t * K + j] = (uint16_t)psi;
+        if (f & F_LEAF_TABLE) slot_leaf(a, slot)[(int64_t)rr.aux * Kp + j] = (uint16_t)psi;
         if (f & (F_ANC_FIRST | F_ANC_CHAIN)) slot_anc(a, slot, t & 1)[j] = anc;
         if (f & F_SNAP_SUB) slot_snap(a, slot)[j] = dnew;
         if (f & F_SNAP_ROOT) {
@@ -1643,6 +1656,68 @@ __device__ __noinline__ void dense_finalize(cargs_t& a_in, const Row& r) {
     __syncthreads();
 }
 
+// End of a leaf subtask (one block): the end-only step at the known end
+// state q*_n gives q*_{n-1} (first maximum of delta_{n-1}(i) + log A(i, q*_n),
+// lowest i on ties), then the leaf's backpointer rows are walked back,
+// q*_{t-1} = psi_t(q*_t) for t = n-1 .. m+1.  Table rows are copied to LDS in
+// chunks (16-byte loads) and walked there by one thread.
+__device__ __noinline__ void leaf_end(cargs_t& a_in, const Row& r) {
+    cargs_t& a = uniform_args(a_in);
+    const int tid = threadIdx.x;
+    SeqInfo& sq = a.seqs[r.seq];
+    const int32_t K = a.K, Kp = a.Kp, m = r.m, n = r.n;
+    const int32_t slot = clampi(r.slot, a.n_slots);
+    __shared__ int32_t lv[2];
+    if (tid == 0) lv[0] = ld_c(&sq.status) < 0 ? -1 : ld_c(sq.path + n);
+    __syncthreads();
+    const int32_t qn = lv[0];
+    __syncthreads();
+    if (qn < 0 || qn >= K) return;
+    const float* dprev = slot_delta(a, slot, (n - 1) & 1);
+    const float* ac = a.Acol + qn;
+    unsigned long long key = 0;
+    for (int32_t i = tid; i < K; i += kEngBlock) {
+        const unsigned long long k = order_key(dprev[i] + ac[(int64_t)i * Kp], i);
+        if (k > key) key = k;
+    }
+    int32_t q = clampi(block_argmax_key(key), K);
+    if (tid == 0) st_c(sq.path + n - 1, q);
+    uint4* buf = reinterpret_cast<uint4*>(&g_lds);
+    constexpr int32_t kBufU16 = (int32_t)(sizeof(EngineLds) / 16) * 8;
+    const int32_t per = max(1, kBufU16 / Kp);   // table rows per chunk
+    const uint16_t* tab = slot_leaf(a, slot);
+    for (int32_t hi = n - 1; hi >= m + 1; hi -= per) {   // table rows of t in [lo, hi]
+        const int32_t lo = max(m + 1, hi - per + 1);
+        const int32_t n16 = (hi - lo + 1) * Kp / 8;      // Kp is a multiple of 64
+        const uint4* src = reinterpret_cast<const uint4*>(tab + (int64_t)(lo - m) * Kp);
+        for (int32_t k0 = tid; k0 < n16; k0 += kEngBlock * 8) {
+            uint4 v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int32_t k = k0 + u * kEngBlock;
+                if (k < n16) v[u] = src[k];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int32_t k = k0 + u * kEngBlock;
+                if (k < n16) buf[k] = v[u];
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            const uint16_t* b16 = reinterpret_cast<const uint16_t*>(buf);
+            for (int32_t t = hi; t >= lo; --t) {
+                q = clampi(b16[(int64_t)(t - lo) * Kp + q], K);
+                st_c(sq.path + t - 1, q);
+            }
+            lv[1] = q;
+        }
+        __syncthreads();
+        q = lv[1];
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------- scheduler
 // What a row of step s turns into at step s+1 (its XCD never changes).
 struct Next {
@@ -1672,7 +1747,7 @@ __device__ Next classify(cargs_t& a, const Row& r, int src) {
     x.list = -1;
     x.freed = x.spawn = 0;
     const int32_t T = r.T, pp = r.pp;
-    if (src == 2 && !is_beam(r.kind)) {  // finalize of a vanilla pass or FLASH root
+    if (src == 2 && !is_beam(r.kind)) {  // finalize of a vanilla pass or FLASH root, or a leaf's end
         x.freed = 1;
         if (r.kind == KIND_ROOT && pp >= 2) x.spawn = root_segments(T, pp);
         return x;
@@ -1698,10 +1773,12 @@ __device__ Next classify(cargs_t& a, const Row& r, int src) {
     if (src == 0 || r.aux == L_INIT) {
         const int32_t nt = src == 0 ? r.t + 1 : r.m + 1;
         if (sub) {
-            if (nt < r.n) { x.list = 0; x.row = make_dense_row(r, nt); }
+            const bool leaf = is_leaf(a, r.kind, r.m, r.n);
+            if (nt < r.n) { x.list = 0; x.row = make_dense_row(r, nt, leaf); }
+            else if (leaf) { x.list = 2; x.row = make_light_row(r, r.n, L_LEAF_END, true); }
             else { x.list = 1; x.row = make_light_row(r, r.n, L_END); }
         } else {
-            if (nt < T) { x.list = 0; x.row = make_dense_row(r, nt); }
+            if (nt < T) { x.list = 0; x.row = make_dense_row(r, nt, false); }
             else { x.list = 2; x.row = make_light_row(r, T, L_FINALIZE); }
         }
     } else if (r.aux == L_END) {
@@ -2135,6 +2212,7 @@ __device__ void run_units(cargs_t& a, const float* __restrict__ Ap, uint32_t x, 
         const int32_t part = u % a.bw;
         const Row r = ld_row(Bl + u / a.bw);
         if (is_beam(r.kind)) beam_row(a, Ap, r, part);
+        else if (part == 0 && r.aux == L_LEAF_END) leaf_end(a, r);
         else if (part == 0) dense_finalize(a, r);
         u = -1;
     }

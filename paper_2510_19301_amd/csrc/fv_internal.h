@@ -39,13 +39,23 @@ enum : int32_t {
     F_SNAP_ROOT = 1 << 5,  // copy delta_t (and anc_t) to the root's division copy aux
     F_FINAL = 1 << 6,      // t = T-1 of a full-length pass: feed the final arg max
     F_START = 1 << 7,      // sparse rows: this step computes the task's start vector
+    F_LEAF_TABLE = 1 << 8, // leaf subtask: store psi_t in the slot's leaf table, row aux (= t - m)
 };
 
 // Light (O(K)) operations.  L_BSPAWN does nothing: it holds a finished
 // beam subtask for one step so that the scheduler, which classifies a
 // step's rows while they run, reads the task's fallback flag after the
 // step that wrote it.
-enum : int32_t { L_INIT = 0, L_END = 1, L_FINALIZE = 2, L_BSPAWN = 3 };
+enum : int32_t { L_INIT = 0, L_END = 1, L_FINALIZE = 2, L_BSPAWN = 3, L_LEAF_END = 4 };
+
+// Leaf subtasks.  A FLASH subtask of at most kLeafLen steps is not bisected
+// further: its forward pass keeps a small backpointer table (uint16, one row
+// per step) in its slot, and its end step walks that table back from the
+// known end state, resolving every position of the segment at once.  The
+// anchored start makes its pointers along the path equal vanilla's, so the
+// result is unchanged; the subtask tree loses its lower levels.
+constexpr int32_t kLeafLen = 64;
+constexpr int32_t kLeafMaxKp = 2048;   // larger K: no leaves (table too large per slot)
 
 // Operations of a beam row (one block each): start step, full beam step,
 // end-only step of a subtask, final selection of a root.
@@ -136,6 +146,8 @@ struct EngineArgs {
     int32_t n_slots;            // multiple of kXcd
     int32_t has_anc;            // slots carry anc[2] + snap
     int32_t wide;               // wide rows: every block takes a column slice of every dense row
+    int32_t leaf_len;           // subtasks of at most this many steps are leaves (0: none)
+    int64_t leaf_off;           // floats from a slot's start to its leaf table
     // sparse transitions (CSR out-edges and their in-edge transpose in edge
     // order); null for dense models
     int32_t sparse;

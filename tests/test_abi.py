@@ -156,7 +156,10 @@ def test_multimodel_workspace_size(fv):
     assert sum(parts) - 3 * 4096 <= both <= sum(parts) + 4096
     # a model without sequences costs nothing
     mh2 = np.array([0, 1, 1, 1], np.int32)
-    assert d.workspace_bytes_models("flash", models, 3, lens, mh2, 16, 0) < both
+    parts2 = [d.workspace_bytes_models("flash", (fv._lib.FvTrans * 1)(models[m]), 1, lens[mh2 == m],
+                                       np.zeros((mh2 == m).sum(), np.int32), 16, 0) for m in range(2)]
+    both2 = d.workspace_bytes_models("flash", models, 3, lens, mh2, 16, 0)
+    assert sum(parts2) - 2 * 4096 <= both2 <= sum(parts2) + 4096
     l = fv.lib()
     out = C.c_size_t(0)
     # several models need the per-sequence model indices, and they must be in range
