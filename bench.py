@@ -37,7 +37,7 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3
 
 
 # ------------------------------------------------------------------ work model
-LEAF_LEN = 64   # subtasks of at most this many steps are leaves (the library's default schedule)
+LEAF_LEN = 128  # subtasks of at most this many steps are leaves (the library's default schedule)
 
 
 def _sub_candidates(m: int, n: int, K: int, memo: dict, leaf_len: int) -> int:

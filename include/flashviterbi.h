@@ -75,8 +75,8 @@ enum { FV_FLAG_WIDE_ROWS = 1u << 0, FV_FLAG_LOCAL_ROWS = 1u << 1 };
  * emissions hold NaN or +inf gets status FV_E_INVALID_ARG (written
  * asynchronously, like every status). */
 enum { FV_FLAG_VALIDATE = 1u << 2 };
-/* FLASH schedule.  By default a subtask of at most 64 steps (dense model,
- * K <= 2048, rows on their XCD) is a leaf: it keeps a 64 x K uint16
+/* FLASH schedule.  By default a subtask of at most 128 steps (dense model,
+ * K <= 2048, rows on their XCD) is a leaf: it keeps a 128 x K uint16
  * backpointer table in its row buffer and resolves all its positions at its
  * end instead of being bisected further (same result, much less
  * recomputation; the workspace grows by that table per row buffer).

@@ -54,7 +54,7 @@ enum : int32_t { L_INIT = 0, L_END = 1, L_FINALIZE = 2, L_BSPAWN = 3, L_LEAF_END
 // known end state, resolving every position of the segment at once.  The
 // anchored start makes its pointers along the path equal vanilla's, so the
 // result is unchanged; the subtask tree loses its lower levels.
-constexpr int32_t kLeafLen = 64;
+constexpr int32_t kLeafLen = 128;
 constexpr int32_t kLeafMaxKp = 2048;   // larger K: no leaves (table too large per slot)
 
 // Operations of a beam row (one block each): start step, full beam step,

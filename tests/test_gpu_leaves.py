@@ -30,7 +30,7 @@ def _bits(x):
     return np.asarray(x, np.float32).reshape(-1).view(np.uint32)
 
 
-@pytest.mark.parametrize("K,T", [(37, 63), (37, 64), (37, 65), (64, 200), (100, 513), (256, 129)])
+@pytest.mark.parametrize("K,T", [(37, 63), (37, 127), (37, 128), (37, 129), (64, 300), (100, 513), (256, 260)])
 @pytest.mark.parametrize("P", [1, 2, 5])
 @pytest.mark.parametrize("leaves", [True, False])
 def test_flash_schedules_match_vanilla(fv, K, T, P, leaves):
@@ -56,7 +56,7 @@ def test_flash_leaves_batch_and_placements(fv):
     rng = np.random.default_rng(91)
     for K, rows in ((64, "local"), (64, "wide"), (2100, "auto")):
         _, la, _ = hmm.random_dense(K, 1, 92 + K)
-        lens = [1, 2, 64, 65, 130, 300] if K < 2000 else [1, 70, 140]
+        lens = [1, 2, 128, 129, 260, 600] if K < 2000 else [1, 70, 140]
         lbs = [(rng.standard_normal((T, K)) * 2).astype(np.float32) for T in lens]
         batch = fv.Batch([_dev(x) for x in lbs])
         fv.decode_batch(_dev(la), batch, None, method="flash", P=3, rows=rows)
