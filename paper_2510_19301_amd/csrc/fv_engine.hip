@@ -2219,7 +2219,9 @@ __device__ void run_units(cargs_t& a, const float* __restrict__ Ap, uint32_t x, 
 }
 
 // Every step of one model's decode (its own state, lists and buffers).
-__device__ void engine_model(cargs_t& a, const float* __restrict__ Ap) {
+__device__ __noinline__ void engine_model(cargs_t& a_in) {
+    cargs_t& a = uniform_args(a_in);
+    const float* __restrict__ Ap = a.Acol;
     const bool is_sched = blockIdx.x == 0;
     const uint32_t x = my_xcd();
     __shared__ int32_t s_rank;
@@ -2273,7 +2275,7 @@ extern "C" __global__ __launch_bounds__(kEngBlock) void fv_engine_kernel(const E
     for (int32_t mi = 0; mi < n_models; ++mi) {
         __syncthreads();
         cargs_t& a = *reinterpret_cast<cargs_t*>(reinterpret_cast<uint64_t>(table + mi));
-        engine_model(a, a.Acol);
+        engine_model(a);
     }
 }
 
