@@ -177,6 +177,35 @@ def large_runs(fv, torch, hmm, dev):
     return res
 
 
+def sparse_runs(fv, torch, hmm, dev):
+    """The map-matching workload: K = 100000 states on a 9-nearest-neighbour
+    CSR graph, 64 trajectories of length U[200, 2000], Gaussian GPS
+    emissions (generated on the device).  Vanilla and FLASH pull over
+    in-edges; FLASH-BS pushes the beam's out-edges."""
+    wl = hmm.map_matching_workload()
+    print(f"[bench] sparse: K={wl.K} n={wl.n} sum T={wl.total_steps()}", file=sys.stderr, flush=True)
+    lbs = [wl.log_b(b, dev) for b in range(wl.n)]
+    model = fv.CsrModel(torch.from_numpy(wl.row_ptr).to(dev), torch.from_numpy(wl.col).to(dev),
+                        torch.from_numpy(wl.val).to(dev))
+    lp = torch.from_numpy(wl.log_pi).to(dev)
+    batch = fv.Batch(lbs)
+    torch.cuda.synchronize()
+    res = {"workload": f"map matching: K={wl.K} states, 9-NN CSR graph ({len(wl.col)} edges), {wl.n} "
+                       f"trajectories T~U[200,2000] (sum T={wl.total_steps()}), Gaussian GPS emissions"}
+    steps = wl.total_steps() * wl.K
+    for method, P, B in (("beam", 16, 128), ("flash", 16, 0), ("vanilla", 1, 0)):
+        ms, eng_ms, ws, bad = _time_method(fv, torch, model, lp, batch, method, P, B, 1, 1)
+        key = {"flash": f"flash_P{P}", "vanilla": "vanilla", "beam": f"beam_P{P}_B{B}"}[method]
+        res[key] = {"ms": round(ms, 1), "engine_ms": round(eng_ms, 1), "state_steps_per_s": steps / (ms / 1e3),
+                    "workspace_bytes": int(ws.numel()), "bad_status": bad}
+        print(f"[bench] sparse {key}: {ms:.1f} ms", file=sys.stderr, flush=True)
+        del ws
+        torch.cuda.empty_cache()
+    del lbs, batch
+    torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline(wl, budget_s: float):
     """The oracle's vanilla decode on a prefix of the workload's sequences,
     all host cores in parallel (one sequence per thread at a time)."""
@@ -217,6 +246,8 @@ def main():
                     help="extra methods timed once each (method[:P[:B]])")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the K=16384, T=10000 single-sequence runs")
+    ap.add_argument("--no-sparse", action="store_true",
+                    help="skip the K=100000 map-matching (CSR) runs")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--n", type=int, default=256)
@@ -322,6 +353,9 @@ def main():
         del lbs, batch, ws
         torch.cuda.empty_cache()
         out["large"] = large_runs(fv, torch, hmm, dev)
+    if not args.no_sparse:
+        torch.cuda.empty_cache()
+        out["sparse"] = sparse_runs(fv, torch, hmm, dev)
     if not args.no_cpu:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
