@@ -571,9 +571,8 @@ __device__ __noinline__ void dense_tile(cargs_t& a_in, const float* __restrict__
 // with coherent loads; the step barrier's release makes the stores visible.
 
 
-__device__ __noinline__ void wide_item(cargs_t& a_in, const float* __restrict__ Ap, const Row* list, int32_t nlist,
-                          int32_t rg, int32_t chunk, int32_t coh) {
-    cargs_t& a = uniform_args(a_in);
+__device__ __forceinline__ void wide_item(cargs_t& a, const float* __restrict__ Ap, const Row* list, int32_t nlist,
+                                          int32_t rg, int32_t chunk, int32_t coh) {
     WideLds& L = g_lds.wide;
     const int32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int32_t K = a.K, Kp = __builtin_amdgcn_readfirstlane(a.Kp);
@@ -2065,7 +2064,9 @@ __device__ bool barrier_master(cargs_t& a, uint32_t epoch) {
 // Wide-row phase of a step: items (XCD list, group of 16 rows, 64-column
 // chunk) over the dense rows of every XCD, taken by all blocks of the chip:
 // first by global rank, then claimed from one counter.
-__device__ void run_wide(cargs_t& a, const float* __restrict__ Ap, int cur) {
+__device__ __noinline__ void run_wide(cargs_t& a_in, int cur) {
+    cargs_t& a = uniform_args(a_in);
+    const float* __restrict__ Ap = a.Acol;
     __shared__ int32_t s_item;
     const int32_t nch = a.Kp / kWideCols;
     int32_t nf[kXcd], base[kXcd + 1];
@@ -2094,6 +2095,33 @@ __device__ void run_wide(cargs_t& a, const float* __restrict__ Ap, int cur) {
     }
 }
 
+// Column items of an XCD with few dense rows, claimed from its counter.  The
+// item body is inlined here: one call per step instead of one per item
+// (a call saves and restores the callee-saved registers the body uses).
+__device__ __noinline__ void local_col_items(cargs_t& a_in, uint32_t x, int32_t nx, int32_t rank, int cur,
+                                             int32_t nf) {
+    cargs_t& a = uniform_args(a_in);
+    const float* __restrict__ Ap = a.Acol;
+    __shared__ int32_t s_citem;
+    const int32_t nch = a.Kp / kWideCols;
+    const int32_t total = ((nf + kWideRows - 1) / kWideRows) * nch;
+    const Row* Fl = list_full(a, cur, x);
+    int32_t item = rank;
+    for (;;) {
+        if (item < 0) {
+            if (threadIdx.x == 0)
+                s_citem = nx + __hip_atomic_fetch_add(&a.st->claim[cur][x][8], 1, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+            __syncthreads();
+            item = s_citem;
+            __syncthreads();
+        }
+        if (item >= total) break;
+        wide_item(a, Ap, Fl, nf, item / nch, item % nch, 0);
+        item = -1;
+    }
+}
+
 // Work of one XCD at one step.  Phase 1: dense tiles and light rows, taken
 // by tile groups (nsplit waves) one item at a time: a tile, or nsplit light
 // rows (one per wave).  Groups run independently, so one group's
@@ -2113,7 +2141,7 @@ __device__ void run_units(cargs_t& a, const float* __restrict__ Ap, uint32_t x, 
     const bool local_cols = !a.wide && !a.sparse && nf > 0 && nf <= kLocalColRows;
     const int32_t n_tiles =
         (a.wide || local_cols || a.sparse) ? 0 : ((nf + kTileRows - 1) / kTileRows) * (a.Kp / kTileCols);
-    if (a.wide) run_wide(a, Ap, cur);
+    if (a.wide) run_wide(a, cur);
     if (a.sparse && nf > 0) {
         // sparse rows: units of (row, 64 destinations), one per wave, 16 per block item
         __shared__ int32_t s_sitem;
@@ -2137,26 +2165,7 @@ __device__ void run_units(cargs_t& a, const float* __restrict__ Ap, uint32_t x, 
             item = -1;
         }
     }
-    if (local_cols) {
-        __shared__ int32_t s_citem;
-        const int32_t nch = a.Kp / kWideCols;
-        const int32_t total = ((nf + kWideRows - 1) / kWideRows) * nch;
-        const Row* Fl = list_full(a, cur, x);
-        int32_t item = rank;
-        for (;;) {
-            if (item < 0) {
-                if (threadIdx.x == 0)
-                    s_citem = nx + __hip_atomic_fetch_add(&a.st->claim[cur][x][8], 1, __ATOMIC_RELAXED,
-                                                          __HIP_MEMORY_SCOPE_AGENT);
-                __syncthreads();
-                item = s_citem;
-                __syncthreads();
-            }
-            if (item >= total) break;
-            wide_item(a, Ap, Fl, nf, item / nch, item % nch, 0);
-            item = -1;
-        }
-    }
+    if (local_cols) local_col_items(a, x, nx, rank, cur, nf);
     // waves per tile: 4 (one per SIMD) while every group gets two tiles or
     // more, else more waves per tile (fewer, faster groups); at most one wave
     // per 16 predecessors.  Decided from a nominal XCD of 32 blocks, so that
