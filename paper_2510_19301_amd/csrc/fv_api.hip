@@ -470,6 +470,7 @@ fv_status run_batch(int32_t method, const fv_trans* models, const float* const* 
         a.has_anc = L.has_anc;
         a.wide = use_wide_rows(flags, A->K, n_local, sparse) ? 1 : 0;
         a.leaf_len = (L.leaves && !a.wide && !(flags & FV_FLAG_NO_LEAVES)) ? kLeafLen : 0;
+        a.beam_q = (meth == FV_BEAM && !sparse && L.bw == 1 && L.Kp <= 2048 && L.B <= 256) ? 1 : 0;
         a.leaf_off = L.leaf_off;
         if (sparse) {
             a.sparse = 1;

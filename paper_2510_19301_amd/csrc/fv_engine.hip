@@ -211,11 +211,43 @@ struct SpBeamLds {
     int32_t estart[kBeamMaxB];   // first out-edge of each beam entry
 };
 
+// Grouped beam rows: with a dense model of Kp <= kQK, B <= kQB and one part
+// per step, each 256-thread group (4 waves) of a block runs its own beam
+// row, so a block has four beam steps in flight (the step is bound by
+// latency: barriers, selection passes, log A row loads).
+constexpr int kQThreads = 256;
+constexpr int kQWaves = kQThreads / 64;
+constexpr int kQGroups = kEngBlock / kQThreads;
+constexpr int32_t kQK = 2048;
+constexpr int32_t kQB = 256;
+
+struct QBeamLds {                 // one group's share
+    int32_t cs[kQB];              // candidates of a rebuild (one part: at most B)
+    float cv[kQB];
+    int32_t ca[kQB];
+    float sc[kQK];                // scores and anchors of every destination
+    int32_t an[kQK];
+    int32_t bs[kQB];              // the rebuilt beam, in state order
+    float bv[kQB];
+    int32_t ba[kQB];
+    uint32_t hist[256];
+    int32_t wsum[kQWaves];
+    unsigned long long wkey[kQWaves];
+    int32_t misc[8];
+};
+
+struct QuarterLds {
+    QBeamLds g[kQGroups];
+    uint32_t gsync[kQGroups];     // per group: barrier arrivals
+    int32_t gitem[kQGroups];      // per group: the row it claimed
+};
+
 union EngineLds {
     TileLds tile;
     WideLds wide;
     BeamLds beam;
     SpBeamLds spbeam;
+    QuarterLds qbeam;
 };
 static_assert(sizeof(SpBeamLds) <= offsetof(BeamLds, bs), "sparse beam scratch overlaps the beam");
 
@@ -1717,6 +1749,365 @@ __device__ __noinline__ void leaf_end(cargs_t& a_in, const Row& r) {
     }
 }
 
+// ---------------------------------------------------------------- grouped beam rows
+// The same operations as beam_row (dense model, one part), computed by one
+// 256-thread group with barriers among its 4 waves (LDS arrival counters).
+__device__ __forceinline__ int32_t q_grp() { return threadIdx.x / kQThreads; }
+__device__ __forceinline__ int32_t q_tid() { return threadIdx.x % kQThreads; }
+__device__ __forceinline__ void q_sync() { group_sync(&g_lds.qbeam.gsync[q_grp()], kQWaves); }
+
+// Exclusive prefix sum of one int per thread over the group; *total = the sum.
+__device__ int32_t q_exscan(int32_t v, int32_t* total, int32_t* wsum) {
+    const int lane = threadIdx.x & 63, w = q_tid() >> 6;
+    int32_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    q_sync();
+    int32_t before = 0, all = 0;
+#pragma unroll
+    for (int u = 0; u < kQWaves; ++u) {
+        const int32_t y = wsum[u];
+        if (u < w) before += y;
+        all += y;
+    }
+    q_sync();
+    *total = all;
+    return before + x - v;
+}
+
+// The index held in the largest key over the group (keys: 0 = none).
+__device__ int32_t q_argmax_key(QBeamLds& L, unsigned long long key) {
+    const int lane = threadIdx.x & 63, w = q_tid() >> 6;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const unsigned long long o = __shfl_xor(key, off, 64);
+        if (o > key) key = o;
+    }
+    if (lane == 0) L.wkey[w] = key;
+    q_sync();
+    unsigned long long best = 0;
+    for (int u = 0; u < kQWaves; ++u) best = L.wkey[u] > best ? L.wkey[u] : best;
+    q_sync();
+    return (int32_t)(0xFFFFFFFFu - (uint32_t)(best & 0xFFFFFFFFull));
+}
+
+// beam_select for one group: top B of n entries in state order by (score
+// desc, state asc), -inf dropped; out(p, state, score, anchor) in state order.
+template <typename Out>
+__device__ int32_t q_select(QBeamLds& L, int32_t n, int32_t B, const float* v, const int32_t* s, int32_t s0,
+                            const int32_t* an, Out out) {
+    const int tid = q_tid();
+    const int32_t per = (n + kQThreads - 1) / kQThreads;
+    const int32_t k0 = min(n, tid * per), k1 = min(n, k0 + per);
+    int32_t nfin = 0;
+    for (int32_t k = k0; k < k1; ++k) nfin += v[k] != -INFINITY;
+    int32_t n_finite;
+    q_exscan(nfin, &n_finite, L.wsum);
+    const bool all = n_finite <= B;
+    uint32_t kth = 0;
+    int32_t take_eq = 0;
+    if (!all) {
+        uint32_t prefix = 0, mask = 0;
+        int32_t rem = B;
+        for (int shift = 24; shift >= 0; shift -= 8) {
+            for (int k = tid; k < 256; k += kQThreads) L.hist[k] = 0;
+            q_sync();
+            for (int32_t k = k0; k < k1; ++k) {
+                const float x = v[k];
+                if (x == -INFINITY) continue;
+                const uint32_t u = score_key(x);
+                if ((u & mask) == prefix) atomicAdd(&L.hist[(u >> shift) & 255u], 1u);
+            }
+            q_sync();
+            if (tid < 64) {
+                int32_t c[4];
+#pragma unroll
+                for (int d = 0; d < 4; ++d) c[d] = (int32_t)L.hist[4 * tid + d];
+                const int32_t own = c[0] + c[1] + c[2] + c[3];
+                int32_t incl = own;   // sum over lanes >= tid
+#pragma unroll
+                for (int off = 1; off < 64; off <<= 1) {
+                    const int32_t y = __shfl_down(incl, off, 64);
+                    if (tid + off < 64) incl += y;
+                }
+                int32_t above = incl - own;
+                for (int d = 3; d >= 0; --d) {
+                    if (above < rem && above + c[d] >= rem) {
+                        L.misc[0] = 4 * tid + d;
+                        L.misc[1] = rem - above;
+                    }
+                    above += c[d];
+                }
+            }
+            q_sync();
+            prefix |= (uint32_t)L.misc[0] << shift;
+            mask |= 255u << shift;
+            rem = L.misc[1];
+            q_sync();
+        }
+        kth = prefix;
+        take_eq = rem;
+    }
+    int32_t neq = 0;
+    if (!all)
+        for (int32_t k = k0; k < k1; ++k) neq += (v[k] != -INFINITY && score_key(v[k]) == kth);
+    int32_t dummy;
+    const int32_t eq_before = q_exscan(neq, &dummy, L.wsum);
+    int32_t nsel = 0;
+    {
+        int32_t r = eq_before;
+        for (int32_t k = k0; k < k1; ++k) {
+            const float x = v[k];
+            if (x == -INFINITY) continue;
+            const uint32_t u = score_key(x);
+            bool keep = all || u > kth;
+            if (!all && u == kth) keep = r++ < take_eq;
+            nsel += keep;
+        }
+    }
+    int32_t n_kept;
+    int32_t p = q_exscan(nsel, &n_kept, L.wsum);
+    {
+        int32_t r = eq_before;
+        for (int32_t k = k0; k < k1; ++k) {
+            const float x = v[k];
+            if (x == -INFINITY) continue;
+            const uint32_t u = score_key(x);
+            bool keep = all || u > kth;
+            if (!all && u == kth) keep = r++ < take_eq;
+            if (keep) { out(p, s ? s[k] : s0 + k, x, an[k]); ++p; }
+        }
+    }
+    q_sync();
+    return n_kept;
+}
+
+// The beam of the step stored at `parity` (one part) into L.bs/bv/ba.
+__device__ int32_t q_rebuild(cargs_t& a, QBeamLds& L, int32_t slot, int32_t parity) {
+    const int tid = q_tid();
+    const int32_t B = a.B, K = a.K;
+    const BeamRec rp = slot_part(a, slot, parity, 0);
+    const int32_t np = clampi(rp.hdr[0], B + 1);
+    for (int32_t k = tid; k < np; k += kQThreads) {
+        L.cs[k] = clampi(rp.s[k], K);
+        L.cv[k] = rp.v[k];
+        L.ca[k] = rp.a[k];
+    }
+    q_sync();
+    return q_select(L, np, B, L.cv, L.cs, 0, L.ca, [&](int32_t p, int32_t st, float sv, int32_t av) {
+        L.bs[p] = st; L.bv[p] = sv; L.ba[p] = av;
+    });
+}
+
+__device__ void q_store(const QBeamLds& L, const BeamRec& rec, int32_t nb) {
+    for (int32_t k = q_tid(); k < nb; k += kQThreads) {
+        rec.s[k] = L.bs[k];
+        rec.v[k] = L.bv[k];
+        rec.a[k] = L.ba[k];
+    }
+    if (q_tid() == 0) rec.hdr[0] = nb;
+}
+
+// Division chain of a finished beam root (beam_chain_walk for one group; the
+// score/anchor area holds the records).
+__device__ void q_chain_walk(cargs_t& a, QBeamLds& L, const Row& r, int32_t q) {
+    const int tid = q_tid();
+    SeqInfo& sq = a.seqs[r.seq];
+    const int32_t K = a.K, B = a.B, T = r.T, pp = r.pp;
+    int32_t* buf = reinterpret_cast<int32_t*>(L.sc);   // sc and an: 2 * kQK ints
+    const int32_t stride = 1 + 3 * B;
+    const int32_t per = max(1, (2 * kQK) / stride);
+    for (int32_t dhi = pp - 2; dhi >= 0; dhi -= per) {
+        const int32_t dlo = max(0, dhi - per + 1);
+        for (int32_t d = dlo; d <= dhi; ++d) {
+            const BeamRec rs = root_beam(a, r.off, d);
+            int32_t* dst = buf + (d - dlo) * stride;
+            const int32_t n = clampi(rs.hdr[0], B + 1);
+            if (tid == 0) dst[0] = n;
+            for (int32_t k = tid; k < n; k += kQThreads) {
+                dst[1 + k] = rs.s[k];
+                dst[1 + B + k] = __float_as_int(rs.v[k]);
+                dst[1 + 2 * B + k] = rs.a[k];
+            }
+        }
+        q_sync();
+        if (tid == 0) {
+            for (int32_t d = dhi; d >= dlo; --d) {
+                const int32_t* rec = buf + (d - dlo) * stride;
+                const int64_t e = seg_end(T, pp, d);
+                st_c(sq.path + e, q);
+                int32_t at = -1;
+                for (int32_t lo = 0, hi = rec[0]; lo < hi;) {
+                    const int32_t mid = (lo + hi) >> 1;
+                    const int32_t sm = rec[1 + mid];
+                    if (sm == q) { at = mid; break; }
+                    if (sm < q) lo = mid + 1; else hi = mid;
+                }
+                st_cf(a.alpha_at + sq.alpha_off + e, at >= 0 ? __int_as_float(rec[1 + B + at]) : __builtin_nanf(""));
+                if (d >= 1) q = (at >= 0 && q >= 0 && q < K) ? rec[1 + 2 * B + at] : -1;
+            }
+            L.misc[6] = q;
+        }
+        q_sync();
+        q = L.misc[6];
+        q_sync();
+    }
+}
+
+// One beam task step (dense model, one part) by this thread's group.
+__device__ __noinline__ void beam_row_q(cargs_t& a_in, const Row& r) {
+    cargs_t& a = uniform_args(a_in);
+    const float* __restrict__ Ap = a.Acol;
+    QBeamLds& L = g_lds.qbeam.g[q_grp()];
+    const int tid = q_tid();
+    SeqInfo& sq = a.seqs[r.seq];
+    const int32_t K = a.K, Kp = a.Kp, B = a.B;
+    gfloat_t* Ag = as_global(Ap);
+    const int32_t slot = clampi(r.slot, a.n_slots);
+    const bool root = r.kind == KIND_BROOT;
+    const int32_t T = r.T, pp = r.pp, m = r.m, n = r.n, t = r.t;
+    const int32_t tmid = (m + n) >> 1;
+    if (r.aux == B_INIT) {
+        if (tid == 0) {
+            L.misc[2] = m > 0 ? ld_c(sq.path + m - 1) : -1;
+            L.misc[3] = m > 0 ? (int32_t)__float_as_uint(ld_cf(a.alpha_at + sq.alpha_off + m - 1)) : 0;
+            st_c(beam_fallback_flag(a, slot), 0);
+        }
+        q_sync();
+        int32_t q = L.misc[2];
+        const float alpha = __uint_as_float((uint32_t)L.misc[3]);
+        if (q < 0 || q >= K) q = -1;
+        const float* bm = r.log_b + (int64_t)m * r.ld;
+        for (int32_t j = tid; j < K; j += kQThreads) {
+            float v = -INFINITY;
+            if (m == 0) v = a.log_pi ? a.log_pi[j] + bm[j] : bm[j];
+            else if (q >= 0) { const float c = alpha + Ap[(int64_t)q * Kp + j]; v = c + bm[j]; }
+            L.sc[j] = v;
+            L.an[j] = -1;
+        }
+        q_sync();
+        const BeamRec out = slot_part(a, slot, m & 1, 0);
+        const int32_t nk = q_select(L, K, B, L.sc, nullptr, 0, L.an, [&](int32_t p, int32_t st, float sv, int32_t av) {
+            out.s[p] = st; out.v[p] = sv; out.a[p] = av;
+        });
+        if (tid == 0) out.hdr[0] = nk;
+    } else if (r.aux == B_STEP) {
+        const int32_t nb = q_rebuild(a, L, slot, (t - 1) & 1);
+        if (root && pp >= 2) {
+            const int32_t d = div_index(T, pp, t - 1);
+            if (d >= 0) q_store(L, root_beam(a, r.off, d), nb);
+        }
+        if (!root && t - 1 == tmid) q_store(L, slot_snap_beam(a, slot), nb);
+        int32_t mode;  // anchor: 0 none, 1 the predecessor, 2 the predecessor's anchor
+        if (root) {
+            if (pp >= 2 && div_index(T, pp, t - 1) >= 0) mode = 1;
+            else if (pp >= 2 && t > seg_end(T, pp, 0) + 1) mode = 2;
+            else mode = 0;
+        } else {
+            mode = t == tmid + 1 ? 1 : (t > tmid + 1 ? 2 : 0);
+        }
+        const float* bt = r.log_b + (int64_t)t * r.ld;
+        for (int32_t j = tid; j < K; j += kQThreads) {
+            float c = -INFINITY;
+            int32_t w = -1;
+            for (int32_t b0 = 0; b0 < nb; b0 += 16) {
+                float av[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    const int32_t sb = __builtin_amdgcn_readfirstlane(L.bs[min(b0 + u, nb - 1)]);
+                    av[u] = Ag[(int64_t)sb * Kp + j];
+                }
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    if (b0 + u < nb) {
+                        const float x = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
+                                            __builtin_bit_cast(int32_t, L.bv[b0 + u]))) + av[u];
+                        if (w < 0 || x > c) { c = x; w = b0 + u; }
+                    }
+                }
+            }
+            L.sc[j] = w < 0 ? -INFINITY : c + bt[j];
+            L.an[j] = w < 0 ? -1 : (mode == 1 ? L.bs[w] : (mode == 2 ? L.ba[w] : -1));
+        }
+        q_sync();
+        const BeamRec out = slot_part(a, slot, t & 1, 0);
+        const int32_t nk = q_select(L, K, B, L.sc, nullptr, 0, L.an, [&](int32_t p, int32_t st, float sv, int32_t av) {
+            out.s[p] = st; out.v[p] = sv; out.a[p] = av;
+        });
+        if (tid == 0) out.hdr[0] = nk;
+    } else if (r.aux == B_END) {
+        if (tid == 0) L.misc[4] = ld_c(&sq.status) < 0 ? -1 : ld_c(sq.path + n);
+        q_sync();
+        const int32_t qn = L.misc[4];
+        q_sync();
+        if (qn < 0 || qn >= K) return;
+        const int32_t nb = q_rebuild(a, L, slot, (n - 1) & 1);
+        unsigned long long key = 0;
+        for (int32_t b = tid; b < nb; b += kQThreads) {
+            const float x = L.bv[b] + Ap[(int64_t)L.bs[b] * Kp + qn];
+            if (x != -INFINITY) {
+                const unsigned long long k = order_key(x, b);
+                if (k > key) key = k;
+            }
+        }
+        const int32_t wb = q_argmax_key(L, key);   // 0xFFFFFFFF - 0 when no key: no beam state reaches q*_n
+        if (tid == 0) {
+            if (wb < 0 || wb >= nb) {
+                st_c(beam_fallback_flag(a, slot), 1);
+                if (ld_c(&sq.status) == FV_OK) st_c(&sq.status, (int32_t)FV_W_BEAM_FALLBACK);
+            } else {
+                const int32_t qmid = (n == tmid + 1) ? L.bs[wb] : L.ba[wb];
+                float amid = __builtin_nanf("");
+                if (qmid >= 0 && qmid < K) {
+                    if (n - 1 == tmid) {
+                        const int32_t at = beam_find_lds(L.bs, nb, qmid);
+                        if (at >= 0) amid = L.bv[at];
+                    } else {
+                        const BeamRec snap = slot_snap_beam(a, slot);
+                        const int32_t ns = clampi(snap.hdr[0], B + 1);
+                        int32_t lo = 0, hi = ns;
+                        while (lo < hi) {
+                            const int32_t mid = (lo + hi) >> 1;
+                            const int32_t sm = snap.s[mid];
+                            if (sm == qmid) { amid = snap.v[mid]; break; }
+                            if (sm < qmid) lo = mid + 1; else hi = mid;
+                        }
+                    }
+                }
+                st_c(sq.path + tmid, qmid);
+                st_cf(a.alpha_at + sq.alpha_off + tmid, amid);
+            }
+        }
+    } else {  // B_FINAL
+        const int32_t nb = q_rebuild(a, L, slot, (T - 1) & 1);
+        if (nb == 0) {
+            for (int32_t k = tid; k < T; k += kQThreads) st_c(sq.path + k, -1);
+            if (tid == 0) {
+                st_cf(sq.score, -INFINITY);
+                st_c(&sq.status, (int32_t)FV_E_INFEASIBLE);
+            }
+            return;
+        }
+        unsigned long long key = 0;
+        for (int32_t k = tid; k < nb; k += kQThreads) {
+            const unsigned long long kk = order_key(L.bv[k], L.bs[k]);
+            if (kk > key) key = kk;
+        }
+        const int32_t top_state = q_argmax_key(L, key);
+        if (tid == 0) {
+            const int32_t top = clampi(beam_find_lds(L.bs, nb, top_state), nb);
+            st_c(sq.path + T - 1, top_state);
+            L.misc[5] = L.ba[top];
+        }
+        q_sync();
+        if (pp >= 2) q_chain_walk(a, L, r, L.misc[5]);
+    }
+}
+
 // ---------------------------------------------------------------- scheduler
 // What a row of step s turns into at step s+1 (its XCD never changes).
 struct Next {
@@ -2209,6 +2600,26 @@ __device__ void run_units(cargs_t& a, const float* __restrict__ Ap, uint32_t x, 
     __syncthreads();
     const Row* Bl = list_beam(a, cur, x);
     int32_t* ctr2 = &a.st->claim[cur][x][16];
+    if (a.beam_q) {   // beam rows four to a block: each 256-thread group claims rows
+        QuarterLds& Q = g_lds.qbeam;
+        if (threadIdx.x < kQGroups) Q.gsync[threadIdx.x] = 0;
+        __syncthreads();
+        const int32_t g = q_grp();
+        int32_t item = rank >= 0 ? rank * kQGroups + g : -1;
+        for (;;) {
+            if (item < 0) {
+                if (q_tid() == 0)
+                    Q.gitem[g] = nx * kQGroups + __hip_atomic_fetch_add(ctr2, 1, __ATOMIC_RELAXED,
+                                                                      __HIP_MEMORY_SCOPE_AGENT);
+                q_sync();
+                item = Q.gitem[g];
+            }
+            if (item >= nbm) break;
+            beam_row_q(a, ld_row(Bl + item));
+            item = -1;
+        }
+        return;
+    }
     int32_t u = rank;
     for (;;) {
         if (u < 0) {
