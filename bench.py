@@ -206,6 +206,57 @@ def sparse_runs(fv, torch, hmm, dev):
     return res
 
 
+def small_runs(fv, torch, hmm, dev):
+    """Latency-bound decodes: one discrete HMM (K = 64, V = 128, T = 1000;
+    microseconds per step of the single sequence) and the CRF training step
+    (512 sequences, K = 256, T ~ U[32, 512]: ViterbiScore forward + the
+    hand-written backward)."""
+    res = {}
+    h = hmm.discrete_hmm(K=64, V=128, T=1000, seed=1)
+    log_e = torch.from_numpy(h.log_e).to(dev)
+    obs = torch.from_numpy(h.obs).to(dev)
+    la = torch.from_numpy(h.log_a).to(dev)
+    lp = torch.from_numpy(h.log_pi).to(dev)
+    lb = torch.empty((h.T, h.K), dtype=torch.float32, device=dev)
+    lib = fv.lib()
+    stream = torch.cuda.current_stream().cuda_stream
+    entry = {"workload": "discrete HMM: K=64, V=128, T=1000 (Dirichlet(1) transitions, Dirichlet(0.5) emissions)"}
+    for method, P in (("vanilla", 1), ("flash", 16)):
+        for rep in range(2):   # warm-up, then timed
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fv._lib.check(lib.fv_gather_emissions(h.K, h.V, log_e.data_ptr(), obs.data_ptr(), h.T, lb.data_ptr(),
+                                                  h.K, stream), "fv_gather_emissions")
+            fv.decode(la, lb, lp, method, P=P)
+            e1.record()
+            torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        entry[f"{method}_P{P}" if method == "flash" else method] = {"ms": round(ms, 3),
+                                                                     "us_per_step": round(ms * 1e3 / h.T, 2)}
+    res["discrete"] = entry
+    wl = hmm.crf_batch()
+    em = torch.from_numpy(wl.emissions).to(dev).requires_grad_(True)
+    tr = torch.from_numpy(wl.transitions).to(dev).requires_grad_(True)
+    entry = {"workload": f"CRF step: {len(wl.lengths)} sequences, K={wl.K}, T~U[32,512], "
+                         f"Linear(512->256) emissions, no start scores"}
+    for method, P in (("vanilla", 1), ("flash", 16)):
+        for rep in range(2):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            scores, _ = fv.ViterbiScore.apply(em, wl.lengths, tr, None, method, P)
+            scores.sum().backward()
+            e1.record()
+            torch.cuda.synchronize()
+            em.grad = None
+            tr.grad = None
+        steps = int(np.asarray(wl.lengths, np.int64).sum()) * wl.K
+        ms = e0.elapsed_time(e1)
+        entry[f"{method}_P{P}" if method == "flash" else method] = {
+            "ms_forward_backward": round(ms, 3), "state_steps_per_s": steps / (ms / 1e3)}
+    res["crf"] = entry
+    return res
+
+
 def cpu_baseline(wl, budget_s: float):
     """The oracle's vanilla decode on a prefix of the workload's sequences,
     all host cores in parallel (one sequence per thread at a time)."""
@@ -248,6 +299,8 @@ def main():
                     help="skip the K=16384, T=10000 single-sequence runs")
     ap.add_argument("--no-sparse", action="store_true",
                     help="skip the K=100000 map-matching (CSR) runs")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the discrete-HMM and CRF-step runs")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--n", type=int, default=256)
@@ -356,6 +409,8 @@ def main():
     if not args.no_sparse:
         torch.cuda.empty_cache()
         out["sparse"] = sparse_runs(fv, torch, hmm, dev)
+    if not args.no_small:
+        out.update(small_runs(fv, torch, hmm, dev))
     if not args.no_cpu:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
