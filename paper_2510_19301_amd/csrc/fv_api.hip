@@ -19,6 +19,7 @@ extern "C" __global__ void fv_model_check_kernel(const fv_seq* seqs_dev, int32_t
                                                  int32_t* status);
 extern "C" __global__ void fv_prep_dense_kernel(const float* __restrict__ log_a, int32_t K, int32_t Kp,
                                                 float* __restrict__ Ap);
+extern "C" __global__ void fv_transpose_dense_kernel(const float* __restrict__ Ap, int32_t Kp, float* __restrict__ At);
 extern "C" __global__ void fv_setup_kernel(EngineArgs a, SetupArgs sa);
 extern "C" __global__ void fv_finish_kernel(EngineArgs a, int32_t* status);
 extern "C" __global__ void fv_beam_finish_kernel(EngineArgs a, const float* __restrict__ Ap, int32_t* status);
@@ -98,7 +99,7 @@ struct DenseLayout {
     int64_t nnz = 0;
     int32_t leaves = 0;          // slots carry a leaf backpointer table
     int64_t leaf_off = 0;        // its offset in a slot, in floats
-    Region Ap, seq1, seqinfo, keys, args, state, arrive, rows_full, rows_light, rows_beam, queue, free_stack,
+    Region Ap, At, seq1, seqinfo, keys, args, state, arrive, rows_full, rows_light, rows_beam, queue, free_stack,
         slots, alpha, root, psi, csr_flag, csr_ptr, csr_deg, csr_eid, csr_src, csr_val;
     size_t total = 0;
 };
@@ -197,6 +198,8 @@ fv_status plan_dense(int32_t method, const fv_trans* A, const int32_t* T_host, i
     L.pool = L.n_slots / kXcd;
     size_t cur = 0;
     put(cur, L.Ap, (!sparse && L.Kp != K) ? (size_t)L.Kp * L.Kp * 4 : 0);  // padded dense copy only when needed
+    // transposed copy for the two-column items of moderate K
+    put(cur, L.At, (!sparse && L.Kp <= kColMaxKp) ? (size_t)L.Kp * L.Kp * 4 : 0);
     put(cur, L.seq1, single ? sizeof(fv_seq) : 0);
     put(cur, L.seqinfo, (size_t)std::max(n_seqs, 1) * sizeof(SeqInfo));
     put(cur, L.keys, (size_t)std::max(n_seqs, 1) * 8);
@@ -438,6 +441,13 @@ fv_status run_batch(int32_t method, const fv_trans* models, const float* const* 
             Ap = pad;
         }
         aps[p] = Ap;
+        const bool wide = use_wide_rows(flags, A->K, n_local, sparse);
+        float* At = nullptr;
+        if (L.At.bytes && !wide) {   // wide rows never use it
+            At = static_cast<float*>(at(L.At));
+            hipLaunchKernelGGL(fv_transpose_dense_kernel, dim3(L.Kp / 64, L.Kp / 64), dim3(kBlock), 0, stream, Ap,
+                               L.Kp, At);
+        }
         if (validate) {
             const int64_t kk = (int64_t)A->K;
             if (sparse) {
@@ -461,6 +471,7 @@ fv_status run_batch(int32_t method, const fv_trans* models, const float* const* 
         a.Kp = L.Kp;
         a.log_pi = log_pi ? log_pi[bp.model[p]] : nullptr;
         a.Acol = Ap;
+        a.At = At;
         a.seqs = static_cast<SeqInfo*>(at(L.seqinfo));
         a.n_seqs = n_local;
         a.method = meth;
@@ -468,7 +479,7 @@ fv_status run_batch(int32_t method, const fv_trans* models, const float* const* 
         a.slot_floats = L.slot_floats;
         a.n_slots = L.n_slots;
         a.has_anc = L.has_anc;
-        a.wide = use_wide_rows(flags, A->K, n_local, sparse) ? 1 : 0;
+        a.wide = wide ? 1 : 0;
         a.leaf_len = (L.leaves && !a.wide && !(flags & FV_FLAG_NO_LEAVES)) ? kLeafLen : 0;
         a.beam_q = (meth == FV_BEAM && !sparse && L.bw == 1 && L.Kp <= 2048 && L.B <= 256) ? 1 : 0;
         a.leaf_off = L.leaf_off;

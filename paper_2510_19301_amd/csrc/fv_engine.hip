@@ -180,6 +180,17 @@ struct WideLds {
     Row rows[kWideRows];
 };
 
+// Two-column items (Kp <= kColMaxKp): 8 rows x 128 destinations, the rows'
+// previous scores staged whole, partial results merged through 64-bit keys.
+constexpr int32_t kColRows = 8;
+constexpr int32_t kColCols = 128;
+struct ColLds {
+    float d[kColRows * kColMaxKp];
+    unsigned long long key[kColRows * kColCols];
+    Row rows[kColRows];
+};
+static_assert(kColRows * kColCols == kEngBlock, "one refine output per thread");
+
 constexpr int32_t kBeamPartMax = 4096;   // destinations per part
 constexpr int32_t kBeamCandMax = 8192;   // W * B: candidates of a rebuild
 
@@ -248,6 +259,7 @@ union EngineLds {
     BeamLds beam;
     SpBeamLds spbeam;
     QuarterLds qbeam;
+    ColLds col;
 };
 static_assert(sizeof(SpBeamLds) <= offsetof(BeamLds, bs), "sparse beam scratch overlaps the beam");
 
@@ -526,9 +538,18 @@ __device__ __noinline__ void dense_tile(cargs_t& a_in, const float* __restrict__
                 const int cc = cb + c2;
                 if (need[cc]) {
                     const int32_t src0 = gi[cc] * kGroup;
-                    const float* ac = a.Acol + (int64_t)src0 * Kp + (j0 + cq + cc);
+                    if (a.At) {   // the group's 16 values: one contiguous run of the transposed copy
+                        const float4* at4 = reinterpret_cast<const float4*>(a.At + (int64_t)(j0 + cq + cc) * Kp + src0);
 #pragma unroll
-                    for (int k = 0; k < kGroup; ++k) av[c2][k] = ac[(int64_t)k * Kp];
+                        for (int k = 0; k < kGroup; k += 4) {
+                            const float4 v = at4[k >> 2];
+                            av[c2][k] = v.x; av[c2][k + 1] = v.y; av[c2][k + 2] = v.z; av[c2][k + 3] = v.w;
+                        }
+                    } else {
+                        const float* ac = a.Acol + (int64_t)src0 * Kp + (j0 + cq + cc);
+#pragma unroll
+                        for (int k = 0; k < kGroup; ++k) av[c2][k] = ac[(int64_t)k * Kp];
+                    }
 #pragma unroll
                     for (int k = 0; k < kGroup; k += 4) {
                         const float4 d4 = *reinterpret_cast<const float4*>(drow + src0 + k);
@@ -718,6 +739,159 @@ __device__ __forceinline__ void wide_item(cargs_t& a, const float* __restrict__ 
             if (o > key) key = o;
         }
         if (lane == 0) key_max(&a.keys[L.rows[w].seq], key);
+    }
+    __syncthreads();
+}
+
+// Two-column items, for XCDs with few dense rows and Kp <= kColMaxKp: a block
+// computes 8 rows x 128 destinations, each lane two of them (j and j + 64).
+// The rows' previous scores are staged whole in LDS and read there as
+// broadcasts; the 16 waves split the predecessors, each keeping per row and
+// column the maximum and the winning group of 16 predecessors (the earliest
+// on ties).  The partial results merge through 64-bit LDS max keys (score in
+// total order with -0 folded into +0, then the complement of the group), which
+// selects the earliest group holding the maximum, as a merge in wave order
+// does.  All 1024 threads then take one output each and refine its group: the
+// group's 16 log A values are one contiguous run of the transposed copy, its
+// 16 scores come from LDS.
+__device__ __forceinline__ uint32_t score_order(float v) {
+    const uint32_t u = __float_as_uint(v + 0.0f);   // -0 + +0 = +0
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float score_from_order(uint32_t k) {
+    return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
+}
+
+__device__ __forceinline__ void col_item(cargs_t& a, const float* __restrict__ Ap, const Row* list, int32_t nlist,
+                                         int32_t rg, int32_t chunk) {
+    ColLds& L = g_lds.col;
+    const int32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int32_t K = a.K, Kp = __builtin_amdgcn_readfirstlane(a.Kp);
+    gfloat_t* Ag = as_global(Ap);
+    const int32_t r0 = rg * kColRows;
+    const int32_t R = min(kColRows, nlist - r0);
+    if (tid < R) L.rows[tid] = ld_row(list + r0 + tid);
+    L.key[tid] = 0ull;
+    __syncthreads();
+    // stage the rows' previous scores (16-byte aligned rows of Kp floats)
+    {
+        const int32_t q4 = Kp >> 2;
+        for (int32_t q = tid; q < R * q4; q += kEngBlock) {
+            const int32_t r = q / q4, i = (q - r * q4) << 2;
+            const Row& rr = L.rows[r];
+            const float* dp = slot_delta(a, clampi(rr.slot, a.n_slots), (rr.t - 1) & 1);
+            *reinterpret_cast<float4*>(&L.d[r * Kp + i]) = *reinterpret_cast<const float4*>(dp + i);
+        }
+    }
+    // this thread's output (row ro, destination jo): its emission score, early
+    const int32_t ro = tid >> 7, jo = chunk * kColCols + (tid & (kColCols - 1));
+    const bool out_ok = ro < R && jo < K;
+    float bpre = 0.0f;
+    if (out_ok) {
+        const Row& rr = L.rows[ro];
+        bpre = rr.log_b[(int64_t)rr.t * rr.ld + jo];
+    }
+    __syncthreads();
+    // predecessors [i_lo, i_hi) of this wave, whole groups of 16
+    const int32_t ng = Kp / kGroup;
+    const int32_t i_lo = ((w * ng) / kEngWaves) * kGroup, i_hi = (((w + 1) * ng) / kEngWaves) * kGroup;
+    const int32_t ja = chunk * kColCols + lane;
+    const int32_t jb = ja + 64 < Kp ? ja + 64 : ja;   // the last chunk may hold one column only
+    float m[kColRows][2];
+    int32_t g[kColRows][2];
+#pragma unroll
+    for (int r = 0; r < kColRows; ++r) {
+        m[r][0] = m[r][1] = -INFINITY;
+        g[r][0] = g[r][1] = i_lo / kGroup;
+    }
+    for (int32_t i0 = i_lo; i0 < i_hi; i0 += kGroup) {
+        float a0[kGroup], a1[kGroup];
+#pragma unroll
+        for (int k = 0; k < kGroup; ++k) {
+            a0[k] = Ag[(int64_t)(i0 + k) * Kp + ja];
+            a1[k] = Ag[(int64_t)(i0 + k) * Kp + jb];
+        }
+        const int32_t gi = i0 / kGroup;
+#pragma unroll
+        for (int r = 0; r < kColRows; ++r) {
+            if (r < R) {
+                const float* sd = static_cast<const float*>(__builtin_assume_aligned(&L.d[r * Kp + i0], 16));
+                float g0 = -INFINITY, g1 = -INFINITY;
+#pragma unroll
+                for (int k = 0; k < kGroup; k += 2) {
+                    g0 = fmaxf(fmaxf(g0, sd[k] + a0[k]), sd[k + 1] + a0[k + 1]);
+                    g1 = fmaxf(fmaxf(g1, sd[k] + a1[k]), sd[k + 1] + a1[k + 1]);
+                }
+                if (g0 > m[r][0]) { m[r][0] = g0; g[r][0] = gi; }
+                if (g1 > m[r][1]) { m[r][1] = g1; g[r][1] = gi; }
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < kColRows; ++r) {
+        if (r < R) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const unsigned long long k = ((unsigned long long)score_order(m[r][c]) << 32) |
+                                             (uint32_t)(0xffffffffu - (uint32_t)g[r][c]);
+                __hip_atomic_fetch_max(&L.key[r * kColCols + c * 64 + lane], k, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        }
+    }
+    __syncthreads();
+    unsigned long long fkey = 0;
+    if (out_ok) {
+        const Row& rr = L.rows[ro];
+        const int32_t t = rr.t, f = rr.flags, slot = clampi(rr.slot, a.n_slots);
+        const unsigned long long key = L.key[tid];
+        const float mv = score_from_order((uint32_t)(key >> 32));
+        const int32_t gi = clampi((int32_t)(0xffffffffu - (uint32_t)key), ng);
+        float val = mv;
+        int32_t psi = 0;
+        if ((f & F_NEED_ARG) || mv == 0.0f) {
+            // the first candidate of the group equal to the maximum; its value
+            // is the one stored (signed zero)
+            const int32_t src0 = gi * kGroup;
+            const float4* at4 = reinterpret_cast<const float4*>(a.At + (int64_t)jo * Kp + src0);
+            float av[kGroup];
+#pragma unroll
+            for (int k = 0; k < kGroup; k += 4) {
+                const float4 v = at4[k >> 2];
+                av[k] = v.x; av[k + 1] = v.y; av[k + 2] = v.z; av[k + 3] = v.w;
+            }
+            const float* sd = &L.d[ro * Kp + src0];
+            int32_t p = -1;
+#pragma unroll
+            for (int k = 0; k < kGroup; ++k) {
+                const float x = sd[k] + av[k];
+                if (p < 0 && x == mv) { p = src0 + k; val = x; }
+            }
+            psi = clampi(p < 0 ? src0 : p, K);   // p < 0 is unreachable for finite/-inf inputs
+        }
+        int32_t anc = 0;
+        if (f & F_ANC_FIRST) anc = psi;
+        else if (f & F_ANC_CHAIN) anc = clampi(slot_anc(a, slot, (t - 1) & 1)[psi], K);
+        const float dnew = val + bpre;
+        slot_delta(a, slot, t & 1)[jo] = dnew;
+        if (f & F_PSI_TABLE) a.psi16[rr.off + (int64_t)t * K + jo] = (uint16_t)psi;
+        if (f & F_LEAF_TABLE) slot_leaf(a, slot)[(int64_t)rr.aux * Kp + jo] = (uint16_t)psi;
+        if (f & (F_ANC_FIRST | F_ANC_CHAIN)) slot_anc(a, slot, t & 1)[jo] = anc;
+        if (f & F_SNAP_SUB) slot_snap(a, slot)[jo] = dnew;
+        if (f & F_SNAP_ROOT) {
+            root_dsnap(a, rr.off, rr.aux)[jo] = dnew;
+            if (rr.aux >= 1) root_link(a, rr.off, rr.pp, rr.aux)[jo] = anc;
+        }
+        if (f & F_FINAL) fkey = order_key(dnew, jo);
+    }
+    // a wave holds 64 destinations of one row (wave-uniform test)
+    if (ro < R && (L.rows[ro].flags & F_FINAL)) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const unsigned long long o = __shfl_xor(fkey, off, 64);
+            if (o > fkey) fkey = o;
+        }
+        if (lane == 0) key_max(&a.keys[L.rows[ro].seq], fkey);
     }
     __syncthreads();
 }
@@ -2494,8 +2668,10 @@ __device__ __noinline__ void local_col_items(cargs_t& a_in, uint32_t x, int32_t 
     cargs_t& a = uniform_args(a_in);
     const float* __restrict__ Ap = a.Acol;
     __shared__ int32_t s_citem;
-    const int32_t nch = a.Kp / kWideCols;
-    const int32_t total = ((nf + kWideRows - 1) / kWideRows) * nch;
+    const bool two = a.At != nullptr;   // two-column items (Kp <= kColMaxKp)
+    const int32_t nch = two ? (a.Kp + kColCols - 1) / kColCols : a.Kp / kWideCols;
+    const int32_t nrow = two ? kColRows : kWideRows;
+    const int32_t total = ((nf + nrow - 1) / nrow) * nch;
     const Row* Fl = list_full(a, cur, x);
     int32_t item = rank;
     for (;;) {
@@ -2508,7 +2684,8 @@ __device__ __noinline__ void local_col_items(cargs_t& a_in, uint32_t x, int32_t 
             __syncthreads();
         }
         if (item >= total) break;
-        wide_item(a, Ap, Fl, nf, item / nch, item % nch, 0);
+        if (two) col_item(a, Ap, Fl, nf, item / nch, item % nch);
+        else wide_item(a, Ap, Fl, nf, item / nch, item % nch, 0);
         item = -1;
     }
 }
@@ -2709,6 +2886,19 @@ extern "C" __global__ __launch_bounds__(kBlock) void fv_prep_dense_kernel(const 
     if (idx >= (int64_t)Kp * Kp) return;
     const int32_t i = (int32_t)(idx / Kp), j = (int32_t)(idx - (int64_t)i * Kp);
     Ap[idx] = (i < K && j < K) ? log_a[(int64_t)i * K + j] : -INFINITY;
+}
+
+// At[j * Kp + i] = Ap[i * Kp + j]: the transposed (column-major) copy of the
+// padded log A, read by the two-column items' refine.  64 x 64 tiles through
+// LDS, 256 threads per tile; grid (Kp / 64, Kp / 64).
+extern "C" __global__ __launch_bounds__(kBlock) void fv_transpose_dense_kernel(const float* __restrict__ Ap,
+                                                                               int32_t Kp, float* __restrict__ At) {
+    __shared__ float tile[64][65];
+    const int32_t i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+    const int32_t c = threadIdx.x & 63, r4 = threadIdx.x >> 6;
+    for (int32_t r = r4; r < 64; r += 4) tile[r][c] = Ap[(int64_t)(i0 + r) * Kp + j0 + c];
+    __syncthreads();
+    for (int32_t r = r4; r < 64; r += 4) At[(int64_t)(j0 + r) * Kp + i0 + c] = tile[c][r];
 }
 
 // Per-sequence setup and the first step's row list (one block).  The

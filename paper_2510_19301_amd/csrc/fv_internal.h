@@ -57,6 +57,10 @@ enum : int32_t { L_INIT = 0, L_END = 1, L_FINALIZE = 2, L_BSPAWN = 3, L_LEAF_END
 constexpr int32_t kLeafLen = 128;
 constexpr int32_t kLeafMaxKp = 2048;   // larger K: no leaves (table too large per slot)
 
+// Column items of two destinations per lane stage their rows' scores whole
+// in LDS and refine from a transposed copy of log A: up to this Kp.
+constexpr int32_t kColMaxKp = 4096;
+
 // Operations of a beam row (one block each): start step, full beam step,
 // end-only step of a subtask, final selection of a root.
 enum : int32_t { B_INIT = 0, B_STEP = 1, B_END = 2, B_FINAL = 3 };
@@ -133,6 +137,7 @@ struct EngineArgs {
     int32_t K, Kp;
     const float* log_pi;        // may be null
     const float* Acol;          // the same matrix as the engine's Ap: row-major, pitch Kp
+    const float* At;            // its transpose (At[j * Kp + i]), Kp <= kColMaxKp; else null
     // sequences
     SeqInfo* seqs;
     int32_t n_seqs;

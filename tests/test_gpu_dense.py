@@ -155,3 +155,24 @@ def test_batch_uneven_lengths(fv):
             po, so, _ = oracle.vanilla(lp, la, lbs[b])
             assert (paths[b, :T] == po).all(), (method, P, b)
             assert _bits(scores[b]) == _bits(so)
+
+
+@pytest.mark.parametrize("method,P", [("vanilla", 1), ("flash", 4)])
+def test_batch_column_items_ragged_width(fv, method, P):
+    """About 100 short sequences at K = 300 (padded width 320, so the last
+    128-destination chunk holds one destination per lane): every XCD has
+    more than one 8-row group of few-row column items."""
+    K = 300
+    r = np.random.default_rng(11)
+    lengths = r.integers(5, 61, size=100)
+    _, la, _ = hmm.random_dense(K, 1, 91)
+    lp = hmm.uniform_log_pi(K)
+    lbs = [(r.standard_normal((int(T), K)) * 2).astype(np.float32) for T in lengths]
+    batch = fv.Batch([_dev(x) for x in lbs])
+    fv.decode_batch(_dev(la), batch, _dev(lp), method=method, P=P)
+    torch.cuda.synchronize()
+    paths, scores, status = batch.paths.cpu().numpy(), batch.scores.cpu().numpy(), batch.status.cpu().numpy()
+    for b, T in enumerate(lengths):
+        po, so, _ = oracle.vanilla(lp, la, lbs[b])
+        assert status[b] == 0 and (paths[b, :T] == po).all(), (method, P, b)
+        assert _bits(scores[b]) == _bits(so)
