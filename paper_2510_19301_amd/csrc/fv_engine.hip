@@ -762,14 +762,12 @@ __device__ __forceinline__ float score_from_order(uint32_t k) {
     return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
 }
 
-__device__ __forceinline__ void col_item(cargs_t& a, const float* __restrict__ Ap, const Row* list, int32_t nlist,
-                                         int32_t rg, int32_t chunk) {
+__device__ __forceinline__ void col_item(cargs_t& a, const float* __restrict__ Ap, const Row* list, int32_t r0,
+                                         int32_t R, int32_t chunk) {
     ColLds& L = g_lds.col;
     const int32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int32_t K = a.K, Kp = __builtin_amdgcn_readfirstlane(a.Kp);
     gfloat_t* Ag = as_global(Ap);
-    const int32_t r0 = rg * kColRows;
-    const int32_t R = min(kColRows, nlist - r0);
     if (tid < R) L.rows[tid] = ld_row(list + r0 + tid);
     L.key[tid] = 0ull;
     __syncthreads();
@@ -2670,8 +2668,14 @@ __device__ __noinline__ void local_col_items(cargs_t& a_in, uint32_t x, int32_t 
     __shared__ int32_t s_citem;
     const bool two = a.At != nullptr;   // two-column items (Kp <= kColMaxKp)
     const int32_t nch = two ? (a.Kp + kColCols - 1) / kColCols : a.Kp / kWideCols;
-    const int32_t nrow = two ? kColRows : kWideRows;
-    const int32_t total = ((nf + nrow - 1) / nrow) * nch;
+    // row groups of two-column items, at most kColRows rows each.  When one
+    // round of items fits on the XCD's blocks, as many groups as fit, rows
+    // spread evenly; otherwise full groups with the remainder last, so that
+    // the items claimed in a second round are the cheapest.
+    const int32_t gmin = (nf + kColRows - 1) / kColRows, gfit = nx / nch;
+    const bool spread = two && gmin <= gfit;
+    const int32_t ngrp = two ? (spread ? min(nf, gfit) : gmin) : (nf + kWideRows - 1) / kWideRows;
+    const int32_t total = ngrp * nch;
     const Row* Fl = list_full(a, cur, x);
     int32_t item = rank;
     for (;;) {
@@ -2684,7 +2688,12 @@ __device__ __noinline__ void local_col_items(cargs_t& a_in, uint32_t x, int32_t 
             __syncthreads();
         }
         if (item >= total) break;
-        if (two) col_item(a, Ap, Fl, nf, item / nch, item % nch);
+        if (two) {
+            const int32_t gq = item / nch;
+            const int32_t r0 = spread ? (gq * nf) / ngrp : gq * kColRows;
+            const int32_t r1 = spread ? ((gq + 1) * nf) / ngrp : min(nf, r0 + kColRows);
+            col_item(a, Ap, Fl, r0, r1 - r0, item - gq * nch);
+        }
         else wide_item(a, Ap, Fl, nf, item / nch, item % nch, 0);
         item = -1;
     }
