@@ -2661,7 +2661,7 @@ __device__ __noinline__ void run_wide(cargs_t& a_in, int cur) {
 // Column items of an XCD with few dense rows, claimed from its counter.  The
 // item body is inlined here: one call per step instead of one per item
 // (a call saves and restores the callee-saved registers the body uses).
-__device__ __noinline__ void local_col_items(cargs_t& a_in, uint32_t x, int32_t nx, int32_t rank, int cur,
+__device__ __forceinline__ void local_col_items(cargs_t& a_in, uint32_t x, int32_t nx, int32_t rank, int cur,
                                              int32_t nf) {
     cargs_t& a = uniform_args(a_in);
     const float* __restrict__ Ap = a.Acol;
