@@ -2627,7 +2627,7 @@ __device__ bool barrier_master(cargs_t& a, uint32_t epoch) {
 // Wide-row phase of a step: items (XCD list, group of 16 rows, 64-column
 // chunk) over the dense rows of every XCD, taken by all blocks of the chip:
 // first by global rank, then claimed from one counter.
-__device__ __noinline__ void run_wide(cargs_t& a_in, int cur) {
+__device__ __forceinline__ void run_wide(cargs_t& a_in, int cur) {
     cargs_t& a = uniform_args(a_in);
     const float* __restrict__ Ap = a.Acol;
     __shared__ int32_t s_item;
@@ -2706,6 +2706,7 @@ __device__ __forceinline__ void local_col_items(cargs_t& a_in, uint32_t x, int32
 // beam rows, one per block.  Each phase hands items out from a per-XCD
 // counter; every block (and the scheduler block once its own work is done)
 // takes a first item by rank, then claims until none are left.
+template <bool WIDE>
 __device__ void run_units(cargs_t& a, const float* __restrict__ Ap, uint32_t x, int32_t nx, int32_t rank,
                           int cur) {
     EngineLds& lds = g_lds;
@@ -2715,10 +2716,10 @@ __device__ void run_units(cargs_t& a, const float* __restrict__ Ap, uint32_t x, 
     const int32_t nbm = ld_c(&a.st->cnt[cur][x][2]);
     // few rows on this XCD: lane tiles would run mostly empty, so its rows are
     // computed as column items (lanes = destinations) by its own blocks
-    const bool local_cols = !a.wide && !a.sparse && nf > 0 && nf <= kLocalColRows;
+    const bool local_cols = !WIDE && !a.sparse && nf > 0 && nf <= kLocalColRows;
     const int32_t n_tiles =
-        (a.wide || local_cols || a.sparse) ? 0 : ((nf + kTileRows - 1) / kTileRows) * (a.Kp / kTileCols);
-    if (a.wide) run_wide(a, cur);
+        (WIDE || local_cols || a.sparse) ? 0 : ((nf + kTileRows - 1) / kTileRows) * (a.Kp / kTileCols);
+    if constexpr (WIDE) run_wide(a, cur);
     if (a.sparse && nf > 0) {
         // sparse rows: units of (row, 64 destinations), one per wave, 16 per block item
         __shared__ int32_t s_sitem;
@@ -2824,7 +2825,10 @@ __device__ void run_units(cargs_t& a, const float* __restrict__ Ap, uint32_t x, 
     }
 }
 
-// Every step of one model's decode (its own state, lists and buffers).
+// Every step of one model's decode (its own state, lists and buffers),
+// specialised for wide or local rows: each step loop inlines its own per-step
+// work function, so no call saves registers at every step.
+template <bool WIDE>
 __device__ __noinline__ void engine_model(cargs_t& a_in) {
     cargs_t& a = uniform_args(a_in);
     const float* __restrict__ Ap = a.Acol;
@@ -2867,7 +2871,7 @@ __device__ __noinline__ void engine_model(cargs_t& a_in) {
             break;
         }
         if (is_sched) scheduler(a, s);
-        run_units(a, Ap, x, nx, rank, cur);
+        run_units<WIDE>(a, Ap, x, nx, rank, cur);
         ++epoch;
         ok = is_sched ? barrier_master(a, epoch) : barrier_arrive_wait(a, epoch, x);
     }
@@ -2881,7 +2885,8 @@ extern "C" __global__ __launch_bounds__(kEngBlock) void fv_engine_kernel(const E
     for (int32_t mi = 0; mi < n_models; ++mi) {
         __syncthreads();
         cargs_t& a = *reinterpret_cast<cargs_t*>(reinterpret_cast<uint64_t>(table + mi));
-        engine_model(a);
+        if (a.wide) engine_model<true>(a);
+        else engine_model<false>(a);
     }
 }
 
