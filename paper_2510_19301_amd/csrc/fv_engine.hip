@@ -173,7 +173,7 @@ struct TileLds {
 constexpr int32_t kWideRows = 16;
 constexpr int32_t kWideCols = 64;
 constexpr int32_t kWideStage = 64;   // predecessors staged per LDS refill (4 groups)
-constexpr int32_t kLocalColRows = 40;  // an XCD with at most this many dense rows uses column items
+constexpr int32_t kLocalColRows = 96;  // an XCD with at most this many dense rows uses column items
 
 struct WideLds {
     float area[kEngWaves][2 * kWideRows * kWideCols];   // per wave: staged scores, later (max, group)
