@@ -173,7 +173,7 @@ struct TileLds {
 constexpr int32_t kWideRows = 16;
 constexpr int32_t kWideCols = 64;
 constexpr int32_t kWideStage = 64;   // predecessors staged per LDS refill (4 groups)
-constexpr int32_t kLocalColRows = 96;  // an XCD with at most this many dense rows uses column items
+constexpr int32_t kLocalColRows = 160;  // an XCD with at most this many dense rows uses column items
 
 struct WideLds {
     float area[kEngWaves][2 * kWideRows * kWideCols];   // per wave: staged scores, later (max, group)
@@ -184,6 +184,7 @@ struct WideLds {
 // previous scores staged whole, partial results merged through 64-bit keys.
 constexpr int32_t kColRows = 8;
 constexpr int32_t kColCols = 128;
+constexpr int32_t kColItemFixed = 2;     // an item's fixed cost, in rows of work
 struct ColLds {
     float d[kColRows * kColMaxKp];
     unsigned long long key[kColRows * kColCols];
@@ -2671,10 +2672,23 @@ __device__ __forceinline__ void local_col_items(cargs_t& a_in, uint32_t x, int32
     // row groups of two-column items, at most kColRows rows each.  When one
     // round of items fits on the XCD's blocks, as many groups as fit, rows
     // spread evenly; otherwise full groups with the remainder last, so that
-    // the items claimed in a second round are the cheapest.
+    // the items claimed in a second round are the cheapest, unless two
+    // rounds of evenly spread groups cost less.
     const int32_t gmin = (nf + kColRows - 1) / kColRows, gfit = nx / nch;
-    const bool spread = two && gmin <= gfit;
-    const int32_t ngrp = two ? (spread ? min(nf, gfit) : gmin) : (nf + kWideRows - 1) / kWideRows;
+    bool spread = two && gmin <= gfit;
+    int32_t ngrp = two ? (spread ? min(nf, gfit) : gmin) : (nf + kWideRows - 1) / kWideRows;
+    if (two && !spread && nx > 0) {
+        // full groups need a second round: compare with rows spread evenly
+        // over two rounds' worth of groups (cost in rows, fixed part
+        // kColItemFixed per item)
+        const int32_t over = gmin * nch - nx;   // items beyond the first round
+        const int32_t rem = nf - (gmin - 1) * kColRows;   // rows of the last group
+        const int32_t c_full = over <= nch ? (kColItemFixed + kColRows) + (kColItemFixed + rem)
+                                           : ((gmin * nch + nx - 1) / nx) * (kColItemFixed + kColRows);
+        const int32_t g2 = max(gmin, min(nf, (2 * nx) / nch));
+        const int32_t c_spread = ((g2 * nch + nx - 1) / nx) * (kColItemFixed + (nf + g2 - 1) / g2);
+        if (c_spread < c_full) { spread = true; ngrp = g2; }
+    }
     const int32_t total = ngrp * nch;
     const Row* Fl = list_full(a, cur, x);
     int32_t item = rank;
