@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <string>
+#include <map>
 #include <vector>
 
 #include "fv_internal.h"
@@ -98,11 +99,29 @@ struct DenseLayout {
     int32_t sparse = 0;
     int64_t nnz = 0;
     int32_t leaves = 0;          // slots carry a leaf backpointer table
+    int32_t leaf_len = 0;        // the longest leaf that can occur (table rows per slot)
     int64_t leaf_off = 0;        // its offset in a slot, in floats
+    int64_t leaf_tasks = 0;      // task-tree nodes when leaves end the bisection (slot sizing)
     Region Ap, At, seq1, seqinfo, keys, args, state, arrive, rows_full, rows_light, rows_beam, queue, free_stack,
         slots, alpha, root, psi, csr_flag, csr_ptr, csr_deg, csr_eid, csr_src, csr_val;
     size_t total = 0;
 };
+
+// Nodes of the bisection tree of a subtask with `pos` positions whose
+// subtasks of at most leaf_len positions are leaves (children follow
+// Alg. 1: [m, tmid] and, when the segment has more than 3 positions,
+// [tmid + 1, n]).  Depends only on the length; memoised.
+int64_t leaf_tree_nodes(int32_t pos, int32_t leaf_len, std::map<int32_t, int64_t>& memo) {
+    if (pos <= leaf_len) return 1;
+    auto it = memo.find(pos);
+    if (it != memo.end()) return it->second;
+    const int32_t len = pos - 1;
+    int64_t c = 1;
+    if (len >= 2) c += leaf_tree_nodes(len / 2 + 1, leaf_len, memo);
+    if (len > 2) c += leaf_tree_nodes(len - len / 2, leaf_len, memo);
+    memo[pos] = c;
+    return c;
+}
 
 size_t put(size_t& cur, Region& r, size_t bytes) {
     r.off = (cur + kAlign - 1) / kAlign * kAlign;
@@ -170,13 +189,31 @@ fv_status plan_dense(int32_t method, const fv_trans* A, const int32_t* T_host, i
         }
     }
     L.has_anc = method != FV_VANILLA;
+    // FLASH on a dense model of moderate K: leaf subtasks, their tables sized
+    // to the longest leaf that can occur, the slot pool to the leaf-cut tree
+    L.leaves = method == FV_FLASH && !sparse && L.Kp <= kLeafMaxKp;
+    if (L.leaves) {
+        std::map<int32_t, int64_t> memo;
+        for (int32_t b = 0; b < n_seqs; ++b) {
+            const int32_t T = T_host[b];
+            if (T <= 1) continue;
+            const int32_t pp = eff_parallelism(T, P);
+            L.leaf_tasks += 1;
+            for (int32_t d = 0; d < pp; ++d) {
+                const int64_t m = d == 0 ? 0 : seg_end(T, pp, d - 1) + 1, n = seg_end(T, pp, d);
+                if (n - m < 1) continue;
+                const int32_t pos = (int32_t)(n - m + 1);
+                L.leaf_len = std::max(L.leaf_len, std::min(pos, kLeafLen));
+                L.leaf_tasks += leaf_tree_nodes(pos, kLeafLen, memo);
+            }
+        }
+        if (L.leaf_len < 2) L.leaves = 0;
+    }
     // dense rows: delta[2] (+ anc[2] + snapshot); beam rows: three beam
     // records, and room for a dense row should the task need its exact re-decode
     L.slot_floats = (int64_t)L.Kp * (method == FV_VANILLA ? 2 : 5);
-    // FLASH on a dense model of moderate K: room for a leaf subtask's table
-    L.leaves = method == FV_FLASH && !sparse && L.Kp <= kLeafMaxKp;
     L.leaf_off = 5 * (int64_t)L.Kp;
-    if (L.leaves) L.slot_floats += (int64_t)kLeafLen * L.Kp / 2;
+    if (L.leaves) L.slot_floats += (int64_t)L.leaf_len * L.Kp / 2;
     if (beam) L.slot_floats = std::max<int64_t>(L.slot_floats, (2 * (int64_t)L.bw + 1) * L.brec);
     // a beam subtask may be queued twice (its exact re-decode)
     L.q_cap = std::max<int64_t>(1, beam ? 2 * L.n_tasks : L.n_tasks);
@@ -189,7 +226,8 @@ fv_status plan_dense(int32_t method, const fv_trans* A, const int32_t* T_host, i
         // bounded budget of row buffers allows (parallelism vs memory)
         const int64_t budget = (int64_t)(L.leaves ? 512 : 128) << 20;
         const int64_t cap = std::max<int64_t>(256, std::min<int64_t>(4096, budget / slot_bytes));
-        slots = std::min<int64_t>(L.n_tasks, std::max<int64_t>(std::min<int64_t>(nonempty, 1 << 16), cap));
+        const int64_t tasks = L.leaves ? L.leaf_tasks : L.n_tasks;
+        slots = std::min<int64_t>(tasks, std::max<int64_t>(std::min<int64_t>(nonempty, 1 << 16), cap));
     }
     if (slots < 1) slots = 1;
     slots = round_up(slots, kXcd);  // equal slot pools, one per XCD
@@ -480,7 +518,7 @@ fv_status run_batch(int32_t method, const fv_trans* models, const float* const* 
         a.n_slots = L.n_slots;
         a.has_anc = L.has_anc;
         a.wide = wide ? 1 : 0;
-        a.leaf_len = (L.leaves && !a.wide && !(flags & FV_FLAG_NO_LEAVES)) ? kLeafLen : 0;
+        a.leaf_len = (L.leaves && !a.wide && !(flags & FV_FLAG_NO_LEAVES)) ? L.leaf_len : 0;
         a.beam_q = (meth == FV_BEAM && !sparse && L.bw == 1 && L.Kp <= 2048 && L.B <= 256) ? 1 : 0;
         a.leaf_off = L.leaf_off;
         if (sparse) {

@@ -51,8 +51,14 @@ def test_workspace_size_properties(fv):
     big = [8000] * 64
     assert d.workspace_bytes("flash", K, big, P=16) < d.workspace_bytes("vanilla", K, big)
     assert f_long > 0
-    # P only changes the per-sequence division copies
-    assert d.workspace_bytes("flash", K, [8000], P=64) > d.workspace_bytes("flash", K, [8000], P=2)
+    # with the slot pool at its cap for both, P only changes the per-sequence division copies
+    assert d.workspace_bytes("flash", K, big, P=64) > d.workspace_bytes("flash", K, big, P=2)
+    # below the cap the pool follows the leaf-cut task tree: one root and 16
+    # leaves of 32 steps for T = 512, P = 16, so FLASH stays near vanilla's size
+    f_small = d.workspace_bytes("flash", 512, [512], P=16)
+    v_small = d.workspace_bytes("vanilla", 512, [512])
+    assert f_small < 2 * v_small
+    assert d.workspace_bytes("flash", 512, [512], P=16) < d.workspace_bytes("flash", 512, [512], P=2)
 
 
 def test_workspace_size_rejects_bad_args(fv):
