@@ -206,6 +206,56 @@ def sparse_runs(fv, torch, hmm, dev):
     return res
 
 
+def er_runs(fv, torch, hmm, dev):
+    """The paper's synthetic sweeps (Sec. VII) on single sequences: Erdos-Renyi
+    transition graphs, |O| = 50, defaults p = 0.253, K = 512, T = 512; p from
+    0.05 up by x1.5 (and 1), K and T from 32 to 2048, and a beam-width sweep
+    B = 1024..32 at K = 2048 (an ER model standing in for the paper's
+    forced-alignment data).  Decode time in ms (emission scores already on the
+    device) and workspace bytes; FLASH with P = 16."""
+    lib = fv.lib()
+
+    def one(h, runs):
+        la = torch.from_numpy(h.log_a).to(dev)
+        lp = torch.from_numpy(h.log_pi).to(dev)
+        log_e = torch.from_numpy(h.log_e).to(dev)
+        obs = torch.from_numpy(h.obs).to(dev)
+        lb = torch.empty((h.T, h.K), dtype=torch.float32, device=dev)
+        fv._lib.check(lib.fv_gather_emissions(h.K, h.V, log_e.data_ptr(), obs.data_ptr(), h.T, lb.data_ptr(),
+                                              h.K, torch.cuda.current_stream().cuda_stream), "fv_gather_emissions")
+        out = {}
+        for method, P, B in runs:
+            fv.decode(la, lb, lp, method, P=P, B=B)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            _, _, status = fv.decode(la, lb, lp, method, P=P, B=B)
+            e1.record()
+            torch.cuda.synchronize()
+            key = {"vanilla": "vanilla", "flash": f"flash_P{P}", "beam": f"beam_B{B}"}[method]
+            out[key] = {"ms": round(e0.elapsed_time(e1), 3), "status": int(status.item()),
+                        "workspace_bytes": fv.workspace_bytes(method, h.K, [h.T], P, B)}
+        return out
+
+    exact = (("vanilla", 1, 0), ("flash", 16, 0))
+    res = {"workload": "single sequences on Erdos-Renyi HMMs, |O|=50, uniform start, emission rows Dirichlet(1), "
+                       "observations sampled from the model; defaults p=0.253, K=512, T=512"}
+    res["p_sweep"] = []
+    for k in range(9):
+        p = 1.0 if k == 8 else 0.05 * 1.5 ** k
+        res["p_sweep"].append({"p": round(p, 4), **one(hmm.er_hmm(512, 512, p, seed=100 + k), exact)})
+    res["K_sweep"] = [{"K": K, **one(hmm.er_hmm(K, 512, 0.253, seed=200 + K), exact)}
+                      for K in (32, 64, 128, 256, 512, 1024, 2048)]
+    res["T_sweep"] = [{"T": T, **one(hmm.er_hmm(512, T, 0.253, seed=300 + T), exact)}
+                      for T in (32, 64, 128, 256, 512, 1024, 2048)]
+    beams = [("beam", 16, B) for B in (1024, 512, 256, 128, 64, 32)]
+    res["B_sweep"] = {"K": 2048, "T": 512, "p": 0.253,
+                      **one(hmm.er_hmm(2048, 512, 0.253, seed=400), [("vanilla", 1, 0), ("flash", 16, 0)] + beams)}
+    print(f"[bench] ER sweeps: default point vanilla {res['K_sweep'][4]['vanilla']['ms']} ms, "
+          f"FLASH {res['K_sweep'][4]['flash_P16']['ms']} ms", file=sys.stderr, flush=True)
+    return res
+
+
 def small_runs(fv, torch, hmm, dev):
     """Latency-bound decodes: one discrete HMM (K = 64, V = 128, T = 1000;
     microseconds per step of the single sequence) and the CRF training step
@@ -301,6 +351,8 @@ def main():
                     help="skip the K=100000 map-matching (CSR) runs")
     ap.add_argument("--no-small", action="store_true",
                     help="skip the discrete-HMM and CRF-step runs")
+    ap.add_argument("--no-er", action="store_true",
+                    help="skip the Erdos-Renyi sweeps (p, K, T, beam width)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--n", type=int, default=256)
@@ -411,6 +463,8 @@ def main():
         out["sparse"] = sparse_runs(fv, torch, hmm, dev)
     if not args.no_small:
         out.update(small_runs(fv, torch, hmm, dev))
+    if not args.no_er:
+        out["er_sweeps"] = er_runs(fv, torch, hmm, dev)
     if not args.no_cpu:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)

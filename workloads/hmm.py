@@ -87,6 +87,35 @@ def discrete_hmm(K: int = 64, V: int = 128, T: int = 1000, alpha_a: float = 1.0,
     return DiscreteHMM(K, V, T, uniform_log_pi(K), log_a, log_e, obs, states)
 
 
+def er_hmm(K: int = 512, T: int = 512, p: float = 0.253, M: int = 50, seed: int = 1) -> DiscreteHMM:
+    """Discrete HMM on an Erdos-Renyi transition graph, the shape of the
+    paper's synthetic experiments (Sec. VII): edge i -> j present with
+    probability p; a row left without edges gets a self-loop; present edges
+    get uniform (0, 1] weights normalised per row (float64), absent edges
+    are -inf.  M observable symbols with Dirichlet(1) emission rows, uniform
+    start, observations sampled from the model."""
+    r = _rng(seed, 10, K, T)
+    mask = r.random((K, K)) < p
+    empty = ~mask.any(axis=1)
+    mask[np.flatnonzero(empty), np.flatnonzero(empty)] = True
+    w = np.where(mask, 1.0 - r.random((K, K)), 0.0)
+    w /= w.sum(axis=1, keepdims=True)
+    with np.errstate(divide="ignore"):
+        log_a = np.where(mask, np.log(w), -np.inf).astype(np.float32)
+    log_e = log_dirichlet_rows(_rng(seed, 11, K, M), K, M, 1.0)
+    rs = _rng(seed, 12, K, T)
+    pa = np.exp(log_a.astype(np.float64))
+    pe = np.exp(log_e.astype(np.float64))
+    states = np.empty(T, np.int32)
+    obs = np.empty(T, np.int32)
+    q = int(rs.integers(0, K))
+    for t in range(T):
+        states[t] = q
+        obs[t] = _categorical(rs, pe[q])
+        q = _categorical(rs, pa[q])
+    return DiscreteHMM(K, M, T, uniform_log_pi(K), log_a, log_e, obs, states)
+
+
 @dataclass
 class DenseBatch:
     """Many sequences sharing one dense transition matrix; emission scores are
