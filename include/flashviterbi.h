@@ -76,11 +76,15 @@ enum { FV_FLAG_WIDE_ROWS = 1u << 0, FV_FLAG_LOCAL_ROWS = 1u << 1 };
  * asynchronously, like every status). */
 enum { FV_FLAG_VALIDATE = 1u << 2 };
 /* FLASH schedule.  By default a subtask of at most 128 steps (dense model,
- * K <= 2048, rows on their XCD) is a leaf: it keeps a 128 x K uint16
- * backpointer table in its row buffer and resolves all its positions at its
- * end instead of being bisected further (same result, much less
- * recomputation; the workspace grows by that table per row buffer).
- * FV_FLAG_NO_LEAVES bisects every subtask down to the paper's minimum. */
+ * K <= 2048, rows on their XCD) is a leaf: it keeps a backpointer table
+ * (uint16, one row of K per step, sized to the longest leaf that can occur)
+ * in its row buffer and resolves all its positions at its end instead of
+ * being bisected further (same result, much less recomputation).  The
+ * workspace plans leaves, and sizes the row-buffer pool to the leaf-cut task
+ * tree, when the default placement keeps rows on their XCD; with
+ * FV_FLAG_WIDE_ROWS such a plan still decodes correctly, without leaves and
+ * with subtasks waiting for row buffers.  FV_FLAG_NO_LEAVES bisects every
+ * subtask down to the paper's minimum. */
 enum { FV_FLAG_NO_LEAVES = 1u << 3 };
 enum { FV_VANILLA = 0, FV_FLASH = 1, FV_BEAM = 2 };
 

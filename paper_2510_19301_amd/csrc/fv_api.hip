@@ -111,6 +111,8 @@ struct DenseLayout {
 // subtasks of at most leaf_len positions are leaves (children follow
 // Alg. 1: [m, tmid] and, when the segment has more than 3 positions,
 // [tmid + 1, n]).  Depends only on the length; memoised.
+bool use_wide_rows(uint32_t flags, int32_t K, int32_t n_seqs, bool sparse);
+
 int64_t leaf_tree_nodes(int32_t pos, int32_t leaf_len, std::map<int32_t, int64_t>& memo) {
     if (pos <= leaf_len) return 1;
     auto it = memo.find(pos);
@@ -189,9 +191,11 @@ fv_status plan_dense(int32_t method, const fv_trans* A, const int32_t* T_host, i
         }
     }
     L.has_anc = method != FV_VANILLA;
-    // FLASH on a dense model of moderate K: leaf subtasks, their tables sized
-    // to the longest leaf that can occur, the slot pool to the leaf-cut tree
-    L.leaves = method == FV_FLASH && !sparse && L.Kp <= kLeafMaxKp;
+    // FLASH on a dense model of moderate K placed on local rows (the default
+    // placement; wide rows run without leaves): leaf subtasks, their tables
+    // sized to the longest leaf that can occur, the slot pool to the
+    // leaf-cut tree
+    L.leaves = method == FV_FLASH && !sparse && L.Kp <= kLeafMaxKp && !use_wide_rows(0, K, n_seqs, sparse);
     if (L.leaves) {
         std::map<int32_t, int64_t> memo;
         for (int32_t b = 0; b < n_seqs; ++b) {
