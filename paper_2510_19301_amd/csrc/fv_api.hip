@@ -549,6 +549,7 @@ fv_status run_batch(int32_t method, const fv_trans* models, const float* const* 
         a.Bc = L.Bc;
         a.brec = L.brec;
         a.bw = L.bw;
+        a.bw_min = std::min<int32_t>(L.bw, std::max<int32_t>(1, (L.Kp + 4095) / 4096));
         a.pool = L.pool;
         a.queue = static_cast<Task*>(at(L.queue));
         a.q_cap = L.q_cap;

@@ -1492,15 +1492,21 @@ __device__ __noinline__ void beam_chain_walk(cargs_t& a, const Row& r, int32_t q
 
 // One part of one beam task's step (parts beyond the first return at once
 // for the single-block operations END and FINAL).
-__device__ __noinline__ void beam_row(cargs_t& a_in, const float* __restrict__ Ap, const Row& r, int32_t part) {
+__device__ __noinline__ void beam_row(cargs_t& a_in, const float* __restrict__ Ap, const Row& r, int32_t part,
+                                     int32_t W) {
     cargs_t& a = uniform_args(a_in);
     BeamLds& L = g_lds.beam;
     const int tid = threadIdx.x;
     SeqInfo& sq = a.seqs[r.seq];
-    const int32_t K = a.K, Kp = a.Kp, B = a.B, W = a.bw;
+    const int32_t K = a.K, Kp = a.Kp, B = a.B;
     gfloat_t* Ag = as_global(Ap);
     const int32_t slot = clampi(r.slot, a.n_slots);
     const bool root = r.kind == KIND_BROOT;
+    // this step runs W of the a.bw parts; part 0 marks the other records of
+    // the parity it writes empty, so the next rebuild merges W lists
+    auto clear_unused = [&](int32_t parity) {
+        if (part == 0 && tid >= W && tid < a.bw) slot_part(a, slot, parity, tid).hdr[0] = 0;
+    };
     const int32_t T = r.T, pp = r.pp, m = r.m, n = r.n, t = r.t;
     const int32_t tmid = (m + n) >> 1;
     const int32_t jlo = part_lo(K, W, part), jhi = part_lo(K, W, part + 1), nj = jhi - jlo;
@@ -1565,6 +1571,7 @@ __device__ __noinline__ void beam_row(cargs_t& a_in, const float* __restrict__ A
             out.s[p] = st; out.v[p] = sv; out.a[p] = av;
         });
         if (tid == 0) out.hdr[0] = nk;
+        clear_unused(m & 1);
     } else if (r.aux == B_STEP) {
         const int32_t nb = beam_rebuild(a, slot, (t - 1) & 1);
         if (part == 0) {
@@ -1625,6 +1632,7 @@ __device__ __noinline__ void beam_row(cargs_t& a_in, const float* __restrict__ A
             out.s[p] = st; out.v[p] = sv; out.a[p] = av;
         });
         if (tid == 0) out.hdr[0] = nk;
+        clear_unused(t & 1);
     } else if (r.aux == B_END) {
         if (part != 0) return;
         // only the known end state q*_n is evaluated
@@ -2821,6 +2829,10 @@ __device__ void run_units(cargs_t& a, const float* __restrict__ Ap, uint32_t x, 
         }
         return;
     }
+    // parts per beam row this step: all a.bw while the XCD's blocks
+    // outnumber its rows' parts, fewer (down to the LDS limit) when many beam
+    // rows are in flight; the results do not depend on the count
+    const int32_t Wu = a.bw > 1 ? max(a.bw_min, min(a.bw, nx / max(nbm, 1))) : 1;
     int32_t u = rank;
     for (;;) {
         if (u < 0) {
@@ -2829,10 +2841,10 @@ __device__ void run_units(cargs_t& a, const float* __restrict__ Ap, uint32_t x, 
             u = s_unit;
             __syncthreads();
         }
-        if (u >= nbm * a.bw) break;   // item = (row, part); finalizes use part 0
-        const int32_t part = u % a.bw;
-        const Row r = ld_row(Bl + u / a.bw);
-        if (is_beam(r.kind)) beam_row(a, Ap, r, part);
+        if (u >= nbm * Wu) break;   // item = (row, part); finalizes use part 0
+        const int32_t part = u % Wu;
+        const Row r = ld_row(Bl + u / Wu);
+        if (is_beam(r.kind)) beam_row(a, Ap, r, part, Wu);
         else if (part == 0 && r.aux == L_LEAF_END) leaf_end(a, r);
         else if (part == 0) dense_finalize(a, r);
         u = -1;

@@ -144,6 +144,7 @@ struct EngineArgs {
     int32_t method;             // FV_VANILLA / FV_FLASH / FV_BEAM
     int32_t B, Bc;              // beam width (<= K) and its padded array length
     int32_t bw;                 // parts of a beam task's step (1 for other methods)
+    int32_t bw_min;             // fewest parts whose destinations fit a block's LDS
     int64_t brec;               // floats per beam record (header + state, score, anchor arrays)
     // storage
     float* slot_base;           // slots * slot_floats

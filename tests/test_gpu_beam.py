@@ -149,3 +149,12 @@ def test_beam_large_k(fv):
     lb = rng.standard_normal((T, K), dtype=np.float32) * np.float32(3.0)
     lp = np.full(K, -np.log(K), np.float32)
     _check(fv, lp, la, lb, 16, 16, "beam K=16384 T=120 B=16")
+
+
+@pytest.mark.parametrize("K,T,B,P", [(1024, 700, 16, 4), (600, 900, 8, 2)])
+def test_beam_fewer_parts_with_many_rows(fv, K, T, B, P):
+    """One sequence: its beam steps are planned in several parts (one block
+    each), but once many subtasks are in flight each step runs fewer parts
+    per row; the rebuilt beam and the result must not change."""
+    lp, la, lb = hmm.random_dense(K, T, 1000 + K)
+    _check(fv, lp, la, lb, B, P, f"beam parts K={K} T={T} B={B} P={P}")
