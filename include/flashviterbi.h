@@ -86,6 +86,20 @@ enum { FV_FLAG_VALIDATE = 1u << 2 };
  * with subtasks waiting for row buffers.  FV_FLAG_NO_LEAVES bisects every
  * subtask down to the paper's minimum. */
 enum { FV_FLAG_NO_LEAVES = 1u << 3 };
+/* Subtask initialisation (Sec. V-B, pruning for parallel decoding).  By
+ * default a subtask starting at m > 0 is anchored: its start scores are
+ * (alpha + log A(q*_{m-1}, j)) + log B_m(j), alpha being the parent's score of
+ * q*_{m-1} (retained pruning, Def. 3), which reproduces vanilla's float32
+ * values along the path, so FLASH and FLASH-BS with B >= K return vanilla's
+ * path.  FV_FLAG_RELATIVE_INIT takes the paper's displayed initialisation,
+ * log A(q*_{m-1}, j) + log B_m(j) (the carried score dropped): exact in real
+ * arithmetic, but in float32 rounding depends on the magnitude of the
+ * running score, so paths can differ from vanilla's at near ties.  Every
+ * subtask is then bisected down to the paper's minimum (no leaves: a leaf
+ * would start once where the bisection restarts at each level, and the two
+ * round differently).  Dense models only (FLASH and FLASH-BS); with a CSR
+ * model the call returns FV_E_UNSUPPORTED.  Vanilla decoding ignores it. */
+enum { FV_FLAG_RELATIVE_INIT = 1u << 4 };
 enum { FV_VANILLA = 0, FV_FLASH = 1, FV_BEAM = 2 };
 
 /* Transition model.  FV_DENSE: log_a[K*K] (device).  FV_CSR: out-edges of

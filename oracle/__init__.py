@@ -56,11 +56,11 @@ def _load():
         lib.fvo_rescore.argtypes = [i32, i32, vp, vp, vp, i64, vp]
         lib.fvo_rescore.restype = f
         lib.fvo_gather_emissions.argtypes = [i32, i32, vp, vp, i32, vp, i64]
-        lib.fvo_flash.argtypes = [i32, i32, i32, vp, vp, vp, i64, vp, vp, u64, C.POINTER(Stats), vp]
+        lib.fvo_flash.argtypes = [i32, i32, i32, vp, vp, vp, i64, vp, vp, u64, C.POINTER(Stats), vp, i32]
         lib.fvo_beam.argtypes = [i32, i32, i32, i32, vp, vp, vp, i64, vp, vp, vp, u64,
-                                 C.POINTER(Stats), vp]
+                                 C.POINTER(Stats), vp, i32]
         lib.fvo_beam_csr.argtypes = [i32, i32, i32, i32, vp, vp, vp, vp, vp, i64, vp, vp, vp, u64,
-                                     C.POINTER(Stats), vp]
+                                     C.POINTER(Stats), vp, i32]
         lib.fvo_backward.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp, vp, i32]
         for fn in (lib.fvo_vanilla, lib.fvo_vanilla_f64, lib.fvo_vanilla_csr, lib.fvo_flash,
                    lib.fvo_beam, lib.fvo_beam_csr, lib.fvo_backward, lib.fvo_gather_emissions):
@@ -143,10 +143,11 @@ def gather_emissions(log_e, obs):
     return out
 
 
-def flash(log_pi, log_a, log_b, P, shuffle_seed=0, want_trace=False):
+def flash(log_pi, log_a, log_b, P, shuffle_seed=0, want_trace=False, relative_init=False):
     """FLASH Viterbi.  Returns (path, score, status, stats dict); with
     want_trace the stats hold 'trace', the (m, n) of every subtask in decode
-    order."""
+    order.  relative_init: the paper's displayed subtask initialisation
+    (Sec. V-B, the carried score dropped) instead of the anchored one."""
     lib = _load()
     log_pi, log_a, log_b, K, T, ld = _prep(log_pi, log_a, log_b)
     path = np.empty(T, np.int32)
@@ -154,16 +155,16 @@ def flash(log_pi, log_a, log_b, P, shuffle_seed=0, want_trace=False):
     st = Stats()
     tr = np.full(2 * T + 2, -1, np.int32) if want_trace else None
     rc = lib.fvo_flash(K, T, int(P), _p(log_pi), _p(log_a), _p(log_b), ld, _p(path), _p(score),
-                       int(shuffle_seed), C.byref(st), _p(tr))
+                       int(shuffle_seed), C.byref(st), _p(tr), int(bool(relative_init)))
     d = {k: getattr(st, k) for k, _ in Stats._fields_}
     if want_trace:
         d["trace"] = [(int(tr[2 * k]), int(tr[2 * k + 1])) for k in range(d["tasks"] - 1)]
     return path, score[0], rc, d
 
 
-def beam(log_pi, log_a, log_b, B, P, shuffle_seed=0):
+def beam(log_pi, log_a, log_b, B, P, shuffle_seed=0, relative_init=False):
     """FLASH-BS.  Returns (path, score, status, stats dict); stats also holds
-    'root_score' and 'fallbacks'."""
+    'root_score' and 'fallbacks'.  relative_init as in flash()."""
     lib = _load()
     log_pi, log_a, log_b, K, T, ld = _prep(log_pi, log_a, log_b)
     path = np.empty(T, np.int32)
@@ -172,14 +173,14 @@ def beam(log_pi, log_a, log_b, B, P, shuffle_seed=0):
     nfb = np.zeros(1, np.int32)
     st = Stats()
     rc = lib.fvo_beam(K, T, int(B), int(P), _p(log_pi), _p(log_a), _p(log_b), ld, _p(path),
-                      _p(score), _p(root), int(shuffle_seed), C.byref(st), _p(nfb))
+                      _p(score), _p(root), int(shuffle_seed), C.byref(st), _p(nfb), int(bool(relative_init)))
     d = {k: getattr(st, k) for k, _ in Stats._fields_}
     d["root_score"] = root[0]
     d["fallbacks"] = int(nfb[0])
     return path, score[0], rc, d
 
 
-def beam_csr(log_pi, row_ptr, col, val, log_b, B, P, shuffle_seed=0):
+def beam_csr(log_pi, row_ptr, col, val, log_b, B, P, shuffle_seed=0, relative_init=False):
     """FLASH-BS on a CSR model (out-edges; missing edges are -inf).  Returns
     (path, score, status, stats dict) like beam()."""
     lib = _load()
@@ -196,7 +197,7 @@ def beam_csr(log_pi, row_ptr, col, val, log_b, B, P, shuffle_seed=0):
     st = Stats()
     rc = lib.fvo_beam_csr(K, T, int(B), int(P), _p(log_pi), _p(row_ptr), _p(col), _p(val), _p(log_b),
                           log_b.shape[1], _p(path), _p(score), _p(root), int(shuffle_seed), C.byref(st),
-                          _p(nfb))
+                          _p(nfb), int(bool(relative_init)))
     d = {k: getattr(st, k) for k, _ in Stats._fields_}
     d["root_score"] = root[0]
     d["fallbacks"] = int(nfb[0])

@@ -272,20 +272,22 @@ static float model_a(const fvo_model* M, int i, int j)
 }
 
 /* sc[j] = (alpha + log A(q, j)) + b_m[j] for every j: the anchored start
+ * (with relative_init the caller passes no alpha: sc[j] = log A(q, j) + b_m[j])
  * of a segment (Def. 3).  CSR: -inf except at q's out-neighbours. */
-static void model_anchor_row(const fvo_model* M, int q, float alpha, const float* b_m, float* sc)
+static void model_anchor_row(const fvo_model* M, int q, float alpha, int relative_init, const float* b_m,
+                             float* sc)
 {
     if (!M->log_a) {   /* only q's out-neighbours are finite */
         for (int j = 0; j < M->K; ++j) sc[j] = -INFINITY;
         for (int e = M->row_ptr[q]; e < M->row_ptr[q + 1]; ++e) {
             int j = M->col[e];
-            float c = alpha + model_a(M, q, j);
+            float c = relative_init ? model_a(M, q, j) : alpha + model_a(M, q, j);
             sc[j] = c + b_m[j];
         }
         return;
     }
     for (int j = 0; j < M->K; ++j) {
-        float c = alpha + model_a(M, q, j);
+        float c = relative_init ? model_a(M, q, j) : alpha + model_a(M, q, j);
         sc[j] = c + b_m[j];
     }
 }
@@ -339,6 +341,9 @@ static float model_rescore(const fvo_model* M, int T, const float* log_pi, const
  *     OptProb_m(i) = (alpha + log A(q*_{m-1}, i)) + log B_m(i),
  * alpha = delta_{m-1}(q*_{m-1}), which reproduces vanilla's float32 values
  * along the optimal path exactly.  m = 0 starts from pi as in Alg. 2.
+ * relative_init != 0 takes the paper's displayed initialisation instead,
+ * OptProb_m(i) = log A(q*_{m-1}, i) + log B_m(i) (the carried score dropped);
+ * its paths can differ from vanilla's where rounding decides a near tie.
  * MidState is tracked from t_mid + 1 on; q*_{t_mid} = MidState(q*_n).  The
  * anchor handed to the right child is OptProb_{t_mid}(q*_{t_mid}).
  *
@@ -349,7 +354,7 @@ static float model_rescore(const fvo_model* M, int T, const float* log_pi, const
  */
 int fvo_flash(int K, int T, int P, const float* log_pi, const float* log_a,
               const float* log_b, int64_t ld, int32_t* path, float* score,
-              uint64_t shuffle_seed, fvo_stats* st, int32_t* trace)
+              uint64_t shuffle_seed, fvo_stats* st, int32_t* trace, int relative_init)
 {
     if (K < 1 || T < 1 || ld < K || !log_a || !log_b || !path || !score)
         return FVO_INVALID;
@@ -445,7 +450,7 @@ int fvo_flash(int K, int T, int P, const float* log_pi, const float* log_a,
             const float* row = log_a + (size_t)tk.q_prev * K;
             const float* b_m = log_b + (size_t)m * ld;
             for (int i = 0; i < K; ++i) {
-                float c = tk.alpha + row[i];
+                float c = relative_init ? row[i] : tk.alpha + row[i];
                 opt[i] = c + b_m[i];
             }
             st->candidates += K;
@@ -608,7 +613,8 @@ static const fvo_ent* beam_find(const fvo_beam_t* b, int s)
 
 static int beam_impl(const fvo_model* M, int T, int B, int P, const float* log_pi,
                      const float* log_b, int64_t ld, int32_t* path, float* score,
-                     float* root_score, uint64_t shuffle_seed, fvo_stats* st, int32_t* n_fallback)
+                     float* root_score, uint64_t shuffle_seed, fvo_stats* st, int32_t* n_fallback,
+                     int relative_init)
 {
     const int K = M->K;
     if (K < 1 || T < 1 || B < 1 || ld < K || !log_b || !path || !score)
@@ -701,7 +707,7 @@ static int beam_impl(const fvo_model* M, int T, int B, int P, const float* log_p
             if (m == 0) {
                 for (int i = 0; i < K; ++i) sc[i] = log_pi ? log_pi[i] + log_b[i] : log_b[i];
             } else {
-                model_anchor_row(M, tk.q_prev, tk.alpha, log_b + (size_t)m * ld, sc);
+                model_anchor_row(M, tk.q_prev, tk.alpha, relative_init, log_b + (size_t)m * ld, sc);
                 st->candidates += K;
             }
             beam_from_scores(K, B, sc, NULL, &cur);
@@ -738,7 +744,7 @@ static int beam_impl(const fvo_model* M, int T, int B, int P, const float* log_p
                 if (m == 0) {
                     for (int i = 0; i < K; ++i) opt[i] = log_pi ? log_pi[i] + log_b[i] : log_b[i];
                 } else {
-                    model_anchor_row(M, tk.q_prev, tk.alpha, log_b + (size_t)m * ld, opt);
+                    model_anchor_row(M, tk.q_prev, tk.alpha, relative_init, log_b + (size_t)m * ld, opt);
                 }
                 float* exsnap = sc;
                 if (tmid == m) memcpy(exsnap, opt, sizeof(float) * K);
@@ -782,11 +788,13 @@ done:
 
 int fvo_beam(int K, int T, int B, int P, const float* log_pi, const float* log_a,
              const float* log_b, int64_t ld, int32_t* path, float* score,
-             float* root_score, uint64_t shuffle_seed, fvo_stats* st, int32_t* n_fallback)
+             float* root_score, uint64_t shuffle_seed, fvo_stats* st, int32_t* n_fallback,
+             int relative_init)
 {
     if (!log_a) return FVO_INVALID;
     fvo_model M = {K, log_a, NULL, NULL, NULL};
-    return beam_impl(&M, T, B, P, log_pi, log_b, ld, path, score, root_score, shuffle_seed, st, n_fallback);
+    return beam_impl(&M, T, B, P, log_pi, log_b, ld, path, score, root_score, shuffle_seed, st, n_fallback,
+                     relative_init);
 }
 
 /* FLASH-BS on a CSR model (out-edges row_ptr[K+1], col, val; missing edges
@@ -794,11 +802,12 @@ int fvo_beam(int K, int T, int B, int P, const float* log_pi, const float* log_a
 int fvo_beam_csr(int K, int T, int B, int P, const float* log_pi, const int32_t* row_ptr,
                  const int32_t* col, const float* val, const float* log_b, int64_t ld,
                  int32_t* path, float* score, float* root_score, uint64_t shuffle_seed,
-                 fvo_stats* st, int32_t* n_fallback)
+                 fvo_stats* st, int32_t* n_fallback, int relative_init)
 {
     if (!row_ptr) return FVO_INVALID;
     fvo_model M = {K, NULL, row_ptr, col, val};
-    return beam_impl(&M, T, B, P, log_pi, log_b, ld, path, score, root_score, shuffle_seed, st, n_fallback);
+    return beam_impl(&M, T, B, P, log_pi, log_b, ld, path, score, root_score, shuffle_seed, st, n_fallback,
+                     relative_init);
 }
 
 /* ------------------------------------------------------------------------ */

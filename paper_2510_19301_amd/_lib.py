@@ -15,6 +15,7 @@ FV_OK, FV_E_INVALID_ARG, FV_E_UNSUPPORTED, FV_E_WORKSPACE, FV_E_DEVICE, FV_E_INF
 FV_W_BEAM_FALLBACK = 1
 FV_DENSE, FV_CSR = 0, 1
 FV_FLAG_WIDE_ROWS, FV_FLAG_LOCAL_ROWS, FV_FLAG_VALIDATE, FV_FLAG_NO_LEAVES = 1, 2, 4, 8
+FV_FLAG_RELATIVE_INIT = 16
 FV_VANILLA, FV_FLASH, FV_BEAM = 0, 1, 2
 METHODS = {"vanilla": FV_VANILLA, "flash": FV_FLASH, "beam": FV_BEAM}
 

@@ -414,11 +414,16 @@ fv_status plan_batch(int32_t method, const fv_trans* models, int32_t n_models, c
     return FV_OK;
 }
 
-fv_status check_flags(uint32_t flags, const fv_trans* models, int32_t n_models) {
+fv_status check_flags(uint32_t flags, int32_t method, const fv_trans* models, int32_t n_models) {
     if ((flags & FV_FLAG_WIDE_ROWS) && (flags & FV_FLAG_LOCAL_ROWS))
         return fail(FV_E_INVALID_ARG, "FV_FLAG_WIDE_ROWS and FV_FLAG_LOCAL_ROWS exclude each other");
-    if (flags & ~(uint32_t)(FV_FLAG_WIDE_ROWS | FV_FLAG_LOCAL_ROWS | FV_FLAG_VALIDATE | FV_FLAG_NO_LEAVES))
+    if (flags & ~(uint32_t)(FV_FLAG_WIDE_ROWS | FV_FLAG_LOCAL_ROWS | FV_FLAG_VALIDATE | FV_FLAG_NO_LEAVES |
+                            FV_FLAG_RELATIVE_INIT))
         return fail(FV_E_INVALID_ARG, "unknown flags 0x%x", flags);
+    if ((flags & FV_FLAG_RELATIVE_INIT) && method != FV_VANILLA)
+        for (int32_t m = 0; models && m < n_models; ++m)
+            if (models[m].kind == FV_CSR)
+                return fail(FV_E_UNSUPPORTED, "FV_FLAG_RELATIVE_INIT applies to dense models only");
     if (flags & FV_FLAG_WIDE_ROWS)
         for (int32_t m = 0; models && m < n_models; ++m)
             if (models[m].kind == FV_CSR) return fail(FV_E_INVALID_ARG, "FV_FLAG_WIDE_ROWS applies to dense models only");
@@ -432,7 +437,7 @@ fv_status run_batch(int32_t method, const fv_trans* models, const float* const* 
                     const fv_seq* seqs_dev, const int32_t* T_host, const int32_t* model_host, int32_t n_seqs,
                     int32_t P, int32_t B, const fv_seq* single, int32_t* status, uint32_t flags, void* ws,
                     size_t ws_bytes, hipStream_t stream) {
-    fv_status rc = check_flags(flags, models, n_models);
+    fv_status rc = check_flags(flags, method, models, n_models);
     if (rc != FV_OK) return rc;
     BatchPlan bp;
     rc = plan_batch(method, models, n_models, T_host, model_host, n_seqs, P, B, single != nullptr, bp);
@@ -522,7 +527,11 @@ fv_status run_batch(int32_t method, const fv_trans* models, const float* const* 
         a.n_slots = L.n_slots;
         a.has_anc = L.has_anc;
         a.wide = wide ? 1 : 0;
-        a.leaf_len = (L.leaves && !a.wide && !(flags & FV_FLAG_NO_LEAVES)) ? L.leaf_len : 0;
+        // leaves are exact only with anchored starts: the paper's displayed
+        // start restarts every bisection level, and so does the decode
+        a.leaf_len = (L.leaves && !a.wide && !(flags & (FV_FLAG_NO_LEAVES | FV_FLAG_RELATIVE_INIT))) ? L.leaf_len
+                                                                                                      : 0;
+        a.relative_init = (flags & FV_FLAG_RELATIVE_INIT) ? 1 : 0;
         a.beam_q = (meth == FV_BEAM && !sparse && L.bw == 1 && L.Kp <= 2048 && L.B <= 256) ? 1 : 0;
         a.leaf_off = L.leaf_off;
         if (sparse) {

@@ -1048,7 +1048,7 @@ __device__ __noinline__ void light_row(cargs_t& a_in, const float* __restrict__ 
                 float v = -INFINITY;
                 if (j < K) {
                     if (m == 0) v = a.log_pi ? xv[u] + bv[u] : bv[u];
-                    else if (q >= 0) { const float c = alpha + xv[u]; v = c + bv[u]; }
+                    else if (q >= 0) { const float c = a.relative_init ? xv[u] : alpha + xv[u]; v = c + bv[u]; }
                     if (r.flags & F_SNAP_SUB) slot_snap(a, slot)[j] = v;
                     if (r.flags & F_SNAP_ROOT) root_dsnap(a, r.off, 0)[j] = v;
                     if (r.flags & F_FINAL) {
@@ -1561,7 +1561,11 @@ __device__ __noinline__ void beam_row(cargs_t& a_in, const float* __restrict__ A
             const int32_t j = jlo + k;
             float v = -INFINITY;
             if (m == 0) v = a.log_pi ? a.log_pi[j] + bm[j] : bm[j];
-            else if (q >= 0) { const float c = alpha + Ap[(int64_t)q * Kp + j]; v = c + bm[j]; }
+            else if (q >= 0) {
+                const float aq = Ap[(int64_t)q * Kp + j];
+                const float c = a.relative_init ? aq : alpha + aq;
+                v = c + bm[j];
+            }
             L.sc[k] = v;
             L.an[k] = -1;
         }
@@ -2166,7 +2170,11 @@ __device__ __noinline__ void beam_row_q(cargs_t& a_in, const Row& r) {
         for (int32_t j = tid; j < K; j += kQThreads) {
             float v = -INFINITY;
             if (m == 0) v = a.log_pi ? a.log_pi[j] + bm[j] : bm[j];
-            else if (q >= 0) { const float c = alpha + Ap[(int64_t)q * Kp + j]; v = c + bm[j]; }
+            else if (q >= 0) {
+                const float aq = Ap[(int64_t)q * Kp + j];
+                const float c = a.relative_init ? aq : alpha + aq;
+                v = c + bm[j];
+            }
             L.sc[j] = v;
             L.an[j] = -1;
         }

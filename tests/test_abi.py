@@ -92,6 +92,10 @@ def test_decode_argument_errors_are_synchronous(fv):
     assert l.fv_decode_flash(C.byref(csr), None, fake, 8, 5, 4, fake, fake, None, fv._lib.FV_FLAG_WIDE_ROWS,
                              fake, 1 << 20, None) == -1
     assert l.fv_decode_vanilla(C.byref(csr), None, fake, 8, 5, fake, fake, None, 0, fake, 16, None) == -3
+    # the paper's displayed subtask start is offered for dense models only
+    rel = fv._lib.FV_FLAG_RELATIVE_INIT
+    assert l.fv_decode_flash(C.byref(csr), None, fake, 8, 5, 4, fake, fake, None, rel, fake, 1 << 20, None) == -2
+    assert l.fv_decode_flash(C.byref(m), None, fake, 8, 5, 4, fake, fake, None, 1 << 9, fake, 1 << 20, None) == -1
     assert l.fv_last_error()
 
 

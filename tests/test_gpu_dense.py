@@ -176,3 +176,46 @@ def test_batch_column_items_ragged_width(fv, method, P):
         po, so, _ = oracle.vanilla(lp, la, lbs[b])
         assert status[b] == 0 and (paths[b, :T] == po).all(), (method, P, b)
         assert _bits(scores[b]) == _bits(so)
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_relative_init_matches_oracle(fv, seed):
+    """FV_FLAG_RELATIVE_INIT (the paper's displayed subtask start, carried
+    score dropped): on inputs where its path differs from vanilla's, FLASH
+    and FLASH-BS must still equal the oracle's same procedure bit for bit."""
+    lp, la, lb = hmm.random_dense(64, 2000, seed)
+    lb = (lb * 20).astype(np.float32)
+    po, _, _ = oracle.vanilla(lp, la, lb)
+    diverged = False
+    for P in (4, 16):
+        pr, sr, rc, _ = oracle.flash(lp, la, lb, P, relative_init=True)
+        diverged |= bool((pr != po).any())
+        path, score, st = fv.decode(_dev(la), _dev(lb), _dev(lp), method="flash", P=P, relative_init=True)
+        torch.cuda.synchronize()
+        assert int(st.cpu()[0]) == rc
+        assert (path.cpu().numpy() == pr).all(), np.flatnonzero(path.cpu().numpy() != pr)[:10]
+        assert _bits(score.cpu().numpy()) == _bits(sr)
+    assert diverged
+    for B in (8, 32):
+        pr, sr, rc, _ = oracle.beam(lp, la, lb, B, 4, relative_init=True)
+        path, score, st = fv.decode(_dev(la), _dev(lb), _dev(lp), method="beam", P=4, B=B, relative_init=True)
+        torch.cuda.synchronize()
+        assert int(st.cpu()[0]) == rc
+        assert (path.cpu().numpy() == pr).all(), (B, np.flatnonzero(path.cpu().numpy() != pr)[:10])
+        assert _bits(score.cpu().numpy()) == _bits(np.float32(sr))
+
+
+def test_relative_init_batched(fv):
+    """The flag through fv_decode_batch (uneven lengths, one launch)."""
+    K = 96
+    r = np.random.default_rng(21)
+    _, la, _ = hmm.random_dense(K, 1, 31)
+    lp = hmm.uniform_log_pi(K)
+    lbs = [(r.standard_normal((T, K)) * 40).astype(np.float32) for T in (300, 1200, 77, 900)]
+    batch = fv.Batch([_dev(x) for x in lbs])
+    fv.decode_batch(_dev(la), batch, _dev(lp), method="flash", P=8, relative_init=True)
+    torch.cuda.synchronize()
+    paths, scores = batch.paths.cpu().numpy(), batch.scores.cpu().numpy()
+    for b, x in enumerate(lbs):
+        pr, sr, rc, _ = oracle.flash(lp, la, x, 8, relative_init=True)
+        assert (paths[b, :x.shape[0]] == pr).all() and _bits(scores[b]) == _bits(sr)

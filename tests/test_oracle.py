@@ -616,3 +616,40 @@ def test_vanilla_csr_duplicates_take_the_largest_edge():
     # the same path as the dense oracle (ties broken identically)
     pd, sd, _ = oracle.vanilla(lp, la.astype(np.float32), lb)
     assert (p == pd).all() and _bits(s) == _bits(sd)
+
+
+# ---- the paper's displayed subtask initialisation (relative_init) ----------
+# In exact arithmetic the carried score is a constant over a subtask's start
+# scores and changes no arg max (Sec. V-B); integer-valued inputs keep every
+# float32 sum exact, so there the literal initialisation must return
+# vanilla's path (FLASH) and the anchored beam's result (FLASH-BS).
+
+@pytest.mark.parametrize("seed", range(6))
+def test_relative_init_exact_on_integer_inputs(seed):
+    K, T = 5 + seed, 40 + 7 * seed
+    lp, la, lb = hmm.random_dense(K, T, 500 + seed, integer=True)
+    po, so, _ = oracle.vanilla(lp, la, lb)
+    for P in (1, 3, 8):
+        p, s, rc, _ = oracle.flash(lp, la, lb, P, relative_init=True)
+        assert rc == 0 and (p == po).all() and s == so
+        for B in (2, K):
+            pa, sa, rca, _ = oracle.beam(lp, la, lb, B, P)
+            pr, sr, rcr, _ = oracle.beam(lp, la, lb, B, P, relative_init=True)
+            assert rcr == rca and (pr == pa).all() and sr == sa
+
+
+def test_relative_init_diverges_in_float32():
+    """With float scores the literal start rounds differently from the
+    anchored one, and the path follows vanilla's near ties differently in
+    some cases; the anchored start never does."""
+    diverged = 0
+    for seed in range(6):
+        lp, la, lb = hmm.random_dense(64, 2000, seed)
+        lb = (lb * 20).astype(np.float32)
+        po, so, _ = oracle.vanilla(lp, la, lb)
+        pa, _, _, _ = oracle.flash(lp, la, lb, 4)
+        pr, sr, rc, _ = oracle.flash(lp, la, lb, 4, relative_init=True)
+        assert (pa == po).all()
+        assert rc == 0 and np.isfinite(oracle.rescore(lp, la, lb, pr))
+        diverged += int((pr != po).any())
+    assert diverged >= 1
