@@ -143,6 +143,31 @@ def _time_method(fv, torch, la, lp, batch, method, P, B, steps, warmup, ws=None,
     return start.elapsed_time(stop) / steps, float(ms.value), ws, int((st != 0).sum())
 
 
+def relative_divergence(fv, torch, la, lp, batch, lengths, P):
+    """FV_FLAG_RELATIVE_INIT (the paper's displayed subtask start, carried
+    score dropped) against vanilla on the same batch: sequences and positions
+    whose decoded state differs, and the decode time."""
+    fv.decode_batch(la, batch, lp, method="vanilla")
+    torch.cuda.synchronize()
+    ref = batch.paths.cpu().numpy().copy()
+    fv.decode_batch(la, batch, lp, method="flash", P=P, relative_init=True)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    fv.decode_batch(la, batch, lp, method="flash", P=P, relative_init=True)
+    e1.record()
+    torch.cuda.synchronize()
+    got = batch.paths.cpu().numpy()
+    seqs = pos = 0
+    for b, T in enumerate(lengths):
+        d = int((got[b, :T] != ref[b, :T]).sum())
+        seqs += d > 0
+        pos += d
+    return {"method": f"flash_P{P} with FV_FLAG_RELATIVE_INIT", "ms": round(e0.elapsed_time(e1), 1),
+            "sequences_differing_from_vanilla": int(seqs), "n_seqs": len(lengths),
+            "positions_differing": int(pos), "positions": int(np.sum(lengths))}
+
+
 def large_runs(fv, torch, hmm, dev):
     """One sequence on a large dense HMM: K = 16384 (log A rows
     Dirichlet(0.05), 1 GiB), T = 10000, log B ~ N(0, 3^2).  Vanilla and FLASH
@@ -173,7 +198,15 @@ def large_runs(fv, torch, hmm, dev):
             entry["hbm_roofline"] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
                                      "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 3)}
         res[key] = entry
+        if method == "vanilla":
+            ref = path.cpu().numpy().copy()
         print(f"[bench] large {key}: {ms:.1f} ms", file=sys.stderr, flush=True)
+    path, _, status = fv.decode(la, lb, lp, "flash", P=16, relative_init=True)
+    d = int((path.cpu().numpy() != ref).sum())
+    res["flash_P16_relative_init"] = {"status": int(status.item()), "positions_differing_from_vanilla": d,
+                                      "positions": T}
+    print(f"[bench] large flash_P16 relative init: {d} of {T} positions differ from vanilla",
+          file=sys.stderr, flush=True)
     return res
 
 
@@ -351,6 +384,8 @@ def main():
                     help="skip the K=100000 map-matching (CSR) runs")
     ap.add_argument("--no-small", action="store_true",
                     help="skip the discrete-HMM and CRF-step runs")
+    ap.add_argument("--no-relative", action="store_true",
+                    help="skip the FV_FLAG_RELATIVE_INIT divergence measurement")
     ap.add_argument("--no-er", action="store_true",
                     help="skip the Erdos-Renyi sweeps (p, K, T, beam width)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -432,6 +467,11 @@ def main():
         results[key] = entry
         print(f"[bench] {name} P={P} B={B}: {ms:.2f} ms/step, engine {eng_ms:.2f} ms", file=sys.stderr, flush=True)
 
+    rel = None
+    if not args.no_relative:
+        rel = relative_divergence(fv, torch, la, lp, batch, wl.lengths, args.P)
+        print(f"[bench] relative init: {rel['sequences_differing_from_vanilla']} of {wl.n} sequences, "
+              f"{rel['positions_differing']} positions differ from vanilla", file=sys.stderr, flush=True)
     head = results[f"flash_P{args.P}"]
     ach_tflops = head["candidates"] * 2 / (head["engine_ms"] / 1e3) / 1e12
     out = {
@@ -454,6 +494,8 @@ def main():
                      "frac_of_fp32_vector_peak": round(ach_tflops / PEAK_FP32_VECTOR_TFLOPS, 4)},
         "methods": results,
     }
+    if rel is not None:
+        out["relative_init"] = rel
     if not args.no_large:
         del lbs, batch, ws
         torch.cuda.empty_cache()
