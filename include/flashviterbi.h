@@ -97,8 +97,12 @@ enum { FV_FLAG_NO_LEAVES = 1u << 3 };
  * running score, so paths can differ from vanilla's at near ties.  Every
  * subtask is then bisected down to the paper's minimum (no leaves: a leaf
  * would start once where the bisection restarts at each level, and the two
- * round differently).  Dense models only (FLASH and FLASH-BS); with a CSR
- * model the call returns FV_E_UNSUPPORTED.  Vanilla decoding ignores it. */
+ * round differently).  The score returned is the root pass's maximum for
+ * FLASH and the re-summed score of the decoded path for FLASH-BS; with this
+ * flag the two can differ in the last bits where the path leaves vanilla's.
+ * A beam of width B >= K is decoded as FLASH, so it returns FLASH's result.  Dense models only (FLASH and FLASH-BS);
+ * with a CSR model the call returns FV_E_UNSUPPORTED.  Vanilla decoding
+ * ignores it. */
 enum { FV_FLAG_RELATIVE_INIT = 1u << 4 };
 enum { FV_VANILLA = 0, FV_FLASH = 1, FV_BEAM = 2 };
 

@@ -219,3 +219,19 @@ def test_relative_init_batched(fv):
     for b, x in enumerate(lbs):
         pr, sr, rc, _ = oracle.flash(lp, la, x, 8, relative_init=True)
         assert (paths[b, :x.shape[0]] == pr).all() and _bits(scores[b]) == _bits(sr)
+
+
+def test_relative_init_full_width_beam_is_flash(fv):
+    """A beam of width >= K is decoded as FLASH; with FV_FLAG_RELATIVE_INIT
+    it returns the oracle's FLASH result (on these inputs the beam procedure
+    at full width reports another score: the re-summed score of its path,
+    where FLASH reports the root pass's maximum)."""
+    lp, la, lb = hmm.random_dense(64, 2000, 9)
+    lb = (lb * 20).astype(np.float32)
+    pf, sf, rc, _ = oracle.flash(lp, la, lb, 4, relative_init=True)
+    pb, sb, _, _ = oracle.beam(lp, la, lb, 64, 4, relative_init=True)
+    assert (pb != pf).any() or _bits(sb) != _bits(sf)
+    path, score, st = fv.decode(_dev(la), _dev(lb), _dev(lp), method="beam", P=4, B=64, relative_init=True)
+    torch.cuda.synchronize()
+    assert int(st.cpu()[0]) == rc and (path.cpu().numpy() == pf).all()
+    assert _bits(score.cpu().numpy()) == _bits(sf)
