@@ -2924,6 +2924,81 @@ extern "C" __global__ __launch_bounds__(kEngBlock) void fv_engine_kernel(const E
     }
 }
 
+// ---------------------------------------------------------------- small single decode
+// One vanilla decode of a small dense model (K <= kSmallK) by one wave, in
+// place of the persistent engine: lane j keeps destination j's column of
+// log A in registers and reads the previous step's scores from the other
+// lanes (readlane), so a step needs no barrier and no scheduling.  The
+// arithmetic and tie rules are the engine's: per destination the first
+// maximum over predecessors in index order, its own value kept, delta =
+// that + log B_t(j); the final state is the lowest index of the largest
+// score (-0 and +0 equal).  The backpointers go to the same table, and the
+// finish kernel walks them as after an engine decode.  Emission rows are
+// read kSmallPrefetch steps ahead.
+constexpr int32_t kSmallPrefetch = 4;
+
+extern "C" __global__ __launch_bounds__(64) void fv_small_vanilla_kernel(const EngineArgs* __restrict__ table) {
+    cargs_t& a = *reinterpret_cast<cargs_t*>(reinterpret_cast<uint64_t>(table));
+    const int32_t lane = threadIdx.x;
+    const int32_t K = a.K;
+    SeqInfo& sq = a.seqs[0];
+    const int32_t T = sq.T;
+    if (sq.status != FV_OK || T <= 0 || K > kSmallK) return;
+    const bool on = lane < K;
+    const float* lb = sq.log_b;
+    const int64_t ld = sq.ld;
+    float col[kSmallK];
+#pragma unroll
+    for (int i = 0; i < kSmallK; ++i) col[i] = (on && i < K) ? a.Acol[(int64_t)i * a.Kp + lane] : -INFINITY;
+    float bq[kSmallPrefetch];
+#pragma unroll
+    for (int k = 0; k < kSmallPrefetch; ++k) bq[k] = (on && 1 + k < T) ? lb[(int64_t)(1 + k) * ld + lane] : 0.0f;
+    float d = -INFINITY;
+    if (on) {
+        const float b0 = lb[lane];
+        d = a.log_pi ? a.log_pi[lane] + b0 : b0;
+    }
+    uint16_t* psi = a.psi16 + sq.psi_off;
+    for (int32_t t = 1; t < T; ++t) {
+        const float bt = bq[0];
+#pragma unroll
+        for (int k = 0; k + 1 < kSmallPrefetch; ++k) bq[k] = bq[k + 1];
+        bq[kSmallPrefetch - 1] = (on && t + kSmallPrefetch < T) ? lb[(int64_t)(t + kSmallPrefetch) * ld + lane] : 0.0f;
+        float best = -INFINITY;
+        int32_t arg = 0;
+#pragma unroll
+        for (int i = 0; i < kSmallK; ++i) {
+            if (i < K) {
+                const float di = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(d), i));
+                const float x = di + col[i];
+                if (x > best) { best = x; arg = i; }
+            }
+        }
+        if (on) psi[(int64_t)t * K + lane] = (uint16_t)arg;
+        d = on ? best + bt : -INFINITY;
+    }
+    unsigned long long key = on ? order_key(d, lane) : 0ull;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const unsigned long long o = __shfl_xor(key, off, 64);
+        if (o > key) key = o;
+    }
+    const int32_t qT = clampi((int32_t)(0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull)), K);
+    const float sc = __shfl(d, qT, 64);
+    if (sc == -INFINITY) {
+        for (int32_t t = lane; t < T; t += 64) sq.path[t] = -1;
+        if (lane == 0) {
+            *sq.score = sc;
+            sq.status = FV_E_INFEASIBLE;
+        }
+        return;
+    }
+    if (lane == 0) {
+        *sq.score = sc;
+        sq.path[T - 1] = qT;
+    }
+}
+
 // ---------------------------------------------------------------- preparation kernel
 // Ap[i][j] = log A(i, j) on a Kp x Kp grid, -inf outside K x K (only used
 // when K is not a multiple of the padding granularity).

@@ -61,6 +61,10 @@ constexpr int32_t kLeafMaxKp = 2048;   // larger K: no leaves (table too large p
 // in LDS and refine from a transposed copy of log A: up to this Kp.
 constexpr int32_t kColMaxKp = 4096;
 
+// One vanilla decode of a dense model with K <= kSmallK runs on one wave
+// instead of the persistent engine.
+constexpr int32_t kSmallK = 64;
+
 // Operations of a beam row (one block each): start step, full beam step,
 // end-only step of a subtask, final selection of a root.
 enum : int32_t { B_INIT = 0, B_STEP = 1, B_END = 2, B_FINAL = 3 };
