@@ -185,3 +185,68 @@ def test_autograd_gradients(fv):
     assert np.array_equal(p2.cpu().numpy(), p)
     fd = (s2[b].item() - scores[b].item()) / h
     assert abs(fd - 1.0) < 2 * np.spacing(np.float32(abs(scores[b].item()))) / h + 1e-3
+
+
+def test_central_finite_differences(fv):
+    """CRF-style inputs with continuous noise (a unique arg max): central
+    differences, h = 1e-3, of the Viterbi scores against the hand-written
+    backward, for emission entries on and off the decoded paths (gradient 1
+    and 0) and for transition entries (gradient = the pair's count along the
+    paths).  Every perturbed decode must keep the paths; the tolerance is the
+    float32 spacing of the scores involved over 2h, plus 1e-3."""
+    dev = torch.device("cuda", 0)
+    rng = np.random.default_rng(17)
+    K, lengths = 32, [60, 47, 33, 58]
+    n, tmax = len(lengths), max(lengths)
+    em = np.zeros((n, tmax, K), np.float32)
+    for b, T in enumerate(lengths):
+        em[b, :T] = rng.normal(size=(T, K)).astype(np.float32)
+    tr = (rng.normal(size=(K, K)) * 0.1).astype(np.float32)
+    h = np.float32(1e-3)
+
+    def decode(e, a):
+        s, p = fv.ViterbiScore.apply(torch.from_numpy(e).to(dev), lengths, torch.from_numpy(a).to(dev), None,
+                                     "flash", 4)
+        torch.cuda.synchronize()
+        return s.cpu().numpy().astype(np.float64), p.cpu().numpy()
+
+    E = torch.from_numpy(em).to(dev).requires_grad_(True)
+    A = torch.from_numpy(tr).to(dev).requires_grad_(True)
+    scores, paths = fv.ViterbiScore.apply(E, lengths, A, None, "flash", 4)
+    scores.sum().backward()
+    torch.cuda.synchronize()
+    p0 = paths.cpu().numpy()
+    gE, gA = E.grad.cpu().numpy(), A.grad.cpu().numpy()
+
+    def tol(s_plus, s_minus, seqs):
+        sp = sum(np.spacing(np.float32(max(abs(s_plus[b]), abs(s_minus[b])))) for b in seqs)
+        return 2 * float(sp) / (2 * float(h)) + 1e-3
+
+    checked = 0
+    for k in range(24):   # emissions: half on a path, half off it
+        b = int(rng.integers(n))
+        t = int(rng.integers(lengths[b]))
+        j = int(p0[b, t]) if k % 2 == 0 else int((p0[b, t] + 1 + rng.integers(K - 1)) % K)
+        ep, emn = em.copy(), em.copy()
+        ep[b, t, j] += h
+        emn[b, t, j] -= h
+        sp, pp = decode(ep, tr)
+        sm, pm = decode(emn, tr)
+        assert np.array_equal(pp, p0) and np.array_equal(pm, p0)
+        fd = (sp[b] - sm[b]) / (2 * float(h))
+        assert abs(fd - gE[b, t, j]) <= tol(sp, sm, [b]), (b, t, j, fd, gE[b, t, j])
+        checked += 1
+    used = np.argwhere(gA > 0)
+    cells = [tuple(used[i]) for i in rng.choice(len(used), size=8, replace=False)]
+    cells += [(int(rng.integers(K)), int(rng.integers(K))) for _ in range(8)]
+    for (i, j) in cells:   # transitions: counts along the paths (0 when unused)
+        ap, am = tr.copy(), tr.copy()
+        ap[i, j] += h
+        am[i, j] -= h
+        sp, pp = decode(em, ap)
+        sm, pm = decode(em, am)
+        assert np.array_equal(pp, p0) and np.array_equal(pm, p0)
+        fd = (sp.sum() - sm.sum()) / (2 * float(h))
+        assert abs(fd - gA[i, j]) <= tol(sp, sm, range(n)), (i, j, fd, gA[i, j])
+        checked += 1
+    assert checked == 40
