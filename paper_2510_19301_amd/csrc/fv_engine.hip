@@ -2926,65 +2926,94 @@ extern "C" __global__ __launch_bounds__(kEngBlock) void fv_engine_kernel(const E
 
 // ---------------------------------------------------------------- small single decode
 // One vanilla decode of a small dense model (K <= kSmallK) by one wave, in
-// place of the persistent engine: lane j keeps destination j's column of
-// log A in registers and reads the previous step's scores from the other
-// lanes (readlane), so a step needs no barrier and no scheduling.  The
-// arithmetic and tie rules are the engine's: per destination the first
-// maximum over predecessors in index order, its own value kept, delta =
-// that + log B_t(j); the final state is the lowest index of the largest
-// score (-0 and +0 equal).  The backpointers go to the same table, and the
-// finish kernel walks them as after an engine decode.  Emission rows are
-// read kSmallPrefetch steps ahead.
+// place of the persistent engine: lane l keeps the log A columns of
+// destinations l and l + 64 in registers (the wave has the whole register
+// file of its SIMD) and reads the previous step's scores from the lanes
+// that hold them (readlane), so a step needs no barrier and no scheduling.
+// The arithmetic and tie rules are the engine's: per destination the first
+// maximum over predecessors in index order, its own value kept, delta = that
+// + log B_t(j); the final state is the lowest index of the largest score (-0
+// and +0 equal).  The backpointers go to the same table, and the finish
+// kernel walks them as after an engine decode.  Emission rows are read
+// kSmallPrefetch steps ahead.
 constexpr int32_t kSmallPrefetch = 4;
 
-extern "C" __global__ __launch_bounds__(64) void fv_small_vanilla_kernel(const EngineArgs* __restrict__ table) {
-    cargs_t& a = *reinterpret_cast<cargs_t*>(reinterpret_cast<uint64_t>(table));
+template <int NJ>
+__device__ __forceinline__ void small_vanilla(cargs_t& a, SeqInfo& sq) {
     const int32_t lane = threadIdx.x;
-    const int32_t K = a.K;
-    SeqInfo& sq = a.seqs[0];
-    const int32_t T = sq.T;
-    if (sq.status != FV_OK || T <= 0 || K > kSmallK) return;
-    const bool on = lane < K;
+    const int32_t K = a.K, T = sq.T;
+    constexpr int32_t KMAX = 64 * NJ;
+    bool on[NJ];
+#pragma unroll
+    for (int c = 0; c < NJ; ++c) on[c] = lane + 64 * c < K;
     const float* lb = sq.log_b;
     const int64_t ld = sq.ld;
-    float col[kSmallK];
+    float col[NJ][KMAX];
 #pragma unroll
-    for (int i = 0; i < kSmallK; ++i) col[i] = (on && i < K) ? a.Acol[(int64_t)i * a.Kp + lane] : -INFINITY;
-    float bq[kSmallPrefetch];
+    for (int c = 0; c < NJ; ++c)
 #pragma unroll
-    for (int k = 0; k < kSmallPrefetch; ++k) bq[k] = (on && 1 + k < T) ? lb[(int64_t)(1 + k) * ld + lane] : 0.0f;
-    float d = -INFINITY;
-    if (on) {
-        const float b0 = lb[lane];
-        d = a.log_pi ? a.log_pi[lane] + b0 : b0;
+        for (int i = 0; i < KMAX; ++i)
+            col[c][i] = (on[c] && i < K) ? a.Acol[(int64_t)i * a.Kp + lane + 64 * c] : -INFINITY;
+    float bq[NJ][kSmallPrefetch];
+#pragma unroll
+    for (int c = 0; c < NJ; ++c)
+#pragma unroll
+        for (int k = 0; k < kSmallPrefetch; ++k)
+            bq[c][k] = (on[c] && 1 + k < T) ? lb[(int64_t)(1 + k) * ld + lane + 64 * c] : 0.0f;
+    float d[NJ];
+#pragma unroll
+    for (int c = 0; c < NJ; ++c) {
+        d[c] = -INFINITY;
+        if (on[c]) {
+            const int32_t j = lane + 64 * c;
+            d[c] = a.log_pi ? a.log_pi[j] + lb[j] : lb[j];
+        }
     }
     uint16_t* psi = a.psi16 + sq.psi_off;
     for (int32_t t = 1; t < T; ++t) {
-        const float bt = bq[0];
+        float best[NJ], bt[NJ];
+        int32_t arg[NJ];
 #pragma unroll
-        for (int k = 0; k + 1 < kSmallPrefetch; ++k) bq[k] = bq[k + 1];
-        bq[kSmallPrefetch - 1] = (on && t + kSmallPrefetch < T) ? lb[(int64_t)(t + kSmallPrefetch) * ld + lane] : 0.0f;
-        float best = -INFINITY;
-        int32_t arg = 0;
+        for (int c = 0; c < NJ; ++c) {
+            bt[c] = bq[c][0];
 #pragma unroll
-        for (int i = 0; i < kSmallK; ++i) {
+            for (int k = 0; k + 1 < kSmallPrefetch; ++k) bq[c][k] = bq[c][k + 1];
+            bq[c][kSmallPrefetch - 1] =
+                (on[c] && t + kSmallPrefetch < T) ? lb[(int64_t)(t + kSmallPrefetch) * ld + lane + 64 * c] : 0.0f;
+            best[c] = -INFINITY;
+            arg[c] = 0;
+        }
+#pragma unroll
+        for (int i = 0; i < KMAX; ++i) {
             if (i < K) {
-                const float di = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(d), i));
-                const float x = di + col[i];
-                if (x > best) { best = x; arg = i; }
+                const float di = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(d[i / 64]), i % 64));
+#pragma unroll
+                for (int c = 0; c < NJ; ++c) {
+                    const float x = di + col[c][i];
+                    if (x > best[c]) { best[c] = x; arg[c] = i; }
+                }
             }
         }
-        if (on) psi[(int64_t)t * K + lane] = (uint16_t)arg;
-        d = on ? best + bt : -INFINITY;
+#pragma unroll
+        for (int c = 0; c < NJ; ++c) {
+            if (on[c]) psi[(int64_t)t * K + lane + 64 * c] = (uint16_t)arg[c];
+            d[c] = on[c] ? best[c] + bt[c] : -INFINITY;
+        }
     }
-    unsigned long long key = on ? order_key(d, lane) : 0ull;
+    unsigned long long key = 0;
+#pragma unroll
+    for (int c = 0; c < NJ; ++c) {
+        const unsigned long long k = on[c] ? order_key(d[c], lane + 64 * c) : 0ull;
+        if (k > key) key = k;
+    }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
         const unsigned long long o = __shfl_xor(key, off, 64);
         if (o > key) key = o;
     }
     const int32_t qT = clampi((int32_t)(0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull)), K);
-    const float sc = __shfl(d, qT, 64);
+    float sc = __shfl(d[0], qT % 64, 64);
+    if (NJ > 1 && qT >= 64) sc = __shfl(d[NJ - 1], qT % 64, 64);
     if (sc == -INFINITY) {
         for (int32_t t = lane; t < T; t += 64) sq.path[t] = -1;
         if (lane == 0) {
@@ -2997,6 +3026,14 @@ extern "C" __global__ __launch_bounds__(64) void fv_small_vanilla_kernel(const E
         *sq.score = sc;
         sq.path[T - 1] = qT;
     }
+}
+
+extern "C" __global__ __launch_bounds__(64) void fv_small_vanilla_kernel(const EngineArgs* __restrict__ table) {
+    cargs_t& a = *reinterpret_cast<cargs_t*>(reinterpret_cast<uint64_t>(table));
+    SeqInfo& sq = a.seqs[0];
+    if (sq.status != FV_OK || sq.T <= 0 || a.K > kSmallK) return;
+    if (a.K <= 64) small_vanilla<1>(a, sq);
+    else small_vanilla<2>(a, sq);
 }
 
 // ---------------------------------------------------------------- preparation kernel

@@ -115,6 +115,47 @@ def test_signed_zero(fv):
         assert (p == po).all() and (_bits(s) == _bits(so)).all()
 
 
+@pytest.mark.parametrize("K,T", [(64, 300), (65, 1), (65, 300), (96, 257), (127, 64), (128, 700)])
+def test_single_vanilla_two_columns_per_lane(fv, K, T):
+    """Single vanilla decodes with 64 < K <= 128 (two destinations per lane
+    of the one-wave kernel): random, integer-tie, start-free and infeasible
+    inputs, bit for bit against the oracle."""
+    print(f"one-wave vanilla K={K} T={T}", flush=True)
+    lp, la, lb = hmm.random_dense(K, T, 7 * K + T)
+    p, s, st = _run(fv, lp, la, lb, "vanilla")
+    po, so, _ = oracle.vanilla(lp, la, lb)
+    assert st == fv.FV_OK and (p == po).all() and (_bits(s) == _bits(so)).all()
+    lp, la, lb = hmm.random_dense(K, T, K + 3 * T, integer=True, lo=-2, hi=0)
+    p, s, _ = _run(fv, lp, la, lb, "vanilla")
+    po, so, _ = oracle.vanilla(lp, la, lb)
+    assert (p == po).all() and (_bits(s) == _bits(so)).all()
+    p, s, _ = _run(fv, None, la, lb, "vanilla")
+    po, so, _ = oracle.vanilla(None, la, lb)
+    assert (p == po).all() and (_bits(s) == _bits(so)).all()
+    if T > 1:
+        la[:] = -np.inf
+        p, s, st = _run(fv, lp, la, lb, "vanilla")
+        assert st == fv.FV_E_INFEASIBLE and (p == -1).all() and s[0] == -np.inf
+
+
+@pytest.mark.parametrize("T", [1, 2])
+def test_single_vanilla_signed_zero_across_lanes(fv, T):
+    """Final scores -0 (state 70) and +0 (state 90) on both sides of the
+    lane-64 split, all other states lower: -0 and +0 are equal, so the lower
+    index wins and its score keeps its sign, as in the oracle."""
+    K = 100
+    lp = np.full(K, -5.0, np.float32)
+    lp[70], lp[90] = -0.0, 0.0
+    la = np.full((K, K), -np.inf, np.float32)
+    la[70, 70], la[90, 90] = -0.0, 0.0
+    lb = np.full((T, K), -1.0, np.float32)
+    lb[:, 70], lb[:, 90] = -0.0, 0.0
+    po, so, _ = oracle.vanilla(lp, la, lb)
+    assert po[-1] == 70 and _bits(so)[0] == 0x80000000
+    p, s, _ = _run(fv, lp, la, lb, "vanilla")
+    assert (p == po).all() and (_bits(s) == _bits(so)).all()
+
+
 def test_discrete_hmm_k64_t1000(fv):
     """Single discrete HMM: K=64, V=128, T=1000, Dirichlet rows, emissions
     gathered on the device."""
