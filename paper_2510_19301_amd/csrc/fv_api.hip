@@ -13,6 +13,7 @@
 namespace fv {
 extern "C" __global__ void fv_engine_kernel(const EngineArgs* __restrict__ table, int32_t n_models);
 extern "C" __global__ void fv_small_vanilla_kernel(const EngineArgs* __restrict__ table);
+extern "C" __global__ void fv_small_flash_kernel(const EngineArgs* __restrict__ table);
 extern "C" __global__ void fv_fill_i32_kernel(int32_t* __restrict__ p, int64_t n, int32_t v);
 extern "C" __global__ void fv_validate_array_kernel(const float* __restrict__ p, int64_t n, int32_t* __restrict__ flag);
 extern "C" __global__ void fv_validate_seqs_kernel(const fv_seq* __restrict__ seqs, int32_t n_seqs, int32_t model,
@@ -596,11 +597,14 @@ fv_status run_batch(int32_t method, const fv_trans* models, const float* const* 
     int32_t n_tab = (int32_t)bp.L.size();
     void* kargs[] = {&table_dev, &n_tab};
     if (g_prof_on) HIP_TRY(hipEventRecord(g_prof_ev[0], stream));
-    // one vanilla decode of a small dense model: one wave, no persistent engine
-    const bool small = bp.L.size() == 1 && bp.method[0] == FV_VANILLA && models[bp.model[0]].kind == FV_DENSE &&
-                       bp.L[0].K <= kSmallK && bp.L[0].n_seqs == 1;
+    // one vanilla or FLASH decode of a small dense model: one wave, no persistent engine
+    const bool one_dense = bp.L.size() == 1 && models[bp.model[0]].kind == FV_DENSE && bp.L[0].n_seqs == 1;
+    const bool small = one_dense && bp.method[0] == FV_VANILLA && bp.L[0].K <= kSmallK;
+    const bool small_flash = one_dense && bp.method[0] == FV_FLASH && bp.L[0].K <= kSmallFlashK;
     if (small)
         hipLaunchKernelGGL(fv_small_vanilla_kernel, dim3(1), dim3(64), 0, stream, table_dev);
+    else if (small_flash)
+        hipLaunchKernelGGL(fv_small_flash_kernel, dim3(1), dim3(64), 0, stream, table_dev);
     else
         HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(fv_engine_kernel), dim3(n_compute + 1),
                                            dim3(kEngineBlock), kargs, 0, stream));

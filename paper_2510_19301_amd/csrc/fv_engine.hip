@@ -3036,6 +3036,224 @@ extern "C" __global__ __launch_bounds__(64) void fv_small_vanilla_kernel(const E
     else small_vanilla<2>(a, sq);
 }
 
+// ---------------------------------------------------------------- small single FLASH decode
+// FLASH (Alg. 1 and 2, Sec. V-A/V-B) for one sequence of a dense model with
+// K <= kSmallFlashK, by one wave and with the persistent engine's task
+// structure, so the decode keeps the method's O(P K) state: lane j holds
+// destination j's column of log A and each step reads the previous scores
+// from the other lanes, as in the one-wave vanilla kernel.
+//   - Root pass over the whole sequence: each lane keeps MidState (the state
+//     at the most recent division point on its best path) and, at each
+//     division point e_d (d <= P'-2), stores its score and, for d >= 1, its
+//     MidState (the link to e_{d-1}) in the sequence's root copies.
+//   - The first-level segments are then taken from the last to the first,
+//     following the links back from q*_{T-1}; each segment's subtasks run
+//     depth first from a stack in LDS.  A subtask (m, n) starts from the
+//     single state q*_{m-1} with its carried score (the relative start drops
+//     the score, as the engine's does), tracks MidState from t_mid + 1 and
+//     yields q*_{t_mid}; its children are (m, t_mid) and (t_mid + 1, n).
+//   - Subtasks of at most the engine's leaf length (and kSmallLeafRows) keep
+//     their steps' backpointers in LDS and are walked back from q*_n.
+// Ties and the final arg max follow the engine's rules, so the path and the
+// score equal the engine's FLASH decode bit for bit.
+constexpr int32_t kSmallLeafRows = 128;
+constexpr int32_t kSmallStack = 64;
+
+struct SmallTask {
+    int32_t m, n, q_prev, q_n;
+    float alpha;
+};
+
+// Emission scores of the steps ahead of a pass, kSmallPrefetch rows in flight.
+struct SmallBRing {
+    float q[kSmallPrefetch];
+    __device__ __forceinline__ void start(const float* lb, int64_t ld, int32_t lane, bool on, int32_t t0, int32_t n) {
+#pragma unroll
+        for (int k = 0; k < kSmallPrefetch; ++k) q[k] = (on && t0 + k <= n) ? lb[(int64_t)(t0 + k) * ld + lane] : 0.0f;
+    }
+    __device__ __forceinline__ float next(const float* lb, int64_t ld, int32_t lane, bool on, int32_t t, int32_t n) {
+        const float v = q[0];
+#pragma unroll
+        for (int k = 0; k + 1 < kSmallPrefetch; ++k) q[k] = q[k + 1];
+        q[kSmallPrefetch - 1] = (on && t + kSmallPrefetch <= n) ? lb[(int64_t)(t + kSmallPrefetch) * ld + lane] : 0.0f;
+        return v;
+    }
+};
+
+// One step for destination lane: first maximum over predecessors i < K of
+// d_i + log A(i, lane), its own value kept; returns that + bt.
+__device__ __forceinline__ float small_step(const float (&col)[kSmallFlashK], float d, float bt, int32_t K,
+                                            int32_t& arg) {
+    float best = -INFINITY;
+    int32_t a = 0;
+#pragma unroll
+    for (int i = 0; i < kSmallFlashK; ++i) {
+        if (i < K) {
+            const float x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(d), i)) + col[i];
+            if (x > best) { best = x; a = i; }
+        }
+    }
+    arg = a;
+    return best + bt;
+}
+
+extern "C" __global__ __launch_bounds__(64) void fv_small_flash_kernel(const EngineArgs* __restrict__ table) {
+    cargs_t& a = *reinterpret_cast<cargs_t*>(reinterpret_cast<uint64_t>(table));
+    SeqInfo& sq = a.seqs[0];
+    const int32_t K = a.K, T = sq.T, pp = sq.pp;
+    if (sq.status != FV_OK || T <= 0 || K > kSmallFlashK || pp < 1 || pp > T) return;
+    __shared__ uint16_t leaf_tab[kSmallLeafRows * kSmallFlashK];
+    __shared__ SmallTask stack[kSmallStack];
+    const int32_t lane = threadIdx.x;
+    const bool on = lane < K;
+    const float* lb = sq.log_b;
+    const int64_t ld = sq.ld;
+    int32_t* path = sq.path;
+    const int32_t leaf_max = a.leaf_len < kSmallLeafRows ? a.leaf_len : kSmallLeafRows;
+    float col[kSmallFlashK];
+#pragma unroll
+    for (int i = 0; i < kSmallFlashK; ++i) col[i] = (on && i < K) ? a.Acol[(int64_t)i * a.Kp + lane] : -INFINITY;
+    const float d0 = on ? (a.log_pi ? a.log_pi[lane] + lb[lane] : lb[lane]) : -INFINITY;
+    float* const dsnap = a.root_copy + sq.root_off * (int64_t)a.Kp;                     // [pp-1][Kp]
+    int32_t* const link = reinterpret_cast<int32_t*>(dsnap + (int64_t)(pp - 1) * a.Kp);  // [pp-1][Kp]
+
+    // ---- root pass
+    float d = d0;
+    int32_t mid = 0;
+    int32_t d_next = 0;
+    const int64_t e0 = pp > 1 ? seg_end(T, pp, 0) : (int64_t)T;
+    if (pp > 1 && e0 == 0) {
+        if (on) dsnap[lane] = d;
+        d_next = 1;
+    }
+    int64_t e_prev = d_next >= 1 ? 0 : -1;
+    int64_t e_next = d_next < pp - 1 ? seg_end(T, pp, d_next) : -1;
+    {
+        SmallBRing ring;
+        ring.start(lb, ld, lane, on, 1, T - 1);
+        for (int32_t t = 1; t < T; ++t) {
+            const float bt = ring.next(lb, ld, lane, on, t, T - 1);
+            int32_t pre;
+            const float dn = small_step(col, d, bt, K, pre);
+            if (d_next >= 1 && e_prev == t - 1) mid = pre;
+            else if (pp > 1 && t > e0 + 1) mid = __shfl(mid, pre, 64);
+            d = on ? dn : -INFINITY;
+            if (e_next == t) {
+                if (on) {
+                    dsnap[(int64_t)d_next * a.Kp + lane] = d;
+                    if (d_next >= 1) link[(int64_t)d_next * a.Kp + lane] = mid;
+                }
+                e_prev = t;
+                ++d_next;
+                e_next = d_next < pp - 1 ? seg_end(T, pp, d_next) : -1;
+            }
+        }
+    }
+    unsigned long long key = on ? order_key(d, lane) : 0ull;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const unsigned long long o = __shfl_xor(key, off, 64);
+        if (o > key) key = o;
+    }
+    const int32_t qT = clampi((int32_t)(0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull)), K);
+    const float sc = __shfl(d, qT, 64);
+    if (sc == -INFINITY) {
+        for (int32_t t = lane; t < T; t += 64) path[t] = -1;
+        if (lane == 0) {
+            *sq.score = sc;
+            sq.status = FV_E_INFEASIBLE;
+        }
+        return;
+    }
+    if (lane == 0) {
+        *sq.score = sc;
+        path[T - 1] = qT;
+    }
+    const int32_t q_last_div = __shfl(mid, qT, 64);   // q* at e_{P'-2}
+    __syncthreads();   // the division copies are read back across lanes below
+
+    // ---- first-level segments, last to first, each with its subtasks
+    int32_t qe = qT;
+    for (int32_t ds = pp - 1; ds >= 0; --ds) {
+        const int32_t n0 = (int32_t)seg_end(T, pp, ds);
+        const int32_t m0 = ds == 0 ? 0 : (int32_t)seg_end(T, pp, ds - 1) + 1;
+        int32_t qp = 0;
+        float alpha = 0.0f;
+        if (ds >= 1) {
+            qp = ds == pp - 1 ? q_last_div : link[(int64_t)ds * a.Kp + qe];
+            qp = clampi(qp, K);
+            alpha = dsnap[(int64_t)(ds - 1) * a.Kp + qp];
+            if (lane == 0) path[m0 - 1] = qp;
+        }
+        if (n0 - m0 >= 1) {
+            if (lane == 0) stack[0] = SmallTask{m0, n0, qp, qe, alpha};
+            int32_t sp = 1;
+            __syncthreads();
+            while (sp > 0) {
+                const SmallTask tk = stack[--sp];
+                const int32_t m = tk.m, n = tk.n;
+                float x = d0;
+                if (m > 0) {
+                    const float arow = on ? a.Acol[(int64_t)tk.q_prev * a.Kp + lane] : -INFINITY;
+                    const float c = a.relative_init ? arow : tk.alpha + arow;
+                    x = on ? c + lb[(int64_t)m * ld + lane] : -INFINITY;
+                }
+                SmallBRing ring;
+                ring.start(lb, ld, lane, on, m + 1, n);
+                if (n - m + 1 <= leaf_max) {
+                    for (int32_t t = m + 1; t <= n; ++t) {
+                        const float bt = ring.next(lb, ld, lane, on, t, n);
+                        int32_t pre;
+                        const float xn = small_step(col, x, bt, K, pre);
+                        x = on ? xn : -INFINITY;
+                        leaf_tab[(t - m - 1) * kSmallFlashK + lane] = (uint16_t)pre;
+                    }
+                    __syncthreads();
+                    if (lane == 0) {
+                        int32_t q = tk.q_n;
+                        for (int32_t t = n; t > m; --t) {
+                            q = leaf_tab[(t - m - 1) * kSmallFlashK + q];
+                            path[t - 1] = q;
+                        }
+                    }
+                    __syncthreads();
+                    continue;
+                }
+                const int32_t tmid = (m + n) / 2;
+                float snap = x;
+                int32_t md = 0;
+                for (int32_t t = m + 1; t <= n; ++t) {
+                    const float bt = ring.next(lb, ld, lane, on, t, n);
+                    int32_t pre;
+                    const float xn = small_step(col, x, bt, K, pre);
+                    if (t == tmid + 1) md = pre;
+                    else if (t > tmid + 1) md = __shfl(md, pre, 64);
+                    x = on ? xn : -INFINITY;
+                    if (t == tmid) snap = x;
+                }
+                const int32_t qmid = clampi(__shfl(md, tk.q_n, 64), K);
+                const float amid = __shfl(snap, qmid, 64);
+                if (n - m >= 2 && sp + 2 > kSmallStack) {   // deeper than any sequence of 2^31 steps needs
+                    if (lane == 0) sq.status = FV_E_DEVICE;
+                    return;
+                }
+                if (lane == 0) {
+                    path[tmid] = qmid;
+                    if (n - m > 2) {
+                        stack[sp] = SmallTask{m, tmid, tk.q_prev, qmid, tk.alpha};
+                        stack[sp + 1] = SmallTask{tmid + 1, n, qmid, tk.q_n, amid};
+                    } else if (n - m == 2) {
+                        stack[sp] = SmallTask{m, tmid, tk.q_prev, qmid, tk.alpha};
+                    }
+                }
+                sp += n - m > 2 ? 2 : (n - m == 2 ? 1 : 0);
+                __syncthreads();
+            }
+        }
+        qe = qp;
+    }
+}
+
 // ---------------------------------------------------------------- preparation kernel
 // Ap[i][j] = log A(i, j) on a Kp x Kp grid, -inf outside K x K (only used
 // when K is not a multiple of the padding granularity).

@@ -64,6 +64,8 @@ constexpr int32_t kColMaxKp = 4096;
 // One vanilla decode of a dense model with K <= kSmallK runs on one wave
 // instead of the persistent engine.
 constexpr int32_t kSmallK = 128;
+// One FLASH decode of a dense model with K <= kSmallFlashK runs on one wave too.
+constexpr int32_t kSmallFlashK = 64;
 
 // Operations of a beam row (one block each): start step, full beam step,
 // end-only step of a subtask, final selection of a root.

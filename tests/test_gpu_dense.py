@@ -156,6 +156,51 @@ def test_single_vanilla_signed_zero_across_lanes(fv, T):
     assert (p == po).all() and (_bits(s) == _bits(so)).all()
 
 
+@pytest.mark.parametrize("K,T", [(1, 5), (7, 1), (7, 2), (7, 3), (33, 129), (64, 700), (64, 3000)])
+def test_single_flash_one_wave(fv, K, T):
+    """Single FLASH decodes with K <= 64 (the one-wave FLASH kernel): every
+    P' from 2 to T (and beyond), with and without leaf subtasks, bit for bit
+    against the oracle's vanilla result and the oracle's FLASH."""
+    lp, la, lb = hmm.random_dense(K, T, 5 * K + T)
+    po, so, _ = oracle.vanilla(lp, la, lb)
+    for P in (1, 2, 5, 16, 64, 5000):
+        pf, sf, rc, _ = oracle.flash(lp, la, lb, P)
+        assert rc == 0 and (pf == po).all() and _bits(sf) == _bits(so)
+        for leaves in (True, False):
+            print(f"one-wave flash K={K} T={T} P={P} leaves={leaves}", flush=True)
+            path, score, st = fv.decode(_dev(la), _dev(lb), _dev(lp), method="flash", P=P, leaves=leaves)
+            torch.cuda.synchronize()
+            assert int(st.cpu()[0]) == fv.FV_OK
+            assert (path.cpu().numpy() == po).all(), (P, leaves)
+            assert (_bits(score.cpu().numpy()) == _bits(so)).all()
+
+
+def test_single_flash_one_wave_ties_and_edges(fv):
+    """Integer ties, no start vector, -0 against +0 and an infeasible model
+    through the one-wave FLASH kernel."""
+    K, T = 50, 300
+    lp, la, lb = hmm.random_dense(K, T, 12, integer=True, lo=-2, hi=0)
+    for P in (3, 16):
+        po, so, _ = oracle.vanilla(lp, la, lb)
+        p, s, _ = _run(fv, lp, la, lb, "flash", P=P)
+        assert (p == po).all() and (_bits(s) == _bits(so)).all()
+        po, so, _ = oracle.vanilla(None, la, lb)
+        p, s, _ = _run(fv, None, la, lb, "flash", P=P)
+        assert (p == po).all() and (_bits(s) == _bits(so)).all()
+    lp = np.full(K, -5.0, np.float32)
+    lp[20], lp[40] = -0.0, 0.0
+    zla = np.full((K, K), -np.inf, np.float32)
+    zla[20, 20], zla[40, 40] = -0.0, 0.0
+    zlb = np.full((9, K), -1.0, np.float32)
+    zlb[:, 20], zlb[:, 40] = -0.0, 0.0
+    po, so, _ = oracle.vanilla(lp, zla, zlb)
+    p, s, _ = _run(fv, lp, zla, zlb, "flash", P=4)
+    assert po[-1] == 20 and (p == po).all() and (_bits(s) == _bits(so)).all()
+    la[:] = -np.inf
+    p, s, st = _run(fv, lp, la, lb, "flash", P=4)
+    assert st == fv.FV_E_INFEASIBLE and (p == -1).all() and s[0] == -np.inf
+
+
 def test_discrete_hmm_k64_t1000(fv):
     """Single discrete HMM: K=64, V=128, T=1000, Dirichlet rows, emissions
     gathered on the device."""
