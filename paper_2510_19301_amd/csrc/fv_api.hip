@@ -12,8 +12,12 @@
 
 namespace fv {
 extern "C" __global__ void fv_engine_kernel(const EngineArgs* __restrict__ table, int32_t n_models);
-extern "C" __global__ void fv_small_vanilla_kernel(const EngineArgs* __restrict__ table);
-extern "C" __global__ void fv_small_flash_kernel(const EngineArgs* __restrict__ table);
+extern "C" __global__ void fv_small_vanilla32_kernel(const EngineArgs* __restrict__ table);
+extern "C" __global__ void fv_small_vanilla64_kernel(const EngineArgs* __restrict__ table);
+extern "C" __global__ void fv_small_vanilla128_kernel(const EngineArgs* __restrict__ table);
+extern "C" __global__ void fv_small_flash32_kernel(const EngineArgs* __restrict__ table);
+extern "C" __global__ void fv_small_flash64_kernel(const EngineArgs* __restrict__ table);
+extern "C" __global__ void fv_small_flash128_kernel(const EngineArgs* __restrict__ table);
 extern "C" __global__ void fv_fill_i32_kernel(int32_t* __restrict__ p, int64_t n, int32_t v);
 extern "C" __global__ void fv_validate_array_kernel(const float* __restrict__ p, int64_t n, int32_t* __restrict__ flag);
 extern "C" __global__ void fv_validate_seqs_kernel(const fv_seq* __restrict__ seqs, int32_t n_seqs, int32_t model,
@@ -601,10 +605,15 @@ fv_status run_batch(int32_t method, const fv_trans* models, const float* const* 
     const bool one_dense = bp.L.size() == 1 && models[bp.model[0]].kind == FV_DENSE && bp.L[0].n_seqs == 1;
     const bool small = one_dense && bp.method[0] == FV_VANILLA && bp.L[0].K <= kSmallK;
     const bool small_flash = one_dense && bp.method[0] == FV_FLASH && bp.L[0].K <= kSmallFlashK;
+    const int32_t Ks = bp.L[0].K;
     if (small)
-        hipLaunchKernelGGL(fv_small_vanilla_kernel, dim3(1), dim3(64), 0, stream, table_dev);
+        hipLaunchKernelGGL(Ks <= 32 ? fv_small_vanilla32_kernel : (Ks <= 64 ? fv_small_vanilla64_kernel
+                                                                              : fv_small_vanilla128_kernel),
+                           dim3(1), dim3(64), 0, stream, table_dev);
     else if (small_flash)
-        hipLaunchKernelGGL(fv_small_flash_kernel, dim3(1), dim3(64), 0, stream, table_dev);
+        hipLaunchKernelGGL(Ks <= 32 ? fv_small_flash32_kernel : (Ks <= 64 ? fv_small_flash64_kernel
+                                                                            : fv_small_flash128_kernel),
+                           dim3(1), dim3(64), 0, stream, table_dev);
     else
         HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(fv_engine_kernel), dim3(n_compute + 1),
                                            dim3(kEngineBlock), kargs, 0, stream));

@@ -2938,11 +2938,51 @@ extern "C" __global__ __launch_bounds__(kEngBlock) void fv_engine_kernel(const E
 // kSmallPrefetch steps ahead.
 constexpr int32_t kSmallPrefetch = 4;
 
-template <int NJ>
+// The candidate loop of both one-wave kernels, over a compile-time width
+// KMAX >= K: states K..KMAX-1 have score -inf and log A -inf, so their
+// candidates are -inf and never win the strict comparison; no per-candidate
+// test of K is needed.  Even and odd predecessors are two independent
+// chains (first maximum each), merged so that the larger value wins and
+// equal values (-0 == +0) go to the lower index: the same result as one
+// scan in index order.
+template <int KMAX, int NJ>
+__device__ __forceinline__ void small_candidates(const float (&col)[NJ][KMAX], const float (&d)[NJ],
+                                                 float (&best)[NJ], int32_t (&arg)[NJ]) {
+    float b1[NJ];
+    int32_t a1[NJ];
+#pragma unroll
+    for (int c = 0; c < NJ; ++c) {
+        best[c] = -INFINITY;
+        arg[c] = 0;
+        b1[c] = -INFINITY;
+        a1[c] = 0;
+    }
+#pragma unroll
+    for (int i = 0; i < KMAX; i += 2) {
+        const float d0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(d[i / 64]), i % 64));
+        const float d1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(d[(i + 1) / 64]), (i + 1) % 64));
+#pragma unroll
+        for (int c = 0; c < NJ; ++c) {
+            const float x0 = d0 + col[c][i];
+            const float x1 = d1 + col[c][i + 1];
+            if (x0 > best[c]) { best[c] = x0; arg[c] = i; }
+            if (x1 > b1[c]) { b1[c] = x1; a1[c] = i + 1; }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < NJ; ++c) {
+        if (b1[c] > best[c] || (b1[c] == best[c] && a1[c] < arg[c])) {
+            best[c] = b1[c];
+            arg[c] = a1[c];
+        }
+    }
+}
+
+template <int KMAX>
 __device__ __forceinline__ void small_vanilla(cargs_t& a, SeqInfo& sq) {
+    constexpr int NJ = KMAX > 64 ? 2 : 1;
     const int32_t lane = threadIdx.x;
     const int32_t K = a.K, T = sq.T;
-    constexpr int32_t KMAX = 64 * NJ;
     bool on[NJ];
 #pragma unroll
     for (int c = 0; c < NJ; ++c) on[c] = lane + 64 * c < K;
@@ -2971,8 +3011,7 @@ __device__ __forceinline__ void small_vanilla(cargs_t& a, SeqInfo& sq) {
     }
     uint16_t* psi = a.psi16 + sq.psi_off;
     for (int32_t t = 1; t < T; ++t) {
-        float best[NJ], bt[NJ];
-        int32_t arg[NJ];
+        float bt[NJ];
 #pragma unroll
         for (int c = 0; c < NJ; ++c) {
             bt[c] = bq[c][0];
@@ -2980,20 +3019,10 @@ __device__ __forceinline__ void small_vanilla(cargs_t& a, SeqInfo& sq) {
             for (int k = 0; k + 1 < kSmallPrefetch; ++k) bq[c][k] = bq[c][k + 1];
             bq[c][kSmallPrefetch - 1] =
                 (on[c] && t + kSmallPrefetch < T) ? lb[(int64_t)(t + kSmallPrefetch) * ld + lane + 64 * c] : 0.0f;
-            best[c] = -INFINITY;
-            arg[c] = 0;
         }
-#pragma unroll
-        for (int i = 0; i < KMAX; ++i) {
-            if (i < K) {
-                const float di = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(d[i / 64]), i % 64));
-#pragma unroll
-                for (int c = 0; c < NJ; ++c) {
-                    const float x = di + col[c][i];
-                    if (x > best[c]) { best[c] = x; arg[c] = i; }
-                }
-            }
-        }
+        float best[NJ];
+        int32_t arg[NJ];
+        small_candidates<KMAX, NJ>(col, d, best, arg);
 #pragma unroll
         for (int c = 0; c < NJ; ++c) {
             if (on[c]) psi[(int64_t)t * K + lane + 64 * c] = (uint16_t)arg[c];
@@ -3028,21 +3057,28 @@ __device__ __forceinline__ void small_vanilla(cargs_t& a, SeqInfo& sq) {
     }
 }
 
-extern "C" __global__ __launch_bounds__(64) void fv_small_vanilla_kernel(const EngineArgs* __restrict__ table) {
-    cargs_t& a = *reinterpret_cast<cargs_t*>(reinterpret_cast<uint64_t>(table));
-    SeqInfo& sq = a.seqs[0];
-    if (sq.status != FV_OK || sq.T <= 0 || a.K > kSmallK) return;
-    if (a.K <= 64) small_vanilla<1>(a, sq);
-    else small_vanilla<2>(a, sq);
-}
+// One kernel per width (K <= 32, 64, 128), so each gets the register
+// allocation of its own step loop.
+#define FV_SMALL_VANILLA(NAME, KMAX)                                                                   \
+    extern "C" __global__ __launch_bounds__(64) void NAME(const EngineArgs* __restrict__ table) {       \
+        cargs_t& a = *reinterpret_cast<cargs_t*>(reinterpret_cast<uint64_t>(table));                    \
+        SeqInfo& sq = a.seqs[0];                                                                        \
+        if (sq.status != FV_OK || sq.T <= 0 || a.K > KMAX) return;                                      \
+        small_vanilla<KMAX>(a, sq);                                                                     \
+    }
+FV_SMALL_VANILLA(fv_small_vanilla32_kernel, 32)
+FV_SMALL_VANILLA(fv_small_vanilla64_kernel, 64)
+FV_SMALL_VANILLA(fv_small_vanilla128_kernel, 128)
+#undef FV_SMALL_VANILLA
 
 // ---------------------------------------------------------------- small single FLASH decode
 // FLASH (Alg. 1 and 2, Sec. V-A/V-B) for one sequence of a dense model with
-// K <= kSmallFlashK, by one wave and with the persistent engine's task
-// structure, so the decode keeps the method's O(P K) state: lane j holds
-// destination j's column of log A and each step reads the previous scores
-// from the other lanes, as in the one-wave vanilla kernel.
-//   - Root pass over the whole sequence: each lane keeps MidState (the state
+// K <= kSmallFlashK (128), by one wave and with the persistent engine's task
+// structure, so the decode keeps the method's O(P K) state.  State s lives
+// in lane s % 64 (NJ = 2: s / 64 picks the lane's first or second column),
+// which holds s's column of log A; each step reads the previous scores from
+// the other lanes, as in the one-wave vanilla kernel.
+//   - Root pass over the whole sequence: each state keeps MidState (the state
 //     at the most recent division point on its best path) and, at each
 //     division point e_d (d <= P'-2), stores its score and, for d >= 1, its
 //     MidState (the link to e_{d-1}) in the sequence's root copies.
@@ -3064,99 +3100,138 @@ struct SmallTask {
     float alpha;
 };
 
-// Emission scores of the steps ahead of a pass, kSmallPrefetch rows in flight.
-struct SmallBRing {
-    float q[kSmallPrefetch];
-    __device__ __forceinline__ void start(const float* lb, int64_t ld, int32_t lane, bool on, int32_t t0, int32_t n) {
+// Per-lane state of the one-wave FLASH kernel: NJ destinations per lane.
+template <int KMAX_>
+struct SmallWave {
+    static constexpr int32_t KMAX = KMAX_;
+    static constexpr int NJ = KMAX > 64 ? 2 : 1;
+    int32_t lane, K;
+    bool on[NJ];
+    float col[NJ][KMAX];
+    float bq[NJ][kSmallPrefetch];
+    const float* lb;
+    int64_t ld;
+
+    // emission scores of steps t0.. of a pass ending at n, kSmallPrefetch rows in flight
+    __device__ __forceinline__ void ring_start(int32_t t0, int32_t n) {
 #pragma unroll
-        for (int k = 0; k < kSmallPrefetch; ++k) q[k] = (on && t0 + k <= n) ? lb[(int64_t)(t0 + k) * ld + lane] : 0.0f;
+        for (int c = 0; c < NJ; ++c)
+#pragma unroll
+            for (int k = 0; k < kSmallPrefetch; ++k)
+                bq[c][k] = (on[c] && t0 + k <= n) ? lb[(int64_t)(t0 + k) * ld + lane + 64 * c] : 0.0f;
     }
-    __device__ __forceinline__ float next(const float* lb, int64_t ld, int32_t lane, bool on, int32_t t, int32_t n) {
-        const float v = q[0];
+    // one step at t of a pass ending at n: first maximum over predecessors
+    // of d_i + log A(i, j), its own value kept, + log B_t(j)
+    __device__ __forceinline__ void step(float (&d)[NJ], int32_t (&arg)[NJ], int32_t t, int32_t n) {
+        float bt[NJ], best[NJ];
 #pragma unroll
-        for (int k = 0; k + 1 < kSmallPrefetch; ++k) q[k] = q[k + 1];
-        q[kSmallPrefetch - 1] = (on && t + kSmallPrefetch <= n) ? lb[(int64_t)(t + kSmallPrefetch) * ld + lane] : 0.0f;
-        return v;
+        for (int c = 0; c < NJ; ++c) {
+            bt[c] = bq[c][0];
+#pragma unroll
+            for (int k = 0; k + 1 < kSmallPrefetch; ++k) bq[c][k] = bq[c][k + 1];
+            bq[c][kSmallPrefetch - 1] =
+                (on[c] && t + kSmallPrefetch <= n) ? lb[(int64_t)(t + kSmallPrefetch) * ld + lane + 64 * c] : 0.0f;
+        }
+        small_candidates<KMAX, NJ>(col, d, best, arg);
+#pragma unroll
+        for (int c = 0; c < NJ; ++c) d[c] = on[c] ? best[c] + bt[c] : -INFINITY;
     }
 };
 
-// One step for destination lane: first maximum over predecessors i < K of
-// d_i + log A(i, lane), its own value kept; returns that + bt.
-__device__ __forceinline__ float small_step(const float (&col)[kSmallFlashK], float d, float bt, int32_t K,
-                                            int32_t& arg) {
-    float best = -INFINITY;
-    int32_t a = 0;
-#pragma unroll
-    for (int i = 0; i < kSmallFlashK; ++i) {
-        if (i < K) {
-            const float x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(d), i)) + col[i];
-            if (x > best) { best = x; a = i; }
-        }
+// v of state s (s < 64 * NJ), for every lane's own s
+template <int NJ, typename V>
+__device__ __forceinline__ V small_at(const V (&v)[NJ], int32_t s) {
+    V r = __shfl(v[0], s & 63, 64);
+    if (NJ > 1) {
+        const V hi = __shfl(v[NJ - 1], s & 63, 64);
+        if (s >= 64) r = hi;
     }
-    arg = a;
-    return best + bt;
+    return r;
 }
 
-extern "C" __global__ __launch_bounds__(64) void fv_small_flash_kernel(const EngineArgs* __restrict__ table) {
-    cargs_t& a = *reinterpret_cast<cargs_t*>(reinterpret_cast<uint64_t>(table));
-    SeqInfo& sq = a.seqs[0];
+template <int KMAX>
+__device__ __forceinline__ void small_flash(cargs_t& a, SeqInfo& sq, uint16_t* leaf_tab, SmallTask* stack) {
     const int32_t K = a.K, T = sq.T, pp = sq.pp;
-    if (sq.status != FV_OK || T <= 0 || K > kSmallFlashK || pp < 1 || pp > T) return;
-    __shared__ uint16_t leaf_tab[kSmallLeafRows * kSmallFlashK];
-    __shared__ SmallTask stack[kSmallStack];
-    const int32_t lane = threadIdx.x;
-    const bool on = lane < K;
-    const float* lb = sq.log_b;
-    const int64_t ld = sq.ld;
+    constexpr int NJ = SmallWave<KMAX>::NJ;
+    SmallWave<KMAX> w;
+    w.lane = threadIdx.x;
+    w.K = K;
+    w.lb = sq.log_b;
+    w.ld = sq.ld;
+    const int32_t lane = w.lane;
+#pragma unroll
+    for (int c = 0; c < NJ; ++c) w.on[c] = lane + 64 * c < K;
+#pragma unroll
+    for (int c = 0; c < NJ; ++c)
+#pragma unroll
+        for (int i = 0; i < KMAX; ++i)
+            w.col[c][i] = (w.on[c] && i < K) ? a.Acol[(int64_t)i * a.Kp + lane + 64 * c] : -INFINITY;
     int32_t* path = sq.path;
     const int32_t leaf_max = a.leaf_len < kSmallLeafRows ? a.leaf_len : kSmallLeafRows;
-    float col[kSmallFlashK];
+    float d0[NJ];
 #pragma unroll
-    for (int i = 0; i < kSmallFlashK; ++i) col[i] = (on && i < K) ? a.Acol[(int64_t)i * a.Kp + lane] : -INFINITY;
-    const float d0 = on ? (a.log_pi ? a.log_pi[lane] + lb[lane] : lb[lane]) : -INFINITY;
+    for (int c = 0; c < NJ; ++c) {
+        const int32_t j = lane + 64 * c;
+        d0[c] = w.on[c] ? (a.log_pi ? a.log_pi[j] + w.lb[j] : w.lb[j]) : -INFINITY;
+    }
     float* const dsnap = a.root_copy + sq.root_off * (int64_t)a.Kp;                     // [pp-1][Kp]
     int32_t* const link = reinterpret_cast<int32_t*>(dsnap + (int64_t)(pp - 1) * a.Kp);  // [pp-1][Kp]
 
     // ---- root pass
-    float d = d0;
-    int32_t mid = 0;
+    float d[NJ];
+    int32_t mid[NJ];
+#pragma unroll
+    for (int c = 0; c < NJ; ++c) { d[c] = d0[c]; mid[c] = 0; }
     int32_t d_next = 0;
     const int64_t e0 = pp > 1 ? seg_end(T, pp, 0) : (int64_t)T;
     if (pp > 1 && e0 == 0) {
-        if (on) dsnap[lane] = d;
+#pragma unroll
+        for (int c = 0; c < NJ; ++c)
+            if (w.on[c]) dsnap[lane + 64 * c] = d[c];
         d_next = 1;
     }
     int64_t e_prev = d_next >= 1 ? 0 : -1;
     int64_t e_next = d_next < pp - 1 ? seg_end(T, pp, d_next) : -1;
-    {
-        SmallBRing ring;
-        ring.start(lb, ld, lane, on, 1, T - 1);
-        for (int32_t t = 1; t < T; ++t) {
-            const float bt = ring.next(lb, ld, lane, on, t, T - 1);
-            int32_t pre;
-            const float dn = small_step(col, d, bt, K, pre);
-            if (d_next >= 1 && e_prev == t - 1) mid = pre;
-            else if (pp > 1 && t > e0 + 1) mid = __shfl(mid, pre, 64);
-            d = on ? dn : -INFINITY;
-            if (e_next == t) {
-                if (on) {
-                    dsnap[(int64_t)d_next * a.Kp + lane] = d;
-                    if (d_next >= 1) link[(int64_t)d_next * a.Kp + lane] = mid;
+    w.ring_start(1, T - 1);
+    for (int32_t t = 1; t < T; ++t) {
+        int32_t pre[NJ];
+        w.step(d, pre, t, T - 1);
+        if (d_next >= 1 && e_prev == t - 1) {
+#pragma unroll
+            for (int c = 0; c < NJ; ++c) mid[c] = pre[c];
+        } else if (pp > 1 && t > e0 + 1) {
+            int32_t nm[NJ];
+#pragma unroll
+            for (int c = 0; c < NJ; ++c) nm[c] = small_at<NJ>(mid, pre[c]);
+#pragma unroll
+            for (int c = 0; c < NJ; ++c) mid[c] = nm[c];
+        }
+        if (e_next == t) {
+#pragma unroll
+            for (int c = 0; c < NJ; ++c) {
+                if (w.on[c]) {
+                    dsnap[(int64_t)d_next * a.Kp + lane + 64 * c] = d[c];
+                    if (d_next >= 1) link[(int64_t)d_next * a.Kp + lane + 64 * c] = mid[c];
                 }
-                e_prev = t;
-                ++d_next;
-                e_next = d_next < pp - 1 ? seg_end(T, pp, d_next) : -1;
             }
+            e_prev = t;
+            ++d_next;
+            e_next = d_next < pp - 1 ? seg_end(T, pp, d_next) : -1;
         }
     }
-    unsigned long long key = on ? order_key(d, lane) : 0ull;
+    unsigned long long key = 0;
+#pragma unroll
+    for (int c = 0; c < NJ; ++c) {
+        const unsigned long long k = w.on[c] ? order_key(d[c], lane + 64 * c) : 0ull;
+        if (k > key) key = k;
+    }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
         const unsigned long long o = __shfl_xor(key, off, 64);
         if (o > key) key = o;
     }
     const int32_t qT = clampi((int32_t)(0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull)), K);
-    const float sc = __shfl(d, qT, 64);
+    const float sc = small_at<NJ>(d, qT);
     if (sc == -INFINITY) {
         for (int32_t t = lane; t < T; t += 64) path[t] = -1;
         if (lane == 0) {
@@ -3169,7 +3244,7 @@ extern "C" __global__ __launch_bounds__(64) void fv_small_flash_kernel(const Eng
         *sq.score = sc;
         path[T - 1] = qT;
     }
-    const int32_t q_last_div = __shfl(mid, qT, 64);   // q* at e_{P'-2}
+    const int32_t q_last_div = small_at<NJ>(mid, qT);   // q* at e_{P'-2}
     __syncthreads();   // the division copies are read back across lanes below
 
     // ---- first-level segments, last to first, each with its subtasks
@@ -3192,27 +3267,31 @@ extern "C" __global__ __launch_bounds__(64) void fv_small_flash_kernel(const Eng
             while (sp > 0) {
                 const SmallTask tk = stack[--sp];
                 const int32_t m = tk.m, n = tk.n;
-                float x = d0;
-                if (m > 0) {
-                    const float arow = on ? a.Acol[(int64_t)tk.q_prev * a.Kp + lane] : -INFINITY;
-                    const float c = a.relative_init ? arow : tk.alpha + arow;
-                    x = on ? c + lb[(int64_t)m * ld + lane] : -INFINITY;
+                float x[NJ];
+#pragma unroll
+                for (int c = 0; c < NJ; ++c) {
+                    x[c] = d0[c];
+                    if (m > 0) {
+                        const int32_t j = lane + 64 * c;
+                        const float arow = w.on[c] ? a.Acol[(int64_t)tk.q_prev * a.Kp + j] : -INFINITY;
+                        const float cc = a.relative_init ? arow : tk.alpha + arow;
+                        x[c] = w.on[c] ? cc + w.lb[(int64_t)m * w.ld + j] : -INFINITY;
+                    }
                 }
-                SmallBRing ring;
-                ring.start(lb, ld, lane, on, m + 1, n);
+                w.ring_start(m + 1, n);
                 if (n - m + 1 <= leaf_max) {
                     for (int32_t t = m + 1; t <= n; ++t) {
-                        const float bt = ring.next(lb, ld, lane, on, t, n);
-                        int32_t pre;
-                        const float xn = small_step(col, x, bt, K, pre);
-                        x = on ? xn : -INFINITY;
-                        leaf_tab[(t - m - 1) * kSmallFlashK + lane] = (uint16_t)pre;
+                        int32_t pre[NJ];
+                        w.step(x, pre, t, n);
+#pragma unroll
+                        for (int c = 0; c < NJ; ++c)
+                            if (w.on[c]) leaf_tab[(t - m - 1) * KMAX + lane + 64 * c] = (uint16_t)pre[c];
                     }
                     __syncthreads();
                     if (lane == 0) {
                         int32_t q = tk.q_n;
                         for (int32_t t = n; t > m; --t) {
-                            q = leaf_tab[(t - m - 1) * kSmallFlashK + q];
+                            q = leaf_tab[(t - m - 1) * KMAX + q];
                             path[t - 1] = q;
                         }
                     }
@@ -3220,19 +3299,30 @@ extern "C" __global__ __launch_bounds__(64) void fv_small_flash_kernel(const Eng
                     continue;
                 }
                 const int32_t tmid = (m + n) / 2;
-                float snap = x;
-                int32_t md = 0;
+                float snap[NJ];
+                int32_t md[NJ];
+#pragma unroll
+                for (int c = 0; c < NJ; ++c) { snap[c] = x[c]; md[c] = 0; }
                 for (int32_t t = m + 1; t <= n; ++t) {
-                    const float bt = ring.next(lb, ld, lane, on, t, n);
-                    int32_t pre;
-                    const float xn = small_step(col, x, bt, K, pre);
-                    if (t == tmid + 1) md = pre;
-                    else if (t > tmid + 1) md = __shfl(md, pre, 64);
-                    x = on ? xn : -INFINITY;
-                    if (t == tmid) snap = x;
+                    int32_t pre[NJ];
+                    w.step(x, pre, t, n);
+                    if (t == tmid + 1) {
+#pragma unroll
+                        for (int c = 0; c < NJ; ++c) md[c] = pre[c];
+                    } else if (t > tmid + 1) {
+                        int32_t nm[NJ];
+#pragma unroll
+                        for (int c = 0; c < NJ; ++c) nm[c] = small_at<NJ>(md, pre[c]);
+#pragma unroll
+                        for (int c = 0; c < NJ; ++c) md[c] = nm[c];
+                    }
+                    if (t == tmid) {
+#pragma unroll
+                        for (int c = 0; c < NJ; ++c) snap[c] = x[c];
+                    }
                 }
-                const int32_t qmid = clampi(__shfl(md, tk.q_n, 64), K);
-                const float amid = __shfl(snap, qmid, 64);
+                const int32_t qmid = clampi(small_at<NJ>(md, tk.q_n), K);
+                const float amid = small_at<NJ>(snap, qmid);
                 if (n - m >= 2 && sp + 2 > kSmallStack) {   // deeper than any sequence of 2^31 steps needs
                     if (lane == 0) sq.status = FV_E_DEVICE;
                     return;
@@ -3253,6 +3343,22 @@ extern "C" __global__ __launch_bounds__(64) void fv_small_flash_kernel(const Eng
         qe = qp;
     }
 }
+
+// One kernel per width (K <= 32, 64, 128), so each gets the register
+// allocation of its own step loop.
+#define FV_SMALL_FLASH(NAME, KMAX)                                                                     \
+    extern "C" __global__ __launch_bounds__(64) void NAME(const EngineArgs* __restrict__ table) {       \
+        cargs_t& a = *reinterpret_cast<cargs_t*>(reinterpret_cast<uint64_t>(table));                    \
+        SeqInfo& sq = a.seqs[0];                                                                        \
+        if (sq.status != FV_OK || sq.T <= 0 || a.K > KMAX || sq.pp < 1 || sq.pp > sq.T) return;         \
+        __shared__ uint16_t leaf_tab[kSmallLeafRows * KMAX];                                            \
+        __shared__ SmallTask stack[kSmallStack];                                                        \
+        small_flash<KMAX>(a, sq, leaf_tab, stack);                                                      \
+    }
+FV_SMALL_FLASH(fv_small_flash32_kernel, 32)
+FV_SMALL_FLASH(fv_small_flash64_kernel, 64)
+FV_SMALL_FLASH(fv_small_flash128_kernel, 128)
+#undef FV_SMALL_FLASH
 
 // ---------------------------------------------------------------- preparation kernel
 // Ap[i][j] = log A(i, j) on a Kp x Kp grid, -inf outside K x K (only used

@@ -65,7 +65,7 @@ constexpr int32_t kColMaxKp = 4096;
 // instead of the persistent engine.
 constexpr int32_t kSmallK = 128;
 // One FLASH decode of a dense model with K <= kSmallFlashK runs on one wave too.
-constexpr int32_t kSmallFlashK = 64;
+constexpr int32_t kSmallFlashK = 128;
 
 // Operations of a beam row (one block each): start step, full beam step,
 // end-only step of a subtask, final selection of a root.

@@ -156,9 +156,10 @@ def test_single_vanilla_signed_zero_across_lanes(fv, T):
     assert (p == po).all() and (_bits(s) == _bits(so)).all()
 
 
-@pytest.mark.parametrize("K,T", [(1, 5), (7, 1), (7, 2), (7, 3), (33, 129), (64, 700), (64, 3000)])
+@pytest.mark.parametrize("K,T", [(1, 5), (7, 1), (7, 2), (7, 3), (33, 129), (64, 700), (64, 3000), (65, 2),
+                                 (65, 300), (100, 129), (128, 1000)])
 def test_single_flash_one_wave(fv, K, T):
-    """Single FLASH decodes with K <= 64 (the one-wave FLASH kernel): every
+    """Single FLASH decodes with K <= 128 (the one-wave FLASH kernel): every
     P' from 2 to T (and beyond), with and without leaf subtasks, bit for bit
     against the oracle's vanilla result and the oracle's FLASH."""
     lp, la, lb = hmm.random_dense(K, T, 5 * K + T)
@@ -175,10 +176,11 @@ def test_single_flash_one_wave(fv, K, T):
             assert (_bits(score.cpu().numpy()) == _bits(so)).all()
 
 
-def test_single_flash_one_wave_ties_and_edges(fv):
+@pytest.mark.parametrize("K", [50, 120])
+def test_single_flash_one_wave_ties_and_edges(fv, K):
     """Integer ties, no start vector, -0 against +0 and an infeasible model
-    through the one-wave FLASH kernel."""
-    K, T = 50, 300
+    through the one-wave FLASH kernel (one and two destinations per lane)."""
+    T = 300
     lp, la, lb = hmm.random_dense(K, T, 12, integer=True, lo=-2, hi=0)
     for P in (3, 16):
         po, so, _ = oracle.vanilla(lp, la, lb)
@@ -199,6 +201,21 @@ def test_single_flash_one_wave_ties_and_edges(fv):
     la[:] = -np.inf
     p, s, st = _run(fv, lp, la, lb, "flash", P=4)
     assert st == fv.FV_E_INFEASIBLE and (p == -1).all() and s[0] == -np.inf
+
+
+@pytest.mark.parametrize("K,seed", [(40, 40), (100, 1), (128, 3)])
+def test_single_flash_one_wave_relative_init(fv, K, seed):
+    """The relative subtask start through the one-wave FLASH kernel equals
+    the oracle's same procedure bit for bit (for K = 100 and 128 these seeds
+    give paths that differ from vanilla's)."""
+    lp, la, lb = hmm.random_dense(K, 2000, seed)
+    lb = (lb * 20).astype(np.float32)
+    for P in (2, 16):
+        pr, sr, rc, _ = oracle.flash(lp, la, lb, P, relative_init=True)
+        path, score, st = fv.decode(_dev(la), _dev(lb), _dev(lp), method="flash", P=P, relative_init=True)
+        torch.cuda.synchronize()
+        assert int(st.cpu()[0]) == rc == 0
+        assert (path.cpu().numpy() == pr).all() and (_bits(score.cpu().numpy()) == _bits(sr)).all()
 
 
 def test_discrete_hmm_k64_t1000(fv):
