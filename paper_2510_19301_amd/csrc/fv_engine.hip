@@ -2945,9 +2945,13 @@ constexpr int32_t kSmallPrefetch = 4;
 // chains (first maximum each), merged so that the larger value wins and
 // equal values (-0 == +0) go to the lower index: the same result as one
 // scan in index order.
-template <int KMAX, int NJ>
+// LDS_SCORES: the scores are published in LDS (dsh, KMAX floats) and read
+// back four at a time, every lane reading the same address, instead of one
+// readlane per predecessor (measured faster for the 128-wide FLASH kernel,
+// slower for the 128-wide vanilla one).
+template <int KMAX, int NJ, bool LDS_SCORES>
 __device__ __forceinline__ void small_candidates(const float (&col)[NJ][KMAX], const float (&d)[NJ],
-                                                 float (&best)[NJ], int32_t (&arg)[NJ]) {
+                                                 float (&best)[NJ], int32_t (&arg)[NJ], float* dsh) {
     float b1[NJ];
     int32_t a1[NJ];
 #pragma unroll
@@ -2957,16 +2961,38 @@ __device__ __forceinline__ void small_candidates(const float (&col)[NJ][KMAX], c
         b1[c] = -INFINITY;
         a1[c] = 0;
     }
+    if constexpr (LDS_SCORES) {
 #pragma unroll
-    for (int i = 0; i < KMAX; i += 2) {
-        const float d0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(d[i / 64]), i % 64));
-        const float d1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(d[(i + 1) / 64]), (i + 1) % 64));
+        for (int c = 0; c < NJ; ++c) dsh[threadIdx.x + 64 * c] = d[c];
+        __syncthreads();
 #pragma unroll
-        for (int c = 0; c < NJ; ++c) {
-            const float x0 = d0 + col[c][i];
-            const float x1 = d1 + col[c][i + 1];
-            if (x0 > best[c]) { best[c] = x0; arg[c] = i; }
-            if (x1 > b1[c]) { b1[c] = x1; a1[c] = i + 1; }
+        for (int i = 0; i < KMAX; i += 4) {
+            const float4 v = *reinterpret_cast<const float4*>(dsh + i);
+#pragma unroll
+            for (int c = 0; c < NJ; ++c) {
+                const float x0 = v.x + col[c][i];
+                const float x1 = v.y + col[c][i + 1];
+                const float x2 = v.z + col[c][i + 2];
+                const float x3 = v.w + col[c][i + 3];
+                if (x0 > best[c]) { best[c] = x0; arg[c] = i; }
+                if (x1 > b1[c]) { b1[c] = x1; a1[c] = i + 1; }
+                if (x2 > best[c]) { best[c] = x2; arg[c] = i + 2; }
+                if (x3 > b1[c]) { b1[c] = x3; a1[c] = i + 3; }
+            }
+        }
+        __syncthreads();   // the next step overwrites dsh
+    } else {
+#pragma unroll
+        for (int i = 0; i < KMAX; i += 2) {
+            const float d0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(d[i / 64]), i % 64));
+            const float d1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(d[(i + 1) / 64]), (i + 1) % 64));
+#pragma unroll
+            for (int c = 0; c < NJ; ++c) {
+                const float x0 = d0 + col[c][i];
+                const float x1 = d1 + col[c][i + 1];
+                if (x0 > best[c]) { best[c] = x0; arg[c] = i; }
+                if (x1 > b1[c]) { b1[c] = x1; a1[c] = i + 1; }
+            }
         }
     }
 #pragma unroll
@@ -3022,7 +3048,7 @@ __device__ __forceinline__ void small_vanilla(cargs_t& a, SeqInfo& sq) {
         }
         float best[NJ];
         int32_t arg[NJ];
-        small_candidates<KMAX, NJ>(col, d, best, arg);
+        small_candidates<KMAX, NJ, false>(col, d, best, arg, nullptr);
 #pragma unroll
         for (int c = 0; c < NJ; ++c) {
             if (on[c]) psi[(int64_t)t * K + lane + 64 * c] = (uint16_t)arg[c];
@@ -3111,6 +3137,7 @@ struct SmallWave {
     float bq[NJ][kSmallPrefetch];
     const float* lb;
     int64_t ld;
+    float* dsh;   // KMAX floats of LDS for the published scores (two destinations per lane)
 
     // emission scores of steps t0.. of a pass ending at n, kSmallPrefetch rows in flight
     __device__ __forceinline__ void ring_start(int32_t t0, int32_t n) {
@@ -3132,7 +3159,7 @@ struct SmallWave {
             bq[c][kSmallPrefetch - 1] =
                 (on[c] && t + kSmallPrefetch <= n) ? lb[(int64_t)(t + kSmallPrefetch) * ld + lane + 64 * c] : 0.0f;
         }
-        small_candidates<KMAX, NJ>(col, d, best, arg);
+        small_candidates<KMAX, NJ, (NJ > 1)>(col, d, best, arg, dsh);
 #pragma unroll
         for (int c = 0; c < NJ; ++c) d[c] = on[c] ? best[c] + bt[c] : -INFINITY;
     }
@@ -3150,7 +3177,8 @@ __device__ __forceinline__ V small_at(const V (&v)[NJ], int32_t s) {
 }
 
 template <int KMAX>
-__device__ __forceinline__ void small_flash(cargs_t& a, SeqInfo& sq, uint16_t* leaf_tab, SmallTask* stack) {
+__device__ __forceinline__ void small_flash(cargs_t& a, SeqInfo& sq, uint16_t* leaf_tab, SmallTask* stack,
+                                            float* dsh) {
     const int32_t K = a.K, T = sq.T, pp = sq.pp;
     constexpr int NJ = SmallWave<KMAX>::NJ;
     SmallWave<KMAX> w;
@@ -3158,6 +3186,7 @@ __device__ __forceinline__ void small_flash(cargs_t& a, SeqInfo& sq, uint16_t* l
     w.K = K;
     w.lb = sq.log_b;
     w.ld = sq.ld;
+    w.dsh = dsh;
     const int32_t lane = w.lane;
 #pragma unroll
     for (int c = 0; c < NJ; ++c) w.on[c] = lane + 64 * c < K;
@@ -3353,7 +3382,8 @@ __device__ __forceinline__ void small_flash(cargs_t& a, SeqInfo& sq, uint16_t* l
         if (sq.status != FV_OK || sq.T <= 0 || a.K > KMAX || sq.pp < 1 || sq.pp > sq.T) return;         \
         __shared__ uint16_t leaf_tab[kSmallLeafRows * KMAX];                                            \
         __shared__ SmallTask stack[kSmallStack];                                                        \
-        small_flash<KMAX>(a, sq, leaf_tab, stack);                                                      \
+        __shared__ __align__(16) float dsh[KMAX];                                                       \
+        small_flash<KMAX>(a, sq, leaf_tab, stack, dsh);                                                 \
     }
 FV_SMALL_FLASH(fv_small_flash32_kernel, 32)
 FV_SMALL_FLASH(fv_small_flash64_kernel, 64)
