@@ -601,19 +601,19 @@ fv_status run_batch(int32_t method, const fv_trans* models, const float* const* 
     int32_t n_tab = (int32_t)bp.L.size();
     void* kargs[] = {&table_dev, &n_tab};
     if (g_prof_on) HIP_TRY(hipEventRecord(g_prof_ev[0], stream));
-    // one vanilla or FLASH decode of a small dense model: one wave, no persistent engine
-    const bool one_dense = bp.L.size() == 1 && models[bp.model[0]].kind == FV_DENSE && bp.L[0].n_seqs == 1;
+    // vanilla or FLASH decodes of one small dense model: one wave per sequence, no persistent engine
+    const bool one_dense = bp.L.size() == 1 && models[bp.model[0]].kind == FV_DENSE;
     const bool small = one_dense && bp.method[0] == FV_VANILLA && bp.L[0].K <= kSmallK;
     const bool small_flash = one_dense && bp.method[0] == FV_FLASH && bp.L[0].K <= kSmallFlashK;
     const int32_t Ks = bp.L[0].K;
     if (small)
         hipLaunchKernelGGL(Ks <= 32 ? fv_small_vanilla32_kernel : (Ks <= 64 ? fv_small_vanilla64_kernel
                                                                               : fv_small_vanilla128_kernel),
-                           dim3(1), dim3(64), 0, stream, table_dev);
+                           dim3(std::max(1, bp.L[0].n_seqs)), dim3(64), 0, stream, table_dev);
     else if (small_flash)
         hipLaunchKernelGGL(Ks <= 32 ? fv_small_flash32_kernel : (Ks <= 64 ? fv_small_flash64_kernel
                                                                             : fv_small_flash128_kernel),
-                           dim3(1), dim3(64), 0, stream, table_dev);
+                           dim3(std::max(1, bp.L[0].n_seqs)), dim3(64), 0, stream, table_dev);
     else
         HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(fv_engine_kernel), dim3(n_compute + 1),
                                            dim3(kEngineBlock), kargs, 0, stream));

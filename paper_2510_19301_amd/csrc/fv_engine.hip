@@ -2925,8 +2925,8 @@ extern "C" __global__ __launch_bounds__(kEngBlock) void fv_engine_kernel(const E
 }
 
 // ---------------------------------------------------------------- small single decode
-// One vanilla decode of a small dense model (K <= kSmallK) by one wave, in
-// place of the persistent engine: lane l keeps the log A columns of
+// Vanilla decodes of a small dense model (K <= kSmallK), one wave (block) per
+// sequence, in place of the persistent engine: lane l keeps the log A columns of
 // destinations l and l + 64 in registers (the wave has the whole register
 // file of its SIMD) and reads the previous step's scores from the lanes
 // that hold them (readlane), so a step needs no barrier and no scheduling.
@@ -3088,7 +3088,8 @@ __device__ __forceinline__ void small_vanilla(cargs_t& a, SeqInfo& sq) {
 #define FV_SMALL_VANILLA(NAME, KMAX)                                                                   \
     extern "C" __global__ __launch_bounds__(64) void NAME(const EngineArgs* __restrict__ table) {       \
         cargs_t& a = *reinterpret_cast<cargs_t*>(reinterpret_cast<uint64_t>(table));                    \
-        SeqInfo& sq = a.seqs[0];                                                                        \
+        if ((int32_t)blockIdx.x >= a.n_seqs) return;                                                    \
+        SeqInfo& sq = a.seqs[blockIdx.x];                                                               \
         if (sq.status != FV_OK || sq.T <= 0 || a.K > KMAX) return;                                      \
         small_vanilla<KMAX>(a, sq);                                                                     \
     }
@@ -3098,8 +3099,8 @@ FV_SMALL_VANILLA(fv_small_vanilla128_kernel, 128)
 #undef FV_SMALL_VANILLA
 
 // ---------------------------------------------------------------- small single FLASH decode
-// FLASH (Alg. 1 and 2, Sec. V-A/V-B) for one sequence of a dense model with
-// K <= kSmallFlashK (128), by one wave and with the persistent engine's task
+// FLASH (Alg. 1 and 2, Sec. V-A/V-B) for sequences of a dense model with
+// K <= kSmallFlashK (128), one wave (block) per sequence, with the persistent engine's task
 // structure, so the decode keeps the method's O(P K) state.  State s lives
 // in lane s % 64 (NJ = 2: s / 64 picks the lane's first or second column),
 // which holds s's column of log A; each step reads the previous scores from
@@ -3378,7 +3379,8 @@ __device__ __forceinline__ void small_flash(cargs_t& a, SeqInfo& sq, uint16_t* l
 #define FV_SMALL_FLASH(NAME, KMAX)                                                                     \
     extern "C" __global__ __launch_bounds__(64) void NAME(const EngineArgs* __restrict__ table) {       \
         cargs_t& a = *reinterpret_cast<cargs_t*>(reinterpret_cast<uint64_t>(table));                    \
-        SeqInfo& sq = a.seqs[0];                                                                        \
+        if ((int32_t)blockIdx.x >= a.n_seqs) return;                                                    \
+        SeqInfo& sq = a.seqs[blockIdx.x];                                                               \
         if (sq.status != FV_OK || sq.T <= 0 || a.K > KMAX || sq.pp < 1 || sq.pp > sq.T) return;         \
         __shared__ uint16_t leaf_tab[kSmallLeafRows * KMAX];                                            \
         __shared__ SmallTask stack[kSmallStack];                                                        \

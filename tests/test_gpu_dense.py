@@ -218,6 +218,39 @@ def test_single_flash_one_wave_relative_init(fv, K, seed):
         assert (path.cpu().numpy() == pr).all() and (_bits(score.cpu().numpy()) == _bits(sr)).all()
 
 
+@pytest.mark.parametrize("K", [20, 64, 100])
+def test_batch_small_models_one_wave_per_sequence(fv, K):
+    """Batches of one small dense model (one wave per sequence): ragged
+    lengths with empty sequences, vanilla and FLASH (several P, leaves on and
+    off, the relative start), each sequence bit for bit against the oracle."""
+    r = np.random.default_rng(K)
+    lengths = [int(x) for x in r.integers(0, 400, size=150)]
+    lengths[:4] = [0, 1, 2, 399]
+    _, la, _ = hmm.random_dense(K, 1, 300 + K)
+    lp = hmm.uniform_log_pi(K)
+    lbs = [(r.standard_normal((T, K)) * 2).astype(np.float32) for T in lengths]
+    ref = [oracle.vanilla(lp, la, x) if x.shape[0] else None for x in lbs]
+    runs = [("vanilla", 1, True, False), ("flash", 1, True, False), ("flash", 4, False, False),
+            ("flash", 64, True, False), ("flash", 16, True, True)]
+    for method, P, leaves, rel in runs:
+        print(f"batch K={K} {method} P={P} leaves={leaves} relative={rel}", flush=True)
+        batch = fv.Batch([_dev(x) if x.shape[0] else torch.empty((0, K), device="cuda") for x in lbs])
+        fv.decode_batch(_dev(la), batch, _dev(lp), method=method, P=P, leaves=leaves, relative_init=rel)
+        torch.cuda.synchronize()
+        paths, scores, status = batch.paths.cpu().numpy(), batch.scores.cpu().numpy(), batch.status.cpu().numpy()
+        for b, T in enumerate(lengths):
+            assert status[b] == 0, (method, P, b)
+            if T == 0:
+                assert scores[b] == 0.0
+                continue
+            if rel:
+                po, so, _, _ = oracle.flash(lp, la, lbs[b], P, relative_init=True)
+            else:
+                po, so, _ = ref[b]
+            assert (paths[b, :T] == po).all(), (method, P, b)
+            assert _bits(scores[b]) == _bits(so), (method, P, b)
+
+
 def test_discrete_hmm_k64_t1000(fv):
     """Single discrete HMM: K=64, V=128, T=1000, Dirichlet rows, emissions
     gathered on the device."""
