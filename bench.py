@@ -291,7 +291,8 @@ def er_runs(fv, torch, hmm, dev):
 
 def small_runs(fv, torch, hmm, dev):
     """Latency-bound decodes: one discrete HMM (K = 64, V = 128, T = 1000;
-    microseconds per step of the single sequence) and the CRF training step
+    microseconds per step of the single sequence), a batch of 256 sequences
+    on the same model, and the CRF training step
     (512 sequences, K = 256, T ~ U[32, 512]: ViterbiScore forward + the
     hand-written backward)."""
     res = {}
@@ -317,6 +318,28 @@ def small_runs(fv, torch, hmm, dev):
         entry[f"{method}_P{P}" if method == "flash" else method] = {"ms": round(ms, 3),
                                                                      "us_per_step": round(ms * 1e3 / h.T, 2)}
     res["discrete"] = entry
+    # a batch of discrete HMM sequences sharing the model: one wave per sequence
+    n_b, T_b = 256, 1000
+    obs_b = torch.from_numpy(np.stack([hmm.sample_observations(h, T_b, seed=1000 + i) for i in range(n_b)])).to(dev)
+    lbs = [torch.empty((T_b, h.K), dtype=torch.float32, device=dev) for _ in range(n_b)]
+    for i in range(n_b):
+        fv._lib.check(lib.fv_gather_emissions(h.K, h.V, log_e.data_ptr(), obs_b[i].data_ptr(), T_b,
+                                              lbs[i].data_ptr(), h.K, stream), "fv_gather_emissions")
+    entry = {"workload": f"discrete HMM batch: {n_b} sequences of T={T_b} sharing the K=64, V=128 model "
+                         f"(observations sampled from it, one seed per sequence), decode only"}
+    for method, P in (("vanilla", 1), ("flash", 16)):
+        batch = fv.Batch(lbs)
+        for rep in range(2):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fv.decode_batch(la, batch, lp, method=method, P=P)
+            e1.record()
+            torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        bad = int((batch.status != 0).sum().item())
+        entry[f"{method}_P{P}" if method == "flash" else method] = {
+            "ms": round(ms, 3), "state_steps_per_s": n_b * T_b * h.K / (ms / 1e3), "bad_status": bad}
+    res["discrete_batch"] = entry
     wl = hmm.crf_batch()
     em = torch.from_numpy(wl.emissions).to(dev).requires_grad_(True)
     tr = torch.from_numpy(wl.transitions).to(dev).requires_grad_(True)

@@ -36,3 +36,13 @@ def test_er_hmm_sparse_rows_get_a_self_loop():
     idx = np.flatnonzero(lone)
     # a row with a single edge is either a drawn edge or the added self-loop
     assert fin.any(axis=1).all() and (fin[idx, idx] | (fin[idx].sum(axis=1) == 1)).all()
+
+
+def test_sample_observations_deterministic_and_in_range():
+    h = hmm.discrete_hmm(K=16, V=20, T=50, seed=3)
+    a = hmm.sample_observations(h, 300, seed=7)
+    b = hmm.sample_observations(h, 300, seed=7)
+    c = hmm.sample_observations(h, 300, seed=8)
+    assert a.dtype == np.int32 and a.shape == (300,)
+    assert (a == b).all() and not (a == c).all()
+    assert a.min() >= 0 and a.max() < h.V

@@ -87,6 +87,20 @@ def discrete_hmm(K: int = 64, V: int = 128, T: int = 1000, alpha_a: float = 1.0,
     return DiscreteHMM(K, V, T, uniform_log_pi(K), log_a, log_e, obs, states)
 
 
+def sample_observations(h: DiscreteHMM, T: int, seed: int) -> np.ndarray:
+    """Another observation sequence of length T from the model of h (uniform
+    start state, then the same sampling as discrete_hmm), int32 [T]."""
+    rs = _rng(seed, 3)
+    pa = np.exp(h.log_a.astype(np.float64))
+    pe = np.exp(h.log_e.astype(np.float64))
+    obs = np.empty(T, np.int32)
+    q = int(rs.integers(0, h.K))
+    for t in range(T):
+        obs[t] = _categorical(rs, pe[q])
+        q = _categorical(rs, pa[q])
+    return obs
+
+
 def er_hmm(K: int = 512, T: int = 512, p: float = 0.253, M: int = 50, seed: int = 1) -> DiscreteHMM:
     """Discrete HMM on an Erdos-Renyi transition graph, the shape of the
     paper's synthetic experiments (Sec. VII): edge i -> j present with
