@@ -176,7 +176,9 @@ fv_status fv_decode_beam(const fv_trans* A, const float* log_pi, const float* lo
                          float* score, int32_t* status, uint32_t flags, void* ws,
                          size_t ws_bytes, fv_stream_t stream);
 
-/* Many sequences, uneven lengths, one persistent launch.  models: host
+/* Many sequences, uneven lengths, one decode launch: the persistent engine,
+ * or, for vanilla and FLASH decodes of one dense model with K <= 128, one
+ * wave per sequence running the same method (same results).  models: host
  * array [n_models] (dense and CSR models may be mixed, K may differ);
  * log_pi: host array of n_models device pointers (entries may be NULL);
  * seqs_dev: device array [n_seqs]; T_host / model_host: host copies of each
@@ -223,8 +225,9 @@ fv_status fv_gather_emissions(int32_t K, int32_t V, const float* log_e, const in
 
 /* Measurement hook: while enabled (enable != 0, host thread-local), every
  * decode records a pair of HIP events on its stream immediately before and
- * after its persistent engine kernel.  fv_profile_engine_ms waits for the
- * last pair and returns the engine kernel's duration in milliseconds.
+ * after its decode kernel (the persistent engine, or the one-wave kernels
+ * of small dense models).  fv_profile_engine_ms waits for the last pair
+ * and returns that kernel's duration in milliseconds.
  * Enable outside stream capture (it creates the events). */
 fv_status fv_profile_engine(int32_t enable);
 fv_status fv_profile_engine_ms(float* ms);
