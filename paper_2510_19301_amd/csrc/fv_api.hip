@@ -601,19 +601,28 @@ fv_status run_batch(int32_t method, const fv_trans* models, const float* const* 
     int32_t n_tab = (int32_t)bp.L.size();
     void* kargs[] = {&table_dev, &n_tab};
     if (g_prof_on) HIP_TRY(hipEventRecord(g_prof_ev[0], stream));
-    // vanilla or FLASH decodes of one small dense model: one wave per sequence, no persistent engine
-    const bool one_dense = bp.L.size() == 1 && models[bp.model[0]].kind == FV_DENSE;
-    const bool small = one_dense && bp.method[0] == FV_VANILLA && bp.L[0].K <= kSmallK;
-    const bool small_flash = one_dense && bp.method[0] == FV_FLASH && bp.L[0].K <= kSmallFlashK;
-    const int32_t Ks = bp.L[0].K;
-    if (small)
-        hipLaunchKernelGGL(Ks <= 32 ? fv_small_vanilla32_kernel : (Ks <= 64 ? fv_small_vanilla64_kernel
-                                                                              : fv_small_vanilla128_kernel),
-                           dim3(std::max(1, bp.L[0].n_seqs)), dim3(64), 0, stream, table_dev);
-    else if (small_flash)
-        hipLaunchKernelGGL(Ks <= 32 ? fv_small_flash32_kernel : (Ks <= 64 ? fv_small_flash64_kernel
-                                                                            : fv_small_flash128_kernel),
-                           dim3(std::max(1, bp.L[0].n_seqs)), dim3(64), 0, stream, table_dev);
+    // vanilla or FLASH decodes whose models are all small and dense: one wave per sequence, one
+    // launch per model, no persistent engine
+    bool small = true;
+    for (size_t p = 0; p < bp.L.size(); ++p) {
+        const int32_t Kp_ = bp.L[p].K;
+        small = small && models[bp.model[p]].kind == FV_DENSE &&
+                ((bp.method[p] == FV_VANILLA && Kp_ <= kSmallK) || (bp.method[p] == FV_FLASH && Kp_ <= kSmallFlashK));
+    }
+    if (small) {
+        for (size_t p = 0; p < bp.L.size(); ++p) {
+            const int32_t Ks = bp.L[p].K;
+            const dim3 grid(std::max(1, bp.L[p].n_seqs));
+            if (bp.method[p] == FV_VANILLA)
+                hipLaunchKernelGGL(Ks <= 32 ? fv_small_vanilla32_kernel
+                                            : (Ks <= 64 ? fv_small_vanilla64_kernel : fv_small_vanilla128_kernel),
+                                   grid, dim3(64), 0, stream, table_dev + p);
+            else
+                hipLaunchKernelGGL(Ks <= 32 ? fv_small_flash32_kernel
+                                            : (Ks <= 64 ? fv_small_flash64_kernel : fv_small_flash128_kernel),
+                                   grid, dim3(64), 0, stream, table_dev + p);
+        }
+    }
     else
         HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(fv_engine_kernel), dim3(n_compute + 1),
                                            dim3(kEngineBlock), kargs, 0, stream));

@@ -121,3 +121,34 @@ def test_device_model_index_out_of_range_is_reported(fv):
     assert rc == 0
     torch.cuda.synchronize()
     assert (batch.status.cpu().numpy() == fv.FV_E_INVALID_ARG).all()
+
+
+@pytest.mark.parametrize("method,P", [("vanilla", 1), ("flash", 1), ("flash", 8), ("beam", 4)])
+def test_multimodel_small_dense(fv, method, P):
+    """Dense models of K = 20, 64 and 100 only (vanilla and FLASH run one
+    wave per sequence, one launch per model; beam with B >= K is FLASH):
+    every sequence equals the oracle for its own model."""
+    models = []
+    for k, K in enumerate((20, 64, 100)):
+        lp, la, _ = hmm.random_dense(K, 1, 70 + k)
+        models.append(("dense", K, lp if k != 2 else None, la, _dev(la)))
+    rng = np.random.default_rng(71)
+    seq_models = [0, 1, 2, 2, 1, 0, 0, 2, 1, 1]
+    lens = [40, 300, 1, 0, 77, 129, 2, 250, 64, 5]
+    lbs = [(rng.standard_normal((T, models[m][1])) * 2).astype(np.float32) for m, T in zip(seq_models, lens)]
+    batch = fv.Batch([_dev(x) if len(x) else torch.empty((0, models[m][1]), device="cuda")
+                      for x, m in zip(lbs, seq_models)], models=seq_models)
+    B = 128 if method == "beam" else 0
+    print(f"multi-model small {method} P={P} B={B}", flush=True)
+    fv.decode_batch([m[4] for m in models], batch, [_dev(m[2]) for m in models], method=method, P=P, B=B)
+    torch.cuda.synchronize()
+    paths, scores, status = batch.paths.cpu().numpy(), batch.scores.cpu().numpy(), batch.status.cpu().numpy()
+    for b, (m, T) in enumerate(zip(seq_models, lens)):
+        if T == 0:
+            assert status[b] == fv.FV_OK and scores[b] == 0.0
+            continue
+        kind, K, lp, A, _ = models[m]
+        po, so, rc = _expected(kind, lp, A, lbs[b], method, P, B)
+        assert status[b] == rc, (b, status[b], rc)
+        assert (paths[b, :T] == po).all(), (b, np.flatnonzero(paths[b, :T] != po)[:10])
+        assert _bits(scores[b]) == _bits(so), (b, scores[b], so)
