@@ -636,8 +636,11 @@ fv_status run_batch(int32_t method, const fv_trans* models, const float* const* 
             hipLaunchKernelGGL(fv_beam_finish_kernel, dim3((n_local + kWaves - 1) / kWaves), dim3(kBlock), 0, stream,
                                args[p], aps[p], status);
         else
+        {
+            args[p].path_done = small ? 1 : 0;   // the one-wave vanilla kernel walks its own table
             hipLaunchKernelGGL(fv_finish_kernel, dim3((n_local + kBlock - 1) / kBlock), dim3(kBlock), 0, stream,
                                args[p], status);
+        }
     }
     HIP_TRY(hipGetLastError());
     return FV_OK;

@@ -2933,8 +2933,8 @@ extern "C" __global__ __launch_bounds__(kEngBlock) void fv_engine_kernel(const E
 // The arithmetic and tie rules are the engine's: per destination the first
 // maximum over predecessors in index order, its own value kept, delta = that
 // + log B_t(j); the final state is the lowest index of the largest score (-0
-// and +0 equal).  The backpointers go to the same table, and the finish
-// kernel walks them as after an engine decode.  Emission rows are read
+// and +0 equal).  The backpointers go to the same table as an engine
+// decode's, and one lane walks them back at the end.  Emission rows are read
 // kSmallPrefetch steps ahead.
 constexpr int32_t kSmallPrefetch = 4;
 
@@ -3080,6 +3080,16 @@ __device__ __forceinline__ void small_vanilla(cargs_t& a, SeqInfo& sq) {
     if (lane == 0) {
         *sq.score = sc;
         sq.path[T - 1] = qT;
+    }
+    // backtrace from q*_{T-1} by one lane, while the table rows this wave
+    // wrote are still in its XCD's L2 (the finish kernel skips the walk)
+    __syncthreads();
+    if (lane == 0) {
+        int32_t q = qT;
+        for (int32_t t = T - 1; t > 0; --t) {
+            q = clampi(psi[(int64_t)t * K + q], K);
+            sq.path[t - 1] = q;
+        }
     }
 }
 
@@ -3541,7 +3551,7 @@ extern "C" __global__ __launch_bounds__(kBlock) void fv_finish_kernel(EngineArgs
     }
     if (a.bad_model && stv != FV_E_DEVICE && sq.T > 0 && sq.orig >= 0 && (*a.bad_model || a.bad_seq[sq.orig]))
         stv = FV_E_INVALID_ARG;
-    if (stv == FV_OK && a.method == FV_VANILLA && sq.T > 1) {
+    if (stv == FV_OK && a.method == FV_VANILLA && sq.T > 1 && !a.path_done) {
         int32_t q = sq.path[sq.T - 1];
         const uint16_t* tab = a.psi16 + sq.psi_off;
         for (int32_t t = sq.T - 1; t > 0; --t) {

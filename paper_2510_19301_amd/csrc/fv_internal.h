@@ -161,6 +161,7 @@ struct EngineArgs {
     int32_t leaf_len;           // subtasks of at most this many steps are leaves (0: none)
     int32_t beam_q;             // beam rows run four to a block (dense, one part, small K and B)
     int32_t relative_init;      // subtask starts drop the carried score (FV_FLAG_RELATIVE_INIT)
+    int32_t path_done;          // the decode kernel walked the vanilla table itself (finish skips it)
     int64_t leaf_off;           // floats from a slot's start to its leaf table
     // sparse transitions (CSR out-edges and their in-edge transpose in edge
     // order); null for dense models
