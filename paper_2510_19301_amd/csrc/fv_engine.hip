@@ -3105,8 +3105,90 @@ __device__ __forceinline__ void small_vanilla(cargs_t& a, SeqInfo& sq) {
     }
 FV_SMALL_VANILLA(fv_small_vanilla32_kernel, 32)
 FV_SMALL_VANILLA(fv_small_vanilla64_kernel, 64)
-FV_SMALL_VANILLA(fv_small_vanilla128_kernel, 128)
 #undef FV_SMALL_VANILLA
+
+// 64 < K <= 128: two waves per sequence, thread j for destination j (its
+// column of log A in 128 registers; one wave with two columns per lane
+// would need the whole register file for them).  Each step publishes the
+// scores in LDS, double-buffered so that one barrier per step suffices, and
+// every thread reads them back four at a time (broadcast reads).  Same
+// candidate order, tie rules, finalize and in-kernel backtrace as above.
+extern "C" __global__ __launch_bounds__(128) void fv_small_vanilla128_kernel(const EngineArgs* __restrict__ table) {
+    cargs_t& a = *reinterpret_cast<cargs_t*>(reinterpret_cast<uint64_t>(table));
+    if ((int32_t)blockIdx.x >= a.n_seqs) return;
+    SeqInfo& sq = a.seqs[blockIdx.x];
+    if (sq.status != FV_OK || sq.T <= 0 || a.K > 128) return;
+    constexpr int32_t KMAX = 128;
+    __shared__ __align__(16) float dsh[2][KMAX];
+    __shared__ unsigned long long wkey[2];
+    const int32_t j = threadIdx.x;
+    const int32_t K = a.K, T = sq.T;
+    const bool on = j < K;
+    const float* lb = sq.log_b;
+    const int64_t ld = sq.ld;
+    float col[KMAX];
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) col[i] = (on && i < K) ? a.Acol[(int64_t)i * a.Kp + j] : -INFINITY;
+    float bq[kSmallPrefetch];
+#pragma unroll
+    for (int k = 0; k < kSmallPrefetch; ++k) bq[k] = (on && 1 + k < T) ? lb[(int64_t)(1 + k) * ld + j] : 0.0f;
+    float d = on ? (a.log_pi ? a.log_pi[j] + lb[j] : lb[j]) : -INFINITY;
+    uint16_t* psi = a.psi16 + sq.psi_off;
+    int32_t cur = 0;
+    for (int32_t t = 1; t < T; ++t) {
+        const float bt = bq[0];
+#pragma unroll
+        for (int k = 0; k + 1 < kSmallPrefetch; ++k) bq[k] = bq[k + 1];
+        bq[kSmallPrefetch - 1] = (on && t + kSmallPrefetch < T) ? lb[(int64_t)(t + kSmallPrefetch) * ld + j] : 0.0f;
+        dsh[cur][j] = d;
+        __syncthreads();
+        float b0 = -INFINITY, b1 = -INFINITY;
+        int32_t a0 = 0, a1 = 0;
+#pragma unroll
+        for (int i = 0; i < KMAX; i += 4) {
+            const float4 v = *reinterpret_cast<const float4*>(&dsh[cur][i]);
+            const float x0 = v.x + col[i], x1 = v.y + col[i + 1], x2 = v.z + col[i + 2], x3 = v.w + col[i + 3];
+            if (x0 > b0) { b0 = x0; a0 = i; }
+            if (x1 > b1) { b1 = x1; a1 = i + 1; }
+            if (x2 > b0) { b0 = x2; a0 = i + 2; }
+            if (x3 > b1) { b1 = x3; a1 = i + 3; }
+        }
+        if (b1 > b0 || (b1 == b0 && a1 < a0)) { b0 = b1; a0 = a1; }
+        if (on) psi[(int64_t)t * K + j] = (uint16_t)a0;
+        d = on ? b0 + bt : -INFINITY;
+        cur ^= 1;
+    }
+    // final state: the lowest index of the largest score (-0 and +0 equal)
+    unsigned long long key = on ? order_key(d, j) : 0ull;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const unsigned long long o = __shfl_xor(key, off, 64);
+        if (o > key) key = o;
+    }
+    if ((j & 63) == 0) wkey[j >> 6] = key;
+    dsh[cur][j] = d;
+    __syncthreads();
+    key = wkey[0] > wkey[1] ? wkey[0] : wkey[1];
+    const int32_t qT = clampi((int32_t)(0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull)), K);
+    const float sc = dsh[cur][qT];
+    if (sc == -INFINITY) {
+        for (int32_t t = j; t < T; t += 128) sq.path[t] = -1;
+        if (j == 0) {
+            *sq.score = sc;
+            sq.status = FV_E_INFEASIBLE;
+        }
+        return;
+    }
+    if (j == 0) {
+        *sq.score = sc;
+        sq.path[T - 1] = qT;
+        int32_t q = qT;
+        for (int32_t t = T - 1; t > 0; --t) {
+            q = clampi(psi[(int64_t)t * K + q], K);
+            sq.path[t - 1] = q;
+        }
+    }
+}
 
 // ---------------------------------------------------------------- small single FLASH decode
 // FLASH (Alg. 1 and 2, Sec. V-A/V-B) for sequences of a dense model with
