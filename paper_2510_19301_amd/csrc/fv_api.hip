@@ -620,7 +620,7 @@ fv_status run_batch(int32_t method, const fv_trans* models, const float* const* 
             else
                 hipLaunchKernelGGL(Ks <= 32 ? fv_small_flash32_kernel
                                             : (Ks <= 64 ? fv_small_flash64_kernel : fv_small_flash128_kernel),
-                                   grid, dim3(64), 0, stream, table_dev + p);
+                                   grid, dim3(Ks <= 64 ? 64 : 128), 0, stream, table_dev + p);
         }
     }
     else

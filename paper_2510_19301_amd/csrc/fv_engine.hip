@@ -3481,8 +3481,224 @@ __device__ __forceinline__ void small_flash(cargs_t& a, SeqInfo& sq, uint16_t* l
     }
 FV_SMALL_FLASH(fv_small_flash32_kernel, 32)
 FV_SMALL_FLASH(fv_small_flash64_kernel, 64)
-FV_SMALL_FLASH(fv_small_flash128_kernel, 128)
 #undef FV_SMALL_FLASH
+
+// 64 < K <= 128: the same FLASH schedule with two waves per sequence,
+// thread j for state j (one column of log A in registers).  Each step
+// publishes the scores and the tracked MidState in double-buffered LDS, so
+// one barrier per step serves both the candidates and the MidState gather;
+// one-off gathers (q* at a midpoint, its anchor score, the final state) go
+// through LDS as well.  Every barrier is on block-uniform control flow.
+extern "C" __global__ __launch_bounds__(128) void fv_small_flash128_kernel(const EngineArgs* __restrict__ table) {
+    cargs_t& a = *reinterpret_cast<cargs_t*>(reinterpret_cast<uint64_t>(table));
+    if ((int32_t)blockIdx.x >= a.n_seqs) return;
+    SeqInfo& sq = a.seqs[blockIdx.x];
+    if (sq.status != FV_OK || sq.T <= 0 || a.K > 128 || sq.pp < 1 || sq.pp > sq.T) return;
+    constexpr int32_t KMAX = 128;
+    __shared__ uint16_t leaf_tab[kSmallLeafRows * KMAX];
+    __shared__ SmallTask stack[kSmallStack];
+    __shared__ __align__(16) float dsh[2][KMAX];
+    __shared__ int32_t msh[2][KMAX];
+    __shared__ float xsh[KMAX];
+    __shared__ int32_t ish[KMAX];
+    __shared__ unsigned long long wkey[2];
+    const int32_t K = a.K, T = sq.T, pp = sq.pp;
+    const int32_t j = threadIdx.x;
+    const bool on = j < K;
+    const float* lb = sq.log_b;
+    const int64_t ld = sq.ld;
+    int32_t* path = sq.path;
+    const int32_t leaf_max = a.leaf_len < kSmallLeafRows ? a.leaf_len : kSmallLeafRows;
+    float col[KMAX];
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) col[i] = (on && i < K) ? a.Acol[(int64_t)i * a.Kp + j] : -INFINITY;
+    const float d0 = on ? (a.log_pi ? a.log_pi[j] + lb[j] : lb[j]) : -INFINITY;
+    float* const dsnap = a.root_copy + sq.root_off * (int64_t)a.Kp;                     // [pp-1][Kp]
+    int32_t* const link = reinterpret_cast<int32_t*>(dsnap + (int64_t)(pp - 1) * a.Kp);  // [pp-1][Kp]
+    float bq[kSmallPrefetch];
+    auto ring_start = [&](int32_t t0, int32_t n) {
+#pragma unroll
+        for (int k = 0; k < kSmallPrefetch; ++k) bq[k] = (on && t0 + k <= n) ? lb[(int64_t)(t0 + k) * ld + j] : 0.0f;
+    };
+    auto ring_next = [&](int32_t t, int32_t n) {
+        const float v = bq[0];
+#pragma unroll
+        for (int k = 0; k + 1 < kSmallPrefetch; ++k) bq[k] = bq[k + 1];
+        bq[kSmallPrefetch - 1] = (on && t + kSmallPrefetch <= n) ? lb[(int64_t)(t + kSmallPrefetch) * ld + j] : 0.0f;
+        return v;
+    };
+    // first maximum over the published scores dsh[c] (even and odd chains,
+    // merged by value, equal values to the lower index)
+    auto candidates = [&](int32_t c, int32_t& arg) {
+        float b0 = -INFINITY, b1 = -INFINITY;
+        int32_t a0 = 0, a1 = 0;
+#pragma unroll
+        for (int i = 0; i < KMAX; i += 4) {
+            const float4 v = *reinterpret_cast<const float4*>(&dsh[c][i]);
+            const float x0 = v.x + col[i], x1 = v.y + col[i + 1], x2 = v.z + col[i + 2], x3 = v.w + col[i + 3];
+            if (x0 > b0) { b0 = x0; a0 = i; }
+            if (x1 > b1) { b1 = x1; a1 = i + 1; }
+            if (x2 > b0) { b0 = x2; a0 = i + 2; }
+            if (x3 > b1) { b1 = x3; a1 = i + 3; }
+        }
+        if (b1 > b0 || (b1 == b0 && a1 < a0)) { b0 = b1; a0 = a1; }
+        arg = a0;
+        return b0;
+    };
+    int32_t cur = 0;
+
+    // ---- root pass
+    float d = d0;
+    int32_t mid = 0;
+    int32_t d_next = 0;
+    const int64_t e0 = pp > 1 ? seg_end(T, pp, 0) : (int64_t)T;
+    if (pp > 1 && e0 == 0) {
+        if (on) dsnap[j] = d;
+        d_next = 1;
+    }
+    int64_t e_prev = d_next >= 1 ? 0 : -1;
+    int64_t e_next = d_next < pp - 1 ? seg_end(T, pp, d_next) : -1;
+    ring_start(1, T - 1);
+    for (int32_t t = 1; t < T; ++t) {
+        const float bt = ring_next(t, T - 1);
+        dsh[cur][j] = d;
+        msh[cur][j] = mid;
+        __syncthreads();
+        int32_t pre;
+        const float best = candidates(cur, pre);
+        if (d_next >= 1 && e_prev == t - 1) mid = pre;
+        else if (pp > 1 && t > e0 + 1) mid = msh[cur][pre];
+        d = on ? best + bt : -INFINITY;
+        if (e_next == t) {
+            if (on) {
+                dsnap[(int64_t)d_next * a.Kp + j] = d;
+                if (d_next >= 1) link[(int64_t)d_next * a.Kp + j] = mid;
+            }
+            e_prev = t;
+            ++d_next;
+            e_next = d_next < pp - 1 ? seg_end(T, pp, d_next) : -1;
+        }
+        cur ^= 1;
+    }
+    unsigned long long key = on ? order_key(d, j) : 0ull;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const unsigned long long o = __shfl_xor(key, off, 64);
+        if (o > key) key = o;
+    }
+    if ((j & 63) == 0) wkey[j >> 6] = key;
+    dsh[cur][j] = d;
+    msh[cur][j] = mid;
+    __syncthreads();   // also orders the division copies before they are read back
+    key = wkey[0] > wkey[1] ? wkey[0] : wkey[1];
+    const int32_t qT = clampi((int32_t)(0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull)), K);
+    const float sc = dsh[cur][qT];
+    const int32_t q_last_div = msh[cur][qT];   // q* at e_{P'-2}
+    cur ^= 1;
+    if (sc == -INFINITY) {
+        for (int32_t t = j; t < T; t += KMAX) path[t] = -1;
+        if (j == 0) {
+            *sq.score = sc;
+            sq.status = FV_E_INFEASIBLE;
+        }
+        return;
+    }
+    if (j == 0) {
+        *sq.score = sc;
+        path[T - 1] = qT;
+    }
+
+    // ---- first-level segments, last to first, each with its subtasks
+    int32_t qe = qT;
+    for (int32_t ds = pp - 1; ds >= 0; --ds) {
+        const int32_t n0 = (int32_t)seg_end(T, pp, ds);
+        const int32_t m0 = ds == 0 ? 0 : (int32_t)seg_end(T, pp, ds - 1) + 1;
+        int32_t qp = 0;
+        float alpha = 0.0f;
+        if (ds >= 1) {
+            qp = ds == pp - 1 ? q_last_div : link[(int64_t)ds * a.Kp + qe];
+            qp = clampi(qp, K);
+            alpha = dsnap[(int64_t)(ds - 1) * a.Kp + qp];
+            if (j == 0) path[m0 - 1] = qp;
+        }
+        if (n0 - m0 >= 1) {
+            __syncthreads();   // earlier readers of stack[0] are done
+            if (j == 0) stack[0] = SmallTask{m0, n0, qp, qe, alpha};
+            int32_t sp = 1;
+            __syncthreads();
+            while (sp > 0) {
+                const SmallTask tk = stack[--sp];
+                const int32_t m = tk.m, n = tk.n;
+                float x = d0;
+                if (m > 0) {
+                    const float arow = on ? a.Acol[(int64_t)tk.q_prev * a.Kp + j] : -INFINITY;
+                    const float cc = a.relative_init ? arow : tk.alpha + arow;
+                    x = on ? cc + lb[(int64_t)m * ld + j] : -INFINITY;
+                }
+                ring_start(m + 1, n);
+                if (n - m + 1 <= leaf_max) {
+                    for (int32_t t = m + 1; t <= n; ++t) {
+                        const float bt = ring_next(t, n);
+                        dsh[cur][j] = x;
+                        __syncthreads();
+                        int32_t pre;
+                        const float best = candidates(cur, pre);
+                        x = on ? best + bt : -INFINITY;
+                        if (on) leaf_tab[(t - m - 1) * KMAX + j] = (uint16_t)pre;
+                        cur ^= 1;
+                    }
+                    __syncthreads();
+                    if (j == 0) {
+                        int32_t q = tk.q_n;
+                        for (int32_t t = n; t > m; --t) {
+                            q = leaf_tab[(t - m - 1) * KMAX + q];
+                            path[t - 1] = q;
+                        }
+                    }
+                    __syncthreads();
+                    continue;
+                }
+                const int32_t tmid = (m + n) / 2;
+                float snap = x;
+                int32_t md = 0;
+                for (int32_t t = m + 1; t <= n; ++t) {
+                    const float bt = ring_next(t, n);
+                    dsh[cur][j] = x;
+                    msh[cur][j] = md;
+                    __syncthreads();
+                    int32_t pre;
+                    const float best = candidates(cur, pre);
+                    if (t == tmid + 1) md = pre;
+                    else if (t > tmid + 1) md = msh[cur][pre];
+                    x = on ? best + bt : -INFINITY;
+                    if (t == tmid) snap = x;
+                    cur ^= 1;
+                }
+                ish[j] = md;
+                xsh[j] = snap;
+                __syncthreads();
+                const int32_t qmid = clampi(ish[tk.q_n], K);
+                const float amid = xsh[qmid];
+                if (n - m >= 2 && sp + 2 > kSmallStack) {   // deeper than any sequence of 2^31 steps needs
+                    if (j == 0) sq.status = FV_E_DEVICE;
+                    return;
+                }
+                if (j == 0) {
+                    path[tmid] = qmid;
+                    if (n - m > 2) {
+                        stack[sp] = SmallTask{m, tmid, tk.q_prev, qmid, tk.alpha};
+                        stack[sp + 1] = SmallTask{tmid + 1, n, qmid, tk.q_n, amid};
+                    } else if (n - m == 2) {
+                        stack[sp] = SmallTask{m, tmid, tk.q_prev, qmid, tk.alpha};
+                    }
+                }
+                sp += n - m > 2 ? 2 : (n - m == 2 ? 1 : 0);
+                __syncthreads();
+            }
+        }
+        qe = qp;
+    }
+}
 
 // ---------------------------------------------------------------- preparation kernel
 // Ap[i][j] = log A(i, j) on a Kp x Kp grid, -inf outside K x K (only used
