@@ -2925,11 +2925,11 @@ extern "C" __global__ __launch_bounds__(kEngBlock) void fv_engine_kernel(const E
 }
 
 // ---------------------------------------------------------------- small single decode
-// Vanilla decodes of a small dense model (K <= kSmallK), one wave (block) per
-// sequence, in place of the persistent engine: lane l keeps the log A columns of
-// destinations l and l + 64 in registers (the wave has the whole register
-// file of its SIMD) and reads the previous step's scores from the lanes
-// that hold them (readlane), so a step needs no barrier and no scheduling.
+// Vanilla decodes of a small dense model (K <= 64), one wave (block) per
+// sequence, in place of the persistent engine: lane l keeps destination l's
+// column of log A in registers and reads the previous step's scores from the
+// lanes that hold them (readlane), so a step needs no barrier and no
+// scheduling.  (64 < K <= kSmallK runs two waves per sequence, below.)
 // The arithmetic and tie rules are the engine's: per destination the first
 // maximum over predecessors in index order, its own value kept, delta = that
 // + log B_t(j); the final state is the lowest index of the largest score (-0
@@ -2945,13 +2945,9 @@ constexpr int32_t kSmallPrefetch = 4;
 // chains (first maximum each), merged so that the larger value wins and
 // equal values (-0 == +0) go to the lower index: the same result as one
 // scan in index order.
-// LDS_SCORES: the scores are published in LDS (dsh, KMAX floats) and read
-// back four at a time, every lane reading the same address, instead of one
-// readlane per predecessor (measured faster for the 128-wide FLASH kernel,
-// slower for the 128-wide vanilla one).
-template <int KMAX, int NJ, bool LDS_SCORES>
+template <int KMAX, int NJ>
 __device__ __forceinline__ void small_candidates(const float (&col)[NJ][KMAX], const float (&d)[NJ],
-                                                 float (&best)[NJ], int32_t (&arg)[NJ], float* dsh) {
+                                                 float (&best)[NJ], int32_t (&arg)[NJ]) {
     float b1[NJ];
     int32_t a1[NJ];
 #pragma unroll
@@ -2961,38 +2957,16 @@ __device__ __forceinline__ void small_candidates(const float (&col)[NJ][KMAX], c
         b1[c] = -INFINITY;
         a1[c] = 0;
     }
-    if constexpr (LDS_SCORES) {
 #pragma unroll
-        for (int c = 0; c < NJ; ++c) dsh[threadIdx.x + 64 * c] = d[c];
-        __syncthreads();
+    for (int i = 0; i < KMAX; i += 2) {
+        const float d0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(d[i / 64]), i % 64));
+        const float d1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(d[(i + 1) / 64]), (i + 1) % 64));
 #pragma unroll
-        for (int i = 0; i < KMAX; i += 4) {
-            const float4 v = *reinterpret_cast<const float4*>(dsh + i);
-#pragma unroll
-            for (int c = 0; c < NJ; ++c) {
-                const float x0 = v.x + col[c][i];
-                const float x1 = v.y + col[c][i + 1];
-                const float x2 = v.z + col[c][i + 2];
-                const float x3 = v.w + col[c][i + 3];
-                if (x0 > best[c]) { best[c] = x0; arg[c] = i; }
-                if (x1 > b1[c]) { b1[c] = x1; a1[c] = i + 1; }
-                if (x2 > best[c]) { best[c] = x2; arg[c] = i + 2; }
-                if (x3 > b1[c]) { b1[c] = x3; a1[c] = i + 3; }
-            }
-        }
-        __syncthreads();   // the next step overwrites dsh
-    } else {
-#pragma unroll
-        for (int i = 0; i < KMAX; i += 2) {
-            const float d0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(d[i / 64]), i % 64));
-            const float d1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(d[(i + 1) / 64]), (i + 1) % 64));
-#pragma unroll
-            for (int c = 0; c < NJ; ++c) {
-                const float x0 = d0 + col[c][i];
-                const float x1 = d1 + col[c][i + 1];
-                if (x0 > best[c]) { best[c] = x0; arg[c] = i; }
-                if (x1 > b1[c]) { b1[c] = x1; a1[c] = i + 1; }
-            }
+        for (int c = 0; c < NJ; ++c) {
+            const float x0 = d0 + col[c][i];
+            const float x1 = d1 + col[c][i + 1];
+            if (x0 > best[c]) { best[c] = x0; arg[c] = i; }
+            if (x1 > b1[c]) { b1[c] = x1; a1[c] = i + 1; }
         }
     }
 #pragma unroll
@@ -3048,7 +3022,7 @@ __device__ __forceinline__ void small_vanilla(cargs_t& a, SeqInfo& sq) {
         }
         float best[NJ];
         int32_t arg[NJ];
-        small_candidates<KMAX, NJ, false>(col, d, best, arg, nullptr);
+        small_candidates<KMAX, NJ>(col, d, best, arg);
 #pragma unroll
         for (int c = 0; c < NJ; ++c) {
             if (on[c]) psi[(int64_t)t * K + lane + 64 * c] = (uint16_t)arg[c];
@@ -3093,8 +3067,8 @@ __device__ __forceinline__ void small_vanilla(cargs_t& a, SeqInfo& sq) {
     }
 }
 
-// One kernel per width (K <= 32, 64, 128), so each gets the register
-// allocation of its own step loop.
+// One kernel per width (K <= 32, 64), so each gets the register allocation
+// of its own step loop.
 #define FV_SMALL_VANILLA(NAME, KMAX)                                                                   \
     extern "C" __global__ __launch_bounds__(64) void NAME(const EngineArgs* __restrict__ table) {       \
         cargs_t& a = *reinterpret_cast<cargs_t*>(reinterpret_cast<uint64_t>(table));                    \
@@ -3192,11 +3166,11 @@ extern "C" __global__ __launch_bounds__(128) void fv_small_vanilla128_kernel(con
 
 // ---------------------------------------------------------------- small single FLASH decode
 // FLASH (Alg. 1 and 2, Sec. V-A/V-B) for sequences of a dense model with
-// K <= kSmallFlashK (128), one wave (block) per sequence, with the persistent engine's task
+// K <= 64, one wave (block) per sequence, with the persistent engine's task
 // structure, so the decode keeps the method's O(P K) state.  State s lives
-// in lane s % 64 (NJ = 2: s / 64 picks the lane's first or second column),
-// which holds s's column of log A; each step reads the previous scores from
-// the other lanes, as in the one-wave vanilla kernel.
+// in lane s, which holds s's column of log A; each step reads the previous
+// scores from the other lanes, as in the one-wave vanilla kernel.
+// (64 < K <= kSmallFlashK runs two waves per sequence, below.)
 //   - Root pass over the whole sequence: each state keeps MidState (the state
 //     at the most recent division point on its best path) and, at each
 //     division point e_d (d <= P'-2), stores its score and, for d >= 1, its
@@ -3230,7 +3204,6 @@ struct SmallWave {
     float bq[NJ][kSmallPrefetch];
     const float* lb;
     int64_t ld;
-    float* dsh;   // KMAX floats of LDS for the published scores (two destinations per lane)
 
     // emission scores of steps t0.. of a pass ending at n, kSmallPrefetch rows in flight
     __device__ __forceinline__ void ring_start(int32_t t0, int32_t n) {
@@ -3252,7 +3225,7 @@ struct SmallWave {
             bq[c][kSmallPrefetch - 1] =
                 (on[c] && t + kSmallPrefetch <= n) ? lb[(int64_t)(t + kSmallPrefetch) * ld + lane + 64 * c] : 0.0f;
         }
-        small_candidates<KMAX, NJ, (NJ > 1)>(col, d, best, arg, dsh);
+        small_candidates<KMAX, NJ>(col, d, best, arg);
 #pragma unroll
         for (int c = 0; c < NJ; ++c) d[c] = on[c] ? best[c] + bt[c] : -INFINITY;
     }
@@ -3270,8 +3243,7 @@ __device__ __forceinline__ V small_at(const V (&v)[NJ], int32_t s) {
 }
 
 template <int KMAX>
-__device__ __forceinline__ void small_flash(cargs_t& a, SeqInfo& sq, uint16_t* leaf_tab, SmallTask* stack,
-                                            float* dsh) {
+__device__ __forceinline__ void small_flash(cargs_t& a, SeqInfo& sq, uint16_t* leaf_tab, SmallTask* stack) {
     const int32_t K = a.K, T = sq.T, pp = sq.pp;
     constexpr int NJ = SmallWave<KMAX>::NJ;
     SmallWave<KMAX> w;
@@ -3279,7 +3251,6 @@ __device__ __forceinline__ void small_flash(cargs_t& a, SeqInfo& sq, uint16_t* l
     w.K = K;
     w.lb = sq.log_b;
     w.ld = sq.ld;
-    w.dsh = dsh;
     const int32_t lane = w.lane;
 #pragma unroll
     for (int c = 0; c < NJ; ++c) w.on[c] = lane + 64 * c < K;
@@ -3466,8 +3437,8 @@ __device__ __forceinline__ void small_flash(cargs_t& a, SeqInfo& sq, uint16_t* l
     }
 }
 
-// One kernel per width (K <= 32, 64, 128), so each gets the register
-// allocation of its own step loop.
+// One kernel per width (K <= 32, 64), so each gets the register allocation
+// of its own step loop.
 #define FV_SMALL_FLASH(NAME, KMAX)                                                                     \
     extern "C" __global__ __launch_bounds__(64) void NAME(const EngineArgs* __restrict__ table) {       \
         cargs_t& a = *reinterpret_cast<cargs_t*>(reinterpret_cast<uint64_t>(table));                    \
@@ -3476,8 +3447,7 @@ __device__ __forceinline__ void small_flash(cargs_t& a, SeqInfo& sq, uint16_t* l
         if (sq.status != FV_OK || sq.T <= 0 || a.K > KMAX || sq.pp < 1 || sq.pp > sq.T) return;         \
         __shared__ uint16_t leaf_tab[kSmallLeafRows * KMAX];                                            \
         __shared__ SmallTask stack[kSmallStack];                                                        \
-        __shared__ __align__(16) float dsh[KMAX];                                                       \
-        small_flash<KMAX>(a, sq, leaf_tab, stack, dsh);                                                 \
+        small_flash<KMAX>(a, sq, leaf_tab, stack);                                                      \
     }
 FV_SMALL_FLASH(fv_small_flash32_kernel, 32)
 FV_SMALL_FLASH(fv_small_flash64_kernel, 64)
