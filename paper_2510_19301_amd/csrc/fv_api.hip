@@ -15,9 +15,11 @@ extern "C" __global__ void fv_engine_kernel(const EngineArgs* __restrict__ table
 extern "C" __global__ void fv_small_vanilla32_kernel(const EngineArgs* __restrict__ table);
 extern "C" __global__ void fv_small_vanilla64_kernel(const EngineArgs* __restrict__ table);
 extern "C" __global__ void fv_small_vanilla128_kernel(const EngineArgs* __restrict__ table);
+extern "C" __global__ void fv_small_vanilla256_kernel(const EngineArgs* __restrict__ table);
 extern "C" __global__ void fv_small_flash32_kernel(const EngineArgs* __restrict__ table);
 extern "C" __global__ void fv_small_flash64_kernel(const EngineArgs* __restrict__ table);
 extern "C" __global__ void fv_small_flash128_kernel(const EngineArgs* __restrict__ table);
+extern "C" __global__ void fv_small_flash256_kernel(const EngineArgs* __restrict__ table);
 extern "C" __global__ void fv_fill_i32_kernel(int32_t* __restrict__ p, int64_t n, int32_t v);
 extern "C" __global__ void fv_validate_array_kernel(const float* __restrict__ p, int64_t n, int32_t* __restrict__ flag);
 extern "C" __global__ void fv_validate_seqs_kernel(const fv_seq* __restrict__ seqs, int32_t n_seqs, int32_t model,
@@ -613,14 +615,19 @@ fv_status run_batch(int32_t method, const fv_trans* models, const float* const* 
         for (size_t p = 0; p < bp.L.size(); ++p) {
             const int32_t Ks = bp.L[p].K;
             const dim3 grid(std::max(1, bp.L[p].n_seqs));
+            const dim3 block(Ks <= 64 ? 64 : (Ks <= 128 ? 128 : 256));
             if (bp.method[p] == FV_VANILLA)
                 hipLaunchKernelGGL(Ks <= 32 ? fv_small_vanilla32_kernel
-                                            : (Ks <= 64 ? fv_small_vanilla64_kernel : fv_small_vanilla128_kernel),
-                                   grid, dim3(Ks <= 64 ? 64 : 128), 0, stream, table_dev + p);
+                                            : (Ks <= 64 ? fv_small_vanilla64_kernel
+                                                        : (Ks <= 128 ? fv_small_vanilla128_kernel
+                                                                     : fv_small_vanilla256_kernel)),
+                                   grid, block, 0, stream, table_dev + p);
             else
                 hipLaunchKernelGGL(Ks <= 32 ? fv_small_flash32_kernel
-                                            : (Ks <= 64 ? fv_small_flash64_kernel : fv_small_flash128_kernel),
-                                   grid, dim3(Ks <= 64 ? 64 : 128), 0, stream, table_dev + p);
+                                            : (Ks <= 64 ? fv_small_flash64_kernel
+                                                        : (Ks <= 128 ? fv_small_flash128_kernel
+                                                                     : fv_small_flash256_kernel)),
+                                   grid, block, 0, stream, table_dev + p);
         }
     }
     else

@@ -3081,20 +3081,20 @@ FV_SMALL_VANILLA(fv_small_vanilla32_kernel, 32)
 FV_SMALL_VANILLA(fv_small_vanilla64_kernel, 64)
 #undef FV_SMALL_VANILLA
 
-// 64 < K <= 128: two waves per sequence, thread j for destination j (its
-// column of log A in 128 registers; one wave with two columns per lane
-// would need the whole register file for them).  Each step publishes the
+// 64 < K <= 256: KMAX / 64 waves per sequence (KMAX = 128 or 256), thread j
+// for destination j (its column of log A in registers; one wave with
+// several columns per lane would need more than the whole register file).  Each step publishes the
 // scores in LDS, double-buffered so that one barrier per step suffices, and
 // every thread reads them back four at a time (broadcast reads).  Same
 // candidate order, tie rules, finalize and in-kernel backtrace as above.
-extern "C" __global__ __launch_bounds__(128) void fv_small_vanilla128_kernel(const EngineArgs* __restrict__ table) {
+template <int KMAX>
+__device__ __forceinline__ void small_vanilla_waves(const EngineArgs* __restrict__ table) {
     cargs_t& a = *reinterpret_cast<cargs_t*>(reinterpret_cast<uint64_t>(table));
     if ((int32_t)blockIdx.x >= a.n_seqs) return;
     SeqInfo& sq = a.seqs[blockIdx.x];
-    if (sq.status != FV_OK || sq.T <= 0 || a.K > 128) return;
-    constexpr int32_t KMAX = 128;
+    if (sq.status != FV_OK || sq.T <= 0 || a.K > KMAX) return;
     __shared__ __align__(16) float dsh[2][KMAX];
-    __shared__ unsigned long long wkey[2];
+    __shared__ unsigned long long wkey[KMAX / 64];
     const int32_t j = threadIdx.x;
     const int32_t K = a.K, T = sq.T;
     const bool on = j < K;
@@ -3142,11 +3142,13 @@ extern "C" __global__ __launch_bounds__(128) void fv_small_vanilla128_kernel(con
     if ((j & 63) == 0) wkey[j >> 6] = key;
     dsh[cur][j] = d;
     __syncthreads();
-    key = wkey[0] > wkey[1] ? wkey[0] : wkey[1];
+    key = wkey[0];
+#pragma unroll
+    for (int w = 1; w < KMAX / 64; ++w) key = wkey[w] > key ? wkey[w] : key;
     const int32_t qT = clampi((int32_t)(0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull)), K);
     const float sc = dsh[cur][qT];
     if (sc == -INFINITY) {
-        for (int32_t t = j; t < T; t += 128) sq.path[t] = -1;
+        for (int32_t t = j; t < T; t += KMAX) sq.path[t] = -1;
         if (j == 0) {
             *sq.score = sc;
             sq.status = FV_E_INFEASIBLE;
@@ -3162,6 +3164,14 @@ extern "C" __global__ __launch_bounds__(128) void fv_small_vanilla128_kernel(con
             sq.path[t - 1] = q;
         }
     }
+}
+
+extern "C" __global__ __launch_bounds__(128) void fv_small_vanilla128_kernel(const EngineArgs* __restrict__ table) {
+    small_vanilla_waves<128>(table);
+}
+
+extern "C" __global__ __launch_bounds__(256) void fv_small_vanilla256_kernel(const EngineArgs* __restrict__ table) {
+    small_vanilla_waves<256>(table);
 }
 
 // ---------------------------------------------------------------- small single FLASH decode
@@ -3453,25 +3463,26 @@ FV_SMALL_FLASH(fv_small_flash32_kernel, 32)
 FV_SMALL_FLASH(fv_small_flash64_kernel, 64)
 #undef FV_SMALL_FLASH
 
-// 64 < K <= 128: the same FLASH schedule with two waves per sequence,
-// thread j for state j (one column of log A in registers).  Each step
+// 64 < K <= 256: the same FLASH schedule with KMAX / 64 waves per sequence
+// (KMAX = 128 or 256), thread j for state j (one column of log A in
+// registers).  Each step
 // publishes the scores and the tracked MidState in double-buffered LDS, so
 // one barrier per step serves both the candidates and the MidState gather;
 // one-off gathers (q* at a midpoint, its anchor score, the final state) go
 // through LDS as well.  Every barrier is on block-uniform control flow.
-extern "C" __global__ __launch_bounds__(128) void fv_small_flash128_kernel(const EngineArgs* __restrict__ table) {
+template <int KMAX>
+__device__ __forceinline__ void small_flash_waves(const EngineArgs* __restrict__ table) {
     cargs_t& a = *reinterpret_cast<cargs_t*>(reinterpret_cast<uint64_t>(table));
     if ((int32_t)blockIdx.x >= a.n_seqs) return;
     SeqInfo& sq = a.seqs[blockIdx.x];
-    if (sq.status != FV_OK || sq.T <= 0 || a.K > 128 || sq.pp < 1 || sq.pp > sq.T) return;
-    constexpr int32_t KMAX = 128;
+    if (sq.status != FV_OK || sq.T <= 0 || a.K > KMAX || sq.pp < 1 || sq.pp > sq.T) return;
     __shared__ uint16_t leaf_tab[kSmallLeafRows * KMAX];
     __shared__ SmallTask stack[kSmallStack];
     __shared__ __align__(16) float dsh[2][KMAX];
     __shared__ int32_t msh[2][KMAX];
     __shared__ float xsh[KMAX];
     __shared__ int32_t ish[KMAX];
-    __shared__ unsigned long long wkey[2];
+    __shared__ unsigned long long wkey[KMAX / 64];
     const int32_t K = a.K, T = sq.T, pp = sq.pp;
     const int32_t j = threadIdx.x;
     const bool on = j < K;
@@ -3560,7 +3571,9 @@ extern "C" __global__ __launch_bounds__(128) void fv_small_flash128_kernel(const
     dsh[cur][j] = d;
     msh[cur][j] = mid;
     __syncthreads();   // also orders the division copies before they are read back
-    key = wkey[0] > wkey[1] ? wkey[0] : wkey[1];
+    key = wkey[0];
+#pragma unroll
+    for (int w = 1; w < KMAX / 64; ++w) key = wkey[w] > key ? wkey[w] : key;
     const int32_t qT = clampi((int32_t)(0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull)), K);
     const float sc = dsh[cur][qT];
     const int32_t q_last_div = msh[cur][qT];   // q* at e_{P'-2}
@@ -3668,6 +3681,14 @@ extern "C" __global__ __launch_bounds__(128) void fv_small_flash128_kernel(const
         }
         qe = qp;
     }
+}
+
+extern "C" __global__ __launch_bounds__(128) void fv_small_flash128_kernel(const EngineArgs* __restrict__ table) {
+    small_flash_waves<128>(table);
+}
+
+extern "C" __global__ __launch_bounds__(256) void fv_small_flash256_kernel(const EngineArgs* __restrict__ table) {
+    small_flash_waves<256>(table);
 }
 
 // ---------------------------------------------------------------- preparation kernel

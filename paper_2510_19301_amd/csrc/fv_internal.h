@@ -63,9 +63,9 @@ constexpr int32_t kColMaxKp = 4096;
 
 // One vanilla decode of a dense model with K <= kSmallK runs on one wave
 // instead of the persistent engine.
-constexpr int32_t kSmallK = 128;
+constexpr int32_t kSmallK = 256;
 // One FLASH decode of a dense model with K <= kSmallFlashK runs on one wave too.
-constexpr int32_t kSmallFlashK = 128;
+constexpr int32_t kSmallFlashK = 256;
 
 // Operations of a beam row (one block each): start step, full beam step,
 // end-only step of a subtask, final selection of a root.

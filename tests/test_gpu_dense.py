@@ -115,11 +115,12 @@ def test_signed_zero(fv):
         assert (p == po).all() and (_bits(s) == _bits(so)).all()
 
 
-@pytest.mark.parametrize("K,T", [(64, 300), (65, 1), (65, 300), (96, 257), (127, 64), (128, 700)])
+@pytest.mark.parametrize("K,T", [(64, 300), (65, 1), (65, 300), (96, 257), (127, 64), (128, 700), (129, 40),
+                                 (200, 300), (256, 129)])
 def test_single_vanilla_two_columns_per_lane(fv, K, T):
-    """Single vanilla decodes with 64 < K <= 128 (two destinations per lane
-    of the one-wave kernel): random, integer-tie, start-free and infeasible
-    inputs, bit for bit against the oracle."""
+    """Single vanilla decodes with 64 <= K <= 256 (the one-wave kernel at 64,
+    the two- and four-wave kernels above): random, integer-tie, start-free
+    and infeasible inputs, bit for bit against the oracle."""
     print(f"one-wave vanilla K={K} T={T}", flush=True)
     lp, la, lb = hmm.random_dense(K, T, 7 * K + T)
     p, s, st = _run(fv, lp, la, lb, "vanilla")
@@ -157,9 +158,9 @@ def test_single_vanilla_signed_zero_across_lanes(fv, T):
 
 
 @pytest.mark.parametrize("K,T", [(1, 5), (7, 1), (7, 2), (7, 3), (33, 129), (64, 700), (64, 3000), (65, 2),
-                                 (65, 300), (100, 129), (128, 1000)])
+                                 (65, 300), (100, 129), (128, 1000), (129, 130), (200, 257), (256, 150)])
 def test_single_flash_one_wave(fv, K, T):
-    """Single FLASH decodes with K <= 128 (the one-wave FLASH kernel): every
+    """Single FLASH decodes with K <= 256 (the one- and multi-wave FLASH kernels): every
     P' from 2 to T (and beyond), with and without leaf subtasks, bit for bit
     against the oracle's vanilla result and the oracle's FLASH."""
     lp, la, lb = hmm.random_dense(K, T, 5 * K + T)
@@ -176,7 +177,7 @@ def test_single_flash_one_wave(fv, K, T):
             assert (_bits(score.cpu().numpy()) == _bits(so)).all()
 
 
-@pytest.mark.parametrize("K", [50, 120])
+@pytest.mark.parametrize("K", [50, 120, 250])
 def test_single_flash_one_wave_ties_and_edges(fv, K):
     """Integer ties, no start vector, -0 against +0 and an infeasible model
     through the one-wave FLASH kernel (one and two destinations per lane)."""
@@ -233,6 +234,37 @@ def test_batch_small_models_one_wave_per_sequence(fv, K):
     runs = [("vanilla", 1, True, False), ("flash", 1, True, False), ("flash", 4, False, False),
             ("flash", 64, True, False), ("flash", 16, True, True)]
     for method, P, leaves, rel in runs:
+        print(f"batch K={K} {method} P={P} leaves={leaves} relative={rel}", flush=True)
+        batch = fv.Batch([_dev(x) if x.shape[0] else torch.empty((0, K), device="cuda") for x in lbs])
+        fv.decode_batch(_dev(la), batch, _dev(lp), method=method, P=P, leaves=leaves, relative_init=rel)
+        torch.cuda.synchronize()
+        paths, scores, status = batch.paths.cpu().numpy(), batch.scores.cpu().numpy(), batch.status.cpu().numpy()
+        for b, T in enumerate(lengths):
+            assert status[b] == 0, (method, P, b)
+            if T == 0:
+                assert scores[b] == 0.0
+                continue
+            if rel:
+                po, so, _, _ = oracle.flash(lp, la, lbs[b], P, relative_init=True)
+            else:
+                po, so, _ = ref[b]
+            assert (paths[b, :T] == po).all(), (method, P, b)
+            assert _bits(scores[b]) == _bits(so), (method, P, b)
+
+
+def test_batch_k200_four_waves_per_sequence(fv):
+    """A ragged batch on one K = 200 model (four waves per sequence): vanilla,
+    FLASH with and without leaves, and the relative start."""
+    K = 200
+    r = np.random.default_rng(200)
+    lengths = [int(x) for x in r.integers(0, 200, size=40)]
+    lengths[:3] = [0, 1, 199]
+    _, la, _ = hmm.random_dense(K, 1, 201)
+    lp = hmm.uniform_log_pi(K)
+    lbs = [(r.standard_normal((T, K)) * 2).astype(np.float32) for T in lengths]
+    ref = [oracle.vanilla(lp, la, x) if x.shape[0] else None for x in lbs]
+    for method, P, leaves, rel in (("vanilla", 1, True, False), ("flash", 4, True, False),
+                                   ("flash", 4, False, False), ("flash", 16, True, True)):
         print(f"batch K={K} {method} P={P} leaves={leaves} relative={rel}", flush=True)
         batch = fv.Batch([_dev(x) if x.shape[0] else torch.empty((0, K), device="cuda") for x in lbs])
         fv.decode_batch(_dev(la), batch, _dev(lp), method=method, P=P, leaves=leaves, relative_init=rel)
