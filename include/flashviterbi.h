@@ -177,8 +177,9 @@ fv_status fv_decode_beam(const fv_trans* A, const float* log_pi, const float* lo
                          size_t ws_bytes, fv_stream_t stream);
 
 /* Many sequences, uneven lengths, one decode launch: the persistent engine,
- * or, for vanilla and FLASH decodes of one dense model with K <= 128, one
- * wave per sequence running the same method (same results).  models: host
+ * or, for vanilla and FLASH decodes whose dense models all have K <= 256,
+ * one block (one to four waves) per sequence running the same method (same
+ * results).  models: host
  * array [n_models] (dense and CSR models may be mixed, K may differ);
  * log_pi: host array of n_models device pointers (entries may be NULL);
  * seqs_dev: device array [n_seqs]; T_host / model_host: host copies of each
@@ -225,8 +226,8 @@ fv_status fv_gather_emissions(int32_t K, int32_t V, const float* log_e, const in
 
 /* Measurement hook: while enabled (enable != 0, host thread-local), every
  * decode records a pair of HIP events on its stream immediately before and
- * after its decode kernel (the persistent engine, or the one-wave kernels
- * of small dense models).  fv_profile_engine_ms waits for the last pair
+ * after its decode kernel (the persistent engine, or the per-sequence
+ * kernels of small dense models).  fv_profile_engine_ms waits for the last pair
  * and returns that kernel's duration in milliseconds.
  * Enable outside stream capture (it creates the events). */
 fv_status fv_profile_engine(int32_t enable);

@@ -193,8 +193,8 @@ def decode_batch(log_a, batch: Batch, log_pi=None, method: str = "flash", P: int
                  ws: torch.Tensor | None = None, rows: str = "auto", validate: bool = False,
                  leaves: bool = True, relative_init: bool = False):
     """Decode all sequences of `batch` in one decode launch (the persistent
-    engine, or one wave per sequence for vanilla and FLASH on one dense
-    model with K <= 128).  log_a: a
+    engine, or one block per sequence for vanilla and FLASH when every dense
+    model has K <= 256).  log_a: a
     dense [K, K] tensor or a CsrModel, or a list of them when the batch's
     sequences use several models (batch.models indexes it); log_pi: a [K]
     tensor or None, or a list matching log_a.  Results land in batch.paths
