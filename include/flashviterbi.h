@@ -198,7 +198,11 @@ fv_status fv_decode_batch(const fv_trans* models, const float* const* log_pi, in
                           size_t ws_bytes, fv_stream_t stream);
 
 /* Gradient of the Viterbi scores S_b (the decoded path's summed log-scores)
- * given upstream gradients grad_score[n]:
+ * given upstream gradients grad_score[n].  No passage of the paper defines
+ * this operation: it is the subgradient of the score of Sec. III-A (a sum of
+ * log-scores along the decoded path) with respect to its inputs, for
+ * structured-hinge training; at ties it takes the decoded path's indicator.
+ *
  *   grad_log_b[b][t][j] = grad_score[b] * [j == paths[b][t]]   (t < lengths[b], else 0)
  *   grad_log_a[i][j]    = sum over b ascending of fl(grad_score[b] * c_b(i,j)),
  *                         c_b(i,j) = #{t >= 1 : (q_{b,t-1}, q_{b,t}) = (i, j)}
@@ -216,7 +220,11 @@ fv_status fv_viterbi_backward(int32_t K, int32_t n_seqs, int32_t Tmax, const int
 fv_status fv_backward_workspace_size(int32_t K, int32_t n_seqs, int32_t Tmax, size_t* bytes);
 
 /* score_out[b] = step-by-step float32 re-sum of paths[b] (dense model):
- * s = log pi[q0] + log B_0[q0]; s = (s + log A[q_{t-1}][q_t]) + log B_t[q_t]. */
+ * s = log pi[q0] + log B_0[q0]; s = (s + log A[q_{t-1}][q_t]) + log B_t[q_t]
+ * (the path's score of Sec. III-A, added in time order; log pi NULL drops
+ * the first term).  seqs_dev: device array [n_seqs] whose `path` fields are
+ * read (int32 [T] each, entries in [0, K); an entry outside gives -inf) and
+ * whose `score` fields are ignored; score_out: device float32 [n_seqs]. */
 fv_status fv_rescore(const fv_trans* A, const float* log_pi, const fv_seq* seqs_dev,
                      int32_t n_seqs, float* score_out, fv_stream_t stream);
 
@@ -232,6 +240,17 @@ fv_status fv_gather_emissions(int32_t K, int32_t V, const float* log_e, const in
  * Enable outside stream capture (it creates the events). */
 fv_status fv_profile_engine(int32_t enable);
 fv_status fv_profile_engine_ms(float* ms);
+/* Disabling (enable == 0) waits for the last recorded pair and destroys the
+ * events, so no HIP object of the library outlives the measurement. */
+
+/* Test hook for the persistent engine's watchdog.  Nonzero max_steps or
+ * spin_limit replace, for later decodes issued by this host thread, the
+ * engine's bound on global steps (by default far above any valid schedule)
+ * and on the iterations of each wait at its step barrier.  A decode that
+ * reaches either bound stops normally on every block and reports
+ * FV_E_DEVICE in every status entry.  0 restores the defaults; negative
+ * values return FV_E_INVALID_ARG. */
+fv_status fv_debug_engine_limits(int64_t max_steps, int64_t spin_limit);
 
 const char* fv_status_str(fv_status s);
 const char* fv_last_error(void);   /* thread-local message of the last failure */

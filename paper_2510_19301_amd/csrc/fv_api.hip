@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <string>
 #include <map>
+#include <mutex>
 #include <vector>
 
 #include "fv_internal.h"
@@ -54,6 +55,10 @@ static thread_local std::string g_last_error;
 static thread_local bool g_prof_on = false;
 static thread_local hipEvent_t g_prof_ev[2] = {nullptr, nullptr};
 static thread_local bool g_prof_recorded = false;
+// test hook (fv_debug_engine_limits): nonzero values replace the engine's
+// step and barrier-wait limits for decodes issued by this host thread
+static thread_local int64_t g_dbg_max_steps = 0;
+static thread_local int64_t g_dbg_spin_limit = 0;
 
 static fv_status fail(fv_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 static fv_status fail(fv_status s, const char* fmt, ...) {
@@ -323,17 +328,32 @@ struct DeviceInfo {
     int engine_blocks_per_cu = 0;
 };
 
+// Queried once per device and cached: a decode call then does no property
+// or occupancy query between the caller's events and its launches.
+constexpr int kMaxDevices = 64;
+std::mutex g_dev_mutex;
+DeviceInfo g_dev_info[kMaxDevices];
+bool g_dev_known[kMaxDevices] = {};
+
 fv_status device_info(DeviceInfo& di) {
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
-    hipDeviceProp_t p;
-    HIP_TRY(hipGetDeviceProperties(&p, dev));
-    di.cus = p.multiProcessorCount;
-    int nb = 0;
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(fv_engine_kernel),
-                                                         kEngineBlock, 0));
-    di.engine_blocks_per_cu = nb;
-    if (nb < 1) return fail(FV_E_DEVICE, "engine kernel cannot be resident");
+    if (dev < 0 || dev >= kMaxDevices) return fail(FV_E_DEVICE, "device ordinal %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_dev_mutex);
+    if (!g_dev_known[dev]) {
+        hipDeviceProp_t p;
+        HIP_TRY(hipGetDeviceProperties(&p, dev));
+        DeviceInfo d;
+        d.cus = p.multiProcessorCount;
+        int nb = 0;
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(fv_engine_kernel),
+                                                             kEngineBlock, 0));
+        d.engine_blocks_per_cu = nb;
+        if (nb < 1) return fail(FV_E_DEVICE, "engine kernel cannot be resident");
+        g_dev_info[dev] = d;
+        g_dev_known[dev] = true;
+    }
+    di = g_dev_info[dev];
     return FV_OK;
 }
 
@@ -573,9 +593,9 @@ fv_status run_batch(int32_t method, const fv_trans* models, const float* const* 
         a.free_stack = static_cast<int32_t*>(at(L.free_stack));
         // one engine block per CU: block 0 schedules, the others compute
         a.n_compute_blocks = n_compute;
-        a.spin_limit = (int64_t)1 << 24;
+        a.spin_limit = g_dbg_spin_limit ? g_dbg_spin_limit : (int64_t)1 << 24;
         // beam: exact re-decodes add at most one pass per subtask
-        a.max_steps = (meth == FV_BEAM ? 16 : 8) * (L.sum_T + L.n_tasks) + 4096;
+        a.max_steps = g_dbg_max_steps ? g_dbg_max_steps : (meth == FV_BEAM ? 16 : 8) * (L.sum_T + L.n_tasks) + 4096;
         if (validate) {
             a.bad_seq = bad_seq;
             a.bad_model = bad_model + p;
@@ -679,8 +699,28 @@ fv_status fv_profile_engine(int32_t enable) {
         HIP_TRY(hipEventCreate(&g_prof_ev[0]));
         HIP_TRY(hipEventCreate(&g_prof_ev[1]));
     }
+    if (!enable && g_prof_ev[0]) {
+        // the events are released here, not left to process teardown: wait
+        // for the last recorded pair, then destroy both
+        hipError_t e0 = hipEventSynchronize(g_prof_ev[1]);
+        hipError_t e1 = hipEventDestroy(g_prof_ev[0]);
+        hipError_t e2 = hipEventDestroy(g_prof_ev[1]);
+        g_prof_ev[0] = g_prof_ev[1] = nullptr;
+        g_prof_on = false;
+        g_prof_recorded = false;
+        for (hipError_t e : {e0, e1, e2})
+            if (e != hipSuccess) return fail(FV_E_DEVICE, "profiling events: %s", hipGetErrorString(e));
+        return FV_OK;
+    }
     g_prof_on = enable != 0;
     g_prof_recorded = false;
+    return FV_OK;
+}
+
+fv_status fv_debug_engine_limits(int64_t max_steps, int64_t spin_limit) {
+    if (max_steps < 0 || spin_limit < 0) return fail(FV_E_INVALID_ARG, "limits must be >= 0");
+    g_dbg_max_steps = max_steps;
+    g_dbg_spin_limit = spin_limit;
     return FV_OK;
 }
 

@@ -14,7 +14,7 @@ torch = pytest.importorskip("torch")
 @pytest.fixture(scope="module")
 def fv():
     if not torch.cuda.is_available():
-        pytest.skip("no GPU")
+        pytest.fail("GPU tests need a GPU")
     import paper_2510_19301_amd as m
     m.lib()
     return m
