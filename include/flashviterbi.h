@@ -164,6 +164,25 @@ fv_status fv_decode_flash(const fv_trans* A, const float* log_pi, const float* l
                           int32_t* status, uint32_t flags, void* ws, size_t ws_bytes,
                           fv_stream_t stream);
 
+/* fv_decode_flash without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Scratch comes from a fixed
+ * device array of FV_NOALLOC_SCRATCH_BYTES inside the library (one per GPU,
+ * held until the process ends); the call allocates nothing and enqueues the
+ * same kernels as fv_decode_flash, with the same result.  A decode needing
+ * more scratch than the array holds (fv_workspace_size(FV_FLASH, ...) >
+ * FV_NOALLOC_SCRATCH_BYTES; a K = 1024 sequence of T = 8000 at P = 64
+ * needs about 86 MB, K = 4096 at T = 1000 about 142 MB) returns
+ * FV_E_WORKSPACE with a message.  Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (other streams,
+ * other host threads) race and give unspecified results; calls on one
+ * stream are ordered and safe.  The engine's setup kernel re-initialises
+ * every field it reads, so no state carries over between calls. */
+#define FV_NOALLOC_SCRATCH_BYTES (128u << 20)
+fv_status fv_decode_flash_noalloc(const fv_trans* A, const float* log_pi, const float* log_b,
+                                  int64_t ld, int32_t T, int32_t P, int32_t* path, float* score,
+                                  int32_t* status, uint32_t flags, fv_stream_t stream);
+
 /* FLASH-BS (Sec. V-C): the FLASH task structure where every step keeps only
  * the B best states, ranked by (score desc, state asc).  B >= K behaves as
  * FLASH.  For B < K the result depends on P (each segment restarts its beam

@@ -46,6 +46,7 @@ SIGNATURES = {
     "fv_workspace_size": (_i32, [_i32, _P(FvTrans), _i32, _vp, _vp, _i32, _i32, _i32, _P(_sz)]),
     "fv_decode_vanilla": (_i32, [_P(FvTrans), _vp, _vp, _i64, _i32, _vp, _vp, _vp, _u32, _vp, _sz, _vp]),
     "fv_decode_flash": (_i32, [_P(FvTrans), _vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp, _u32, _vp, _sz, _vp]),
+    "fv_decode_flash_noalloc": (_i32, [_P(FvTrans), _vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp, _u32, _vp]),
     "fv_decode_beam": (_i32, [_P(FvTrans), _vp, _vp, _i64, _i32, _i32, _i32, _vp, _vp, _vp, _u32, _vp, _sz, _vp]),
     "fv_decode_batch": (_i32, [_P(FvTrans), _vp, _i32, _vp, _vp, _vp, _i32, _i32, _i32, _i32, _vp, _u32, _vp, _sz, _vp]),
     "fv_viterbi_backward": (_i32, [_i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _sz, _vp]),

@@ -88,6 +88,13 @@ fv_status fv_set_error(fv_status s, const char* fmt, ...) {
             return fail(FV_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));       \
     } while (0)
 
+// Fixed device scratch of fv_decode_flash_noalloc: every GPU the library
+// runs on holds one copy until the process ends.  Host code never passes
+// the array's name to a kernel (on the host it is only a stand-in for the
+// symbol): the device address comes from hipGetSymbolAddress, once per
+// device, and is kept in g_scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[FV_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 constexpr size_t kAlign = 256;
@@ -334,6 +341,25 @@ constexpr int kMaxDevices = 64;
 std::mutex g_dev_mutex;
 DeviceInfo g_dev_info[kMaxDevices];
 bool g_dev_known[kMaxDevices] = {};
+
+void* g_scratch_ptr[kMaxDevices] = {};
+
+fv_status scratch_address(void** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(FV_E_DEVICE, "device ordinal %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_dev_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(FV_E_DEVICE, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev,
+                        hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return FV_OK;
+}
 
 fv_status device_info(DeviceInfo& di) {
     int dev = 0;
@@ -773,6 +799,26 @@ fv_status fv_decode_flash(const fv_trans* A, const float* log_pi, const float* l
                           uint32_t flags, void* ws, size_t ws_bytes, fv_stream_t stream) {
     if (P <= 0 && T >= 1) P = auto_parallelism(&T, 1);
     return decode_one(FV_FLASH, A, log_pi, log_b, ld, T, P, 0, path, score, status, flags, ws, ws_bytes, stream);
+}
+
+fv_status fv_decode_flash_noalloc(const fv_trans* A, const float* log_pi, const float* log_b, int64_t ld,
+                                  int32_t T, int32_t P, int32_t* path, float* score, int32_t* status,
+                                  uint32_t flags, fv_stream_t stream) {
+    if (T < 1) return fail(FV_E_INVALID_ARG, "T must be >= 1 (got %d)", T);
+    if (P <= 0) P = auto_parallelism(&T, 1);
+    size_t need = 0;
+    fv_status rc = fv_workspace_size(FV_FLASH, A, 1, &T, nullptr, 1, P, 0, &need);
+    if (rc != FV_OK) return rc;
+    if (need > (size_t)FV_NOALLOC_SCRATCH_BYTES)
+        return fail(FV_E_WORKSPACE,
+                    "fv_decode_flash_noalloc: this decode needs %zu bytes of scratch; the fixed scratch holds %zu "
+                    "(use fv_decode_flash with a workspace)",
+                    need, (size_t)FV_NOALLOC_SCRATCH_BYTES);
+    void* ws = nullptr;
+    rc = scratch_address(&ws);
+    if (rc != FV_OK) return rc;
+    return decode_one(FV_FLASH, A, log_pi, log_b, ld, T, P, 0, path, score, status, flags, ws,
+                      (size_t)FV_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 fv_status fv_decode_beam(const fv_trans* A, const float* log_pi, const float* log_b, int64_t ld, int32_t T,
