@@ -271,6 +271,18 @@ fv_status fv_profile_engine_ms(float* ms);
  * values return FV_E_INVALID_ARG. */
 fv_status fv_debug_engine_limits(int64_t max_steps, int64_t spin_limit);
 
+/* Measurement hook: while set (steps > 0, host thread-local), persistent
+ * engine decodes issued by this thread record, for each of their first
+ * `steps` global steps, 16 words in trace[step * 16 ...] (device buffer,
+ * uint64): the step's start and the scheduler's end (real-time counter,
+ * 100 MHz ticks), the first and last compute block's end of work, the sum
+ * of all compute blocks' ends, the rows in flight (full | light << 21 |
+ * block rows << 42), the number of compute blocks that reported (word 6)
+ * and, in words 8..15, the last end on each XCD.  The caller zeroes the
+ * buffer except word 2 (set it to all ones) before each decode.  steps == 0
+ * turns it off. */
+fv_status fv_debug_engine_trace(unsigned long long* trace, int32_t steps);
+
 const char* fv_status_str(fv_status s);
 const char* fv_last_error(void);   /* thread-local message of the last failure */
 int32_t fv_abi_version(void);

@@ -56,6 +56,7 @@ SIGNATURES = {
     "fv_profile_engine": (_i32, [_i32]),
     "fv_profile_engine_ms": (_i32, [_P(_f)]),
     "fv_debug_engine_limits": (_i32, [_i64, _i64]),
+    "fv_debug_engine_trace": (_i32, [_vp, _i32]),
     "fv_status_str": (C.c_char_p, [_i32]),
     "fv_last_error": (C.c_char_p, []),
     "fv_abi_version": (_i32, []),

@@ -59,6 +59,8 @@ static thread_local bool g_prof_recorded = false;
 // step and barrier-wait limits for decodes issued by this host thread
 static thread_local int64_t g_dbg_max_steps = 0;
 static thread_local int64_t g_dbg_spin_limit = 0;
+static thread_local unsigned long long* g_dbg_trace = nullptr;
+static thread_local int32_t g_dbg_trace_steps = 0;
 
 static fv_status fail(fv_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 static fv_status fail(fv_status s, const char* fmt, ...) {
@@ -258,6 +260,7 @@ fv_status plan_dense(int32_t method, const fv_trans* A, const int32_t* T_host, i
     if (slots > (1 << 26)) return fail(FV_E_UNSUPPORTED, "too many concurrent sequences");
     L.n_slots = (int32_t)slots;
     L.pool = L.n_slots / kXcd;
+    if (L.pool > kMaxPool) return fail(FV_E_UNSUPPORTED, "too many rows in flight per XCD (%d)", L.pool);
     size_t cur = 0;
     put(cur, L.Ap, (!sparse && L.Kp != K) ? (size_t)L.Kp * L.Kp * 4 : 0);  // padded dense copy only when needed
     // transposed copy for the two-column items of moderate K
@@ -581,6 +584,7 @@ fv_status run_batch(int32_t method, const fv_trans* models, const float* const* 
         a.n_slots = L.n_slots;
         a.has_anc = L.has_anc;
         a.wide = wide ? 1 : 0;
+        a.slab = (!wide && !sparse && At && A->K == L.Kp && (L.Kp == 512 || L.Kp == 1024)) ? 1 : 0;
         // leaves are exact only with anchored starts: the paper's displayed
         // start restarts every bisection level, and so does the decode
         a.leaf_len = (L.leaves && !a.wide && !(flags & (FV_FLAG_NO_LEAVES | FV_FLAG_RELATIVE_INIT))) ? L.leaf_len
@@ -625,6 +629,10 @@ fv_status run_batch(int32_t method, const fv_trans* models, const float* const* 
         if (validate) {
             a.bad_seq = bad_seq;
             a.bad_model = bad_model + p;
+        }
+        if (g_dbg_trace && p == 0) {   // the first model's steps only
+            a.trace = g_dbg_trace;
+            a.trace_steps = g_dbg_trace_steps;
         }
 
         SetupArgs sa{};
@@ -740,6 +748,13 @@ fv_status fv_profile_engine(int32_t enable) {
     }
     g_prof_on = enable != 0;
     g_prof_recorded = false;
+    return FV_OK;
+}
+
+fv_status fv_debug_engine_trace(unsigned long long* trace, int32_t steps) {
+    if (steps < 0 || (steps > 0 && !trace)) return fail(FV_E_INVALID_ARG, "bad trace buffer");
+    g_dbg_trace = steps > 0 ? trace : nullptr;
+    g_dbg_trace_steps = steps;
     return FV_OK;
 }
 

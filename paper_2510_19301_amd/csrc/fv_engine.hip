@@ -254,8 +254,20 @@ struct QuarterLds {
     int32_t gitem[kQGroups];      // per group: the row it claimed
 };
 
+// Column slabs (dense local rows, K = Kp = 512 or 1024): a chunk of rows'
+// previous scores staged whole, one 64-bit partial key per output.
+constexpr int32_t kSlabMaxKp = 1024;
+constexpr int32_t kSlabChunkMax = kEngBlock / 64;   // rows of a chunk (16 at Kp = 1024, 8 at 512)
+struct SlabLds {
+    float d[kSlabChunkMax * kSlabMaxKp];
+    unsigned long long key[kEngBlock];
+    Row rows[kSlabChunkMax];
+    int32_t upass[kSlabChunkMax];   // column pass of each unit of the chunk
+};
+
 union EngineLds {
     TileLds tile;
+    SlabLds slab;
     WideLds wide;
     BeamLds beam;
     SpBeamLds spbeam;
@@ -269,10 +281,12 @@ constexpr int kSchedGroupWaves = kSchedGroup / 64;
 
 struct SchedLds {
     int32_t q_head, q_tail, max_rows;
+    int32_t total_next;        // rows of the step the last admission prepared
+    int32_t q_spawn;           // next free queue position while a step's rows spawn tasks
+    int32_t out_cnt[kXcd][4];  // per XCD: next rows written (full, light, beam), slots freed
     int32_t n_free[kXcd];
     int32_t nblk[kXcd];        // compute blocks on each XCD
     int32_t admit[kXcd];
-    int32_t spawn_total[kXcd];
     int32_t n_next[kXcd][3];   // rows written for the next step: full, light, beam
     int32_t wave_sums[kXcd][kSchedGroupWaves][5];
 };
@@ -893,6 +907,186 @@ __device__ __forceinline__ void col_item(cargs_t& a, const float* __restrict__ A
         if (lane == 0) key_max(&a.keys[L.rows[ro].seq], fkey);
     }
     __syncthreads();
+}
+
+// ---------------------------------------------------------------- column slabs
+// Local dense rows of a model with K = Kp = 512 or 1024 (KP).  Each block
+// keeps a slab of log A in registers for a whole column pass: lane l of wave
+// w holds A(i, j) for its destination j (one per lane) and the 64
+// predecessors i = 64 pw + k of its wave's share (pw = w mod KP/64), so a
+// pass covers 64 columns at KP = 1024 (16 waves over the predecessors) or
+// 128 at 512 (two sets of 8 waves).  A row's previous scores are read from
+// LDS four at a time with every lane of the wave at the same address (a
+// broadcast), so a candidate costs one add and half a three-input max.  Each
+// lane keeps, per row, the maximum of each group of 16 predecessors and the
+// first group reaching its running maximum; partials meet in a 64-bit LDS
+// atomic max (score in total order, then the complement of the group index,
+// so ties go to the earliest group).  The epilogue refines the winning group
+// from the transposed copy of log A exactly as a column item does.
+//
+// The work of a step on an XCD is nf rows x (KP^2 / 65536) column passes,
+// split evenly over the XCD's compute blocks by unit ranges (a unit = one
+// row in one pass, ordered pass-major), so every block gets the same number
+// of units to within one and loads at most two slabs.
+
+// Partial key of one row: the lane's 64 predecessors (its wave's share pw)
+// for its destination; dr = the row's previous scores from predecessor 64 pw.
+__device__ __forceinline__ unsigned long long slab_row_key(const float* dr, const float (&av)[64], int32_t pw) {
+    float best = -INFINITY;
+    int32_t bg = 0;
+    const float4* d4 = reinterpret_cast<const float4*>(dr);
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        float m = -INFINITY;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float4 v = d4[4 * g + q];   // the same address in every lane
+            m = fmaxf(fmaxf(m, v.x + av[16 * g + 4 * q]), v.y + av[16 * g + 4 * q + 1]);
+            m = fmaxf(fmaxf(m, v.z + av[16 * g + 4 * q + 2]), v.w + av[16 * g + 4 * q + 3]);
+        }
+        if (m > best) { best = m; bg = g; }
+    }
+    return ((unsigned long long)score_order(best) << 32) | (uint32_t)(0xffffffffu - (uint32_t)(pw * 4 + bg));
+}
+
+// One chunk of R units (u0 .., pass-major: unit u is row u mod nf of pass
+// u / nf) that may span column passes: rows loaded and scores staged once,
+// the slab reloaded where the pass changes, then one merge, refine and store
+// (the outputs of a column item).
+template <int KP>
+__device__ __forceinline__ void slab_chunk(cargs_t& a, gfloat_t* Ag, const Row* list, int32_t nf, int64_t u0,
+                                           int32_t R, float (&av)[64], int32_t& loaded) {
+    constexpr int32_t wpc = KP / 64, pcols = (kEngWaves / wpc) * 64;
+    SlabLds& L = g_lds.slab;
+    const int32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int32_t K = a.K;
+    const int32_t csl = w / wpc, pw = w - csl * wpc;
+    if (tid < R) {
+        const int64_t u = u0 + tid;
+        const int32_t p = (int32_t)(u / nf);
+        L.rows[tid] = ld_row(list + (int32_t)(u - (int64_t)p * nf));
+        L.upass[tid] = p;
+    }
+    L.key[tid] = 0ull;
+    __syncthreads();
+    {
+        constexpr int32_t q4 = KP / 4;
+        for (int32_t q = tid; q < R * q4; q += kEngBlock) {
+            const int32_t r = q / q4, i = (q - r * q4) * 4;
+            const Row& rr = L.rows[r];
+            const float* dp = slot_delta(a, clampi(rr.slot, a.n_slots), (rr.t - 1) & 1);
+            *reinterpret_cast<float4*>(&L.d[r * KP + i]) = *reinterpret_cast<const float4*>(dp + i);
+        }
+    }
+    const int32_t ro = tid / pcols;
+    const bool out_ok = ro < R;
+    const int32_t jo = (out_ok ? L.upass[ro] : 0) * pcols + (tid - ro * pcols);
+    float bpre = 0.0f;
+    if (out_ok) {
+        const Row& rr = L.rows[ro];
+        bpre = rr.log_b[(int64_t)rr.t * rr.ld + jo];
+    }
+    __syncthreads();
+    for (int32_t rc = 0; rc < R; ++rc) {
+        const int32_t p = L.upass[rc];   // block-uniform
+        if (p != loaded) {
+            gfloat_t* col = Ag + (int64_t)(pw * 64) * KP + p * pcols + csl * 64 + lane;
+#pragma unroll
+            for (int k = 0; k < 64; ++k) av[k] = col[k * KP];
+            loaded = p;
+        }
+        const unsigned long long k = slab_row_key(&L.d[rc * KP + pw * 64], av, pw);
+        __hip_atomic_fetch_max(&L.key[rc * pcols + csl * 64 + lane], k, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    __syncthreads();
+    unsigned long long fkey = 0;
+    if (out_ok) {
+        const Row& rr = L.rows[ro];
+        const int32_t t = rr.t, f = rr.flags, slot = clampi(rr.slot, a.n_slots);
+        const unsigned long long key = L.key[tid];
+        const float mv = score_from_order((uint32_t)(key >> 32));
+        float val = mv;
+        int32_t psi = 0;
+        if ((f & F_NEED_ARG) || mv == 0.0f) {
+            const int32_t gi = clampi((int32_t)(0xffffffffu - (uint32_t)key), KP / kGroup);
+            const int32_t src0 = gi * kGroup;
+            const float4* at4 = reinterpret_cast<const float4*>(a.At + (int64_t)jo * KP + src0);
+            float avr[kGroup];
+#pragma unroll
+            for (int k = 0; k < kGroup; k += 4) {
+                const float4 v = at4[k >> 2];
+                avr[k] = v.x; avr[k + 1] = v.y; avr[k + 2] = v.z; avr[k + 3] = v.w;
+            }
+            const float* sd = &L.d[ro * KP + src0];
+            int32_t q = -1;
+#pragma unroll
+            for (int k = 0; k < kGroup; ++k) {
+                const float x = sd[k] + avr[k];
+                if (q < 0 && x == mv) { q = src0 + k; val = x; }
+            }
+            psi = clampi(q < 0 ? src0 : q, K);
+        }
+        int32_t anc = 0;
+        if (f & F_ANC_FIRST) anc = psi;
+        else if (f & F_ANC_CHAIN) anc = clampi(slot_anc(a, slot, (t - 1) & 1)[psi], K);
+        const float dnew = val + bpre;
+        slot_delta(a, slot, t & 1)[jo] = dnew;
+        if (f & F_PSI_TABLE) a.psi16[rr.off + (int64_t)t * K + jo] = (uint16_t)psi;
+        if (f & F_LEAF_TABLE) slot_leaf(a, slot)[(int64_t)rr.aux * KP + jo] = (uint16_t)psi;
+        if (f & (F_ANC_FIRST | F_ANC_CHAIN)) slot_anc(a, slot, t & 1)[jo] = anc;
+        if (f & F_SNAP_SUB) slot_snap(a, slot)[jo] = dnew;
+        if (f & F_SNAP_ROOT) {
+            root_dsnap(a, rr.off, rr.aux)[jo] = dnew;
+            if (rr.aux >= 1) root_link(a, rr.off, rr.pp, rr.aux)[jo] = anc;
+        }
+        if (f & F_FINAL) fkey = order_key(dnew, jo);
+    }
+    // a wave holds 64 destinations of one row (wave-uniform test)
+    if (ro < R && (L.rows[ro].flags & F_FINAL)) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const unsigned long long o = __shfl_xor(fkey, off, 64);
+            if (o > fkey) fkey = o;
+        }
+        if (lane == 0) key_max(&a.keys[L.rows[ro].seq], fkey);
+    }
+    __syncthreads();
+}
+
+// This block's share of the dense rows of its XCD at one step (rank among the
+// XCD's nx compute blocks; the scheduler block, rank -1, takes none).  When
+// the blocks divide evenly over the column passes, each pass gets a team of
+// nx / npass blocks that split its rows, so no block loads two slabs; else
+// the units (row, pass), pass-major, are split evenly, and a chunk may span
+// two passes.
+template <int KP>
+__device__ __forceinline__ void slab_items_kp(cargs_t& a, const float* __restrict__ Ap, int32_t nx, int32_t rank,
+                                              const Row* list, int32_t nf) {
+    constexpr int32_t wpc = KP / 64, pcols = (kEngWaves / wpc) * 64;
+    constexpr int32_t npass = KP / pcols, crows = kEngBlock / pcols;
+    int64_t u, u1;
+    if (nx % npass == 0) {
+        const int32_t team = nx / npass, p = rank / team, m = rank - p * team;
+        u = (int64_t)p * nf + ((int64_t)m * nf) / team;
+        u1 = (int64_t)p * nf + ((int64_t)(m + 1) * nf) / team;
+    } else {
+        const int64_t U = (int64_t)nf * npass;
+        u = U * rank / nx;
+        u1 = U * (rank + 1) / nx;
+    }
+    gfloat_t* Ag = as_global(Ap);
+    float av[64];
+    int32_t loaded = -1;
+    for (; u < u1; u += crows) slab_chunk<KP>(a, Ag, list, nf, u, (int32_t)min((int64_t)crows, u1 - u), av, loaded);
+}
+
+__device__ __forceinline__ void slab_items(cargs_t& a_in, const float* __restrict__ Ap, int32_t nx, int32_t rank,
+                                           const Row* list, int32_t nf) {
+    cargs_t& a = uniform_args(a_in);
+    if (rank < 0 || nf <= 0 || nx <= 0) return;
+    if (a.Kp == 1024) slab_items_kp<1024>(a, Ap, nx, rank, list, nf);
+    else slab_items_kp<512>(a, Ap, nx, rank, list, nf);
 }
 
 // ---------------------------------------------------------------- sparse rows
@@ -2435,7 +2629,7 @@ __device__ void group_scan(int32_t (&v)[N], int32_t (&tot)[N], int32_t (&ws)[kSc
 // (beam tasks to the beam list, the others to the light list).  Called by
 // the whole scheduler block; sl.n_next holds the rows already written for
 // step nxt.
-__device__ __noinline__ void admit(cargs_t& a_in, int nxt) {
+__device__ __noinline__ void admit(cargs_t& a_in, int nxt, uint32_t tag) {
     cargs_t& a = uniform_args(a_in);
     SchedLds& sl = g_sched;
     if (threadIdx.x == 0) {
@@ -2474,18 +2668,28 @@ __device__ __noinline__ void admit(cargs_t& a_in, int nxt) {
     }
     __syncthreads();
     const int x = threadIdx.x / kSchedGroup, tg = threadIdx.x % kSchedGroup;
-    int32_t qbase = sl.q_head;
-    for (int y = 0; y < x; ++y) qbase += sl.admit[y];
+    // the admitted tasks are dealt round-robin over the XCDs in queue order:
+    // XCD x's k-th task is batch entry sum_y min(admit[y], k) + #{y < x :
+    // admit[y] > k}, so consecutive (similar) tasks land on different XCDs
+    int32_t qa[kXcd];
+#pragma unroll
+    for (int y = 0; y < kXcd; ++y) qa[y] = sl.admit[y];
+    auto dealt = [&](int32_t k) -> int32_t {
+        int32_t pos = sl.q_head;
+#pragma unroll
+        for (int y = 0; y < kXcd; ++y) pos += min(qa[y], k) + ((y < x && qa[y] > k) ? 1 : 0);
+        return pos;
+    };
     const int32_t ax = sl.admit[x];
-    // this thread's tasks: a contiguous range, so list order follows the queue
+    // this thread's tasks: a contiguous range, so list order follows the deal
     const int32_t per = (ax + kSchedGroup - 1) / kSchedGroup;
     const int32_t lo = min(ax, tg * per), hi = min(ax, lo + per);
     int32_t c[3] = {0, 0, 0}, tot[3];
-    for (int32_t k = lo; k < hi; ++k) c[start_list(a, a.queue[qbase + k].kind)]++;
+    for (int32_t k = lo; k < hi; ++k) c[start_list(a, a.queue[dealt(k)].kind)]++;
     group_scan<3>(c, tot, sl.wave_sums[x]);
     Row* out[3] = {list_full(a, nxt, x), list_light(a, nxt, x), list_beam(a, nxt, x)};
     for (int32_t k = lo; k < hi; ++k) {
-        const Task tk = a.queue[qbase + k];
+        const Task tk = a.queue[dealt(k)];
         const int32_t slot = a.free_stack[(int64_t)x * a.pool + sl.n_free[x] - 1 - k];
         const Row r = row_from_task(a, tk, slot);
         const int32_t li = start_list(a, tk.kind);
@@ -2511,63 +2715,59 @@ __device__ __noinline__ void admit(cargs_t& a_in, int nxt) {
         }
         st_c(&a.st->wclaim[nxt][0], 0);
         st_c(&a.st->total[nxt], all);
+        for (int y = 0; y < kXcd; ++y)
+            st_c(&a.st->cntw[y][0], pack_counts(tag, all == 0, sl.n_next[y][0], sl.n_next[y][1], sl.n_next[y][2]));
+        sl.total_next = all;
         if (all > sl.max_rows) sl.max_rows = all;
         st_c(&a.st->max_rows, sl.max_rows);
     }
     __syncthreads();
 }
 
-__device__ __noinline__ void scheduler(cargs_t& a_in, int32_t s) {
+// One pass over this step's rows of each XCD (a 128-thread group per XCD):
+// each row is loaded once, classified, and its successor row, freed slot and
+// spawned tasks take their positions from LDS counters.  The order of the
+// next lists, of the free stack and of the spawned tasks then depends on
+// timing; no result does (every row and task is computed on its own).
+__device__ __noinline__ void scheduler(cargs_t& a_in, int32_t s, uint32_t tag) {
     cargs_t& a = uniform_args(a_in);
     SchedLds& sl = g_sched;
     const int cur = s & 1, nxt = cur ^ 1;
     const int x = threadIdx.x / kSchedGroup, tg = threadIdx.x % kSchedGroup;
-    const int32_t nf = ld_c(&a.st->cnt[cur][x][0]);
-    const int32_t nl = ld_c(&a.st->cnt[cur][x][1]);
-    const int32_t nbm = ld_c(&a.st->cnt[cur][x][2]);
+    // this step's counts: the previous admission left them in LDS
+    const int32_t nf = sl.n_next[x][0];
+    const int32_t nl = sl.n_next[x][1];
+    const int32_t nbm = sl.n_next[x][2];
+    __syncthreads();
+    if (tg < 4) sl.out_cnt[x][tg] = 0;   // full, light, beam, freed
+    if (threadIdx.x == 0) sl.q_spawn = sl.q_tail;
+    __syncthreads();
     const int32_t total = nf + nl + nbm;
-    const int32_t per = (total + kSchedGroup - 1) / kSchedGroup;
-    const int32_t lo = min(total, tg * per), hi = min(total, lo + per);
     const Row* lists[3] = {list_full(a, cur, x), list_light(a, cur, x), list_beam(a, cur, x)};
     Row* out[3] = {list_full(a, nxt, x), list_light(a, nxt, x), list_beam(a, nxt, x)};
-
-    // pass 0 counts what the group's rows turn into, pass 1 writes it
-    int32_t cnt[5] = {0, 0, 0, 0, 0}, tot[5] = {0, 0, 0, 0, 0};  // full, light, beam, freed, spawned
-    for (int pass = 0; pass < 2; ++pass) {
-        if (pass == 1) {
-            group_scan<5>(cnt, tot, sl.wave_sums[x]);
-            if (tg == 0) sl.spawn_total[x] = tot[4];
-            __syncthreads();
-            int32_t qoff = sl.q_tail;
-            for (int y = 0; y < x; ++y) qoff += sl.spawn_total[y];
-            cnt[4] += qoff;
+    for (int32_t i = tg; i < total; i += kSchedGroup) {
+        const int src = i < nf ? 0 : (i < nf + nl ? 1 : 2);
+        const int32_t k = src == 0 ? i : (src == 1 ? i - nf : i - nf - nl);
+        const Row r = ld_row(lists[src] + k);
+        const Next n = classify(a, r, src);
+        if (n.list >= 0) {
+            const int32_t pos = atomicAdd(&sl.out_cnt[x][n.list], 1);
+            st_row(out[n.list] + pos, n.row);
         }
-        for (int32_t i = lo; i < hi; ++i) {
-            const int src = i < nf ? 0 : (i < nf + nl ? 1 : 2);
-            const int32_t k = src == 0 ? i : (src == 1 ? i - nf : i - nf - nl);
-            const Row r = ld_row(lists[src] + k);
-            const Next n = classify(a, r, src);
-            if (pass == 0) {
-                if (n.list >= 0) cnt[n.list]++;
-                cnt[3] += n.freed;
-                cnt[4] += n.spawn;
-            } else {
-                if (n.list >= 0) st_row(out[n.list] + cnt[n.list]++, n.row);
-                if (n.freed) a.free_stack[(int64_t)x * a.pool + sl.n_free[x] + cnt[3]++] = r.slot;
-                if (n.spawn) { write_spawns(a, r, src, (int64_t)cnt[4]); cnt[4] += n.spawn; }
-            }
+        if (n.freed) {
+            const int32_t pos = atomicAdd(&sl.out_cnt[x][3], 1);
+            a.free_stack[(int64_t)x * a.pool + sl.n_free[x] + pos] = r.slot;
         }
+        if (n.spawn) write_spawns(a, r, src, (int64_t)atomicAdd(&sl.q_spawn, n.spawn));
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int y = 0; y < kXcd; ++y) sl.q_tail += sl.spawn_total[y];
-    }
+    if (threadIdx.x == 0) sl.q_tail = sl.q_spawn;
     if (tg == 0) {
-        sl.n_free[x] += tot[3];
-        for (int k = 0; k < 3; ++k) sl.n_next[x][k] = tot[k];
+        sl.n_free[x] += sl.out_cnt[x][3];
+        for (int k = 0; k < 3; ++k) sl.n_next[x][k] = sl.out_cnt[x][k];
     }
     __syncthreads();
-    admit(a, nxt);
+    admit(a, nxt, tag);
 }
 
 // ---------------------------------------------------------------- step barrier
@@ -2591,8 +2791,13 @@ __device__ __forceinline__ void step_release(bool wide) {
 }
 __device__ __forceinline__ void step_acquire(bool) { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 
-__device__ bool barrier_arrive_wait(cargs_t& a, uint32_t epoch, uint32_t x) {
+// The wait also returns the counts word the scheduler published for the
+// step after this barrier (tagged with this epoch; both words are polled
+// together, so the counts need no load of their own after the release).
+__device__ bool barrier_arrive_wait(cargs_t& a, uint32_t epoch, uint32_t x, unsigned long long& counts,
+                                    bool with_counts = true) {
     __shared__ int s_err;
+    __shared__ unsigned long long s_counts;
     __syncthreads();
     if (threadIdx.x == 0) {
         const bool wide = a.wide != 0;
@@ -2600,15 +2805,22 @@ __device__ bool barrier_arrive_wait(cargs_t& a, uint32_t epoch, uint32_t x) {
         st_c(a.arrive + blockIdx.x, epoch);
         int err = 0;
         int64_t spins = 0;
-        while (ld_c(&a.st->go[x][0]) < epoch) {
+        const unsigned long long want = (unsigned long long)(epoch & kTagMask);
+        unsigned long long cw = 0;
+        for (;;) {
+            const uint32_t g = ld_c(&a.st->go[x][0]);
+            cw = ld_c(&a.st->cntw[x][0]);
+            if (g >= epoch && (!with_counts || (cw >> kTagShift) == want)) break;
             __builtin_amdgcn_s_sleep(1);
             if (++spins > a.spin_limit) { st_c(&a.st->error, 1); err = 1; break; }
             if ((spins & 255) == 0 && ld_c(&a.st->error)) { err = 1; break; }
         }
         step_acquire(wide);
         s_err = err || ld_c(&a.st->error) != 0;
+        s_counts = cw;
     }
     __syncthreads();
+    counts = s_counts;
     return s_err == 0;
 }
 
@@ -2736,14 +2948,11 @@ __device__ __forceinline__ void local_col_items(cargs_t& a_in, uint32_t x, int32
 // beam rows, one per block.  Each phase hands items out from a per-XCD
 // counter; every block (and the scheduler block once its own work is done)
 // takes a first item by rank, then claims until none are left.
-template <bool WIDE>
+template <bool WIDE, bool SLAB>
 __device__ void run_units(cargs_t& a, const float* __restrict__ Ap, uint32_t x, int32_t nx, int32_t rank,
-                          int cur) {
+                          int cur, int32_t nf, int32_t nl, int32_t nbm) {
     EngineLds& lds = g_lds;
     __shared__ int32_t s_unit;
-    const int32_t nf = ld_c(&a.st->cnt[cur][x][0]);
-    const int32_t nl = ld_c(&a.st->cnt[cur][x][1]);
-    const int32_t nbm = ld_c(&a.st->cnt[cur][x][2]);
     // few rows on this XCD: lane tiles would run mostly empty, so its rows are
     // computed as column items (lanes = destinations) by its own blocks
     const bool local_cols = !WIDE && !a.sparse && nf > 0 && nf <= kLocalColRows;
@@ -2773,7 +2982,11 @@ __device__ void run_units(cargs_t& a, const float* __restrict__ Ap, uint32_t x, 
             item = -1;
         }
     }
-    if (local_cols) local_col_items(a, x, nx, rank, cur, nf);
+    if constexpr (SLAB) {
+        if (local_cols) slab_items(a, Ap, nx, rank, list_full(a, cur, x), nf);
+    } else {
+        if (local_cols) local_col_items(a, x, nx, rank, cur, nf);
+    }
     // waves per tile: 4 (one per SIMD) while every group gets two tiles or
     // more, else more waves per tile (fewer, faster groups); at most one wave
     // per 16 predecessors.  Decided from a nominal XCD of 32 blocks, so that
@@ -2862,7 +3075,7 @@ __device__ void run_units(cargs_t& a, const float* __restrict__ Ap, uint32_t x, 
 // Every step of one model's decode (its own state, lists and buffers),
 // specialised for wide or local rows: each step loop inlines its own per-step
 // work function, so no call saves registers at every step.
-template <bool WIDE>
+template <bool WIDE, bool SLAB>
 __device__ __noinline__ void engine_model(cargs_t& a_in) {
     cargs_t& a = uniform_args(a_in);
     const float* __restrict__ Ap = a.Acol;
@@ -2874,7 +3087,9 @@ __device__ __noinline__ void engine_model(cargs_t& a_in) {
                           : (int32_t)__hip_atomic_fetch_add(&a.st->xcd_blocks[x][0], 1u, __ATOMIC_RELAXED,
                                                             __HIP_MEMORY_SCOPE_SYSTEM);
     uint32_t epoch = 1;
-    bool ok = is_sched ? barrier_master(a, epoch) : barrier_arrive_wait(a, epoch, x);
+    unsigned long long cw = 0;   // counts word of the coming step (compute blocks)
+    // the first barrier publishes no counts (the first admission follows it)
+    bool ok = is_sched ? barrier_master(a, epoch) : barrier_arrive_wait(a, epoch, x, cw, false);
     const int32_t rank = s_rank;
     const int32_t nx = (int32_t)ld_c(&a.st->xcd_blocks[x][0]);
 
@@ -2891,23 +3106,58 @@ __device__ __noinline__ void engine_model(cargs_t& a_in) {
             }
         }
         __syncthreads();
-        if (ok) admit(a, 0);
+        if (ok) admit(a, 0, epoch + 1);
     }
     ++epoch;
-    if (ok) ok = is_sched ? barrier_master(a, epoch) : barrier_arrive_wait(a, epoch, x);
+    if (ok) ok = is_sched ? barrier_master(a, epoch) : barrier_arrive_wait(a, epoch, x, cw);
 
     int32_t s = 0;
     for (; ok; ++s) {
         const int cur = s & 1;
-        if (ld_c(&a.st->total[cur]) == 0) break;
+        // this step's counts on this XCD, and whether any row is left anywhere
+        int32_t nf, nl, nbm;
+        bool done;
+        if (is_sched) {
+            SchedLds& sl = g_sched;
+            nf = sl.n_next[x][0]; nl = sl.n_next[x][1]; nbm = sl.n_next[x][2];
+            done = sl.total_next == 0;
+            __syncthreads();   // read before the scheduler rewrites them
+        } else {
+            nf = (int32_t)(cw & 0x3fff); nl = (int32_t)((cw >> 14) & 0x3fff); nbm = (int32_t)((cw >> 28) & 0x3fff);
+            done = ((cw >> 42) & 1) != 0;
+        }
+        if (done) break;
         if (s > a.max_steps) {  // schedule longer than any valid one: report, stop
             if (is_sched && threadIdx.x == 0) st_c(&a.st->error, 2);
             break;
         }
-        if (is_sched) scheduler(a, s);
-        run_units<WIDE>(a, Ap, x, nx, rank, cur);
+        unsigned long long* tr = (a.trace && s < a.trace_steps) ? a.trace + (int64_t)s * kTraceWords : nullptr;
+        if (tr && is_sched && threadIdx.x == 0) {
+            tr[TR_START] = __builtin_amdgcn_s_memrealtime();
+            int32_t nf = 0, nl = 0, nb = 0;
+            for (int y = 0; y < kXcd; ++y) {
+                nf += ld_c(&a.st->cnt[cur][y][0]);
+                nl += ld_c(&a.st->cnt[cur][y][1]);
+                nb += ld_c(&a.st->cnt[cur][y][2]);
+            }
+            tr[TR_ROWS] = (unsigned long long)nf | ((unsigned long long)nl << 21) | ((unsigned long long)nb << 42);
+        }
+        if (is_sched) scheduler(a, s, epoch + 1);
+        if (tr && is_sched && threadIdx.x == 0) tr[TR_SCHED] = __builtin_amdgcn_s_memrealtime();
+        run_units<WIDE, SLAB>(a, Ap, x, nx, rank, cur, nf, nl, nbm);
+        if (tr && !is_sched) {
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                const unsigned long long now = __builtin_amdgcn_s_memrealtime();
+                __hip_atomic_fetch_min(&tr[TR_END_MIN], now, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_max(&tr[TR_END_MAX], now, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(&tr[TR_END_SUM], now, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(&tr[TR_NBLK], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_max(&tr[TR_XCD_END + x], now, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
         ++epoch;
-        ok = is_sched ? barrier_master(a, epoch) : barrier_arrive_wait(a, epoch, x);
+        ok = is_sched ? barrier_master(a, epoch) : barrier_arrive_wait(a, epoch, x, cw);
     }
     if (is_sched && threadIdx.x == 0) st_c(&a.st->steps, s);
 }
@@ -2919,8 +3169,9 @@ extern "C" __global__ __launch_bounds__(kEngBlock) void fv_engine_kernel(const E
     for (int32_t mi = 0; mi < n_models; ++mi) {
         __syncthreads();
         cargs_t& a = *reinterpret_cast<cargs_t*>(reinterpret_cast<uint64_t>(table + mi));
-        if (a.wide) engine_model<true>(a);
-        else engine_model<false>(a);
+        if (a.wide) engine_model<true, false>(a);
+        else if (a.slab) engine_model<false, true>(a);
+        else engine_model<false, false>(a);
     }
 }
 
@@ -3795,6 +4046,42 @@ extern "C" __global__ __launch_bounds__(kBlock) void fv_setup_kernel(EngineArgs 
         }
         if (has) a.queue[n_tasks + scan[0][tid] - 1] = Task{b, sa.kind, 0, a.seqs[b].T - 1};
         n_tasks += (int32_t)scan[0][kBlock - 1];
+        __syncthreads();
+    }
+    // longest tasks first (ties by sequence index), when they fit one LDS sort:
+    // together with the round-robin admission this spreads the lengths, and
+    // so the rows over time, evenly over the XCDs (any order gives the same
+    // results)
+    constexpr int32_t kSortMax = 4096;
+    if (n_tasks > 1 && n_tasks <= kSortMax) {
+        __shared__ unsigned long long skey[kSortMax];
+        int32_t n2 = 1;
+        while (n2 < n_tasks) n2 <<= 1;
+        for (int32_t k = tid; k < n2; k += kBlock) {
+            unsigned long long key = ~0ull;
+            if (k < n_tasks) {
+                const Task tk = a.queue[k];
+                key = ((unsigned long long)(uint32_t)(0x7fffffff - (tk.n - tk.m)) << 32) | (uint32_t)tk.seq;
+            }
+            skey[k] = key;
+        }
+        __syncthreads();
+        for (int32_t k = 2; k <= n2; k <<= 1) {
+            for (int32_t h = k >> 1; h > 0; h >>= 1) {
+                for (int32_t i = tid; i < n2; i += kBlock) {
+                    const int32_t l = i ^ h;
+                    if (l > i) {
+                        const unsigned long long u = skey[i], v = skey[l];
+                        if ((u > v) == ((i & k) == 0)) { skey[i] = v; skey[l] = u; }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (int32_t k = tid; k < n_tasks; k += kBlock) {
+            const int32_t b = (int32_t)(uint32_t)skey[k];
+            a.queue[k] = Task{b, sa.kind, 0, a.seqs[b].T - 1};
+        }
         __syncthreads();
     }
     // local sequences the setup never reached (fewer members than the host counted)

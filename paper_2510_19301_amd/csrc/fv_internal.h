@@ -135,7 +135,25 @@ struct EngineState {
     uint32_t xcd_blocks[kXcd][kLine];  // compute blocks per XCD (counted at start)
     int32_t claim[2][kXcd][kLine];     // [parity][xcd] next unclaimed work unit of a step
     int32_t wclaim[2][kLine];          // [parity] next unclaimed wide item of a step
+    // a step's row counts of each XCD, tagged with the epoch of the barrier
+    // that publishes them (see pack_counts), so that a block waiting at that
+    // barrier receives them with its release flag
+    unsigned long long cntw[kXcd][kLine / 2];
 };
+
+// Counts word: tag (20 bits: the publishing barrier's epoch; only the
+// previous epoch's word can be stale, so the wrap is harmless) | done (no
+// rows anywhere) | block rows | light rows | full rows (14 bits each; rows
+// per XCD are at most the slots per XCD, kMaxPool).
+constexpr uint32_t kTagMask = 0xfffffu;
+constexpr int kTagShift = 43;
+constexpr int32_t kMaxPool = 16383;
+inline __host__ __device__ unsigned long long pack_counts(uint32_t tag, bool done, int32_t nf, int32_t nl,
+                                                          int32_t nb) {
+    return ((unsigned long long)(tag & kTagMask) << kTagShift) | ((unsigned long long)(done ? 1 : 0) << 42) |
+           ((unsigned long long)(nb & 0x3fff) << 28) | ((unsigned long long)(nl & 0x3fff) << 14) |
+           (unsigned long long)(nf & 0x3fff);
+}
 
 // Everything the persistent engine needs (one model).
 struct EngineArgs {
@@ -158,6 +176,7 @@ struct EngineArgs {
     int32_t n_slots;            // multiple of kXcd
     int32_t has_anc;            // slots carry anc[2] + snap
     int32_t wide;               // wide rows: every block takes a column slice of every dense row
+    int32_t slab;               // local dense rows as column slabs (K = Kp = 512 or 1024)
     int32_t leaf_len;           // subtasks of at most this many steps are leaves (0: none)
     int32_t beam_q;             // beam rows run four to a block (dense, one part, small K and B)
     int32_t relative_init;      // subtask starts drop the carried score (FV_FLAG_RELATIVE_INIT)
@@ -194,7 +213,19 @@ struct EngineArgs {
     // input validation (FV_FLAG_VALIDATE): null when not requested
     const int32_t* bad_seq;     // [caller's n_seqs] nonzero: NaN or +inf in that sequence's log B
     const int32_t* bad_model;   // nonzero: NaN or +inf in this model's log A or log pi
+    // measurement (fv_debug_engine_trace): per-step timestamps, or null
+    unsigned long long* trace;  // [trace_steps][kTraceWords]
+    int32_t trace_steps;
 };
+
+// Per-step trace words (real-time counter ticks, 100 MHz): the step's start
+// as the scheduler block leaves the barrier, the scheduler's end, the first
+// and last compute block's end of work, the sum of all compute blocks' ends,
+// the step's row counts (full, light, block rows) packed in one word, the
+// number of compute blocks that reported, and each XCD's last end.
+constexpr int kTraceWords = 16;
+enum { TR_START = 0, TR_SCHED = 1, TR_END_MIN = 2, TR_END_MAX = 3, TR_END_SUM = 4, TR_ROWS = 5, TR_NBLK = 6,
+       TR_XCD_END = 8 };   // words 8..15: the last compute block's end on each XCD
 
 // Arguments of the per-call setup kernel (per-sequence layout, first row list).
 struct SetupArgs {
