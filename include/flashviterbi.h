@@ -104,6 +104,16 @@ enum { FV_FLAG_NO_LEAVES = 1u << 3 };
  * with a CSR model the call returns FV_E_UNSUPPORTED.  Vanilla decoding
  * ignores it. */
 enum { FV_FLAG_RELATIVE_INIT = 1u << 4 };
+/* Kernel choices for tuning; none changes a result.  Dense rows kept on
+ * their XCD normally run as column slabs (K = 512 or 1024: a block holds 64
+ * columns of log A in registers), else as column items (rows' scores in LDS,
+ * two destinations per lane) while an XCD holds at most 160 rows, else as
+ * lane tiles (lanes = rows, log A as wave-uniform scalars).
+ * FV_FLAG_STEP_ITEMS takes column items instead of slabs; FV_FLAG_STEP_TILES
+ * takes lane tiles for any number of rows (they exclude each other).
+ * FV_FLAG_ENGINE decodes vanilla and FLASH on a small dense model (K <= 256)
+ * with the persistent engine instead of one block per sequence. */
+enum { FV_FLAG_STEP_ITEMS = 1u << 5, FV_FLAG_STEP_TILES = 1u << 6, FV_FLAG_ENGINE = 1u << 7 };
 enum { FV_VANILLA = 0, FV_FLASH = 1, FV_BEAM = 2 };
 
 /* Transition model.  FV_DENSE: log_a[K*K] (device).  FV_CSR: out-edges of

@@ -16,6 +16,7 @@ FV_W_BEAM_FALLBACK = 1
 FV_DENSE, FV_CSR = 0, 1
 FV_FLAG_WIDE_ROWS, FV_FLAG_LOCAL_ROWS, FV_FLAG_VALIDATE, FV_FLAG_NO_LEAVES = 1, 2, 4, 8
 FV_FLAG_RELATIVE_INIT = 16
+FV_FLAG_STEP_ITEMS, FV_FLAG_STEP_TILES, FV_FLAG_ENGINE = 32, 64, 128
 FV_VANILLA, FV_FLASH, FV_BEAM = 0, 1, 2
 METHODS = {"vanilla": FV_VANILLA, "flash": FV_FLASH, "beam": FV_BEAM}
 

@@ -121,6 +121,8 @@ struct DenseLayout {
     int32_t sparse = 0;
     int64_t nnz = 0;
     int32_t leaves = 0;          // slots carry a leaf backpointer table
+    int32_t wsplit = 0;          // FLASH subtasks split kWSplit ways (slots carry division copies)
+    int64_t div_off = 0;         // their offset in a slot, in floats
     int32_t leaf_len = 0;        // the longest leaf that can occur (table rows per slot)
     int64_t leaf_off = 0;        // its offset in a slot, in floats
     int64_t leaf_tasks = 0;      // task-tree nodes when leaves end the bisection (slot sizing)
@@ -240,6 +242,15 @@ fv_status plan_dense(int32_t method, const fv_trans* A, const int32_t* T_host, i
     L.slot_floats = (int64_t)L.Kp * (method == FV_VANILLA ? 2 : 5);
     L.leaf_off = 5 * (int64_t)L.Kp;
     if (L.leaves) L.slot_floats += (int64_t)L.leaf_len * L.Kp / 2;
+    // FLASH above the leaf limit on wide rows (the default placement there):
+    // w-way subtasks, their division copies (kWSplit - 1 delta rows and
+    // kWSplit - 2 link rows) in each slot
+    L.wsplit = (method == FV_FLASH && !sparse && L.Kp > kLeafMaxKp && use_wide_rows(0, K, n_seqs, sparse)) ? kWSplit
+                                                                                                          : 0;
+    if (L.wsplit) {
+        L.div_off = L.slot_floats;
+        L.slot_floats += (int64_t)(2 * kWSplit - 3) * L.Kp;
+    }
     if (beam) L.slot_floats = std::max<int64_t>(L.slot_floats, (2 * (int64_t)L.bw + 1) * L.brec);
     // a beam subtask may be queued twice (its exact re-decode)
     L.q_cap = std::max<int64_t>(1, beam ? 2 * L.n_tasks : L.n_tasks);
@@ -475,8 +486,10 @@ fv_status check_flags(uint32_t flags, int32_t method, const fv_trans* models, in
     if ((flags & FV_FLAG_WIDE_ROWS) && (flags & FV_FLAG_LOCAL_ROWS))
         return fail(FV_E_INVALID_ARG, "FV_FLAG_WIDE_ROWS and FV_FLAG_LOCAL_ROWS exclude each other");
     if (flags & ~(uint32_t)(FV_FLAG_WIDE_ROWS | FV_FLAG_LOCAL_ROWS | FV_FLAG_VALIDATE | FV_FLAG_NO_LEAVES |
-                            FV_FLAG_RELATIVE_INIT))
+                            FV_FLAG_RELATIVE_INIT | FV_FLAG_STEP_ITEMS | FV_FLAG_STEP_TILES | FV_FLAG_ENGINE))
         return fail(FV_E_INVALID_ARG, "unknown flags 0x%x", flags);
+    if ((flags & FV_FLAG_STEP_ITEMS) && (flags & FV_FLAG_STEP_TILES))
+        return fail(FV_E_INVALID_ARG, "FV_FLAG_STEP_ITEMS and FV_FLAG_STEP_TILES exclude each other");
     if ((flags & FV_FLAG_RELATIVE_INIT) && method != FV_VANILLA)
         for (int32_t m = 0; models && m < n_models; ++m)
             if (models[m].kind == FV_CSR)
@@ -584,12 +597,19 @@ fv_status run_batch(int32_t method, const fv_trans* models, const float* const* 
         a.n_slots = L.n_slots;
         a.has_anc = L.has_anc;
         a.wide = wide ? 1 : 0;
-        a.slab = (!wide && !sparse && At && A->K == L.Kp && (L.Kp == 512 || L.Kp == 1024)) ? 1 : 0;
+        a.slab = (!wide && !sparse && At && A->K == L.Kp && (L.Kp == 512 || L.Kp == 1024) &&
+                  !(flags & (FV_FLAG_STEP_ITEMS | FV_FLAG_STEP_TILES))) ? 1 : 0;
+        a.force_tiles = (flags & FV_FLAG_STEP_TILES) ? 1 : 0;
         // leaves are exact only with anchored starts: the paper's displayed
         // start restarts every bisection level, and so does the decode
         a.leaf_len = (L.leaves && !a.wide && !(flags & (FV_FLAG_NO_LEAVES | FV_FLAG_RELATIVE_INIT))) ? L.leaf_len
                                                                                                       : 0;
         a.relative_init = (flags & FV_FLAG_RELATIVE_INIT) ? 1 : 0;
+        // w-way subtasks on wide rows only; the paper's bisection under
+        // FV_FLAG_NO_LEAVES, and under the relative start (whose result
+        // depends on the schedule)
+        a.wsplit = (L.wsplit && wide && !(flags & (FV_FLAG_NO_LEAVES | FV_FLAG_RELATIVE_INIT))) ? L.wsplit : 0;
+        a.div_off = L.div_off;
         a.beam_q = (meth == FV_BEAM && !sparse && L.bw == 1 && L.Kp <= 2048 && L.B <= 256) ? 1 : 0;
         a.leaf_off = L.leaf_off;
         if (sparse) {
@@ -659,7 +679,7 @@ fv_status run_batch(int32_t method, const fv_trans* models, const float* const* 
     if (g_prof_on) HIP_TRY(hipEventRecord(g_prof_ev[0], stream));
     // vanilla or FLASH decodes whose models are all small and dense: one wave per sequence, one
     // launch per model, no persistent engine
-    bool small = true;
+    bool small = !(flags & FV_FLAG_ENGINE);
     for (size_t p = 0; p < bp.L.size(); ++p) {
         const int32_t Kp_ = bp.L[p].K;
         small = small && models[bp.model[p]].kind == FV_DENSE &&

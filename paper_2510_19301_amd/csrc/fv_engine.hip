@@ -142,6 +142,16 @@ __device__ __forceinline__ uint16_t* slot_leaf(cargs_t& a, int32_t slot) {
 __device__ __forceinline__ bool is_leaf(cargs_t& a, int32_t kind, int32_t m, int32_t n) {
     return kind == KIND_SUB && a.leaf_len > 0 && n - m + 1 <= a.leaf_len;
 }
+// Division copies of a w-way subtask in its slot: delta at e_k (k < kWSplit - 1),
+// then the chain links at e_k (k >= 1: the state at e_{k-1} on the best path
+// into each state at e_k).
+__device__ __forceinline__ float* slot_div_d(cargs_t& a, int32_t slot, int32_t k) {
+    return a.slot_base + (int64_t)slot * a.slot_floats + a.div_off + (int64_t)k * a.Kp;
+}
+__device__ __forceinline__ int32_t* slot_div_l(cargs_t& a, int32_t slot, int32_t k) {
+    return reinterpret_cast<int32_t*>(a.slot_base + (int64_t)slot * a.slot_floats + a.div_off +
+                                      (int64_t)(kWSplit - 2 + k) * a.Kp);
+}
 __device__ __forceinline__ float* root_dsnap(cargs_t& a, int64_t root_off, int32_t d) {
     return a.root_copy + (root_off + d) * (int64_t)a.Kp;
 }
@@ -296,7 +306,7 @@ static __shared__ SchedLds g_sched;
 
 // ---------------------------------------------------------------- row flags
 // Row of `base`'s task at time t as a dense step (leaf: a leaf subtask).
-__device__ Row make_dense_row(const Row& base, int32_t t, bool leaf) {
+__device__ Row make_dense_row(const Row& base, int32_t t, bool leaf, int32_t wsplit = 0) {
     Row r = base;
     const int32_t kind = r.kind, m = r.m, n = r.n, T = r.T, pp = r.pp;
     r.t = t;
@@ -317,6 +327,15 @@ __device__ Row make_dense_row(const Row& base, int32_t t, bool leaf) {
     } else if (leaf) {
         f = F_NEED_ARG | F_LEAF_TABLE;
         aux = t - m;
+    } else if (kind == KIND_SUB && wsplit > 2) {
+        // the root's division rules over the subtask's own span [m, n]
+        const int32_t L = n - m + 1, wp = sub_parts(m, n, wsplit);
+        const int64_t e0 = m + seg_end(L, wp, 0);
+        if (t > e0) f |= F_NEED_ARG;
+        if (div_index(L, wp, t - 1 - m) >= 0) f |= F_ANC_FIRST;
+        else if (t > e0 + 1) f |= F_ANC_CHAIN;
+        const int32_t d = div_index(L, wp, t - m);
+        if (d >= 0) { f |= F_SNAP_DIV; aux = d; }
     } else {
         int32_t tmid = (m + n) >> 1;
         if (t > tmid) f |= F_NEED_ARG;
@@ -330,14 +349,16 @@ __device__ Row make_dense_row(const Row& base, int32_t t, bool leaf) {
 }
 
 // Row of `base`'s task at time t as a light operation (leaf: a leaf subtask).
-__device__ Row make_light_row(const Row& base, int32_t t, int32_t op, bool leaf = false) {
+__device__ Row make_light_row(const Row& base, int32_t t, int32_t op, bool leaf = false, int32_t wsplit = 0) {
     Row r = base;
     const int32_t kind = r.kind, m = r.m, n = r.n, T = r.T, pp = r.pp;
     r.t = t;
     r.aux = op;
     int32_t f = 0;
     if (op == L_INIT) {
-        if (is_dense_sub(kind) && !leaf && ((m + n) >> 1) == m) f |= F_SNAP_SUB;
+        if (kind == KIND_SUB && !leaf && wsplit > 2) {
+            if (seg_end(n - m + 1, sub_parts(m, n, wsplit), 0) == 0) f |= F_SNAP_DIV;   // division 0 at m
+        } else if (is_dense_sub(kind) && !leaf && ((m + n) >> 1) == m) f |= F_SNAP_SUB;
         if (kind == KIND_ROOT && pp >= 2 && seg_end(T, pp, 0) == 0) f |= F_SNAP_ROOT;
         if ((kind == KIND_VANILLA || kind == KIND_ROOT) && T == 1) f |= F_FINAL;
     }
@@ -358,7 +379,7 @@ __device__ Row row_from_task(cargs_t& a, const Task& tk, int32_t slot) {
         b.aux = B_INIT;
         return b;
     }
-    Row r = make_light_row(b, tk.m, L_INIT, is_leaf(a, tk.kind, tk.m, tk.n));
+    Row r = make_light_row(b, tk.m, L_INIT, is_leaf(a, tk.kind, tk.m, tk.n), a.wsplit);
     if (a.sparse) {   // a sparse start step is a row of the full list (see sparse_unit)
         r.flags |= F_START;
         r.aux = 0;    // division 0 for F_SNAP_ROOT
@@ -745,6 +766,10 @@ __device__ __forceinline__ void wide_item(cargs_t& a, const float* __restrict__ 
             root_dsnap(a, rr.off, rr.aux)[j] = dnew;
             if (rr.aux >= 1) root_link(a, rr.off, rr.pp, rr.aux)[j] = anc;
         }
+        if (f & F_SNAP_DIV) {
+            slot_div_d(a, slot, rr.aux)[j] = dnew;
+            if (rr.aux >= 1) slot_div_l(a, slot, rr.aux)[j] = anc;
+        }
         if (f & F_FINAL) key = order_key(dnew, j);
     }
     if (w < R && (L.rows[w].flags & F_FINAL)) {   // wave-uniform: the whole wave reduces
@@ -969,6 +994,16 @@ __device__ __forceinline__ void slab_chunk(cargs_t& a, gfloat_t* Ag, const Row* 
     }
     L.key[tid] = 0ull;
     __syncthreads();
+    // this thread's output: its emission score first, so that its latency
+    // overlaps the staging loads
+    const int32_t ro = tid / pcols;
+    const bool out_ok = ro < R;
+    const int32_t jo = (out_ok ? L.upass[ro] : 0) * pcols + (tid - ro * pcols);
+    float bpre = 0.0f;
+    if (out_ok) {
+        const Row& rr = L.rows[ro];
+        bpre = rr.log_b[(int64_t)rr.t * rr.ld + jo];
+    }
     {
         constexpr int32_t q4 = KP / 4;
         for (int32_t q = tid; q < R * q4; q += kEngBlock) {
@@ -977,14 +1012,6 @@ __device__ __forceinline__ void slab_chunk(cargs_t& a, gfloat_t* Ag, const Row* 
             const float* dp = slot_delta(a, clampi(rr.slot, a.n_slots), (rr.t - 1) & 1);
             *reinterpret_cast<float4*>(&L.d[r * KP + i]) = *reinterpret_cast<const float4*>(dp + i);
         }
-    }
-    const int32_t ro = tid / pcols;
-    const bool out_ok = ro < R;
-    const int32_t jo = (out_ok ? L.upass[ro] : 0) * pcols + (tid - ro * pcols);
-    float bpre = 0.0f;
-    if (out_ok) {
-        const Row& rr = L.rows[ro];
-        bpre = rr.log_b[(int64_t)rr.t * rr.ld + jo];
     }
     __syncthreads();
     for (int32_t rc = 0; rc < R; ++rc) {
@@ -1244,6 +1271,7 @@ __device__ __noinline__ void light_row(cargs_t& a_in, const float* __restrict__ 
                     if (m == 0) v = a.log_pi ? xv[u] + bv[u] : bv[u];
                     else if (q >= 0) { const float c = a.relative_init ? xv[u] : alpha + xv[u]; v = c + bv[u]; }
                     if (r.flags & F_SNAP_SUB) slot_snap(a, slot)[j] = v;
+                    if (r.flags & F_SNAP_DIV) slot_div_d(a, slot, 0)[j] = v;
                     if (r.flags & F_SNAP_ROOT) root_dsnap(a, r.off, 0)[j] = v;
                     if (r.flags & F_FINAL) {
                         const unsigned long long k = order_key(v, j);
@@ -1299,7 +1327,25 @@ __device__ __noinline__ void light_row(cargs_t& a_in, const float* __restrict__ 
             }
             wave_argmax(best, arg);
         }
-        if (lane == 0) {
+        if (lane == 0 && r.kind == KIND_SUB && a.wsplit > 2) {
+            // w-way: the last division state from the anchors, then the chain
+            // of division links down to the first; each with its score
+            arg = clampi(arg, K);
+            const int32_t L = n - r.m + 1, wp = sub_parts(r.m, n, a.wsplit);
+            const int32_t last = r.m + (int32_t)seg_end(L, wp, wp - 2);
+            const int32_t* ap = slot_anc(a, slot, (n - 1) & 1);
+            int32_t q = clampi((n - 1 == last) ? arg : (a.wide ? ld_c(ap + arg) : ap[arg]), K);
+            for (int32_t k = wp - 2; k >= 0; --k) {
+                const int32_t e = r.m + (int32_t)seg_end(L, wp, k);
+                const float* dk = slot_div_d(a, slot, k);
+                st_c(sq.path + e, q);
+                st_cf(a.alpha_at + sq.alpha_off + e, a.wide ? ld_cf(dk + q) : dk[q]);
+                if (k >= 1) {
+                    const int32_t* lk = slot_div_l(a, slot, k);
+                    q = clampi(a.wide ? ld_c(lk + q) : lk[q], K);
+                }
+            }
+        } else if (lane == 0) {
             arg = clampi(arg, K);
             const int32_t* ap = slot_anc(a, slot, (n - 1) & 1);
             const int32_t qmid = clampi((n == tmid + 1) ? arg : (a.wide ? ld_c(ap + arg) : ap[arg]), K);
@@ -2513,6 +2559,18 @@ __device__ __forceinline__ int32_t child_count(const Row& r) {
     return len > 2 ? 2 : (len == 2 ? 1 : 0);
 }
 
+// Children of a w-way subtask: its segments of at least two positions.
+__device__ __forceinline__ int32_t wchild_count(const Row& r, int32_t wsplit) {
+    const int32_t L = r.n - r.m + 1, wp = sub_parts(r.m, r.n, wsplit);
+    int32_t c = 0, lo = 0;
+    for (int32_t k = 0; k < wp; ++k) {
+        const int32_t hi = k < wp - 1 ? (int32_t)seg_end(L, wp, k) : L - 1;
+        c += hi - lo >= 1;
+        lo = hi + 1;
+    }
+    return c;
+}
+
 // src: the list r came from (0 full, 1 light, 2 block rows: beam tasks and
 // the finalize of dense roots and vanilla passes).
 __device__ Next classify(cargs_t& a, const Row& r, int src) {
@@ -2547,7 +2605,7 @@ __device__ Next classify(cargs_t& a, const Row& r, int src) {
         const int32_t nt = src == 0 ? r.t + 1 : r.m + 1;
         if (sub) {
             const bool leaf = is_leaf(a, r.kind, r.m, r.n);
-            if (nt < r.n) { x.list = 0; x.row = make_dense_row(r, nt, leaf); }
+            if (nt < r.n) { x.list = 0; x.row = make_dense_row(r, nt, leaf, a.wsplit); }
             else if (leaf) { x.list = 2; x.row = make_light_row(r, r.n, L_LEAF_END, true); }
             else { x.list = 1; x.row = make_light_row(r, r.n, L_END); }
         } else {
@@ -2556,7 +2614,7 @@ __device__ Next classify(cargs_t& a, const Row& r, int src) {
         }
     } else if (r.aux == L_END) {
         x.freed = 1;
-        x.spawn = child_count(r);
+        x.spawn = (r.kind == KIND_SUB && a.wsplit > 2) ? wchild_count(r, a.wsplit) : child_count(r);
     } else {  // L_BSPAWN
         x.freed = 1;
         x.spawn = ld_c(beam_fallback_flag(a, clampi(r.slot, a.n_slots))) ? 1 : child_count(r);
@@ -2574,6 +2632,16 @@ __device__ void write_spawns(cargs_t& a, const Row& r, int src, int64_t pos) {
             return;
         }
         const int32_t kind = (beam_end || r.kind == KIND_FSUB) ? KIND_BSUB : KIND_SUB;
+        if (!beam_end && r.kind == KIND_SUB && a.wsplit > 2) {
+            const int32_t L = r.n - r.m + 1, wp = sub_parts(r.m, r.n, a.wsplit);
+            int32_t lo = 0;
+            for (int32_t k = 0; k < wp; ++k) {
+                const int32_t hi = k < wp - 1 ? (int32_t)seg_end(L, wp, k) : L - 1;
+                if (hi - lo >= 1) a.queue[pos++] = Task{r.seq, KIND_SUB, r.m + lo, r.m + hi};
+                lo = hi + 1;
+            }
+            return;
+        }
         const int32_t tmid = (r.m + r.n) >> 1;
         const int32_t len = r.n - r.m;
         if (len >= 2) a.queue[pos++] = Task{r.seq, kind, r.m, tmid};
@@ -2668,16 +2736,19 @@ __device__ __noinline__ void admit(cargs_t& a_in, int nxt, uint32_t tag) {
     }
     __syncthreads();
     const int x = threadIdx.x / kSchedGroup, tg = threadIdx.x % kSchedGroup;
-    // the admitted tasks are dealt round-robin over the XCDs in queue order:
-    // XCD x's k-th task is batch entry sum_y min(admit[y], k) + #{y < x :
-    // admit[y] > k}, so consecutive (similar) tasks land on different XCDs
+    // the admitted tasks are dealt over the XCDs in queue order, round k
+    // going up the XCDs for even k and down for odd k (a snake, so that with
+    // the queue sorted longest first no XCD always gets the longest of a
+    // round): XCD x's k-th task is batch entry sum_y min(admit[y], k) plus the
+    // XCDs dealt before x in round k
     int32_t qa[kXcd];
 #pragma unroll
     for (int y = 0; y < kXcd; ++y) qa[y] = sl.admit[y];
     auto dealt = [&](int32_t k) -> int32_t {
         int32_t pos = sl.q_head;
+        const bool up = (k & 1) == 0;
 #pragma unroll
-        for (int y = 0; y < kXcd; ++y) pos += min(qa[y], k) + ((y < x && qa[y] > k) ? 1 : 0);
+        for (int y = 0; y < kXcd; ++y) pos += min(qa[y], k) + (((up ? y < x : y > x) && qa[y] > k) ? 1 : 0);
         return pos;
     };
     const int32_t ax = sl.admit[x];
@@ -2955,7 +3026,7 @@ __device__ void run_units(cargs_t& a, const float* __restrict__ Ap, uint32_t x, 
     __shared__ int32_t s_unit;
     // few rows on this XCD: lane tiles would run mostly empty, so its rows are
     // computed as column items (lanes = destinations) by its own blocks
-    const bool local_cols = !WIDE && !a.sparse && nf > 0 && nf <= kLocalColRows;
+    const bool local_cols = !WIDE && !a.sparse && nf > 0 && nf <= kLocalColRows && !a.force_tiles;
     const int32_t n_tiles =
         (WIDE || local_cols || a.sparse) ? 0 : ((nf + kTileRows - 1) / kTileRows) * (a.Kp / kTileCols);
     if constexpr (WIDE) run_wide(a, cur);
@@ -2982,8 +3053,37 @@ __device__ void run_units(cargs_t& a, const float* __restrict__ Ap, uint32_t x, 
             item = -1;
         }
     }
+    // light and block rows below these indices are taken by blocks set aside
+    // from the slab share; the rest go to the claims below
+    int32_t lo_light = 0, lo_block = 0;
     if constexpr (SLAB) {
-        if (local_cols) slab_items(a, Ap, nx, rank, list_full(a, cur, x), nf);
+        if (local_cols) {
+            // A block row (a finalize or a leaf's end) or a light row run
+            // after a full slab share would finish last: up to a quarter of
+            // the XCD's blocks take them instead (one block row per block, one
+            // light row per wave) and the others split the slab units.
+            int32_t nsl = nx;
+            if (a.method != FV_BEAM && nx > 0) {
+                const int32_t cap = nx / 4;
+                const int32_t nbx = min(nbm, cap);
+                const int32_t nlx = min((nl + kEngWaves - 1) / kEngWaves, cap - nbx);
+                nsl = nx - nbx - nlx;
+                lo_block = nbx;
+                lo_light = min(nl, nlx * kEngWaves);
+                if (rank >= nsl) {
+                    const int32_t e = rank - nsl;
+                    if (e < nbx) {
+                        const Row r = ld_row(list_beam(a, cur, x) + e);
+                        if (r.aux == L_LEAF_END) leaf_end(a, r);
+                        else dense_finalize(a, r);
+                    } else {
+                        const int32_t li = (e - nbx) * kEngWaves + (threadIdx.x >> 6);
+                        if (li < lo_light) light_row(a, Ap, ld_row(list_light(a, cur, x) + li));
+                    }
+                }
+            }
+            if (rank >= 0 && rank < nsl) slab_items(a, Ap, nsl, rank, list_full(a, cur, x), nf);
+        }
     } else {
         if (local_cols) local_col_items(a, x, nx, rank, cur, nf);
     }
@@ -2999,7 +3099,7 @@ __device__ void run_units(cargs_t& a, const float* __restrict__ Ap, uint32_t x, 
     }
     const int32_t ngrp = kEngWaves / nsplit;
     const int32_t bw = threadIdx.x >> 6, grp = bw / nsplit, wv = bw & (nsplit - 1);
-    const int32_t n_lu = (nl + nsplit - 1) / nsplit;
+    const int32_t n_lu = (nl - lo_light + nsplit - 1) / nsplit;
     const int32_t n1 = n_tiles + n_lu;
     const Row* F = list_full(a, cur, x);
     const Row* L = list_light(a, cur, x);
@@ -3020,15 +3120,16 @@ __device__ void run_units(cargs_t& a, const float* __restrict__ Ap, uint32_t x, 
             if (item < n_tiles) {
                 dense_tile(a, Ap, F, nf, item, nsplit);
             } else {
-                const int32_t li = (item - n_tiles) * nsplit + wv;
+                const int32_t li = lo_light + (item - n_tiles) * nsplit + wv;
                 if (li < nl) light_row(a, Ap, ld_row(L + li));
             }
             item = -1;
         }
     }
+    nbm -= lo_block;
     if (nbm == 0) return;
     __syncthreads();
-    const Row* Bl = list_beam(a, cur, x);
+    const Row* Bl = list_beam(a, cur, x) + lo_block;
     int32_t* ctr2 = &a.st->claim[cur][x][16];
     if (a.beam_q) {   // beam rows four to a block: each 256-thread group claims rows
         QuarterLds& Q = g_lds.qbeam;

@@ -40,7 +40,21 @@ enum : int32_t {
     F_FINAL = 1 << 6,      // t = T-1 of a full-length pass: feed the final arg max
     F_START = 1 << 7,      // sparse rows: this step computes the task's start vector
     F_LEAF_TABLE = 1 << 8, // leaf subtask: store psi_t in the slot's leaf table, row aux (= t - m)
+    F_SNAP_DIV = 1 << 9,   // w-way subtask: copy delta_t (and anc_t) to the slot's division copy aux
 };
+
+// w-way subtasks.  With leaves off (K above kLeafMaxKp) and wide rows, a
+// FLASH subtask [m, n] is split like the root: w' = min(kWSplit, n - m + 1)
+// segments of its positions, division ends e_k = m + floor(((k+1) L - 1) / w')
+// (L = n - m + 1, k < w' - 1), snapshots of delta and of the division chain
+// at each e_k in its row buffer, all w' - 1 division states resolved at its
+// end, and one child per segment of at least two positions.  w' = 2 is
+// Alg. 1's bisection; every position is still resolved exactly once.
+constexpr int32_t kWSplit = 8;
+inline __host__ __device__ int32_t sub_parts(int32_t m, int32_t n, int32_t w) {
+    const int32_t L = n - m + 1;
+    return L < w ? L : w;
+}
 
 // Light (O(K)) operations.  L_BSPAWN does nothing: it holds a finished
 // beam subtask for one step so that the scheduler, which classifies a
@@ -177,6 +191,9 @@ struct EngineArgs {
     int32_t has_anc;            // slots carry anc[2] + snap
     int32_t wide;               // wide rows: every block takes a column slice of every dense row
     int32_t slab;               // local dense rows as column slabs (K = Kp = 512 or 1024)
+    int32_t wsplit;             // FLASH subtasks split kWSplit ways (0: bisection)
+    int32_t force_tiles;        // local dense rows as lane tiles for any row count
+    int64_t div_off;            // floats from a slot's start to its division copies (w-way subtasks)
     int32_t leaf_len;           // subtasks of at most this many steps are leaves (0: none)
     int32_t beam_q;             // beam rows run four to a block (dense, one part, small K and B)
     int32_t relative_init;      // subtask starts drop the carried score (FV_FLAG_RELATIVE_INIT)

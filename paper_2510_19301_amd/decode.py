@@ -83,16 +83,20 @@ def _workspace(n: int, dev) -> torch.Tensor:
 
 
 ROWS = {"auto": 0, "wide": L.FV_FLAG_WIDE_ROWS, "local": L.FV_FLAG_LOCAL_ROWS}
+STEPS = {"auto": 0, "items": L.FV_FLAG_STEP_ITEMS, "tiles": L.FV_FLAG_STEP_TILES}
 
 
-def _flags(rows: str, validate: bool, leaves: bool = True, relative_init: bool = False) -> int:
+def _flags(rows: str, validate: bool, leaves: bool = True, relative_init: bool = False, step: str = "auto",
+           engine: bool = False) -> int:
     return (ROWS[rows] | (L.FV_FLAG_VALIDATE if validate else 0) | (0 if leaves else L.FV_FLAG_NO_LEAVES)
-            | (L.FV_FLAG_RELATIVE_INIT if relative_init else 0))
+            | (L.FV_FLAG_RELATIVE_INIT if relative_init else 0) | STEPS[step]
+            | (L.FV_FLAG_ENGINE if engine else 0))
 
 
 def decode(log_a, log_b: torch.Tensor, log_pi: torch.Tensor | None = None,
            method: str = "vanilla", P: int = 16, B: int = 0, check_status: bool = True,
-           rows: str = "auto", validate: bool = False, leaves: bool = True, relative_init: bool = False):
+           rows: str = "auto", validate: bool = False, leaves: bool = True, relative_init: bool = False,
+           step: str = "auto", engine: bool = False):
     """Decode one sequence.  log_a: dense [K, K] tensor or a CsrModel;
     log_b [T, >=K] (row stride = ld), log_pi [K] or None; all float32 CUDA
     tensors.  rows: "auto", "wide" or "local" row placement of dense models
@@ -100,7 +104,9 @@ def decode(log_a, log_b: torch.Tensor, log_pi: torch.Tensor | None = None,
     FV_E_INVALID_ARG).  leaves=False: bisect every FLASH subtask (no leaf
     tables; same results).  relative_init: subtasks start from the paper's
     displayed initialisation (the carried score dropped; dense models; paths
-    may differ from vanilla's at near ties).  Returns (path int32 [T], score
+    may differ from vanilla's at near ties).  step ("auto", "items", "tiles")
+    and engine (True: the persistent engine even for K <= 256) choose kernels
+    for tuning; results are the same.  Returns (path int32 [T], score
     float32 [1], status int32 [1]) on the device."""
     model, K, dev = _model(log_a)
     _need(log_b, "log_b")
@@ -118,7 +124,7 @@ def decode(log_a, log_b: torch.Tensor, log_pi: torch.Tensor | None = None,
     ws = _workspace(n, dev)
     pi = log_pi.data_ptr() if log_pi is not None else None
     lib = L.lib()
-    flags = _flags(rows, validate, leaves, relative_init)
+    flags = _flags(rows, validate, leaves, relative_init, step, engine)
     if method == "vanilla":
         rc = lib.fv_decode_vanilla(C.byref(model), pi, log_b.data_ptr(), ld, T, path.data_ptr(),
                                    score.data_ptr(), status.data_ptr(), flags, ws.data_ptr(),
@@ -191,7 +197,7 @@ class Batch:
 
 def decode_batch(log_a, batch: Batch, log_pi=None, method: str = "flash", P: int = 16, B: int = 0,
                  ws: torch.Tensor | None = None, rows: str = "auto", validate: bool = False,
-                 leaves: bool = True, relative_init: bool = False):
+                 leaves: bool = True, relative_init: bool = False, step: str = "auto", engine: bool = False):
     """Decode all sequences of `batch` in one decode launch (the persistent
     engine, or one block per sequence for vanilla and FLASH when every dense
     model has K <= 256).  log_a: a
@@ -221,7 +227,7 @@ def decode_batch(log_a, batch: Batch, log_pi=None, method: str = "flash", P: int
     rc = L.lib().fv_decode_batch(trans, C.cast(pa, C.c_void_p), len(mods), batch.desc.data_ptr(),
                                  lengths.ctypes.data, batch.models.ctypes.data, batch.n, L.METHODS[method],
                                  int(P), int(B or 0), batch.status.data_ptr(),
-                                 _flags(rows, validate, leaves, relative_init),
+                                 _flags(rows, validate, leaves, relative_init, step, engine),
                                  ws.data_ptr(), ws.numel(), _stream(dev))
     L.check(rc, "fv_decode_batch")
     return ws

@@ -1,23 +1,175 @@
-"""Measured choice of the FLASH parallelism P for a given batch.
+"""Measured tuning of the decode's result-neutral choices, with a persisted cache.
 
-The library's own choice for P <= 0 is a closed-form rule (the largest
-power of two with P <= T/16 for the median length).  This helper instead
-decodes the actual batch once per candidate P on the current stream, timed
-with device events, and returns the fastest; results are memoised per
-(model shape, method, length profile).  Every candidate gives the same
-paths and scores (FLASH is exact for every P), so tuning never changes a
-result.
+FLASH is exact for every schedule (the anchored start of Sec. V-B, Def. 3),
+and every kernel choice computes the same float32 operations, so none of the
+knobs tuned here changes a path or a score:
+
+- P, the FLASH parallelism (Alg. 1's first split; FLASH only);
+- the row placement: rows kept on their XCD ("local") or every block taking a
+  column slice of every row ("wide");
+- the dense step kernel for rows kept on their XCD: the library's choice
+  (column slabs at K = 512 / 1024), column items, or lane tiles;
+- leaf subtasks on or off (FLASH);
+- for small dense models (K <= 256), one block per sequence or the
+  persistent engine.
+
+The search is a coordinate descent from the library's defaults (one knob at a
+time, keeping the best value), each candidate decoded on the current stream
+and timed with device events.  Results are stored in a JSON file keyed by the
+device architecture and a signature of the workload (model size and kind,
+method, beam width, batch size and the length profile rounded to powers of
+two), so later processes reuse them without decoding.  The cache file is
+FV_TUNE_CACHE, or ~/.cache/flashviterbi/tune.json.
 """
 from __future__ import annotations
 
 import hashlib
+import json
+import math
+import os
+import tempfile
+from typing import Callable
 
 import numpy as np
 import torch
 
 from .decode import Batch, decode_batch
 
+DEFAULT = {"P": 0, "rows": "auto", "step": "auto", "leaves": True, "engine": False}
+SMALL_K = 256   # one block per sequence up to this K (the library's kSmallK)
+
 _cache: dict = {}
+
+
+def _pow2_bucket(x: float) -> int:
+    return 1 << max(0, int(math.ceil(math.log2(max(1.0, float(x))))))
+
+
+def signature(arch: str, K: int, kind: str, method: str, B: int, lengths) -> str:
+    """Cache key of a workload: lengths enter only as the batch size and the
+    median and longest length, each rounded up to a power of two."""
+    lens = np.asarray(lengths, np.int64)
+    n = int(lens.shape[0])
+    med = float(np.median(lens)) if n else 0.0
+    mx = float(lens.max()) if n else 0.0
+    return (f"{arch}|K{K}|{kind}|{method}|B{int(B or 0)}|n{_pow2_bucket(n)}|"
+            f"tmed{_pow2_bucket(med)}|tmax{_pow2_bucket(mx)}")
+
+
+def search_space(method: str, K: int, kind: str, P_candidates) -> list[tuple[str, list]]:
+    """Knobs and their values, in the order the descent visits them."""
+    space = []
+    if method == "flash":
+        space.append(("P", list(P_candidates)))
+    if kind == "dense":
+        space.append(("rows", ["auto", "wide", "local"]))
+        space.append(("step", ["auto", "items", "tiles"]))
+        if method in ("flash", "vanilla") and K <= SMALL_K:
+            space.append(("engine", [False, True]))
+    if method == "flash" and kind == "dense":
+        space.append(("leaves", [True, False]))
+    return space
+
+
+def coordinate_descent(evaluate: Callable[[dict], float], space, start: dict | None = None) -> tuple[dict, dict]:
+    """Best configuration found by optimising one knob at a time (each value
+    evaluated once, the best kept), and every evaluation {config key: ms}."""
+    best = dict(DEFAULT if start is None else start)
+    seen: dict = {}
+
+    def cost(cfg):
+        key = json.dumps(cfg, sort_keys=True)
+        if key not in seen:
+            seen[key] = float(evaluate(dict(cfg)))
+        return seen[key]
+
+    best_ms = cost(best)
+    for name, values in space:
+        for v in values:
+            cand = dict(best, **{name: v})
+            ms = cost(cand)
+            if ms < best_ms:
+                best, best_ms = cand, ms
+    return best, seen
+
+
+def cache_path() -> str:
+    return os.environ.get("FV_TUNE_CACHE") or os.path.join(os.path.expanduser("~"), ".cache", "flashviterbi",
+                                                           "tune.json")
+
+
+def load_cache(path: str) -> dict:
+    try:
+        with open(path) as f:
+            data = json.load(f)
+        return data if isinstance(data, dict) else {}
+    except (OSError, ValueError):
+        return {}
+
+
+def store(path: str, key: str, entry: dict) -> None:
+    """Add one entry to the cache file (read, update, atomic replace)."""
+    d = os.path.dirname(path)
+    if d:
+        os.makedirs(d, exist_ok=True)
+    data = load_cache(path)
+    data[key] = entry
+    fd, tmp = tempfile.mkstemp(dir=d or ".", prefix=".tune.", suffix=".json")
+    with os.fdopen(fd, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def _arch(dev) -> str:
+    p = torch.cuda.get_device_properties(dev)
+    return getattr(p, "gcnArchName", None) or p.name
+
+
+def _kind_K(log_a) -> tuple[str, int]:
+    if hasattr(log_a, "trans"):
+        return "csr", int(log_a.K)
+    return "dense", int(log_a.shape[0])
+
+
+def tune(log_a, batch: Batch, log_pi=None, method: str = "flash", B: int = 0,
+         P_candidates=(4, 16, 64, 256), repeats: int = 1, path: str | None = None,
+         refresh: bool = False) -> tuple[dict, dict]:
+    """(config, timings) for decoding batches like `batch`: config holds the
+    decode_batch keywords P, rows, step, leaves, engine.  A cached entry for
+    the workload's signature is returned without decoding unless refresh.
+    The batch's outputs hold the last candidate's (identical) results after a
+    search."""
+    kind, K = _kind_K(log_a)
+    key = signature(_arch(batch.device), K, kind, method, B, batch.lengths)
+    path = path or cache_path()
+    if not refresh:
+        hit = load_cache(path).get(key)
+        if hit and isinstance(hit.get("config"), dict):
+            return dict(hit["config"]), dict(hit.get("timings", {}))
+    ws = [None]
+
+    def evaluate(cfg):
+        kw = dict(cfg)
+        P = kw.pop("P") or 16
+        if method == "beam" and P <= 0:
+            P = 16
+        ws[0] = decode_batch(log_a, batch, log_pi, method=method, P=P, B=B, ws=ws[0], **kw)   # warm-up, sizes ws
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(repeats):
+            ws[0] = decode_batch(log_a, batch, log_pi, method=method, P=P, B=B, ws=ws[0], **kw)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / repeats
+
+    start = dict(DEFAULT, P=P_candidates[0] if method == "flash" else 0)
+    if method == "beam":
+        start["P"] = 16
+    best, seen = coordinate_descent(evaluate, search_space(method, K, kind, P_candidates), start)
+    timings = {k: round(v, 4) for k, v in seen.items()}
+    store(path, key, {"config": best, "timings": timings})
+    return best, timings
 
 
 def _key(log_a, batch: Batch, method: str) -> str:
@@ -29,8 +181,9 @@ def _key(log_a, batch: Batch, method: str) -> str:
 
 def best_parallelism(log_a, batch: Batch, log_pi=None, candidates=(16, 32, 64, 128, 256, 512),
                      method: str = "flash", repeats: int = 1) -> tuple[int, dict]:
-    """(best P, {P: ms}) for decoding `batch` with FLASH.  The batch's outputs
-    hold the last candidate's (identical) results afterwards."""
+    """(best P, {P: ms}) for decoding `batch` with FLASH, the other choices at
+    the library's defaults (memoised in this process only).  The batch's
+    outputs hold the last candidate's (identical) results afterwards."""
     key = _key(log_a, batch, method)
     if key in _cache:
         return _cache[key]
