@@ -119,7 +119,7 @@ def _make_inputs(wl, torch, dev):
     return [torch.from_numpy(x).to(dev) for x in host]
 
 
-def _time_method(fv, torch, la, lp, batch, method, P, B, steps, warmup, ws=None, leaves=True):
+def _time_method(fv, torch, la, lp, batch, method, P, B, steps, warmup, ws=None, leaves=True, emission=None):
     """Mean ms per decode over `steps` timed decodes (torch events on the
     current stream, which is the stream the library launches on) and the
     engine kernel's own duration in the last timed decode (HIP events the
@@ -127,13 +127,13 @@ def _time_method(fv, torch, la, lp, batch, method, P, B, steps, warmup, ws=None,
     import ctypes as C
     lib = fv.lib()
     for _ in range(warmup):
-        ws = fv.decode_batch(la, batch, lp, method=method, P=P, B=B, ws=ws, leaves=leaves)
+        ws = fv.decode_batch(la, batch, lp, method=method, P=P, B=B, ws=ws, leaves=leaves, emission=emission)
     torch.cuda.synchronize()
     fv._lib.check(lib.fv_profile_engine(1), "fv_profile_engine")
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     start.record()
     for _ in range(steps):
-        ws = fv.decode_batch(la, batch, lp, method=method, P=P, B=B, ws=ws, leaves=leaves)
+        ws = fv.decode_batch(la, batch, lp, method=method, P=P, B=B, ws=ws, leaves=leaves, emission=emission)
     stop.record()
     torch.cuda.synchronize()
     ms = C.c_float(0)
@@ -213,8 +213,10 @@ def large_runs(fv, torch, hmm, dev):
 def sparse_runs(fv, torch, hmm, dev):
     """The map-matching workload: K = 100000 states on a 9-nearest-neighbour
     CSR graph, 64 trajectories of length U[200, 2000], Gaussian GPS
-    emissions (generated on the device).  Vanilla and FLASH pull over
-    in-edges; FLASH-BS pushes the beam's out-edges."""
+    emissions: first as log B tables (produced on the device by torch before
+    the timed decodes), then generated inside the decode from the GPS points.
+    Vanilla and FLASH pull over in-edges; FLASH-BS pushes the beam's
+    out-edges."""
     wl = hmm.map_matching_workload()
     print(f"[bench] sparse: K={wl.K} n={wl.n} sum T={wl.total_steps()}", file=sys.stderr, flush=True)
     lbs = [wl.log_b(b, dev) for b in range(wl.n)]
@@ -236,6 +238,18 @@ def sparse_runs(fv, torch, hmm, dev):
         torch.cuda.empty_cache()
     del lbs, batch
     torch.cuda.empty_cache()
+    # the same decodes with the emission generated inside the decode from
+    # the GPS points (no log B tables: 28.6 GB less to produce and stream)
+    em = fv.GaussEmission.from_sigma(torch.from_numpy(wl.xy).to(dev), wl.sigma_gps)
+    obs = fv.Batch.observations([torch.from_numpy(wl.gps(b)).to(dev) for b in range(wl.n)])
+    for method, P, B in (("beam", 16, 128), ("flash", 16, 0), ("vanilla", 1, 0)):
+        ms, eng_ms, ws, bad = _time_method(fv, torch, model, lp, obs, method, P, B, 1, 1, emission=em)
+        key = {"flash": f"flash_P{P}", "vanilla": "vanilla", "beam": f"beam_P{P}_B{B}"}[method] + "_generated_emission"
+        res[key] = {"ms": round(ms, 1), "engine_ms": round(eng_ms, 1), "state_steps_per_s": steps / (ms / 1e3),
+                    "workspace_bytes": int(ws.numel()), "bad_status": bad}
+        print(f"[bench] sparse {key}: {ms:.1f} ms", file=sys.stderr, flush=True)
+        del ws
+        torch.cuda.empty_cache()
     return res
 
 

@@ -226,6 +226,42 @@ fv_status fv_decode_batch(const fv_trans* models, const float* const* log_pi, in
                           int32_t P, int32_t B, int32_t* status, uint32_t flags, void* ws,
                           size_t ws_bytes, fv_stream_t stream);
 
+/* Emission model generated inside the decode (Sec. III: observations may
+ * be continuous, e.g. Gaussian), replacing the log_b tables.
+ * FV_EMIT_TABLE: each sequence's fv_seq.log_b table, as in every other call.
+ * FV_EMIT_GAUSS2D: state j sits at the point (state_xy[2j], state_xy[2j+1])
+ * (device, float64 [K][2]) and each observation is a point; a sequence's
+ * fv_seq.log_b field then carries the address of its observations (device,
+ * float64 [T][2], cast to const float*) and its ld is ignored.  The score is
+ * evaluated in float64, every operation rounded once (no fused
+ * multiply-add), then rounded to float32:
+ *     dx = x_j - u_t,  dy = y_j - v_t,  d2 = dx*dx + dy*dy,
+ *     log B_t(j) = (float)(c2 * d2 - c0)
+ * For a Gaussian of standard deviation sigma on the distance,
+ * c2 = -1 / (2 sigma^2) and c0 = ln(sigma sqrt(2 pi)).  c2 must be finite
+ * and <= 0, c0 finite and >= -FLT_MAX (no score can then be +inf); with
+ * finite points no score is NaN.  FV_FLAG_VALIDATE checks that every
+ * coordinate (state points and observations) is finite. */
+enum { FV_EMIT_TABLE = 0, FV_EMIT_GAUSS2D = 1 };
+typedef struct {
+    int32_t kind;
+    const double* state_xy;
+    double c2;
+    double c0;
+} fv_emission;
+
+/* fv_decode_batch with an emission model per transition model: emissions
+ * is a host array [n_models] (NULL: every model reads tables).  A
+ * FV_EMIT_GAUSS2D entry requires a CSR model (FV_E_UNSUPPORTED for a dense
+ * one) and K points.  Each sequence's result equals fv_decode_batch's on the
+ * tables the emission model defines, bit for bit; the tables are never
+ * written to memory. */
+fv_status fv_decode_batch_emit(const fv_trans* models, const fv_emission* emissions,
+                               const float* const* log_pi, int32_t n_models, const fv_seq* seqs_dev,
+                               const int32_t* T_host, const int32_t* model_host, int32_t n_seqs,
+                               int32_t method, int32_t P, int32_t B, int32_t* status, uint32_t flags,
+                               void* ws, size_t ws_bytes, fv_stream_t stream);
+
 /* Gradient of the Viterbi scores S_b (the decoded path's summed log-scores)
  * given upstream gradients grad_score[n].  No passage of the paper defines
  * this operation: it is the subgradient of the score of Sec. III-A (a sum of

@@ -56,6 +56,8 @@ def _load():
         lib.fvo_rescore.argtypes = [i32, i32, vp, vp, vp, i64, vp]
         lib.fvo_rescore.restype = f
         lib.fvo_gather_emissions.argtypes = [i32, i32, vp, vp, i32, vp, i64]
+        lib.fvo_gauss_emissions.argtypes = [i32, vp, vp, i32, C.c_double, C.c_double, vp, i64]
+        lib.fvo_gauss_emissions.restype = C.c_int
         lib.fvo_flash.argtypes = [i32, i32, i32, vp, vp, vp, i64, vp, vp, u64, C.POINTER(Stats), vp, i32]
         lib.fvo_beam.argtypes = [i32, i32, i32, i32, vp, vp, vp, i64, vp, vp, vp, u64,
                                  C.POINTER(Stats), vp, i32]
@@ -141,6 +143,28 @@ def gather_emissions(log_e, obs):
     rc = lib.fvo_gather_emissions(K, V, _p(log_e), _p(obs), obs.shape[0], _p(out), K)
     assert rc == OK
     return out
+
+
+def gauss_emissions(xy, obs, c2, c0):
+    """float32 [T, K] emission scores of a Gaussian observation model on
+    points: xy float64 [K, 2] state points, obs float64 [T, 2] observations,
+    log B_t(j) = c2 * |xy_j - obs_t|^2 - c0 in double, then float32."""
+    lib = _load()
+    xy = np.ascontiguousarray(xy, np.float64)
+    obs = np.ascontiguousarray(obs, np.float64)
+    K, T = xy.shape[0], obs.shape[0]
+    assert xy.shape == (K, 2) and obs.shape == (T, 2)
+    out = np.empty((T, K), np.float32)
+    rc = lib.fvo_gauss_emissions(K, _p(xy), _p(obs), T, float(c2), float(c0), _p(out), K)
+    assert rc == OK
+    return out
+
+
+def gauss_coefficients(sigma):
+    """(c2, c0) of a Gaussian of standard deviation sigma on the distance:
+    log N(d; 0, sigma^2) = c2 * d^2 - c0."""
+    import math
+    return -1.0 / (2.0 * (sigma * sigma)), math.log(sigma * math.sqrt(2.0 * math.pi))
 
 
 def flash(log_pi, log_a, log_b, P, shuffle_seed=0, want_trace=False, relative_init=False):

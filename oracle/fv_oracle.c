@@ -22,6 +22,8 @@
  *   fvo_backward     subgradient of the Viterbi score       (score is a sum of
  *                    the decoded path's log-scores, Sec. III-A)
  *   fvo_gather_emissions  log B_t[j] = log e[j, x_t]        (Sec. III, the HMM triplet)
+ *   fvo_gauss_emissions   log B_t[j] of a Gaussian observation model on
+ *                    points (Sec. III: continuous observations)
  *
  * Readings of points the paper leaves open (tie-breaking, where log B is
  * added, the anchored pruned initialisation, segment boundaries for P that
@@ -168,6 +170,33 @@ int fvo_gather_emissions(int K, int V, const float* log_e, const int32_t* obs, i
     for (int t = 0; t < T; ++t) {
         if (obs[t] < 0 || obs[t] >= V) return FVO_INVALID;
         for (int j = 0; j < K; ++j) log_b[(size_t)t * ld + j] = log_e[(size_t)j * V + obs[t]];
+    }
+    return FVO_OK;
+}
+
+/* Emission rows of a continuous-observation HMM (Sec. III names Gaussian
+ * observation models): state j sits at the point (xy[2j], xy[2j+1]),
+ * observation t is the point (obs[2t], obs[2t+1]), and
+ *     log B_t(j) = c2 * d2 - c0,   d2 = (x_j - u_t)^2 + (y_j - v_t)^2,
+ * evaluated in double, each operation rounded once (the file is built
+ * without contraction), then rounded to float.  For a Gaussian of standard
+ * deviation sigma on the distance, c2 = -1/(2 sigma^2) and
+ * c0 = log(sigma sqrt(2 pi)). */
+int fvo_gauss_emissions(int K, const double* xy, const double* obs, int T, double c2, double c0,
+                        float* log_b, int64_t ld)
+{
+    if (K < 1 || T < 0 || ld < K) return FVO_INVALID;
+    for (int t = 0; t < T; ++t) {
+        const double u = obs[2 * (size_t)t], v = obs[2 * (size_t)t + 1];
+        for (int j = 0; j < K; ++j) {
+            const double dx = xy[2 * (size_t)j] - u;
+            const double dy = xy[2 * (size_t)j + 1] - v;
+            const double sx = dx * dx;
+            const double sy = dy * dy;
+            const double d2 = sx + sy;
+            const double e = c2 * d2;
+            log_b[(size_t)t * ld + j] = (float)(e - c0);
+        }
     }
     return FVO_OK;
 }

@@ -6,12 +6,12 @@ tensors into its C entry points.
 """
 from ._lib import (FV_OK, FV_E_INVALID_ARG, FV_E_UNSUPPORTED, FV_E_WORKSPACE, FV_E_DEVICE,
                    FV_E_INFEASIBLE, FV_W_BEAM_FALLBACK, FvError, lib)
-from .decode import (Batch, CsrModel, decode, decode_batch, dense_model, model_descriptor,
+from .decode import (Batch, CsrModel, GaussEmission, decode, decode_batch, dense_model, model_descriptor,
                      workspace_bytes, workspace_bytes_models)
 from .autograd import ViterbiScore, backward_workspace_bytes, viterbi_backward
 from .tune import best_parallelism, tune
 
 __all__ = ["FV_OK", "FV_E_INVALID_ARG", "FV_E_UNSUPPORTED", "FV_E_WORKSPACE", "FV_E_DEVICE",
-           "FV_E_INFEASIBLE", "FV_W_BEAM_FALLBACK", "FvError", "lib", "Batch", "CsrModel",
+           "FV_E_INFEASIBLE", "FV_W_BEAM_FALLBACK", "FvError", "lib", "Batch", "CsrModel", "GaussEmission",
            "decode", "decode_batch", "dense_model", "model_descriptor", "workspace_bytes", "workspace_bytes_models",
            "ViterbiScore", "viterbi_backward", "backward_workspace_bytes", "best_parallelism", "tune"]

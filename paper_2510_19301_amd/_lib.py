@@ -18,6 +18,7 @@ FV_FLAG_WIDE_ROWS, FV_FLAG_LOCAL_ROWS, FV_FLAG_VALIDATE, FV_FLAG_NO_LEAVES = 1, 
 FV_FLAG_RELATIVE_INIT = 16
 FV_FLAG_STEP_ITEMS, FV_FLAG_STEP_TILES, FV_FLAG_ENGINE = 32, 64, 128
 FV_VANILLA, FV_FLASH, FV_BEAM = 0, 1, 2
+FV_EMIT_TABLE, FV_EMIT_GAUSS2D = 0, 1
 METHODS = {"vanilla": FV_VANILLA, "flash": FV_FLASH, "beam": FV_BEAM}
 
 
@@ -30,6 +31,10 @@ class FvTrans(C.Structure):
 class FvSeq(C.Structure):
     _fields_ = [("model", C.c_int32), ("T", C.c_int32), ("log_b", C.c_void_p),
                 ("ld", C.c_int64), ("path", C.c_void_p), ("score", C.c_void_p)]
+
+
+class FvEmission(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("state_xy", C.c_void_p), ("c2", C.c_double), ("c0", C.c_double)]
 
 
 class FvError(RuntimeError):
@@ -50,6 +55,8 @@ SIGNATURES = {
     "fv_decode_flash_noalloc": (_i32, [_P(FvTrans), _vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp, _u32, _vp]),
     "fv_decode_beam": (_i32, [_P(FvTrans), _vp, _vp, _i64, _i32, _i32, _i32, _vp, _vp, _vp, _u32, _vp, _sz, _vp]),
     "fv_decode_batch": (_i32, [_P(FvTrans), _vp, _i32, _vp, _vp, _vp, _i32, _i32, _i32, _i32, _vp, _u32, _vp, _sz, _vp]),
+    "fv_decode_batch_emit": (_i32, [_P(FvTrans), _P(FvEmission), _vp, _i32, _vp, _vp, _vp, _i32, _i32, _i32, _i32,
+                                    _vp, _u32, _vp, _sz, _vp]),
     "fv_viterbi_backward": (_i32, [_i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _sz, _vp]),
     "fv_backward_workspace_size": (_i32, [_i32, _i32, _i32, _P(_sz)]),
     "fv_rescore": (_i32, [_P(FvTrans), _vp, _vp, _i32, _vp, _vp]),

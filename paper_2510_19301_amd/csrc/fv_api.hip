@@ -1,9 +1,11 @@
 // Host side of the C ABI: argument checks, workspace layout, launches.
 #include <stdarg.h>
 #include <stdio.h>
+#include <float.h>
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <string>
 #include <map>
 #include <mutex>
@@ -23,6 +25,9 @@ extern "C" __global__ void fv_small_flash128_kernel(const EngineArgs* __restrict
 extern "C" __global__ void fv_small_flash256_kernel(const EngineArgs* __restrict__ table);
 extern "C" __global__ void fv_fill_i32_kernel(int32_t* __restrict__ p, int64_t n, int32_t v);
 extern "C" __global__ void fv_validate_array_kernel(const float* __restrict__ p, int64_t n, int32_t* __restrict__ flag);
+extern "C" __global__ void fv_validate_points_kernel(const double* __restrict__ p, int64_t n, int32_t* flag);
+extern "C" __global__ void fv_validate_obs_kernel(const fv_seq* __restrict__ seqs, int32_t n_seqs, int32_t model,
+                                                  int32_t* __restrict__ bad_seq);
 extern "C" __global__ void fv_validate_seqs_kernel(const fv_seq* __restrict__ seqs, int32_t n_seqs, int32_t model,
                                                    int32_t K, int32_t* __restrict__ bad_seq);
 extern "C" __global__ void fv_model_check_kernel(const fv_seq* seqs_dev, int32_t n_seqs, int32_t n_models,
@@ -503,11 +508,29 @@ fv_status check_flags(uint32_t flags, int32_t method, const fv_trans* models, in
 // Decodes every sequence of seqs_dev (or the one sequence `single`) with
 // its model: per model, the preparation kernels and the setup kernel, then
 // one persistent engine launch for all models, then the finish kernels.
+// Emission descriptors (NULL: tables for every model).
+fv_status check_emissions(const fv_emission* emits, const fv_trans* models, int32_t n_models) {
+    for (int32_t m = 0; emits && models && m < n_models; ++m) {
+        const fv_emission& e = emits[m];
+        if (e.kind == FV_EMIT_TABLE) continue;
+        if (e.kind != FV_EMIT_GAUSS2D) return fail(FV_E_INVALID_ARG, "model %d: unknown emission kind %d", m, e.kind);
+        if (models[m].kind != FV_CSR)
+            return fail(FV_E_UNSUPPORTED, "model %d: generated emissions apply to CSR models only", m);
+        if (!e.state_xy) return fail(FV_E_INVALID_ARG, "model %d: null state points", m);
+        if (!std::isfinite(e.c2) || e.c2 > 0.0 || !std::isfinite(e.c0) || e.c0 < -(double)FLT_MAX)
+            return fail(FV_E_INVALID_ARG, "model %d: emission coefficients need finite c2 <= 0 and finite c0 >= -FLT_MAX",
+                        m);
+    }
+    return FV_OK;
+}
+
 fv_status run_batch(int32_t method, const fv_trans* models, const float* const* log_pi, int32_t n_models,
                     const fv_seq* seqs_dev, const int32_t* T_host, const int32_t* model_host, int32_t n_seqs,
                     int32_t P, int32_t B, const fv_seq* single, int32_t* status, uint32_t flags, void* ws,
-                    size_t ws_bytes, hipStream_t stream) {
+                    size_t ws_bytes, hipStream_t stream, const fv_emission* emits = nullptr) {
     fv_status rc = check_flags(flags, method, models, n_models);
+    if (rc != FV_OK) return rc;
+    rc = check_emissions(emits, models, n_models);
     if (rc != FV_OK) return rc;
     BatchPlan bp;
     rc = plan_batch(method, models, n_models, T_host, model_host, n_seqs, P, B, single != nullptr, bp);
@@ -538,6 +561,7 @@ fv_status run_batch(int32_t method, const fv_trans* models, const float* const* 
     for (size_t p = 0; p < bp.L.size(); ++p) {
         const DenseLayout& L = bp.L[p];
         const fv_trans* A = &models[bp.model[p]];
+        const fv_emission emit = emits ? emits[bp.model[p]] : fv_emission{FV_EMIT_TABLE, nullptr, 0.0, 0.0};
         const int32_t meth = bp.method[p];
         const int32_t n_local = L.n_seqs;
         const bool sparse = A->kind == FV_CSR;
@@ -579,8 +603,15 @@ fv_status run_batch(int32_t method, const fv_trans* models, const float* const* 
             if (pi)
                 hipLaunchKernelGGL(fv_validate_array_kernel, dim3(grid_for(kk)), dim3(kBlock), 0, stream, pi, kk,
                                    bad_model + p);
-            hipLaunchKernelGGL(fv_validate_seqs_kernel, dim3((unsigned)std::min(n_desc, 4096)), dim3(kBlock), 0,
-                               stream, sd, n_desc, single ? 0 : bp.model[p], A->K, bad_seq);
+            if (emit.kind == FV_EMIT_GAUSS2D) {
+                hipLaunchKernelGGL(fv_validate_points_kernel, dim3(grid_for(2 * kk)), dim3(kBlock), 0, stream,
+                                   emit.state_xy, 2 * kk, bad_model + p);
+                hipLaunchKernelGGL(fv_validate_obs_kernel, dim3((unsigned)std::min(n_desc, 4096)), dim3(kBlock), 0,
+                                   stream, sd, n_desc, single ? 0 : bp.model[p], bad_seq);
+            } else {
+                hipLaunchKernelGGL(fv_validate_seqs_kernel, dim3((unsigned)std::min(n_desc, 4096)), dim3(kBlock), 0,
+                                   stream, sd, n_desc, single ? 0 : bp.model[p], A->K, bad_seq);
+            }
         }
         EngineArgs& a = args[p];
         a = EngineArgs{};
@@ -623,6 +654,10 @@ fv_status run_batch(int32_t method, const fv_trans* models, const float* const* 
             a.in_val = static_cast<const float*>(at(L.csr_val));
             a.csr_flag = static_cast<int32_t*>(at(L.csr_flag));
         }
+        a.emit_kind = emit.kind;
+        a.emit_xy = emit.state_xy;
+        a.emit_c2 = emit.c2;
+        a.emit_c0 = emit.c0;
         a.alpha_at = static_cast<float*>(at(L.alpha));
         a.root_copy = static_cast<float*>(at(L.root));
         a.psi16 = static_cast<uint16_t*>(at(L.psi));
@@ -666,6 +701,7 @@ fv_status run_batch(int32_t method, const fv_trans* models, const float* const* 
         sa.K = A->K;
         sa.model = single ? 0 : bp.model[p];
         sa.n_local = n_local;
+        sa.emit_kind = emit.kind;
         sa.args_out = table + p;
         hipLaunchKernelGGL(fv_setup_kernel, dim3(1), dim3(kBlock), 0, stream, a, sa);
     }
@@ -875,6 +911,20 @@ fv_status fv_decode_batch(const fv_trans* models, const float* const* log_pi, in
     if (method == FV_FLASH && P <= 0) P = auto_parallelism(T_host, n_seqs);
     return run_batch(method, models, log_pi, n_models, seqs_dev, T_host, model_host, n_seqs, P, B, nullptr, status,
                      flags, ws, ws_bytes, reinterpret_cast<hipStream_t>(stream));
+}
+
+fv_status fv_decode_batch_emit(const fv_trans* models, const fv_emission* emissions, const float* const* log_pi,
+                               int32_t n_models, const fv_seq* seqs_dev, const int32_t* T_host,
+                               const int32_t* model_host, int32_t n_seqs, int32_t method, int32_t P, int32_t B,
+                               int32_t* status, uint32_t flags, void* ws, size_t ws_bytes, fv_stream_t stream) {
+    if (n_seqs < 0) return fail(FV_E_INVALID_ARG, "n_seqs < 0");
+    if (n_seqs > 0 && (!seqs_dev || !T_host)) return fail(FV_E_INVALID_ARG, "null sequence list");
+    if (method != FV_VANILLA && method != FV_FLASH && method != FV_BEAM)
+        return fail(FV_E_INVALID_ARG, "unknown method %d", method);
+    if (method == FV_BEAM && (B < 1 || P < 1)) return fail(FV_E_INVALID_ARG, "beam decoding needs B >= 1 and P >= 1");
+    if (method == FV_FLASH && P <= 0) P = auto_parallelism(T_host, n_seqs);
+    return run_batch(method, models, log_pi, n_models, seqs_dev, T_host, model_host, n_seqs, P, B, nullptr, status,
+                     flags, ws, ws_bytes, reinterpret_cast<hipStream_t>(stream), emissions);
 }
 
 }  // extern "C"

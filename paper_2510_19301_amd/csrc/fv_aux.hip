@@ -79,6 +79,34 @@ extern "C" __global__ __launch_bounds__(kBlock) void fv_validate_seqs_kernel(con
     }
 }
 
+// Observation points of the Gaussian emission model must be finite.
+__device__ __forceinline__ bool bad_point(double x) { return !__builtin_isfinite(x); }
+
+// *flag = 1 if any of p[0..n) (float64 coordinates) is NaN or infinite.
+extern "C" __global__ __launch_bounds__(kBlock) void fv_validate_points_kernel(const double* __restrict__ p, int64_t n,
+                                                                               int32_t* __restrict__ flag) {
+    if (!p) return;
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        bad |= bad_point(p[i]);
+    if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(flag, 1);
+}
+
+// bad_seq[b] = 1 if sequence b (of model `model`) has a NaN or infinite
+// coordinate among its observations (float64 [T][2] at its log_b field).
+extern "C" __global__ __launch_bounds__(kBlock) void fv_validate_obs_kernel(const fv_seq* __restrict__ seqs,
+                                                                            int32_t n_seqs, int32_t model,
+                                                                            int32_t* __restrict__ bad_seq) {
+    for (int32_t b = blockIdx.x; b < n_seqs; b += gridDim.x) {
+        const fv_seq d = seqs[b];
+        if (d.model != model || d.T <= 0 || !d.log_b) continue;
+        const double* o = reinterpret_cast<const double*>(d.log_b);
+        bool bad = false;
+        for (int64_t i = threadIdx.x; i < 2 * (int64_t)d.T; i += kBlock) bad |= bad_point(o[i]);
+        if (__syncthreads_or(bad) && threadIdx.x == 0) bad_seq[b] = 1;
+    }
+}
+
 }  // namespace fv
 
 using namespace fv;

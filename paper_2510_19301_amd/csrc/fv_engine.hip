@@ -124,6 +124,34 @@ __device__ __forceinline__ unsigned long long order_key(float v, int32_t j) {
     return ((unsigned long long)o << 32) | (unsigned long long)(0xFFFFFFFFu - (uint32_t)j);
 }
 
+// Emission score of the Gaussian point model: state j's point xy[j] against
+// observation t's point obs[t], in float64 with each operation rounded once
+// (no contraction into fused multiply-adds), then rounded to float32:
+// (float)(c2 * ((x - u)^2 + (y - v)^2) - c0).
+__device__ __forceinline__ float gauss2d_score(const double* __restrict__ xy, const double* __restrict__ obs,
+                                               double c2, double c0, int32_t t, int32_t j) {
+#pragma clang fp contract(off)
+    const double dx = xy[2 * (int64_t)j] - obs[2 * (int64_t)t];
+    const double dy = xy[2 * (int64_t)j + 1] - obs[2 * (int64_t)t + 1];
+    const double sx = dx * dx;
+    const double sy = dy * dy;
+    const double d2 = sx + sy;
+    const double e = c2 * d2;
+    return (float)(e - c0);
+}
+
+// log B_t(j) of a sequence whose emission data starts at lb: its table's
+// entry lb[t * ld + j], or the Gaussian point model's score with lb
+// addressing the observations (float64 [T][2]).  emit_kind is uniform.
+__device__ __forceinline__ float emission_of(int32_t kind, const double* xy, double c2, double c0,
+                                             const float* __restrict__ lb, int64_t ld, int32_t t, int32_t j) {
+    if (kind == FV_EMIT_TABLE) return lb[(int64_t)t * ld + j];
+    return gauss2d_score(xy, reinterpret_cast<const double*>(lb), c2, c0, t, j);
+}
+__device__ __forceinline__ float emission(cargs_t& a, const float* lb, int64_t ld, int32_t t, int32_t j) {
+    return emission_of(a.emit_kind, a.emit_xy, a.emit_c2, a.emit_c0, lb, ld, t, j);
+}
+
 __device__ __forceinline__ float* slot_delta(cargs_t& a, int32_t slot, int32_t parity) {
     return a.slot_base + (int64_t)slot * a.slot_floats + (int64_t)parity * a.Kp;
 }
@@ -1140,7 +1168,7 @@ __device__ __noinline__ void sparse_unit(cargs_t& a_in, const Row* list, int32_t
     const float* __restrict__ in_val = a.in_val;
     unsigned long long key = 0;
     if (j < K) {
-        const float bt = r.log_b[(int64_t)t * r.ld + j];
+        const float bt = emission(a, r.log_b, r.ld, t, j);
         const int32_t e0 = in_ptr[j], e1 = in_ptr[j + 1];
         float dnew;
         int32_t psi = 0, pslot = 0;
@@ -1651,7 +1679,9 @@ __device__ __forceinline__ void sp_out_range(const int32_t* row_ptr, int64_t nnz
 // predecessor, 2 its anchor); returns their count.  More than kSpCandMax
 // candidates: the sequence fails with FV_E_UNSUPPORTED (the first
 // kSpCandMax are used, so every access stays in range).
-__device__ int32_t sparse_push(cargs_t& a, SeqInfo& sq, int32_t nb, int32_t mode, const float* bt) {
+// lb, ld, t: the emission data of the destinations' step.
+__device__ int32_t sparse_push(cargs_t& a, SeqInfo& sq, int32_t nb, int32_t mode, const float* lb, int64_t ld,
+                               int32_t t) {
     BeamLds& L = g_lds.beam;
     SpBeamLds& S = g_lds.spbeam;
     const int tid = threadIdx.x;
@@ -1720,7 +1750,7 @@ __device__ int32_t sparse_push(cargs_t& a, SeqInfo& sq, int32_t nb, int32_t mode
         }
         const int32_t b = sp_owner(S.offs, nb, w);
         S.ds[o] = (int32_t)j;
-        S.dv[o] = c + bt[j];
+        S.dv[o] = c + emission(a, lb, ld, t, (int32_t)j);
         S.da[o] = mode == 1 ? L.bs[b] : (mode == 2 ? L.ba[b] : -1);
         ++o;
     }
@@ -1774,8 +1804,9 @@ __device__ __noinline__ void beam_row(cargs_t& a_in, const float* __restrict__ A
                     }
                     for (int32_t k = tid; k < nc; k += kEngBlock) {
                         const int32_t j = c0 + k;
+                        const float e = emission(a, r.log_b, r.ld, 0, j);
                         L.cs[nk + k] = j;
-                        L.cv[nk + k] = a.log_pi ? a.log_pi[j] + bm[j] : bm[j];
+                        L.cv[nk + k] = a.log_pi ? a.log_pi[j] + e : e;
                         L.ca[nk + k] = -1;
                     }
                     __syncthreads();
@@ -1789,7 +1820,7 @@ __device__ __noinline__ void beam_row(cargs_t& a_in, const float* __restrict__ A
                 if (tid == 0) { L.bs[0] = q; L.bv[0] = alpha; L.ba[0] = -1; }
                 __syncthreads();
                 const SpBeamLds& S = g_lds.spbeam;
-                const int32_t nd = q >= 0 ? sparse_push(a, sq, 1, 0, bm) : 0;
+                const int32_t nd = q >= 0 ? sparse_push(a, sq, 1, 0, r.log_b, r.ld, m) : 0;
                 nk = beam_select(nd, B, S.dv, S.ds, 0, S.da, [&](int32_t p, int32_t st, float sv, int32_t av) {
                     out.s[p] = st; out.v[p] = sv; out.a[p] = av;
                 });
@@ -1837,7 +1868,7 @@ __device__ __noinline__ void beam_row(cargs_t& a_in, const float* __restrict__ A
         const float* bt = r.log_b + (int64_t)t * r.ld;
         if (a.sparse) {
             const SpBeamLds& S = g_lds.spbeam;
-            const int32_t nd = sparse_push(a, sq, nb, mode, bt);
+            const int32_t nd = sparse_push(a, sq, nb, mode, r.log_b, r.ld, t);
             const BeamRec out = slot_part(a, slot, t & 1, 0);
             const int32_t nk = beam_select(nd, B, S.dv, S.ds, 0, S.da, [&](int32_t p, int32_t st, float sv, int32_t av) {
                 out.s[p] = st; out.v[p] = sv; out.a[p] = av;
@@ -4086,7 +4117,8 @@ extern "C" __global__ __launch_bounds__(kBlock) void fv_setup_kernel(EngineArgs 
         int32_t pp = 1;
         const bool member = b < sa.n_seqs && (d = sa.seqs_dev[b]).model == sa.model;
         if (member) {
-            if (d.T < 0 || (d.T > 0 && (d.ld < sa.K || !d.log_b || !d.path)) || !d.score) s_bad = 1;
+            const bool table = sa.emit_kind == FV_EMIT_TABLE;   // else log_b addresses observations
+            if (d.T < 0 || (d.T > 0 && ((table && d.ld < sa.K) || !d.log_b || !d.path)) || !d.score) s_bad = 1;
             const int32_t T = d.T < 0 ? 0 : d.T;
             pp = sa.kind == KIND_VANILLA ? 1 : eff_parallelism(T, sa.P);
             v[0] = T;
@@ -4107,7 +4139,7 @@ extern "C" __global__ __launch_bounds__(kBlock) void fv_setup_kernel(EngineArgs 
         const int64_t li = base[3] + scan[3][tid] - v[3];
         if (member && li < sa.n_local) {   // more members than the host counted: reported below
             SeqInfo si;
-            si.log_b = d.log_b; si.ld = d.ld; si.path = d.path; si.score = d.score;
+            si.log_b = d.log_b; si.ld = sa.emit_kind == FV_EMIT_TABLE ? d.ld : 0; si.path = d.path; si.score = d.score;
             si.T = d.T < 0 ? 0 : d.T;
             si.pp = pp;
             si.alpha_off = base[0] + scan[0][tid] - v[0];
@@ -4265,7 +4297,10 @@ extern "C" __global__ __launch_bounds__(kBlock) void fv_beam_finish_kernel(Engin
         const int32_t q0 = sq.path[0];
         bool ok = q0 >= 0 && q0 < K;
         float s = -INFINITY;
-        if (ok) s = a.log_pi ? a.log_pi[q0] + sq.log_b[q0] : sq.log_b[q0];
+        if (ok) {
+            const float e = emission_of(a.emit_kind, a.emit_xy, a.emit_c2, a.emit_c0, sq.log_b, sq.ld, 0, q0);
+            s = a.log_pi ? a.log_pi[q0] + e : e;
+        }
         for (int32_t t0 = 1; ok && t0 < T; t0 += 64) {
             const int32_t t = t0 + lane;
             float ta = 0.0f, tb = 0.0f;
@@ -4287,7 +4322,7 @@ extern "C" __global__ __launch_bounds__(kBlock) void fv_beam_finish_kernel(Engin
                     } else {
                         ta = Ap[(int64_t)qp * Kp + q];
                     }
-                    tb = sq.log_b[(int64_t)t * sq.ld + q];
+                    tb = emission_of(a.emit_kind, a.emit_xy, a.emit_c2, a.emit_c0, sq.log_b, sq.ld, t, q);
                 }
             }
             if (__ballot(bad) != 0) { ok = false; break; }

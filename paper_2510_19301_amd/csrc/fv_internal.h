@@ -227,6 +227,12 @@ struct EngineArgs {
     int32_t n_compute_blocks;   // blocks 1..n_compute_blocks compute; block 0 schedules
     int64_t spin_limit;
     int64_t max_steps;          // guard against a runaway schedule
+    // emission model (sparse models only): FV_EMIT_TABLE reads each row's
+    // log_b table; FV_EMIT_GAUSS2D scores the observation points that
+    // log_b then addresses (float64 [T][2]) against emit_xy
+    int32_t emit_kind;
+    const double* emit_xy;      // [K][2] state points
+    double emit_c2, emit_c0;    // log B_t(j) = (float)(c2 * d2 - c0)
     // input validation (FV_FLAG_VALIDATE): null when not requested
     const int32_t* bad_seq;     // [caller's n_seqs] nonzero: NaN or +inf in that sequence's log B
     const int32_t* bad_model;   // nonzero: NaN or +inf in this model's log A or log pi
@@ -256,6 +262,7 @@ struct SetupArgs {
     int32_t K;
     int32_t model;          // this decode takes the sequences whose model index equals this
     int32_t n_local;        // the host's count of them
+    int32_t emit_kind;      // FV_EMIT_TABLE: log_b is a table of ld >= K floats per step
     EngineArgs* args_out;   // the engine's copy of its arguments (workspace)
 };
 

@@ -6,6 +6,7 @@ HIP stream; every decoding step runs in libflashviterbi.so.
 from __future__ import annotations
 
 import ctypes as C
+import math
 
 import numpy as np
 import torch
@@ -143,6 +144,28 @@ def decode(log_a, log_b: torch.Tensor, log_pi: torch.Tensor | None = None,
     return path, score, status
 
 
+class GaussEmission:
+    """Emission model generated inside the decode (CSR models): state j sits
+    at the point state_xy[j] (float64 [K, 2] CUDA tensor) and each
+    observation is a point; log B_t(j) = c2 * |state_xy[j] - obs_t|^2 - c0 in
+    float64 (each operation rounded once), then float32.  Sequences of such a
+    model are given as observations (Batch.observations)."""
+
+    def __init__(self, state_xy: torch.Tensor, c2: float, c0: float):
+        _need(state_xy, "state_xy", torch.float64)
+        if state_xy.dim() != 2 or state_xy.shape[1] != 2 or not state_xy.is_contiguous():
+            raise ValueError("state_xy must be a contiguous [K, 2] tensor")
+        self.K = state_xy.shape[0]
+        self.keep = state_xy
+        self.desc = L.FvEmission(L.FV_EMIT_GAUSS2D, state_xy.data_ptr(), float(c2), float(c0))
+
+    @classmethod
+    def from_sigma(cls, state_xy: torch.Tensor, sigma: float) -> "GaussEmission":
+        """A Gaussian of standard deviation sigma on the distance:
+        c2 = -1 / (2 sigma^2), c0 = ln(sigma sqrt(2 pi))."""
+        return cls(state_xy, -1.0 / (2.0 * (sigma * sigma)), math.log(sigma * math.sqrt(2.0 * math.pi)))
+
+
 class Batch:
     """Device descriptors of a batch of sequences.
 
@@ -150,11 +173,33 @@ class Batch:
     lengths.  models: per-sequence model index (host ints) for batches over
     several transition models (default: all 0).  Outputs are a padded int32
     [n, Tmax] path tensor (entries past each length untouched) and float32
-    [n] scores.
+    [n] scores.  Batch.observations builds a batch of observation sequences
+    for models with a generated emission (GaussEmission).
     """
 
-    def __init__(self, log_b, lengths=None, models=None):
-        if isinstance(log_b, torch.Tensor):
+    @classmethod
+    def observations(cls, obs, models=None) -> "Batch":
+        """A batch of observation sequences: a list of float64 [T_b, 2]
+        contiguous CUDA tensors (each row one observed point)."""
+        seqs = list(obs)
+        for k, x in enumerate(seqs):
+            _need(x, f"obs[{k}]", torch.float64)
+            if x.dim() != 2 or x.shape[1] != 2 or not x.is_contiguous():
+                raise ValueError("each observation sequence must be a contiguous [T, 2] tensor")
+        return cls(seqs, models=models, _observations=True)
+
+    def __init__(self, log_b, lengths=None, models=None, _observations=False):
+        self.is_observations = _observations
+        if _observations:
+            seqs = list(log_b)
+            n = len(seqs)
+            lengths = np.array([x.shape[0] for x in seqs], np.int32)
+            tmax = int(lengths.max()) if n else 0
+            ptrs = [x.data_ptr() for x in seqs]
+            ld = [0] * n
+            self.keep = seqs
+            dev = seqs[0].device if n else torch.device("cuda")
+        elif isinstance(log_b, torch.Tensor):
             _need(log_b, "log_b")
             if log_b.dim() != 3 or log_b.stride(2) != 1:
                 raise ValueError("padded log_b must be [n, Tmax, ld] with unit column stride")
@@ -197,15 +242,18 @@ class Batch:
 
 def decode_batch(log_a, batch: Batch, log_pi=None, method: str = "flash", P: int = 16, B: int = 0,
                  ws: torch.Tensor | None = None, rows: str = "auto", validate: bool = False,
-                 leaves: bool = True, relative_init: bool = False, step: str = "auto", engine: bool = False):
+                 leaves: bool = True, relative_init: bool = False, step: str = "auto", engine: bool = False,
+                 emission=None):
     """Decode all sequences of `batch` in one decode launch (the persistent
     engine, or one block per sequence for vanilla and FLASH when every dense
     model has K <= 256).  log_a: a
     dense [K, K] tensor or a CsrModel, or a list of them when the batch's
     sequences use several models (batch.models indexes it); log_pi: a [K]
     tensor or None, or a list matching log_a.  Results land in batch.paths
-    / batch.scores / batch.status.  Returns the workspace tensor so callers
-    can reuse it."""
+    / batch.scores / batch.status.  emission: a GaussEmission (or a list
+    of them, one per model) whose scores are generated in the decode; the
+    batch then holds observations (Batch.observations).  Returns the
+    workspace tensor so callers can reuse it."""
     many = isinstance(log_a, (list, tuple))
     mods = list(log_a) if many else [log_a]
     pis = list(log_pi) if isinstance(log_pi, (list, tuple)) else [log_pi] * len(mods)
@@ -224,12 +272,33 @@ def decode_batch(log_a, batch: Batch, log_pi=None, method: str = "flash", P: int
         ws = _workspace(n, dev)
     pa = (C.c_void_p * len(mods))(*[p.data_ptr() if p is not None else None for p in pis])
     lengths = np.ascontiguousarray(batch.lengths, np.int32)
-    rc = L.lib().fv_decode_batch(trans, C.cast(pa, C.c_void_p), len(mods), batch.desc.data_ptr(),
-                                 lengths.ctypes.data, batch.models.ctypes.data, batch.n, L.METHODS[method],
-                                 int(P), int(B or 0), batch.status.data_ptr(),
-                                 _flags(rows, validate, leaves, relative_init, step, engine),
-                                 ws.data_ptr(), ws.numel(), _stream(dev))
-    L.check(rc, "fv_decode_batch")
+    flags = _flags(rows, validate, leaves, relative_init, step, engine)
+    if emission is None:
+        if batch.is_observations:
+            raise ValueError("a batch of observations needs an emission model")
+        rc = L.lib().fv_decode_batch(trans, C.cast(pa, C.c_void_p), len(mods), batch.desc.data_ptr(),
+                                     lengths.ctypes.data, batch.models.ctypes.data, batch.n, L.METHODS[method],
+                                     int(P), int(B or 0), batch.status.data_ptr(), flags,
+                                     ws.data_ptr(), ws.numel(), _stream(dev))
+        L.check(rc, "fv_decode_batch")
+        return ws
+    ems = list(emission) if isinstance(emission, (list, tuple)) else [emission]
+    if len(ems) != len(mods):
+        raise ValueError("emission must match the list of models")
+    if any(not isinstance(e, GaussEmission) for e in ems):
+        raise TypeError("emission must be a GaussEmission or a list of them")
+    if not batch.is_observations:
+        raise ValueError("generated emissions need a batch of observations (Batch.observations)")
+    desc = (L.FvEmission * len(mods))()
+    for m, e in enumerate(ems):
+        if e.K != trans[m].K:
+            raise ValueError(f"model {m}: {e.K} state points for K = {trans[m].K}")
+        desc[m] = e.desc
+    rc = L.lib().fv_decode_batch_emit(trans, desc, C.cast(pa, C.c_void_p), len(mods), batch.desc.data_ptr(),
+                                      lengths.ctypes.data, batch.models.ctypes.data, batch.n, L.METHODS[method],
+                                      int(P), int(B or 0), batch.status.data_ptr(), flags,
+                                      ws.data_ptr(), ws.numel(), _stream(dev))
+    L.check(rc, "fv_decode_batch_emit")
     return ws
 
 

@@ -173,6 +173,50 @@ def test_gather_emissions():
             assert lb[t, j] == h.log_e[j, h.obs[t]]
 
 
+# ---------------------------------------------------------------- Gaussian point emissions (Sec. III)
+def test_gauss_emissions_by_hand():
+    """Points whose squared distances are short binary fractions: every
+    score is exact, so each entry is fixed (a swapped axis, a dropped or
+    sign-flipped constant, or transposed output changes one)."""
+    xy = np.array([[0.0, 0.0], [3.0, 4.0], [1.0, 1.0], [-2.0, 0.5]])
+    obs = np.array([[0.0, 0.0], [3.0, 0.0]])
+    got = oracle.gauss_emissions(xy, obs, -0.5, 0.25)
+    # squared distances: t = 0: 0, 25, 2, 4.25; t = 1: 9, 16, 5, 25.25
+    want = np.array([[-0.25, -12.75, -1.25, -2.375], [-4.75, -8.25, -2.75, -12.875]], np.float32)
+    assert got.shape == (2, 4)
+    assert (_bits(got) == _bits(want)).all()
+    # c2 * 0 is -0 for c2 < 0, and -0 - 0 stays -0
+    z = oracle.gauss_emissions(xy[:1], obs[:1], -0.5, 0.0)
+    assert _bits(z)[0, 0] == 0x80000000
+
+
+def test_gauss_emissions_match_normal_log_density():
+    """With c2 = -1/(2 sigma^2) and c0 = ln(sigma sqrt(2 pi)) the score is
+    the normal log-density of the distance (scipy's), to float32 rounding."""
+    from scipy.stats import norm
+    rng = np.random.default_rng(5)
+    xy, obs, sigma = rng.random((300, 2)), rng.random((40, 2)), 0.05
+    c2, c0 = oracle.gauss_coefficients(sigma)
+    got = oracle.gauss_emissions(xy, obs, c2, c0)
+    d = np.hypot(xy[None, :, 0] - obs[:, None, 0], xy[None, :, 1] - obs[:, None, 1])
+    ref = norm.logpdf(d, 0.0, sigma).astype(np.float32)
+    np.testing.assert_array_max_ulp(got, ref, maxulp=1)
+    # at distance sigma the density is exp(-1/2) of its peak
+    on = oracle.gauss_emissions(np.array([[0.0, 0.0]]), np.array([[sigma, 0.0]]), c2, c0)
+    assert abs(float(on[0, 0]) - (-0.5 - np.log(sigma * np.sqrt(2 * np.pi)))) < 1e-6
+
+
+def test_gauss_emissions_equal_map_matching_tables():
+    """The map-matching generator's own float64 tables equal the oracle's
+    evaluation bit for bit (the table decodes and the generated-emission
+    decodes see the same scores)."""
+    wl = hmm.map_matching_workload(K=2000, n=3, t_lo=20, t_hi=50)
+    c2, c0 = oracle.gauss_coefficients(wl.sigma_gps)
+    for b in range(wl.n):
+        got = oracle.gauss_emissions(wl.xy, wl.gps(b), c2, c0)
+        assert (_bits(got) == _bits(wl.log_b(b).numpy())).all()
+
+
 # ---------------------------------------------------------------- FLASH (Alg. 1 + Alg. 2)
 def _ptilde(T, P):
     return min(max(P, 2), T) if T > 1 else 1
