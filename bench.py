@@ -441,6 +441,9 @@ def main():
                     help="skip the FV_FLAG_RELATIVE_INIT divergence measurement")
     ap.add_argument("--no-er", action="store_true",
                     help="skip the Erdos-Renyi sweeps (p, K, T, beam width)")
+    ap.add_argument("--no-headline", action="store_true",
+                    help="skip the batched workload (headline and sweep): a profiling mode for the other "
+                         "parts; the JSON line then carries only those parts")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--n", type=int, default=256)
@@ -482,6 +485,12 @@ def main():
 
     import paper_2510_19301_amd as fv
     from workloads import hmm
+    if args.no_headline:
+        out = {"profiling_mode": "no headline"}
+        _other_parts(args, out, fv, torch, hmm, dev)
+        print(json.dumps(out), flush=True)
+        torch.cuda.synchronize()
+        return
     wl = hmm.batched_flash_workload(n=args.n)
     K = wl.K
     print(f"[bench] generating workload: {wl.n} sequences, K={K}, sum T={wl.total_steps()}", file=sys.stderr, flush=True)
@@ -549,9 +558,19 @@ def main():
     }
     if rel is not None:
         out["relative_init"] = rel
+    del lbs, batch, ws
+    torch.cuda.empty_cache()
+    _other_parts(args, out, fv, torch, hmm, dev)
+    if not args.no_cpu:
+        print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds, args.P)
+    print(json.dumps(out), flush=True)
+    torch.cuda.synchronize()
+
+
+def _other_parts(args, out, fv, torch, hmm, dev):
+    """The runs beside the headline: large dense, sparse, small, sweeps."""
     if not args.no_large:
-        del lbs, batch, ws
-        torch.cuda.empty_cache()
         out["large"] = large_runs(fv, torch, hmm, dev)
     if not args.no_sparse:
         torch.cuda.empty_cache()
@@ -560,11 +579,6 @@ def main():
         out.update(small_runs(fv, torch, hmm, dev))
     if not args.no_er:
         out["er_sweeps"] = er_runs(fv, torch, hmm, dev)
-    if not args.no_cpu:
-        print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds, args.P)
-    print(json.dumps(out), flush=True)
-    torch.cuda.synchronize()
 
 
 def _release_device():

@@ -1008,13 +1008,13 @@ __device__ __forceinline__ unsigned long long slab_row_key(const float* dr, cons
 // (the outputs of a column item).
 template <int KP>
 __device__ __forceinline__ void slab_chunk(cargs_t& a, gfloat_t* Ag, const Row* list, int32_t nf, int64_t u0,
-                                           int32_t R, float (&av)[64], int32_t& loaded) {
+                                           int32_t R, float (&av)[64], int32_t& loaded, bool rows_ready = false) {
     constexpr int32_t wpc = KP / 64, pcols = (kEngWaves / wpc) * 64;
     SlabLds& L = g_lds.slab;
     const int32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int32_t K = a.K;
     const int32_t csl = w / wpc, pw = w - csl * wpc;
-    if (tid < R) {
+    if (tid < R && !rows_ready) {   // (rows_ready: read while the step barrier was closing)
         const int64_t u = u0 + tid;
         const int32_t p = (int32_t)(u / nf);
         L.rows[tid] = ld_row(list + (int32_t)(u - (int64_t)p * nf));
@@ -1110,38 +1110,83 @@ __device__ __forceinline__ void slab_chunk(cargs_t& a, gfloat_t* Ag, const Row* 
 }
 
 // This block's share of the dense rows of its XCD at one step (rank among the
-// XCD's nx compute blocks; the scheduler block, rank -1, takes none).  When
+// XCD's nsl slab blocks; the scheduler block, rank -1, takes none).  When
 // the blocks divide evenly over the column passes, each pass gets a team of
-// nx / npass blocks that split its rows, so no block loads two slabs; else
+// nsl / npass blocks that split its rows, so no block loads two slabs; else
 // the units (row, pass), pass-major, are split evenly, and a chunk may span
 // two passes.
-template <int KP>
-__device__ __forceinline__ void slab_items_kp(cargs_t& a, const float* __restrict__ Ap, int32_t nx, int32_t rank,
-                                              const Row* list, int32_t nf) {
-    constexpr int32_t wpc = KP / 64, pcols = (kEngWaves / wpc) * 64;
-    constexpr int32_t npass = KP / pcols, crows = kEngBlock / pcols;
-    int64_t u, u1;
-    if (nx % npass == 0) {
-        const int32_t team = nx / npass, p = rank / team, m = rank - p * team;
-        u = (int64_t)p * nf + ((int64_t)m * nf) / team;
-        u1 = (int64_t)p * nf + ((int64_t)(m + 1) * nf) / team;
+struct SlabShare {
+    int64_t u, u1;   // this block's units
+    int32_t nsl;     // blocks sharing the slab units (the others take block and light rows)
+    int32_t nbx;     // block rows and light rows set aside for the other blocks
+    int32_t lo_light;
+};
+
+// A block row (a finalize or a leaf's end) or a light row run after a full
+// slab share would finish last: up to a quarter of the XCD's blocks take
+// them instead (one block row per block, one light row per wave) and the
+// others split the slab units.
+__device__ __forceinline__ SlabShare slab_share(cargs_t& a, int32_t nx, int32_t rank, int32_t nf, int32_t nl,
+                                                int32_t nbm) {
+    SlabShare sh;
+    sh.nsl = nx;
+    sh.nbx = 0;
+    sh.lo_light = 0;
+    if (a.method != FV_BEAM && nx > 0) {
+        const int32_t cap = nx / 4;
+        sh.nbx = min(nbm, cap);
+        const int32_t nlx = min((nl + kEngWaves - 1) / kEngWaves, cap - sh.nbx);
+        sh.nsl = nx - sh.nbx - nlx;
+        sh.lo_light = min(nl, nlx * kEngWaves);
+    }
+    const int32_t wpc = a.Kp / 64, pcols = (kEngWaves / wpc) * 64, npass = a.Kp / pcols;
+    sh.u = sh.u1 = 0;
+    if (rank < 0 || rank >= sh.nsl || nf <= 0) return sh;
+    if (sh.nsl % npass == 0) {
+        const int32_t team = sh.nsl / npass, p = rank / team, m = rank - p * team;
+        sh.u = (int64_t)p * nf + ((int64_t)m * nf) / team;
+        sh.u1 = (int64_t)p * nf + ((int64_t)(m + 1) * nf) / team;
     } else {
         const int64_t U = (int64_t)nf * npass;
-        u = U * rank / nx;
-        u1 = U * (rank + 1) / nx;
+        sh.u = U * rank / sh.nsl;
+        sh.u1 = U * (rank + 1) / sh.nsl;
     }
+    return sh;
+}
+
+template <int KP>
+__device__ __forceinline__ void slab_items_kp(cargs_t& a, const float* __restrict__ Ap, const Row* list, int32_t nf,
+                                              int64_t u, int64_t u1, bool first_ready) {
+    constexpr int32_t pcols = (kEngWaves / (KP / 64)) * 64, crows = kEngBlock / pcols;
     gfloat_t* Ag = as_global(Ap);
     float av[64];
     int32_t loaded = -1;
-    for (; u < u1; u += crows) slab_chunk<KP>(a, Ag, list, nf, u, (int32_t)min((int64_t)crows, u1 - u), av, loaded);
+    for (int64_t u0 = u; u0 < u1; u0 += crows)
+        slab_chunk<KP>(a, Ag, list, nf, u0, (int32_t)min((int64_t)crows, u1 - u0), av, loaded,
+                       first_ready && u0 == u);
 }
 
-__device__ __forceinline__ void slab_items(cargs_t& a_in, const float* __restrict__ Ap, int32_t nx, int32_t rank,
-                                           const Row* list, int32_t nf) {
-    cargs_t& a = uniform_args(a_in);
-    if (rank < 0 || nf <= 0 || nx <= 0) return;
-    if (a.Kp == 1024) slab_items_kp<1024>(a, Ap, nx, rank, list, nf);
-    else slab_items_kp<512>(a, Ap, nx, rank, list, nf);
+// While the step barrier closes, once the next step's counts are known:
+// read this block's first chunk of rows for that step into LDS (the
+// scheduler wrote them before the counts word).  Returns the chunk's first
+// unit, or -1.
+__device__ __forceinline__ int64_t slab_prefetch_rows(cargs_t& a, uint32_t x, int32_t nx, int32_t rank, int nxt,
+                                                      unsigned long long cw) {
+    SlabLds& L = g_lds.slab;
+    const int32_t nf = (int32_t)(cw & 0x3fff), nl = (int32_t)((cw >> 14) & 0x3fff), nbm = (int32_t)((cw >> 28) & 0x3fff);
+    if (((cw >> 42) & 1) || nf <= 0 || nf > kLocalColRows || a.force_tiles || a.sparse) return -1;
+    const SlabShare sh = slab_share(a, nx, rank, nf, nl, nbm);
+    if (sh.u >= sh.u1) return -1;
+    const int32_t pcols = (kEngWaves / (a.Kp / 64)) * 64, crows = kEngBlock / pcols;
+    const int32_t R = (int32_t)min((int64_t)crows, sh.u1 - sh.u);
+    const int32_t tid = threadIdx.x;
+    if (tid < R) {
+        const int64_t u = sh.u + tid;
+        const int32_t p = (int32_t)(u / nf);
+        L.rows[tid] = ld_row(list_full(a, nxt, x) + (int32_t)(u - (int64_t)p * nf));
+        L.upass[tid] = p;
+    }
+    return sh.u;
 }
 
 // ---------------------------------------------------------------- sparse rows
@@ -2764,22 +2809,49 @@ __device__ __noinline__ void admit(cargs_t& a_in, int nxt, uint32_t tag) {
             sl.admit[y] -= cut;
             given -= cut;
         }
+        if (a.wide) {
+            // wide rows are computed by every block whatever their list, in
+            // groups of kWideRows per list, and each group streams log A
+            // once per step: fill the lists in order so that rows share
+            // groups (spread over the XCDs, eight single rows would stream
+            // log A eight times)
+            int32_t left = n_admit;
+            for (int y = 0; y < kXcd; ++y) {
+                sl.admit[y] = min(cap[y], left);
+                left -= sl.admit[y];
+            }
+        }
     }
     __syncthreads();
     const int x = threadIdx.x / kSchedGroup, tg = threadIdx.x % kSchedGroup;
-    // the admitted tasks are dealt over the XCDs in queue order, round k
-    // going up the XCDs for even k and down for odd k (a snake, so that with
-    // the queue sorted longest first no XCD always gets the longest of a
-    // round): XCD x's k-th task is batch entry sum_y min(admit[y], k) plus the
-    // XCDs dealt before x in round k
+    // the admitted tasks are dealt over the XCDs in proportion to their
+    // quotas: XCD y's i-th task has the key (2i + 1) / admit[y] (the middle
+    // of its share of the batch), and the batch is taken in key order, so
+    // that with the queue sorted longest first every XCD gets the same mix of
+    // long and short tasks whatever its quota.  Equal keys go up the XCDs for
+    // even i and down for odd i (a snake: with equal quotas no XCD always gets
+    // the longest task of a round).  XCD x's k-th task is batch entry q_head
+    // + k + the number of other XCDs' tasks before it.
     int32_t qa[kXcd];
 #pragma unroll
     for (int y = 0; y < kXcd; ++y) qa[y] = sl.admit[y];
+    auto before = [&](int32_t y, int32_t i, int32_t k) -> bool {   // (y, i) ahead of (x, k)
+        const int64_t l = (int64_t)(2 * i + 1) * qa[x], r = (int64_t)(2 * k + 1) * qa[y];
+        if (l != r) return l < r;
+        const int32_t sy = (i & 1) ? kXcd - 1 - y : y, sx = (k & 1) ? kXcd - 1 - x : x;
+        return sy != sx ? sy < sx : y < x;
+    };
     auto dealt = [&](int32_t k) -> int32_t {
-        int32_t pos = sl.q_head;
-        const bool up = (k & 1) == 0;
-#pragma unroll
-        for (int y = 0; y < kXcd; ++y) pos += min(qa[y], k) + (((up ? y < x : y > x) && qa[y] > k) ? 1 : 0);
+        int32_t pos = sl.q_head + k;
+        for (int y = 0; y < kXcd; ++y) {
+            if (y == x || qa[y] == 0) continue;
+            int32_t lo = 0, hi = qa[y];   // tasks of y ahead of (x, k): a prefix of its range
+            while (lo < hi) {
+                const int32_t mid = (lo + hi) >> 1;
+                if (before(y, mid, k)) lo = mid + 1; else hi = mid;
+            }
+            pos += lo;
+        }
         return pos;
     };
     const int32_t ax = sl.admit[x];
@@ -2797,6 +2869,10 @@ __device__ __noinline__ void admit(cargs_t& a_in, int nxt, uint32_t tag) {
         const int32_t li = start_list(a, tk.kind);
         st_row(out[li] + sl.n_next[x][li] + c[li]++, r);
     }
+    // every row of the coming step (successors and admissions) is written
+    // before the counts word that announces it: compute blocks read their
+    // first rows as soon as they see that word, before the barrier opens
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     if (tg == 0) {
         for (int k = 0; k < 3; ++k) sl.n_next[x][k] += tot[k];
@@ -2926,6 +3002,56 @@ __device__ bool barrier_arrive_wait(cargs_t& a, uint32_t epoch, uint32_t x, unsi
     return s_err == 0;
 }
 
+// The step barrier of a compute block of a slab model: arrive; as soon as
+// the scheduler has published the next step's counts (it does so before the
+// barrier opens), read the block's first rows for that step; then wait for
+// the barrier.  ready_u: the first unit of the rows read, or -1.
+__device__ __forceinline__ bool barrier_slab(cargs_t& a, uint32_t epoch, uint32_t x, int32_t nx, int32_t rank, int nxt,
+                                             unsigned long long& counts, int64_t& ready_u) {
+    __shared__ int s_err2, s_open2;
+    __shared__ unsigned long long s_counts2;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        step_release(false);
+        st_c(a.arrive + blockIdx.x, epoch);
+        int err = 0, open = 0;
+        int64_t spins = 0;
+        const unsigned long long want = (unsigned long long)(epoch & kTagMask);
+        unsigned long long cw = 0;
+        for (;;) {   // until the counts word of the coming step is there
+            const uint32_t g = ld_c(&a.st->go[x][0]);
+            cw = ld_c(&a.st->cntw[x][0]);
+            if ((cw >> kTagShift) == want) { open = g >= epoch; break; }
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > a.spin_limit) { st_c(&a.st->error, 1); err = 1; break; }
+            if ((spins & 255) == 0 && ld_c(&a.st->error)) { err = 1; break; }
+        }
+        s_err2 = err;
+        s_open2 = open;
+        s_counts2 = cw;
+    }
+    __syncthreads();
+    const unsigned long long cw = s_counts2;
+    counts = cw;
+    ready_u = s_err2 == 0 ? slab_prefetch_rows(a, x, nx, rank, nxt, cw) : -1;
+    if (threadIdx.x == 0) {
+        int err = s_err2;
+        int64_t spins = 0;
+        if (!err && !s_open2) {
+            for (;;) {   // until the barrier opens
+                if (ld_c(&a.st->go[x][0]) >= epoch) break;
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > a.spin_limit) { st_c(&a.st->error, 1); err = 1; break; }
+                if ((spins & 255) == 0 && ld_c(&a.st->error)) { err = 1; break; }
+            }
+        }
+        step_acquire(false);
+        s_err2 = err || ld_c(&a.st->error) != 0;
+    }
+    __syncthreads();
+    return s_err2 == 0;
+}
+
 __device__ bool barrier_master(cargs_t& a, uint32_t epoch) {
     __shared__ int s_err;
     __syncthreads();
@@ -3051,8 +3177,9 @@ __device__ __forceinline__ void local_col_items(cargs_t& a_in, uint32_t x, int32
 // counter; every block (and the scheduler block once its own work is done)
 // takes a first item by rank, then claims until none are left.
 template <bool WIDE, bool SLAB>
-__device__ void run_units(cargs_t& a, const float* __restrict__ Ap, uint32_t x, int32_t nx, int32_t rank,
-                          int cur, int32_t nf, int32_t nl, int32_t nbm) {
+__device__ __forceinline__ void run_units(cargs_t& a, const float* __restrict__ Ap, uint32_t x, int32_t nx,
+                                          int32_t rank, int cur, int32_t nf, int32_t nl, int32_t nbm,
+                                          int64_t ready_u) {
     EngineLds& lds = g_lds;
     __shared__ int32_t s_unit;
     // few rows on this XCD: lane tiles would run mostly empty, so its rows are
@@ -3093,14 +3220,12 @@ __device__ void run_units(cargs_t& a, const float* __restrict__ Ap, uint32_t x, 
             // after a full slab share would finish last: up to a quarter of
             // the XCD's blocks take them instead (one block row per block, one
             // light row per wave) and the others split the slab units.
-            int32_t nsl = nx;
+            const SlabShare sh = slab_share(a, nx, rank, nf, nl, nbm);
+            const int32_t nsl = sh.nsl;
             if (a.method != FV_BEAM && nx > 0) {
-                const int32_t cap = nx / 4;
-                const int32_t nbx = min(nbm, cap);
-                const int32_t nlx = min((nl + kEngWaves - 1) / kEngWaves, cap - nbx);
-                nsl = nx - nbx - nlx;
+                const int32_t nbx = sh.nbx;
                 lo_block = nbx;
-                lo_light = min(nl, nlx * kEngWaves);
+                lo_light = sh.lo_light;
                 if (rank >= nsl) {
                     const int32_t e = rank - nsl;
                     if (e < nbx) {
@@ -3113,7 +3238,11 @@ __device__ void run_units(cargs_t& a, const float* __restrict__ Ap, uint32_t x, 
                     }
                 }
             }
-            if (rank >= 0 && rank < nsl) slab_items(a, Ap, nsl, rank, list_full(a, cur, x), nf);
+            if (sh.u < sh.u1) {
+                const bool ready = ready_u == sh.u;
+                if (a.Kp == 1024) slab_items_kp<1024>(a, Ap, list_full(a, cur, x), nf, sh.u, sh.u1, ready);
+                else slab_items_kp<512>(a, Ap, list_full(a, cur, x), nf, sh.u, sh.u1, ready);
+            }
         }
     } else {
         if (local_cols) local_col_items(a, x, nx, rank, cur, nf);
@@ -3244,6 +3373,7 @@ __device__ __noinline__ void engine_model(cargs_t& a_in) {
     if (ok) ok = is_sched ? barrier_master(a, epoch) : barrier_arrive_wait(a, epoch, x, cw);
 
     int32_t s = 0;
+    int64_t ready_u = -1;   // slab models: first unit of the rows read at the last barrier
     for (; ok; ++s) {
         const int cur = s & 1;
         // this step's counts on this XCD, and whether any row is left anywhere
@@ -3276,7 +3406,7 @@ __device__ __noinline__ void engine_model(cargs_t& a_in) {
         }
         if (is_sched) scheduler(a, s, epoch + 1);
         if (tr && is_sched && threadIdx.x == 0) tr[TR_SCHED] = __builtin_amdgcn_s_memrealtime();
-        run_units<WIDE, SLAB>(a, Ap, x, nx, rank, cur, nf, nl, nbm);
+        run_units<WIDE, SLAB>(a, Ap, x, nx, rank, cur, nf, nl, nbm, ready_u);
         if (tr && !is_sched) {
             __syncthreads();
             if (threadIdx.x == 0) {
@@ -3289,7 +3419,11 @@ __device__ __noinline__ void engine_model(cargs_t& a_in) {
             }
         }
         ++epoch;
-        ok = is_sched ? barrier_master(a, epoch) : barrier_arrive_wait(a, epoch, x, cw);
+        if constexpr (SLAB)
+            ok = is_sched ? barrier_master(a, epoch)
+                          : barrier_slab(a, epoch, x, nx, rank, (s + 1) & 1, cw, ready_u);
+        else
+            ok = is_sched ? barrier_master(a, epoch) : barrier_arrive_wait(a, epoch, x, cw);
     }
     if (is_sched && threadIdx.x == 0) st_c(&a.st->steps, s);
 }

@@ -110,3 +110,51 @@ def test_slab_signed_zero_across_columns(fv, K, T):
     assert po[-1] == 70 and _bits(so)[0] == 0x80000000
     for method, P in (("vanilla", 1), ("flash", 4)):
         _check(fv, lp, la, lbs, method, P)
+
+
+@pytest.mark.parametrize("seed,B,P", [(610, 2, 1), (610, 2, 2), (2428, 2, 2)])
+def test_slab_beam_fallback_exact_redecode(fv, seed, B, P):
+    """A narrow beam loses a subtask's known end state; the subtask is then
+    re-decoded exactly as a dense subtask on column slabs.  A small sparse
+    integer instance is embedded in K = 512 (the other states unreachable:
+    -inf start, transitions into and out of them -inf), so the beams, and the
+    fallback, are the small instance's."""
+    lp0, la0, lb0 = hmm.sparse_integer_instance(seed)
+    k0, T, K = la0.shape[0], lb0.shape[0], 512
+    lp = np.full(K, -np.inf, np.float32)
+    lp[:k0] = lp0
+    la = np.full((K, K), -np.inf, np.float32)
+    la[:k0, :k0] = la0
+    lb = np.zeros((T, K), np.float32)
+    lb[:, :k0] = lb0
+    po, so, rc, st = oracle.beam(lp, la, lb, B, P)
+    assert rc == oracle.BEAM_FALLBACK and st["fallbacks"] >= 1
+    print(f"slab beam fallback seed={seed} B={B} P={P}", flush=True)
+    path, score, status = fv.decode(_dev(la), _dev(lb), _dev(lp), method="beam", P=P, B=B, rows="local")
+    torch.cuda.synchronize()
+    assert int(status.item()) == fv.FV_W_BEAM_FALLBACK
+    assert (path.cpu().numpy() == po).all()
+    assert _bits(score.cpu().numpy()) == _bits(so)
+
+
+def test_slab_many_rows_per_xcd(fv):
+    """Row counts that move across the 160-rows-per-XCD line during one
+    launch (1500 sequences of K = 512: the first steps run as lane tiles,
+    later ones as slabs), every sequence checked."""
+    K = 512
+    rng = np.random.default_rng(41)
+    lp, la, _ = hmm.random_dense(K, 1, 41)
+    lens = [int(x) for x in rng.integers(2, 40, size=1500)]
+    lbs = [(rng.standard_normal((T, K)) * 2).astype(np.float32) for T in lens]
+    for method, P in (("flash", 4), ("vanilla", 1)):
+        print(f"slab many rows {method}", flush=True)
+        batch = fv.Batch([_dev(x) for x in lbs])
+        fv.decode_batch(_dev(la), batch, _dev(lp), method=method, P=P, rows="local")
+        torch.cuda.synchronize()
+        paths, scores, st = batch.paths.cpu().numpy(), batch.scores.cpu().numpy(), batch.status.cpu().numpy()
+        assert (st == fv.FV_OK).all()
+        with ThreadPoolExecutor(8) as ex:
+            refs = list(ex.map(lambda x: oracle.vanilla(lp, la, x), lbs))
+        for b, (po, so, _) in enumerate(refs):
+            assert (paths[b, :lens[b]] == po).all(), b
+            assert _bits(scores[b]) == _bits(so), b
