@@ -2809,12 +2809,13 @@ __device__ __noinline__ void admit(cargs_t& a_in, int nxt, uint32_t tag) {
             sl.admit[y] -= cut;
             given -= cut;
         }
-        if (a.wide) {
+        if (a.wide && a.method != FV_BEAM) {
             // wide rows are computed by every block whatever their list, in
             // groups of kWideRows per list, and each group streams log A
             // once per step: fill the lists in order so that rows share
             // groups (spread over the XCDs, eight single rows would stream
-            // log A eight times)
+            // log A eight times).  Beam tasks run on their own XCD's blocks
+            // and stay spread.
             int32_t left = n_admit;
             for (int y = 0; y < kXcd; ++y) {
                 sl.admit[y] = min(cap[y], left);
