@@ -84,6 +84,9 @@ __device__ __forceinline__ void st_row(Row* p, const Row& r) {
     for (int k = 0; k < 8; ++k) st_c(q + k, w[k]);
 }
 __device__ __forceinline__ int32_t clampi(int32_t v, int32_t hi) { return v < 0 ? 0 : (v >= hi ? hi - 1 : v); }
+// A value known to be the same in every lane, moved to a scalar register (so
+// that the addresses and loops it controls are scalar too).
+__device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // Explicit address spaces for the hot loops, which live in non-inlined
 // functions (where pointers are generic): log A is never written during a
@@ -705,14 +708,49 @@ __device__ __forceinline__ void wide_item(cargs_t& a, const float* __restrict__ 
         const Row& rr = L.rows[w];
         bpre = rr.log_b[(int64_t)rr.t * rr.ld + j];
     }
-    // predecessors [i_lo, i_hi) of this wave, whole groups of 16
+    // predecessors [i_lo, i_hi) of this wave, whole groups of 16 (wave-uniform,
+    // so that each log A row's base address is scalar)
     const int32_t ng = Kp / kGroup;
-    const int32_t i_lo = ((w * ng) / kEngWaves) * kGroup, i_hi = (((w + 1) * ng) / kEngWaves) * kGroup;
+    const int32_t i_lo = uni(((w * ng) / kEngWaves) * kGroup), i_hi = uni((((w + 1) * ng) / kEngWaves) * kGroup);
     float m[kWideRows];
     int32_t g[kWideRows];
 #pragma unroll
     for (int r = 0; r < kWideRows; ++r) { m[r] = -INFINITY; g[r] = i_lo / kGroup; }
     float* stage = L.area[w];
+    // log A rows i, lane column j: a scalar row base plus the lane's offset
+    const int32_t jc = min(j, Kp - 1);
+    if (R == 1) {
+        // a single row (a long root pass or a vanilla decode at large K): the
+        // step streams log A, so each lane keeps the loads of a whole stage
+        // (64 predecessors) in flight before its arithmetic
+        float m0 = -INFINITY;
+        int32_t g0 = i_lo / kGroup;
+        const Row& rr = L.rows[0];
+        const float* dp = slot_delta(a, clampi(rr.slot, a.n_slots), (rr.t - 1) & 1);
+        for (int32_t i0 = i_lo; i0 < i_hi; i0 += kWideStage) {
+            const int32_t n = min(kWideStage, i_hi - i0);   // a multiple of 16
+            float av[kWideStage];
+#pragma unroll
+            for (int k = 0; k < kWideStage; ++k)
+                av[k] = k < n ? (Ag + (int64_t)(i0 + k) * Kp)[jc] : -INFINITY;
+            if (lane < n) stage[lane] = coh ? ld_cg(dp + i0 + lane) : as_global(dp)[i0 + lane];
+#pragma unroll
+            for (int q = 0; q < kWideStage / kGroup; ++q) {
+                if (q * kGroup < n) {
+                    const float* sd = stage + q * kGroup;
+                    float gm = -INFINITY;
+#pragma unroll
+                    for (int k = 0; k < kGroup; k += 2)
+                        gm = fmaxf(fmaxf(gm, sd[k] + av[q * kGroup + k]), sd[k + 1] + av[q * kGroup + k + 1]);
+                    const int32_t gi = (i0 + q * kGroup) / kGroup;
+                    g0 = gm > m0 ? gi : g0;
+                    m0 = fmaxf(m0, gm);
+                }
+            }
+        }
+        m[0] = m0;
+        g[0] = g0;
+    } else
     for (int32_t i0 = i_lo; i0 < i_hi; i0 += kWideStage) {
         const int32_t n = min(kWideStage, i_hi - i0);   // a multiple of 16
 #pragma unroll
@@ -726,7 +764,7 @@ __device__ __forceinline__ void wide_item(cargs_t& a, const float* __restrict__ 
         for (int32_t k0 = 0; k0 < n; k0 += kGroup) {
             float av[kGroup];
 #pragma unroll
-            for (int k = 0; k < kGroup; ++k) av[k] = Ag[(int64_t)(i0 + k0 + k) * Kp + j];
+            for (int k = 0; k < kGroup; ++k) av[k] = (Ag + (int64_t)(i0 + k0 + k) * Kp)[jc];
             const int32_t gi = (i0 + k0) / kGroup;
 #pragma unroll
             for (int r = 0; r < kWideRows; ++r) {
@@ -735,7 +773,11 @@ __device__ __forceinline__ void wide_item(cargs_t& a, const float* __restrict__ 
                     float gm = -INFINITY;
 #pragma unroll
                     for (int k = 0; k < kGroup; k += 2) gm = fmaxf(fmaxf(gm, sd[k] + av[k]), sd[k + 1] + av[k + 1]);
-                    if (gm > m[r]) { m[r] = gm; g[r] = gi; }
+                    // the first group reaching the running maximum keeps it
+                    // (m may turn -0 into +0 at equal zeros; the refine takes
+                    // the winning candidate's own value)
+                    g[r] = gm > m[r] ? gi : g[r];
+                    m[r] = fmaxf(m[r], gm);
                 }
             }
         }
