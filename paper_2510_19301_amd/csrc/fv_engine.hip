@@ -148,7 +148,7 @@ __device__ __forceinline__ float gauss2d_score(const double* __restrict__ xy, co
 // addressing the observations (float64 [T][2]).  emit_kind is uniform.
 __device__ __forceinline__ float emission_of(int32_t kind, const double* xy, double c2, double c0,
                                              const float* __restrict__ lb, int64_t ld, int32_t t, int32_t j) {
-    if (kind == FV_EMIT_TABLE) return lb[(int64_t)t * ld + j];
+    if (kind == FV_EMIT_TABLE) return as_global(lb)[(int64_t)t * ld + j];
     return gauss2d_score(xy, reinterpret_cast<const double*>(lb), c2, c0, t, j);
 }
 __device__ __forceinline__ float emission(cargs_t& a, const float* lb, int64_t ld, int32_t t, int32_t j) {
@@ -706,16 +706,12 @@ __device__ __forceinline__ void wide_item(cargs_t& a, const float* __restrict__ 
     float bpre = 0.0f;
     if (w < R && j < K) {
         const Row& rr = L.rows[w];
-        bpre = rr.log_b[(int64_t)rr.t * rr.ld + j];
+        bpre = as_global(rr.log_b)[(int64_t)rr.t * rr.ld + j];
     }
     // predecessors [i_lo, i_hi) of this wave, whole groups of 16 (wave-uniform,
     // so that each log A row's base address is scalar)
     const int32_t ng = Kp / kGroup;
     const int32_t i_lo = uni(((w * ng) / kEngWaves) * kGroup), i_hi = uni((((w + 1) * ng) / kEngWaves) * kGroup);
-    float m[kWideRows];
-    int32_t g[kWideRows];
-#pragma unroll
-    for (int r = 0; r < kWideRows; ++r) { m[r] = -INFINITY; g[r] = i_lo / kGroup; }
     float* stage = L.area[w];
     // log A rows i, lane column j: a scalar row base plus the lane's offset
     const int32_t jc = min(j, Kp - 1);
@@ -743,28 +739,50 @@ __device__ __forceinline__ void wide_item(cargs_t& a, const float* __restrict__ 
                     for (int k = 0; k < kGroup; k += 2)
                         gm = fmaxf(fmaxf(gm, sd[k] + av[q * kGroup + k]), sd[k + 1] + av[q * kGroup + k + 1]);
                     const int32_t gi = (i0 + q * kGroup) / kGroup;
-                    g0 = gm > m0 ? gi : g0;
-                    m0 = fmaxf(m0, gm);
+                    const bool up = gm > m0;
+                    g0 = up ? gi : g0;
+                    m0 = up ? gm : m0;
                 }
             }
         }
-        m[0] = m0;
-        g[0] = g0;
-    } else
+        stage[lane] = m0;   // this wave's partial (its staging is done)
+        reinterpret_cast<int32_t*>(stage)[kWideRows * kWideCols + lane] = g0;
+    } else {
+    float m[kWideRows];
+    int32_t g[kWideRows];
+#pragma unroll
+    for (int r = 0; r < kWideRows; ++r) { m[r] = -INFINITY; g[r] = i_lo / kGroup; }
+    // the next group's log A values are loaded while the current group's
+    // arithmetic runs (one group ahead, across stage boundaries)
+    float an[kGroup];
+#pragma unroll
+    for (int k = 0; k < kGroup; ++k) an[k] = i_lo < i_hi ? (Ag + (int64_t)(i_lo + k) * Kp)[jc] : 0.0f;
     for (int32_t i0 = i_lo; i0 < i_hi; i0 += kWideStage) {
         const int32_t n = min(kWideStage, i_hi - i0);   // a multiple of 16
+        {
+            // all rows' loads in flight before one wait (rows past R re-read
+            // row 0, lanes past n their stage's first predecessor; neither
+            // slot is read)
+            const int32_t ic = i0 + (lane < n ? lane : 0);
+            float sv[kWideRows];
 #pragma unroll
-        for (int r = 0; r < kWideRows; ++r) {
-            if (r < R && lane < n) {
-                const Row& rr = L.rows[r];
+            for (int r = 0; r < kWideRows; ++r) {
+                const Row& rr = L.rows[r < R ? r : 0];
                 const float* dp = slot_delta(a, clampi(rr.slot, a.n_slots), (rr.t - 1) & 1);
-                stage[r * kWideStage + lane] = coh ? ld_cg(dp + i0 + lane) : as_global(dp)[i0 + lane];
+                sv[r] = coh ? ld_cg(dp + ic) : as_global(dp)[ic];
             }
+#pragma unroll
+            for (int r = 0; r < kWideRows; ++r) stage[r * kWideStage + lane] = sv[r];
         }
         for (int32_t k0 = 0; k0 < n; k0 += kGroup) {
             float av[kGroup];
 #pragma unroll
-            for (int k = 0; k < kGroup; ++k) av[k] = (Ag + (int64_t)(i0 + k0 + k) * Kp)[jc];
+            for (int k = 0; k < kGroup; ++k) av[k] = an[k];
+            const int32_t inext = uni(i0 + k0 + kGroup);
+            if (inext < i_hi) {
+#pragma unroll
+                for (int k = 0; k < kGroup; ++k) an[k] = (Ag + (int64_t)(inext + k) * Kp)[jc];
+            }
             const int32_t gi = (i0 + k0) / kGroup;
 #pragma unroll
             for (int r = 0; r < kWideRows; ++r) {
@@ -774,10 +792,10 @@ __device__ __forceinline__ void wide_item(cargs_t& a, const float* __restrict__ 
 #pragma unroll
                     for (int k = 0; k < kGroup; k += 2) gm = fmaxf(fmaxf(gm, sd[k] + av[k]), sd[k + 1] + av[k + 1]);
                     // the first group reaching the running maximum keeps it
-                    // (m may turn -0 into +0 at equal zeros; the refine takes
-                    // the winning candidate's own value)
-                    g[r] = gm > m[r] ? gi : g[r];
-                    m[r] = fmaxf(m[r], gm);
+                    // (a select, not a maximum: no quieting of m)
+                    const bool up = gm > m[r];
+                    g[r] = up ? gi : g[r];
+                    m[r] = up ? gm : m[r];
                 }
             }
         }
@@ -789,6 +807,7 @@ __device__ __forceinline__ void wide_item(cargs_t& a, const float* __restrict__ 
             stage[r * kWideCols + lane] = m[r];
             reinterpret_cast<int32_t*>(stage)[kWideRows * kWideCols + r * kWideCols + lane] = g[r];
         }
+    }
     }
     __syncthreads();
     unsigned long long key = 0;
@@ -897,7 +916,7 @@ __device__ __forceinline__ void col_item(cargs_t& a, const float* __restrict__ A
     float bpre = 0.0f;
     if (out_ok) {
         const Row& rr = L.rows[ro];
-        bpre = rr.log_b[(int64_t)rr.t * rr.ld + jo];
+        bpre = as_global(rr.log_b)[(int64_t)rr.t * rr.ld + jo];
     }
     __syncthreads();
     // predecessors [i_lo, i_hi) of this wave, whole groups of 16
@@ -1072,7 +1091,7 @@ __device__ __forceinline__ void slab_chunk(cargs_t& a, gfloat_t* Ag, const Row* 
     float bpre = 0.0f;
     if (out_ok) {
         const Row& rr = L.rows[ro];
-        bpre = rr.log_b[(int64_t)rr.t * rr.ld + jo];
+        bpre = as_global(rr.log_b)[(int64_t)rr.t * rr.ld + jo];
     }
     {
         constexpr int32_t q4 = KP / 4;
@@ -2265,12 +2284,11 @@ __device__ __noinline__ void leaf_end(cargs_t& a_in, const Row& r) {
         const int32_t n16 = (hi - lo + 1) * Kp / 8;      // Kp is a multiple of 64
         const uint4* src = reinterpret_cast<const uint4*>(tab + (int64_t)(lo - m) * Kp);
         for (int32_t k0 = tid; k0 < n16; k0 += kEngBlock * 8) {
+            // eight loads in flight per thread (indices past the chunk re-read
+            // its last entry, and are not stored)
             uint4 v[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int32_t k = k0 + u * kEngBlock;
-                if (k < n16) v[u] = src[k];
-            }
+            for (int u = 0; u < 8; ++u) v[u] = src[min(k0 + u * kEngBlock, n16 - 1)];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int32_t k = k0 + u * kEngBlock;
@@ -2343,63 +2361,106 @@ __device__ int32_t q_argmax_key(QBeamLds& L, unsigned long long key) {
 template <typename Out>
 __device__ int32_t q_select(QBeamLds& L, int32_t n, int32_t B, const float* v, const int32_t* s, int32_t s0,
                             const int32_t* an, Out out) {
-    const int tid = q_tid();
+    const int tid = q_tid(), lane = threadIdx.x & 63, wv = tid >> 6;
     const int32_t per = (n + kQThreads - 1) / kQThreads;
     const int32_t k0 = min(n, tid * per), k1 = min(n, k0 + per);
+    // finite entries, and the bits all their keys share (AND and OR of the keys)
     int32_t nfin = 0;
-    for (int32_t k = k0; k < k1; ++k) nfin += v[k] != -INFINITY;
-    int32_t n_finite;
-    q_exscan(nfin, &n_finite, L.wsum);
-    const bool all = n_finite <= B;
-    uint32_t kth = 0;
-    int32_t take_eq = 0;
-    if (!all) {
-        uint32_t prefix = 0, mask = 0;
-        int32_t rem = B;
-        for (int shift = 24; shift >= 0; shift -= 8) {
-            for (int k = tid; k < 256; k += kQThreads) L.hist[k] = 0;
-            q_sync();
-            for (int32_t k = k0; k < k1; ++k) {
-                const float x = v[k];
-                if (x == -INFINITY) continue;
-                const uint32_t u = score_key(x);
-                if ((u & mask) == prefix) atomicAdd(&L.hist[(u >> shift) & 255u], 1u);
-            }
-            q_sync();
-            if (tid < 64) {
-                int32_t c[4];
-#pragma unroll
-                for (int d = 0; d < 4; ++d) c[d] = (int32_t)L.hist[4 * tid + d];
-                const int32_t own = c[0] + c[1] + c[2] + c[3];
-                int32_t incl = own;   // sum over lanes >= tid
-#pragma unroll
-                for (int off = 1; off < 64; off <<= 1) {
-                    const int32_t y = __shfl_down(incl, off, 64);
-                    if (tid + off < 64) incl += y;
-                }
-                int32_t above = incl - own;
-                for (int d = 3; d >= 0; --d) {
-                    if (above < rem && above + c[d] >= rem) {
-                        L.misc[0] = 4 * tid + d;
-                        L.misc[1] = rem - above;
-                    }
-                    above += c[d];
-                }
-            }
-            q_sync();
-            prefix |= (uint32_t)L.misc[0] << shift;
-            mask |= 255u << shift;
-            rem = L.misc[1];
-            q_sync();
-        }
-        kth = prefix;
-        take_eq = rem;
+    uint32_t kand = 0xffffffffu, kor = 0u;
+    for (int32_t k = k0; k < k1; ++k) {
+        if (v[k] == -INFINITY) continue;
+        const uint32_t u = score_key(v[k]);
+        ++nfin;
+        kand &= u;
+        kor |= u;
     }
-    int32_t neq = 0;
-    if (!all)
-        for (int32_t k = k0; k < k1; ++k) neq += (v[k] != -INFINITY && score_key(v[k]) == kth);
-    int32_t dummy;
-    const int32_t eq_before = q_exscan(neq, &dummy, L.wsum);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        kand &= (uint32_t)__shfl_xor((int32_t)kand, off, 64);
+        kor |= (uint32_t)__shfl_xor((int32_t)kor, off, 64);
+    }
+    if (lane == 0) L.wkey[wv] = ((unsigned long long)kand << 32) | kor;
+    int32_t n_finite;
+    q_exscan(nfin, &n_finite, L.wsum);   // (its barriers also publish wkey)
+    const bool all = n_finite <= B;
+    // The threshold: radix passes of 8 bits over the keys, from the highest
+    // byte in which the finite keys differ (the bytes above are common, so
+    // their passes would keep every entry).  A pass whose chosen bin holds
+    // exactly the entries still needed ends the search: the whole bin is
+    // kept.  Otherwise the last pass leaves the exact B-th key, whose equal
+    // entries are taken in index order.
+    uint32_t prefix = 0, mask = 0;
+    int32_t rem = B;
+    bool exact = false;
+    if (!all) {
+        uint32_t gand = 0xffffffffu, gor = 0u;
+#pragma unroll
+        for (int u = 0; u < kQWaves; ++u) {
+            gand &= (uint32_t)(L.wkey[u] >> 32);
+            gor |= (uint32_t)L.wkey[u];
+        }
+        const uint32_t diff = gand ^ gor;
+        if (diff == 0u) {   // every finite key equal: the first B in index order
+            prefix = gor;
+            mask = 0xffffffffu;
+            exact = true;
+        } else {
+            const int32_t hb = 31 - __builtin_clz(diff);
+            const int32_t sh0 = (hb >> 3) << 3;
+            mask = sh0 >= 24 ? 0u : ~((1u << (sh0 + 8)) - 1u);
+            prefix = gor & mask;
+            for (int shift = sh0; shift >= 0; shift -= 8) {
+                for (int k = tid; k < 256; k += kQThreads) L.hist[k] = 0;
+                q_sync();
+                for (int32_t k = k0; k < k1; ++k) {
+                    const float x = v[k];
+                    if (x == -INFINITY) continue;
+                    const uint32_t u = score_key(x);
+                    if ((u & mask) == prefix) atomicAdd(&L.hist[(u >> shift) & 255u], 1u);
+                }
+                q_sync();
+                if (tid < 64) {
+                    int32_t c[4];
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) c[d] = (int32_t)L.hist[4 * tid + d];
+                    const int32_t own = c[0] + c[1] + c[2] + c[3];
+                    int32_t incl = own;   // sum over lanes >= tid
+#pragma unroll
+                    for (int off = 1; off < 64; off <<= 1) {
+                        const int32_t y = __shfl_down(incl, off, 64);
+                        if (tid + off < 64) incl += y;
+                    }
+                    int32_t above = incl - own;
+                    for (int d = 3; d >= 0; --d) {
+                        if (above < rem && above + c[d] >= rem) {
+                            L.misc[0] = 4 * tid + d;
+                            L.misc[1] = rem - above;
+                            L.misc[2] = c[d];
+                        }
+                        above += c[d];
+                    }
+                }
+                q_sync();
+                prefix |= (uint32_t)L.misc[0] << shift;
+                mask |= 255u << shift;
+                rem = L.misc[1];
+                const int32_t cbin = L.misc[2];
+                q_sync();
+                if (cbin == rem) break;      // the whole bin is kept (group-uniform)
+                if (shift == 0) exact = true;
+            }
+        }
+    }
+    // keep: everything (all), a masked key at or above the threshold's bits
+    // (a search ended on a whole bin), or a key above the exact threshold
+    // plus its first rem equal entries in index order
+    int32_t eq_before = 0;
+    if (exact) {
+        int32_t neq = 0;
+        for (int32_t k = k0; k < k1; ++k) neq += (v[k] != -INFINITY && score_key(v[k]) == prefix);
+        int32_t dummy;
+        eq_before = q_exscan(neq, &dummy, L.wsum);
+    }
     int32_t nsel = 0;
     {
         int32_t r = eq_before;
@@ -2407,8 +2468,8 @@ __device__ int32_t q_select(QBeamLds& L, int32_t n, int32_t B, const float* v, c
             const float x = v[k];
             if (x == -INFINITY) continue;
             const uint32_t u = score_key(x);
-            bool keep = all || u > kth;
-            if (!all && u == kth) keep = r++ < take_eq;
+            bool keep = all || (!exact && (u & mask) >= prefix) || (exact && u > prefix);
+            if (exact && u == prefix) keep = r++ < rem;
             nsel += keep;
         }
     }
@@ -2420,8 +2481,8 @@ __device__ int32_t q_select(QBeamLds& L, int32_t n, int32_t B, const float* v, c
             const float x = v[k];
             if (x == -INFINITY) continue;
             const uint32_t u = score_key(x);
-            bool keep = all || u > kth;
-            if (!all && u == kth) keep = r++ < take_eq;
+            bool keep = all || (!exact && (u & mask) >= prefix) || (exact && u > prefix);
+            if (exact && u == prefix) keep = r++ < rem;
             if (keep) { out(p, s ? s[k] : s0 + k, x, an[k]); ++p; }
         }
     }
@@ -2435,6 +2496,17 @@ __device__ int32_t q_rebuild(cargs_t& a, QBeamLds& L, int32_t slot, int32_t pari
     const int32_t B = a.B, K = a.K;
     const BeamRec rp = slot_part(a, slot, parity, 0);
     const int32_t np = clampi(rp.hdr[0], B + 1);
+    if (np <= B) {
+        // a record of this group's kind is already the beam: at most B finite
+        // entries in state order (the selection that wrote it dropped -inf)
+        for (int32_t k = tid; k < np; k += kQThreads) {
+            L.bs[k] = clampi(rp.s[k], K);
+            L.bv[k] = rp.v[k];
+            L.ba[k] = rp.a[k];
+        }
+        q_sync();
+        return np;
+    }
     for (int32_t k = tid; k < np; k += kQThreads) {
         L.cs[k] = clampi(rp.s[k], K);
         L.cv[k] = rp.v[k];
@@ -2557,28 +2629,45 @@ __device__ __noinline__ void beam_row_q(cargs_t& a_in, const Row& r) {
         } else {
             mode = t == tmid + 1 ? 1 : (t > tmid + 1 ? 2 : 0);
         }
-        const float* bt = r.log_b + (int64_t)t * r.ld;
-        for (int32_t j = tid; j < K; j += kQThreads) {
-            float c = -INFINITY;
-            int32_t w = -1;
+        gfloat_t* bt = as_global(r.log_b) + (int64_t)t * r.ld;
+        // four destinations per thread (j0 + 256 jj): the loads of 16 beam
+        // states for all four are in flight together
+        constexpr int32_t kJ = 4;
+        for (int32_t j0 = tid; j0 < K; j0 += kQThreads * kJ) {
+            float c[kJ];
+            int32_t w[kJ], jc[kJ];
+#pragma unroll
+            for (int jj = 0; jj < kJ; ++jj) { c[jj] = -INFINITY; w[jj] = -1; jc[jj] = min(j0 + kQThreads * jj, K - 1); }
             for (int32_t b0 = 0; b0 < nb; b0 += 16) {
-                float av[16];
+                float av[kJ][16];
 #pragma unroll
                 for (int u = 0; u < 16; ++u) {
                     const int32_t sb = __builtin_amdgcn_readfirstlane(L.bs[min(b0 + u, nb - 1)]);
-                    av[u] = Ag[(int64_t)sb * Kp + j];
+                    gfloat_t* row = Ag + (int64_t)sb * Kp;
+#pragma unroll
+                    for (int jj = 0; jj < kJ; ++jj) av[jj][u] = row[jc[jj]];
                 }
 #pragma unroll
                 for (int u = 0; u < 16; ++u) {
                     if (b0 + u < nb) {
-                        const float x = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
-                                            __builtin_bit_cast(int32_t, L.bv[b0 + u]))) + av[u];
-                        if (w < 0 || x > c) { c = x; w = b0 + u; }
+                        const float bvu = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
+                                              __builtin_bit_cast(int32_t, L.bv[b0 + u])));
+#pragma unroll
+                        for (int jj = 0; jj < kJ; ++jj) {
+                            const float x = bvu + av[jj][u];
+                            if (w[jj] < 0 || x > c[jj]) { c[jj] = x; w[jj] = b0 + u; }
+                        }
                     }
                 }
             }
-            L.sc[j] = w < 0 ? -INFINITY : c + bt[j];
-            L.an[j] = w < 0 ? -1 : (mode == 1 ? L.bs[w] : (mode == 2 ? L.ba[w] : -1));
+#pragma unroll
+            for (int jj = 0; jj < kJ; ++jj) {
+                const int32_t j = j0 + kQThreads * jj;
+                if (j < K) {
+                    L.sc[j] = w[jj] < 0 ? -INFINITY : c[jj] + bt[j];
+                    L.an[j] = w[jj] < 0 ? -1 : (mode == 1 ? L.bs[w[jj]] : (mode == 2 ? L.ba[w[jj]] : -1));
+                }
+            }
         }
         q_sync();
         const BeamRec out = slot_part(a, slot, t & 1, 0);
@@ -3136,9 +3225,9 @@ __device__ __forceinline__ void run_wide(cargs_t& a_in, int cur) {
     base[0] = 0;
     for (int y = 0; y < kXcd; ++y) {
         nf[y] = ld_c(&a.st->cnt[cur][y][0]);
-        base[y + 1] = base[y] + ((nf[y] + kWideRows - 1) / kWideRows) * nch;
+        base[y + 1] = base[y] + (nf[y] + kWideRows - 1) / kWideRows;
     }
-    const int32_t total = base[kXcd];
+    const int32_t ngrp = base[kXcd], total = ngrp * nch;
     int32_t item = blockIdx.x >= 1 ? (int32_t)blockIdx.x - 1 : -1;
     for (;;) {
         if (item < 0) {
@@ -3150,10 +3239,12 @@ __device__ __forceinline__ void run_wide(cargs_t& a_in, int cur) {
             __syncthreads();
         }
         if (item >= total) break;
+        // chunk-major: the row groups of one column chunk are consecutive
+        // items, taken at about the same time, so they share its log A reads
+        const int32_t chunk = item / ngrp, gq = item - chunk * ngrp;
         int y = 0;
-        while (item >= base[y + 1]) ++y;
-        const int32_t rem = item - base[y];
-        wide_item(a, Ap, list_full(a, cur, y), nf[y], rem / nch, rem % nch, 1);
+        while (gq >= base[y + 1]) ++y;
+        wide_item(a, Ap, list_full(a, cur, y), nf[y], gq - base[y], chunk, 1);
         item = -1;
     }
 }
@@ -3207,7 +3298,7 @@ __device__ __forceinline__ void local_col_items(cargs_t& a_in, uint32_t x, int32
             const int32_t r1 = spread ? ((gq + 1) * nf) / ngrp : min(nf, r0 + kColRows);
             col_item(a, Ap, Fl, r0, r1 - r0, item - gq * nch);
         }
-        else wide_item(a, Ap, Fl, nf, item / nch, item % nch, 0);
+        else wide_item(a, Ap, Fl, nf, item % ngrp, item / ngrp, 0);   // chunk-major, as run_wide
         item = -1;
     }
 }
@@ -3546,7 +3637,7 @@ __device__ __forceinline__ void small_vanilla(cargs_t& a, SeqInfo& sq) {
     bool on[NJ];
 #pragma unroll
     for (int c = 0; c < NJ; ++c) on[c] = lane + 64 * c < K;
-    const float* lb = sq.log_b;
+    gfloat_t* lb = as_global(sq.log_b);
     const int64_t ld = sq.ld;
     float col[NJ][KMAX];
 #pragma unroll
@@ -3658,7 +3749,7 @@ __device__ __forceinline__ void small_vanilla_waves(const EngineArgs* __restrict
     const int32_t j = threadIdx.x;
     const int32_t K = a.K, T = sq.T;
     const bool on = j < K;
-    const float* lb = sq.log_b;
+    gfloat_t* lb = as_global(sq.log_b);
     const int64_t ld = sq.ld;
     float col[KMAX];
 #pragma unroll
@@ -3772,7 +3863,7 @@ struct SmallWave {
     bool on[NJ];
     float col[NJ][KMAX];
     float bq[NJ][kSmallPrefetch];
-    const float* lb;
+    gfloat_t* lb;
     int64_t ld;
 
     // emission scores of steps t0.. of a pass ending at n, kSmallPrefetch rows in flight
@@ -3819,7 +3910,7 @@ __device__ __forceinline__ void small_flash(cargs_t& a, SeqInfo& sq, uint16_t* l
     SmallWave<KMAX> w;
     w.lane = threadIdx.x;
     w.K = K;
-    w.lb = sq.log_b;
+    w.lb = as_global(sq.log_b);
     w.ld = sq.ld;
     const int32_t lane = w.lane;
 #pragma unroll
@@ -4046,7 +4137,7 @@ __device__ __forceinline__ void small_flash_waves(const EngineArgs* __restrict__
     const int32_t K = a.K, T = sq.T, pp = sq.pp;
     const int32_t j = threadIdx.x;
     const bool on = j < K;
-    const float* lb = sq.log_b;
+    gfloat_t* lb = as_global(sq.log_b);
     const int64_t ld = sq.ld;
     int32_t* path = sq.path;
     const int32_t leaf_max = a.leaf_len < kSmallLeafRows ? a.leaf_len : kSmallLeafRows;
