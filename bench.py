@@ -181,7 +181,10 @@ def large_runs(fv, torch, hmm, dev):
     lp = torch.from_numpy(wl.log_pi).to(dev)
     del wl
     res = {"workload": f"one sequence, dense K={K} (log A rows Dirichlet(0.05)), T={T}, log B ~ N(0,3^2)"}
-    for method, P, B in (("vanilla", 1, 0), ("flash", 16, 0), ("beam", 16, 16), ("beam", 16, 64), ("beam", 16, 256)):
+    # FLASH at several P: a larger P stores more division copies in the root
+    # pass and leaves fewer levels of subtasks (time against memory)
+    for method, P, B in (("vanilla", 1, 0), ("flash", 16, 0), ("flash", 64, 0), ("flash", 256, 0),
+                         ("beam", 16, 16), ("beam", 16, 64), ("beam", 16, 256)):
         fv.decode(la, lb, lp, method, P=P, B=B)   # warm-up (also sizes the workspace)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -197,9 +200,14 @@ def large_runs(fv, torch, hmm, dev):
             gbs = (T - 1) * K * K * 4 / (ms / 1e3) / 1e9
             entry["hbm_roofline"] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
                                      "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 3)}
-        res[key] = entry
         if method == "vanilla":
             ref = path.cpu().numpy().copy()
+            ref_score = score.cpu().numpy().copy()
+        elif method == "flash":   # exact: the same path and score bits as vanilla
+            entry["same_as_vanilla"] = bool((path.cpu().numpy() == ref).all() and
+                                            (score.cpu().numpy().reshape(-1).view("u4") ==
+                                             ref_score.reshape(-1).view("u4")).all())
+        res[key] = entry
         print(f"[bench] large {key}: {ms:.1f} ms", file=sys.stderr, flush=True)
     path, _, status = fv.decode(la, lb, lp, "flash", P=16, relative_init=True)
     d = int((path.cpu().numpy() != ref).sum())

@@ -1602,65 +1602,104 @@ template <typename Out>
 __device__ int32_t beam_select(int32_t n, int32_t B, const float* v, const int32_t* s, int32_t s0,
                                const int32_t* an, Out out) {
     BeamLds& L = g_lds.beam;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int32_t per = (n + kEngBlock - 1) / kEngBlock;
     const int32_t k0 = min(n, tid * per), k1 = min(n, k0 + per);
+    // finite entries, and the bits all their keys share (AND and OR of the keys)
     int32_t nfin = 0;
-    for (int32_t k = k0; k < k1; ++k) nfin += v[k] != -INFINITY;
-    int32_t n_finite;
-    block_exscan(nfin, &n_finite, L.wsum);
-    const bool all = n_finite <= B;
-    uint32_t kth = 0;
-    int32_t take_eq = 0;
-    if (!all) {
-        uint32_t prefix = 0, mask = 0;
-        int32_t rem = B;
-        for (int shift = 24; shift >= 0; shift -= 8) {
-            for (int k = tid; k < 256; k += kEngBlock) L.hist[k] = 0;
-            __syncthreads();
-            for (int32_t k = k0; k < k1; ++k) {
-                const float x = v[k];
-                if (x == -INFINITY) continue;
-                const uint32_t u = score_key(x);
-                if ((u & mask) == prefix) atomicAdd(&L.hist[(u >> shift) & 255u], 1u);
-            }
-            __syncthreads();
-            if (tid < 64) {
-                // lane l owns digits 4l..4l+3; find the digit where the count
-                // from the top reaches rem
-                int32_t c[4];
-#pragma unroll
-                for (int d = 0; d < 4; ++d) c[d] = (int32_t)L.hist[4 * tid + d];
-                const int32_t own = c[0] + c[1] + c[2] + c[3];
-                int32_t incl = own;  // sum over lanes >= tid
-#pragma unroll
-                for (int off = 1; off < 64; off <<= 1) {
-                    const int32_t y = __shfl_down(incl, off, 64);
-                    if (tid + off < 64) incl += y;
-                }
-                int32_t above = incl - own;
-                for (int d = 3; d >= 0; --d) {
-                    if (above < rem && above + c[d] >= rem) {
-                        L.misc[0] = 4 * tid + d;
-                        L.misc[1] = rem - above;
-                    }
-                    above += c[d];
-                }
-            }
-            __syncthreads();
-            prefix |= (uint32_t)L.misc[0] << shift;
-            mask |= 255u << shift;
-            rem = L.misc[1];
-            __syncthreads();
-        }
-        kth = prefix;
-        take_eq = rem;
+    uint32_t kand = 0xffffffffu, kor = 0u;
+    for (int32_t k = k0; k < k1; ++k) {
+        if (v[k] == -INFINITY) continue;
+        const uint32_t u = score_key(v[k]);
+        ++nfin;
+        kand &= u;
+        kor |= u;
     }
-    int32_t neq = 0;
-    if (!all)
-        for (int32_t k = k0; k < k1; ++k) neq += (v[k] != -INFINITY && score_key(v[k]) == kth);
-    int32_t dummy;
-    const int32_t eq_before = block_exscan(neq, &dummy, L.wsum);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        kand &= (uint32_t)__shfl_xor((int32_t)kand, off, 64);
+        kor |= (uint32_t)__shfl_xor((int32_t)kor, off, 64);
+    }
+    if (lane == 0) L.wkey[wv] = ((unsigned long long)kand << 32) | kor;
+    int32_t n_finite;
+    block_exscan(nfin, &n_finite, L.wsum);   // (its barriers also publish wkey)
+    const bool all = n_finite <= B;
+    // The threshold: radix passes of 8 bits from the highest byte in which
+    // the finite keys differ; a pass whose chosen bin holds exactly the
+    // entries still needed ends the search (the whole bin is kept), else the
+    // last pass leaves the exact B-th key, whose equal entries are taken in
+    // index order (the same set as the full four passes).
+    uint32_t prefix = 0, mask = 0;
+    int32_t rem = B;
+    bool exact = false;
+    if (!all) {
+        uint32_t gand = 0xffffffffu, gor = 0u;
+#pragma unroll
+        for (int u = 0; u < kEngWaves; ++u) {
+            gand &= (uint32_t)(L.wkey[u] >> 32);
+            gor |= (uint32_t)L.wkey[u];
+        }
+        const uint32_t diff = gand ^ gor;
+        if (diff == 0u) {   // every finite key equal: the first B in index order
+            prefix = gor;
+            mask = 0xffffffffu;
+            exact = true;
+        } else {
+            const int32_t hb = 31 - __builtin_clz(diff);
+            const int32_t sh0 = (hb >> 3) << 3;
+            mask = sh0 >= 24 ? 0u : ~((1u << (sh0 + 8)) - 1u);
+            prefix = gor & mask;
+            for (int shift = sh0; shift >= 0; shift -= 8) {
+                for (int k = tid; k < 256; k += kEngBlock) L.hist[k] = 0;
+                __syncthreads();
+                for (int32_t k = k0; k < k1; ++k) {
+                    const float x = v[k];
+                    if (x == -INFINITY) continue;
+                    const uint32_t u = score_key(x);
+                    if ((u & mask) == prefix) atomicAdd(&L.hist[(u >> shift) & 255u], 1u);
+                }
+                __syncthreads();
+                if (tid < 64) {
+                    // lane l owns digits 4l..4l+3; find the digit where the
+                    // count from the top reaches rem
+                    int32_t c[4];
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) c[d] = (int32_t)L.hist[4 * tid + d];
+                    const int32_t own = c[0] + c[1] + c[2] + c[3];
+                    int32_t incl = own;  // sum over lanes >= tid
+#pragma unroll
+                    for (int off = 1; off < 64; off <<= 1) {
+                        const int32_t y = __shfl_down(incl, off, 64);
+                        if (tid + off < 64) incl += y;
+                    }
+                    int32_t above = incl - own;
+                    for (int d = 3; d >= 0; --d) {
+                        if (above < rem && above + c[d] >= rem) {
+                            L.misc[0] = 4 * tid + d;
+                            L.misc[1] = rem - above;
+                            L.misc[2] = c[d];
+                        }
+                        above += c[d];
+                    }
+                }
+                __syncthreads();
+                prefix |= (uint32_t)L.misc[0] << shift;
+                mask |= 255u << shift;
+                rem = L.misc[1];
+                const int32_t cbin = L.misc[2];
+                __syncthreads();
+                if (cbin == rem) break;      // the whole bin is kept (block-uniform)
+                if (shift == 0) exact = true;
+            }
+        }
+    }
+    int32_t eq_before = 0;
+    if (exact) {
+        int32_t neq = 0;
+        for (int32_t k = k0; k < k1; ++k) neq += (v[k] != -INFINITY && score_key(v[k]) == prefix);
+        int32_t dummy;
+        eq_before = block_exscan(neq, &dummy, L.wsum);
+    }
     int32_t nsel = 0;
     {
         int32_t r = eq_before;
@@ -1668,8 +1707,8 @@ __device__ int32_t beam_select(int32_t n, int32_t B, const float* v, const int32
             const float x = v[k];
             if (x == -INFINITY) continue;
             const uint32_t u = score_key(x);
-            bool keep = all || u > kth;
-            if (!all && u == kth) keep = r++ < take_eq;
+            bool keep = all || (!exact && (u & mask) >= prefix) || (exact && u > prefix);
+            if (exact && u == prefix) keep = r++ < rem;
             nsel += keep;
         }
     }
@@ -1681,8 +1720,8 @@ __device__ int32_t beam_select(int32_t n, int32_t B, const float* v, const int32
             const float x = v[k];
             if (x == -INFINITY) continue;
             const uint32_t u = score_key(x);
-            bool keep = all || u > kth;
-            if (!all && u == kth) keep = r++ < take_eq;
+            bool keep = all || (!exact && (u & mask) >= prefix) || (exact && u > prefix);
+            if (exact && u == prefix) keep = r++ < rem;
             if (keep) { out(p, s ? s[k] : s0 + k, x, an[k]); ++p; }
         }
     }
