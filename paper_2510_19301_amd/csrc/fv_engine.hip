@@ -3569,12 +3569,14 @@ __device__ __noinline__ void engine_model(cargs_t& a_in) {
         unsigned long long* tr = (a.trace && s < a.trace_steps) ? a.trace + (int64_t)s * kTraceWords : nullptr;
         if (tr && is_sched && threadIdx.x == 0) {
             tr[TR_START] = __builtin_amdgcn_s_memrealtime();
+            int32_t c[kXcd][3];   // every load issued before the sums
+#pragma unroll
+            for (int y = 0; y < kXcd; ++y)
+#pragma unroll
+                for (int q = 0; q < 3; ++q) c[y][q] = ld_c(&a.st->cnt[cur][y][q]);
             int32_t nf = 0, nl = 0, nb = 0;
-            for (int y = 0; y < kXcd; ++y) {
-                nf += ld_c(&a.st->cnt[cur][y][0]);
-                nl += ld_c(&a.st->cnt[cur][y][1]);
-                nb += ld_c(&a.st->cnt[cur][y][2]);
-            }
+#pragma unroll
+            for (int y = 0; y < kXcd; ++y) { nf += c[y][0]; nl += c[y][1]; nb += c[y][2]; }
             tr[TR_ROWS] = (unsigned long long)nf | ((unsigned long long)nl << 21) | ((unsigned long long)nb << 42);
         }
         if (is_sched) scheduler(a, s, epoch + 1);
