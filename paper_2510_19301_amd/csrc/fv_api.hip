@@ -247,11 +247,12 @@ fv_status plan_dense(int32_t method, const fv_trans* A, const int32_t* T_host, i
     L.slot_floats = (int64_t)L.Kp * (method == FV_VANILLA ? 2 : 5);
     L.leaf_off = 5 * (int64_t)L.Kp;
     if (L.leaves) L.slot_floats += (int64_t)L.leaf_len * L.Kp / 2;
-    // FLASH above the leaf limit on wide rows (the default placement there):
-    // w-way subtasks, their division copies (kWSplit - 1 delta rows and
-    // kWSplit - 2 link rows) in each slot
-    L.wsplit = (method == FV_FLASH && !sparse && L.Kp > kLeafMaxKp && use_wide_rows(0, K, n_seqs, sparse)) ? kWSplit
-                                                                                                          : 0;
+    // FLASH without leaf tables (dense above the leaf limit on wide rows, the
+    // default placement there; sparse models): w-way subtasks, their
+    // division copies (kWSplit - 1 delta rows and kWSplit - 2 link rows) in
+    // each slot
+    L.wsplit = (method == FV_FLASH &&
+                (sparse || (L.Kp > kLeafMaxKp && use_wide_rows(0, K, n_seqs, sparse)))) ? kWSplit : 0;
     if (L.wsplit) {
         L.div_off = L.slot_floats;
         L.slot_floats += (int64_t)(2 * kWSplit - 3) * L.Kp;
@@ -636,10 +637,11 @@ fv_status run_batch(int32_t method, const fv_trans* models, const float* const* 
         a.leaf_len = (L.leaves && !a.wide && !(flags & (FV_FLAG_NO_LEAVES | FV_FLAG_RELATIVE_INIT))) ? L.leaf_len
                                                                                                       : 0;
         a.relative_init = (flags & FV_FLAG_RELATIVE_INIT) ? 1 : 0;
-        // w-way subtasks on wide rows only; the paper's bisection under
+        // w-way subtasks on wide rows and sparse rows; the paper's bisection under
         // FV_FLAG_NO_LEAVES, and under the relative start (whose result
         // depends on the schedule)
-        a.wsplit = (L.wsplit && wide && !(flags & (FV_FLAG_NO_LEAVES | FV_FLAG_RELATIVE_INIT))) ? L.wsplit : 0;
+        a.wsplit = (L.wsplit && (wide || sparse) && !(flags & (FV_FLAG_NO_LEAVES | FV_FLAG_RELATIVE_INIT))) ? L.wsplit
+                                                                                                           : 0;
         a.div_off = L.div_off;
         a.beam_q = (meth == FV_BEAM && !sparse && L.bw == 1 && L.Kp <= 2048 && L.B <= 256) ? 1 : 0;
         a.leaf_off = L.leaf_off;

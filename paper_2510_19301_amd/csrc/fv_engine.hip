@@ -1337,6 +1337,10 @@ __device__ __noinline__ void sparse_unit(cargs_t& a_in, const Row* list, int32_t
             root_dsnap(a, r.off, r.aux)[j] = dnew;
             if (r.aux >= 1) root_link(a, r.off, r.pp, r.aux)[j] = anc;
         }
+        if (f & F_SNAP_DIV) {   // a division of a w-way subtask
+            slot_div_d(a, slot, r.aux)[j] = dnew;
+            if (r.aux >= 1) slot_div_l(a, slot, r.aux)[j] = anc;
+        }
         if (f & F_FINAL) key = order_key(dnew, j);
     }
     if (f & F_FINAL) {   // wave-uniform
@@ -3536,6 +3540,14 @@ __device__ __noinline__ void engine_model(cargs_t& a_in) {
             for (int y = 0; y < kXcd; ++y) {
                 sl.n_free[y] = a.pool;
                 sl.nblk[y] = (int32_t)ld_c(&a.st->xcd_blocks[y][0]);
+                if (a.slab) {
+                    // an XCD whose compute blocks do not divide evenly over
+                    // the column passes (the scheduler's: 31) splits its
+                    // units across passes, and some blocks load two slabs:
+                    // it is admitted rows as if it had 4 blocks fewer
+                    const int32_t npass = a.Kp / ((kEngWaves / (a.Kp / 64)) * 64);
+                    if (sl.nblk[y] % npass != 0) sl.nblk[y] = max(1, sl.nblk[y] - 4);
+                }
                 for (int k = 0; k < 3; ++k) sl.n_next[y][k] = 0;
             }
         }

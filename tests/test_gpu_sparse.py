@@ -40,23 +40,25 @@ def _model(fv, row_ptr, col, val):
                        _dev(np.asarray(val, np.float32)))
 
 
-def _run(fv, model, lp, lb, method, P=16, B=0):
-    path, score, status = fv.decode(model, _dev(lb), _dev(lp), method=method, P=P, B=B)
+def _run(fv, model, lp, lb, method, P=16, B=0, leaves=True):
+    path, score, status = fv.decode(model, _dev(lb), _dev(lp), method=method, P=P, B=B, leaves=leaves)
     torch.cuda.synchronize()
     return path.cpu().numpy(), score.cpu().numpy(), int(status.cpu()[0])
 
 
 def _check_exact(fv, inst, tag, Ps=(1, 2, 5, 16)):
+    """Vanilla, FLASH at each P (subtasks split 8 ways) and FLASH with
+    FV_FLAG_NO_LEAVES (Alg. 1's bisection) against the oracle."""
     lp, rp, col, val, lb = inst
     print(tag, flush=True)
     po, so, rc = oracle.vanilla_csr(lp, rp, col, val, lb)
     model = _model(fv, rp, col, val)
-    runs = [("vanilla", 1)] + [("flash", P) for P in Ps]
-    for method, P in runs:
-        p, s, st = _run(fv, model, lp, lb, method, P)
-        assert st == rc, (method, P, st, rc)
-        assert (p == po).all(), (method, P, np.flatnonzero(p != po)[:10])
-        assert (_bits(s) == _bits(so)).all(), (method, P, s, so)
+    runs = [("vanilla", 1, True)] + [("flash", P, True) for P in Ps] + [("flash", Ps[-1], False)]
+    for method, P, leaves in runs:
+        p, s, st = _run(fv, model, lp, lb, method, P, leaves=leaves)
+        assert st == rc, (method, P, leaves, st, rc)
+        assert (p == po).all(), (method, P, leaves, np.flatnonzero(p != po)[:10])
+        assert (_bits(s) == _bits(so)).all(), (method, P, leaves, s, so)
 
 
 def _check_beam(fv, inst, B, P, tag):
