@@ -1094,13 +1094,27 @@ __device__ __forceinline__ void slab_chunk(cargs_t& a, gfloat_t* Ag, const Row* 
         bpre = as_global(rr.log_b)[(int64_t)rr.t * rr.ld + jo];
     }
     {
-        constexpr int32_t q4 = KP / 4;
-        for (int32_t q = tid; q < R * q4; q += kEngBlock) {
-            const int32_t r = q / q4, i = (q - r * q4) * 4;
-            const Row& rr = L.rows[r];
-            const float* dp = slot_delta(a, clampi(rr.slot, a.n_slots), (rr.t - 1) & 1);
-            *reinterpret_cast<float4*>(&L.d[r * KP + i]) = *reinterpret_cast<const float4*>(dp + i);
+        // the rows' previous scores go straight from memory to LDS (LDS DMA,
+        // 16 bytes per lane: a wave moves 1 KB of one row), so every load of
+        // the chunk is in flight at once and holds no registers
+        typedef __attribute__((address_space(1))) const void gvoid_t;
+        typedef __attribute__((address_space(3))) void lvoid_t;
+        constexpr int32_t q4 = KP / 4, nq = (kSlabChunkMax * q4 + kEngBlock - 1) / kEngBlock;
+        const int32_t qn = R * q4;   // a multiple of 64: a wave's 64 entries share one row
+#pragma unroll
+        for (int u = 0; u < nq; ++u) {
+            const int32_t qw = uni(u * kEngBlock + (tid & ~63));
+            if (qw < qn) {
+                const int32_t r = qw / q4, i0 = (qw - r * q4) * 4;
+                const Row& rr = L.rows[r];
+                const float* dp = slot_delta(a, clampi(rr.slot, a.n_slots), (rr.t - 1) & 1);
+                lvoid_t* dst = reinterpret_cast<lvoid_t*>(
+                    (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uintptr_t)&L.d[r * KP + i0]));
+                __builtin_amdgcn_global_load_lds(reinterpret_cast<gvoid_t*>(reinterpret_cast<uintptr_t>(dp + i0 + 4 * lane)),
+                                                 dst, 16, 0, 0);
+            }
         }
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     }
     __syncthreads();
     for (int32_t rc = 0; rc < R; ++rc) {
@@ -2538,14 +2552,19 @@ __device__ int32_t q_rebuild(cargs_t& a, QBeamLds& L, int32_t slot, int32_t pari
     const int tid = q_tid();
     const int32_t B = a.B, K = a.K;
     const BeamRec rp = slot_part(a, slot, parity, 0);
+    // the count and the first B entries are read together (B <= the group's
+    // threads; entries past the count are read but not used)
+    int32_t es = 0, ea = 0;
+    float ev = 0.0f;
+    if (tid < B) { es = rp.s[tid]; ev = rp.v[tid]; ea = rp.a[tid]; }
     const int32_t np = clampi(rp.hdr[0], B + 1);
     if (np <= B) {
         // a record of this group's kind is already the beam: at most B finite
         // entries in state order (the selection that wrote it dropped -inf)
-        for (int32_t k = tid; k < np; k += kQThreads) {
-            L.bs[k] = clampi(rp.s[k], K);
-            L.bv[k] = rp.v[k];
-            L.ba[k] = rp.a[k];
+        if (tid < np) {
+            L.bs[tid] = clampi(es, K);
+            L.bv[tid] = ev;
+            L.ba[tid] = ea;
         }
         q_sync();
         return np;
