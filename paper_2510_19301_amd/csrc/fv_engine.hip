@@ -61,6 +61,14 @@ template <typename T>
 __device__ __forceinline__ void st_c(T* p, T v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// st_c on a pointer known to address global memory: a global (not flat)
+// store, so waiting for LDS results does not also wait for it
+template <typename T>
+__device__ __forceinline__ void st_cg(T* p, T v) {
+    typedef __attribute__((address_space(1))) T gT;
+    __hip_atomic_store(reinterpret_cast<gT*>(reinterpret_cast<uint64_t>(p)), v, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
 __device__ __forceinline__ float ld_cf(const float* p) {
     return __uint_as_float(ld_c(reinterpret_cast<const uint32_t*>(p)));
 }
@@ -2195,10 +2203,12 @@ __device__ __noinline__ void beam_chain_walk(cargs_t& a_in, const Row& r, int32_
         }
         __syncthreads();
         if (tid == 0) {
+            int32_t* const path = sq.path;   // (registers: see leaf_end)
+            float* const alpha = a.alpha_at + sq.alpha_off;
             for (int32_t d = dhi; d >= dlo; --d) {
                 const int32_t* rec = buf + (d - dlo) * stride;
                 const int64_t e = seg_end(T, pp, d);
-                st_c(sq.path + e, q);
+                st_cg(path + e, q);
                 int32_t at = -1;
                 for (int32_t lo = 0, hi = rec[0]; lo < hi;) {
                     const int32_t mid = (lo + hi) >> 1;
@@ -2206,7 +2216,7 @@ __device__ __noinline__ void beam_chain_walk(cargs_t& a_in, const Row& r, int32_
                     if (sm == q) { at = mid; break; }
                     if (sm < q) lo = mid + 1; else hi = mid;
                 }
-                st_cf(a.alpha_at + sq.alpha_off + e, at >= 0 ? __int_as_float(rec[1 + B + at]) : __builtin_nanf(""));
+                st_cg(reinterpret_cast<uint32_t*>(alpha + e), at >= 0 ? (uint32_t)rec[1 + B + at] : 0x7fc00000u);
                 if (d >= 1) q = (at >= 0 && q >= 0 && q < K) ? rec[1 + 2 * B + at] : -1;
             }
             L.misc[6] = q;
@@ -2267,8 +2277,9 @@ __device__ __noinline__ void dense_finalize(cargs_t& a_in, const Row& r) {
     }
     if (K > kBufInts) {   // a link row does not fit in LDS: walk in global memory
         if (tid == 0) {
+            int32_t* const path = sq.path;   // (a register: see leaf_end)
             for (int32_t d = pp - 2; d >= 0; --d) {
-                st_c(sq.path + seg_end(T, pp, d), q);
+                st_cg(path + seg_end(T, pp, d), q);
                 const int32_t* lp = root_link(a, r.off, pp, d) + q;
                 if (d >= 1) q = clampi(coh ? ld_c(lp) : *lp, K);
             }
@@ -2287,8 +2298,9 @@ __device__ __noinline__ void dense_finalize(cargs_t& a_in, const Row& r) {
         }
         __syncthreads();
         if (tid == 0) {
+            int32_t* const path = sq.path;   // (a register: see leaf_end)
             for (int32_t d = dhi; d >= dlo; --d) {
-                st_c(sq.path + seg_end(T, pp, d), q);
+                st_cg(path + seg_end(T, pp, d), q);
                 if (d >= 1) q = clampi(buf[(d - dlo) * K + q], K);
             }
             sv[3] = q;
@@ -2354,10 +2366,14 @@ __device__ __noinline__ void leaf_end(cargs_t& a_in, const Row& r) {
         }
         __syncthreads();
         if (tid == 0) {
+            // the path pointer in a register: read from the sequence record
+            // inside the loop, it would be reloaded (and waited for) after
+            // every store, which might alias it
+            int32_t* const path = sq.path;
             const uint16_t* b16 = reinterpret_cast<const uint16_t*>(buf);
             for (int32_t t = hi; t >= lo; --t) {
                 q = clampi(b16[(int64_t)(t - lo) * Kp + q], K);
-                st_c(sq.path + t - 1, q);
+                st_cg(path + t - 1, q);
             }
             lv[1] = q;
         }
@@ -2613,10 +2629,12 @@ __device__ void q_chain_walk(cargs_t& a, QBeamLds& L, const Row& r, int32_t q) {
         }
         q_sync();
         if (tid == 0) {
+            int32_t* const path = sq.path;   // (registers: see leaf_end)
+            float* const alpha = a.alpha_at + sq.alpha_off;
             for (int32_t d = dhi; d >= dlo; --d) {
                 const int32_t* rec = buf + (d - dlo) * stride;
                 const int64_t e = seg_end(T, pp, d);
-                st_c(sq.path + e, q);
+                st_cg(path + e, q);
                 int32_t at = -1;
                 for (int32_t lo = 0, hi = rec[0]; lo < hi;) {
                     const int32_t mid = (lo + hi) >> 1;
@@ -2624,7 +2642,7 @@ __device__ void q_chain_walk(cargs_t& a, QBeamLds& L, const Row& r, int32_t q) {
                     if (sm == q) { at = mid; break; }
                     if (sm < q) lo = mid + 1; else hi = mid;
                 }
-                st_cf(a.alpha_at + sq.alpha_off + e, at >= 0 ? __int_as_float(rec[1 + B + at]) : __builtin_nanf(""));
+                st_cg(reinterpret_cast<uint32_t*>(alpha + e), at >= 0 ? (uint32_t)rec[1 + B + at] : 0x7fc00000u);
                 if (d >= 1) q = (at >= 0 && q >= 0 && q < K) ? rec[1 + 2 * B + at] : -1;
             }
             L.misc[6] = q;
