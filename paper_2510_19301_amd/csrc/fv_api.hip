@@ -271,6 +271,14 @@ fv_status plan_dense(int32_t method, const fv_trans* A, const int32_t* T_host, i
         const int64_t cap = std::max<int64_t>(256, std::min<int64_t>(4096, budget / slot_bytes));
         const int64_t tasks = L.leaves ? L.leaf_tasks : L.n_tasks;
         slots = std::min<int64_t>(tasks, std::max<int64_t>(std::min<int64_t>(nonempty, 1 << 16), cap));
+        if (L.wsplit) {
+            // w-way slots carry 2w - 3 division rows: keep the pool within
+            // three quarters of the backpointer table a vanilla decode of the
+            // same batch would hold (2 bytes per state and step), so that a
+            // small batch at large K does not need more memory than vanilla
+            const int64_t psi_bytes = L.sum_T * (int64_t)K * 2;
+            slots = std::min<int64_t>(slots, std::max<int64_t>(2 * kXcd, (psi_bytes / 4 * 3) / slot_bytes));
+        }
     }
     if (slots < 1) slots = 1;
     slots = round_up(slots, kXcd);  // equal slot pools, one per XCD
