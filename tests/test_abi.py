@@ -99,6 +99,17 @@ def test_decode_argument_errors_are_synchronous(fv):
     assert l.fv_last_error()
 
 
+def test_flash_memory_below_vanilla_at_large_k(fv):
+    """FLASH keeps O(P'K) state instead of the K x T backpointer table
+    (Sec. V-B): with w-way subtasks (dense K above the leaf limit) its slot
+    pool is capped below vanilla's table, so a long sequence needs less
+    memory than vanilla's decode."""
+    for T in (2000, 10000):
+        f = fv.workspace_bytes("flash", 16384, [T], 16, 0)
+        v = fv.workspace_bytes("vanilla", 16384, [T], 1, 0)
+        assert f < v, (T, f, v)
+
+
 def test_sparse_workspace_size(fv):
     d = fv
     fake = 4096
