@@ -3175,6 +3175,10 @@ __device__ __noinline__ void scheduler(cargs_t& a_in, int32_t s, uint32_t tag) {
 // for its stores to complete.  The acquire side is the agent-scope fence in
 // both cases: it invalidates the vector L1 (an L1-only invalidate does not
 // on this device) and leaves the XCD's L2 lines of device memory in place.
+// The go word of a step barrier: the epoch, with this bit set when the engine
+// has an error (so a waiting block learns it without another load).
+constexpr uint32_t kGoErr = 0x80000000u;
+
 __device__ __forceinline__ void step_release(bool wide) {
     if (wide) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -3197,16 +3201,17 @@ __device__ bool barrier_arrive_wait(cargs_t& a, uint32_t epoch, uint32_t x, unsi
         int64_t spins = 0;
         const unsigned long long want = (unsigned long long)(epoch & kTagMask);
         unsigned long long cw = 0;
+        uint32_t g = 0;
         for (;;) {
-            const uint32_t g = ld_c(&a.st->go[x][0]);
+            g = ld_c(&a.st->go[x][0]);
             cw = ld_c(&a.st->cntw[x][0]);
-            if (g >= epoch && (!with_counts || (cw >> kTagShift) == want)) break;
+            if ((g & ~kGoErr) >= epoch && (!with_counts || (cw >> kTagShift) == want)) break;
             __builtin_amdgcn_s_sleep(1);
             if (++spins > a.spin_limit) { st_c(&a.st->error, 1); err = 1; break; }
             if ((spins & 255) == 0 && ld_c(&a.st->error)) { err = 1; break; }
         }
         step_acquire(wide);
-        s_err = err || ld_c(&a.st->error) != 0;
+        s_err = err || (g & kGoErr) != 0;
         s_counts = cw;
     }
     __syncthreads();
@@ -3230,15 +3235,16 @@ __device__ __forceinline__ bool barrier_slab(cargs_t& a, uint32_t epoch, uint32_
         int64_t spins = 0;
         const unsigned long long want = (unsigned long long)(epoch & kTagMask);
         unsigned long long cw = 0;
+        uint32_t g = 0;
         for (;;) {   // until the counts word of the coming step is there
-            const uint32_t g = ld_c(&a.st->go[x][0]);
+            g = ld_c(&a.st->go[x][0]);
             cw = ld_c(&a.st->cntw[x][0]);
-            if ((cw >> kTagShift) == want) { open = g >= epoch; break; }
+            if ((cw >> kTagShift) == want) { open = (g & ~kGoErr) >= epoch; break; }
             __builtin_amdgcn_s_sleep(1);
             if (++spins > a.spin_limit) { st_c(&a.st->error, 1); err = 1; break; }
             if ((spins & 255) == 0 && ld_c(&a.st->error)) { err = 1; break; }
         }
-        s_err2 = err;
+        s_err2 = err || (open && (g & kGoErr) != 0);
         s_open2 = open;
         s_counts2 = cw;
     }
@@ -3251,14 +3257,15 @@ __device__ __forceinline__ bool barrier_slab(cargs_t& a, uint32_t epoch, uint32_
         int64_t spins = 0;
         if (!err && !s_open2) {
             for (;;) {   // until the barrier opens
-                if (ld_c(&a.st->go[x][0]) >= epoch) break;
+                const uint32_t g = ld_c(&a.st->go[x][0]);
+                if ((g & ~kGoErr) >= epoch) { err = (g & kGoErr) != 0; break; }
                 __builtin_amdgcn_s_sleep(1);
                 if (++spins > a.spin_limit) { st_c(&a.st->error, 1); err = 1; break; }
                 if ((spins & 255) == 0 && ld_c(&a.st->error)) { err = 1; break; }
             }
         }
         step_acquire(false);
-        s_err2 = err || ld_c(&a.st->error) != 0;
+        s_err2 = err;
     }
     __syncthreads();
     return s_err2 == 0;
@@ -3269,8 +3276,10 @@ __device__ bool barrier_master(cargs_t& a, uint32_t epoch) {
     __syncthreads();
     int64_t spins = 0;
     int err = 0;
+    uint32_t e_seen = 0;   // the error word, read with the arrivals (thread 0)
     for (;;) {
         int ok = 1;
+        if (threadIdx.x == 0) e_seen = ld_c(&a.st->error);
         for (int32_t b = 1 + threadIdx.x; b <= a.n_compute_blocks; b += kEngBlock)
             if (ld_c(a.arrive + b) < epoch) ok = 0;
         if (__syncthreads_and(ok)) break;
@@ -3281,15 +3290,17 @@ __device__ bool barrier_master(cargs_t& a, uint32_t epoch) {
         const bool wide = a.wide != 0;
         step_acquire(wide);
         step_release(wide);
+        s_err = err || e_seen != 0;
     }
     __syncthreads();
+    const int err_all = s_err;
     if (threadIdx.x < kXcd) {
         if (err) st_c(&a.st->error, 1);
-        st_c(&a.st->go[threadIdx.x][0], epoch);
+        // the error travels with the go word
+        st_c(&a.st->go[threadIdx.x][0], epoch | (err_all ? kGoErr : 0u));
     }
-    if (threadIdx.x == 0) s_err = err || ld_c(&a.st->error) != 0;
     __syncthreads();
-    return s_err == 0;
+    return err_all == 0;
 }
 
 // ---------------------------------------------------------------- engine
