@@ -3168,6 +3168,11 @@ __device__ __noinline__ void scheduler(cargs_t& a_in, int32_t s, uint32_t tag) {
 // per-block cache maintenance of the fences to 256 operations per step.
 // Spins are bounded; on overrun the error flag is raised and every block
 // leaves the step loop.
+
+// The go word of a step barrier: the epoch, with this bit set when the engine
+// has an error (so a waiting block learns it without another load).
+constexpr uint32_t kGoErr = 0x80000000u;
+
 // Step-barrier memory ordering.  With wide rows, plain stores of one XCD
 // are read by others: the agent-scope release writes the L2 back.
 // Otherwise every plain store is read on its own XCD (through its L2) and
@@ -3175,10 +3180,6 @@ __device__ __noinline__ void scheduler(cargs_t& a_in, int32_t s, uint32_t tag) {
 // for its stores to complete.  The acquire side is the agent-scope fence in
 // both cases: it invalidates the vector L1 (an L1-only invalidate does not
 // on this device) and leaves the XCD's L2 lines of device memory in place.
-// The go word of a step barrier: the epoch, with this bit set when the engine
-// has an error (so a waiting block learns it without another load).
-constexpr uint32_t kGoErr = 0x80000000u;
-
 __device__ __forceinline__ void step_release(bool wide) {
     if (wide) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
