@@ -463,8 +463,8 @@ def main():
                          "counter pass covers both kernels)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported on this build "
-              "(sequences shard across GPUs with no exchange; see the design notes)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the library decodes "
+              "on one GPU; sequences would shard across GPUs with no exchange between them)", file=sys.stderr)
         sys.exit(2)
 
     import torch

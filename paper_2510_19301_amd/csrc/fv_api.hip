@@ -785,7 +785,7 @@ const char* fv_status_str(fv_status s) {
     switch (s) {
         case FV_OK: return "FV_OK";
         case FV_E_INVALID_ARG: return "FV_E_INVALID_ARG: invalid argument";
-        case FV_E_UNSUPPORTED: return "FV_E_UNSUPPORTED: size or model kind beyond this build";
+        case FV_E_UNSUPPORTED: return "FV_E_UNSUPPORTED: size or model kind beyond the library's limits";
         case FV_E_WORKSPACE: return "FV_E_WORKSPACE: workspace too small";
         case FV_E_DEVICE: return "FV_E_DEVICE: HIP launch/runtime failure or engine watchdog";
         case FV_E_INFEASIBLE: return "FV_E_INFEASIBLE: best score is -inf";
