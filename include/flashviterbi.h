@@ -83,8 +83,11 @@ enum { FV_FLAG_VALIDATE = 1u << 2 };
  * workspace plans leaves, and sizes the row-buffer pool to the leaf-cut task
  * tree, when the default placement keeps rows on their XCD; with
  * FV_FLAG_WIDE_ROWS such a plan still decodes correctly, without leaves and
- * with subtasks waiting for row buffers.  FV_FLAG_NO_LEAVES bisects every
- * subtask down to the paper's minimum. */
+ * with subtasks waiting for row buffers.  Where there are no leaves (dense
+ * wide rows with K > 2048, and CSR models), a subtask is split into up to 8
+ * segments instead of two: the root's P'-way division rule applied over the
+ * subtask's own span (Sec. V-A), every division state resolved at its end.
+ * FV_FLAG_NO_LEAVES bisects every subtask down to the paper's minimum. */
 enum { FV_FLAG_NO_LEAVES = 1u << 3 };
 /* Subtask initialisation (Sec. V-B, pruning for parallel decoding).  By
  * default a subtask starting at m > 0 is anchored: its start scores are
@@ -182,7 +185,7 @@ fv_status fv_decode_flash(const fv_trans* A, const float* log_pi, const float* l
  * same kernels as fv_decode_flash, with the same result.  A decode needing
  * more scratch than the array holds (fv_workspace_size(FV_FLASH, ...) >
  * FV_NOALLOC_SCRATCH_BYTES; a K = 1024 sequence of T = 8000 at P = 64
- * needs about 86 MB, K = 4096 at T = 1000 about 142 MB) returns
+ * needs about 90 MB, K = 2048 at T = 4000 about 153 MB) returns
  * FV_E_WORKSPACE with a message.  Every call on one GPU
  * shares that GPU's array: calls that overlap on one GPU (other streams,
  * other host threads) race and give unspecified results; calls on one
