@@ -2710,22 +2710,24 @@ __device__ __noinline__ void beam_row_q(cargs_t& a_in, const Row& r) {
             mode = t == tmid + 1 ? 1 : (t > tmid + 1 ? 2 : 0);
         }
         gfloat_t* bt = as_global(r.log_b) + (int64_t)t * r.ld;
-        // four destinations per thread (j0 + 256 jj): the loads of 16 beam
-        // states for all four are in flight together
+        // four consecutive destinations per thread (j0 .. j0 + 3), read as
+        // one 16-byte load per beam state: Kp is a multiple of 64, so the
+        // load stays inside the (padded) row; the loads of 16 beam states are
+        // in flight together
         constexpr int32_t kJ = 4;
-        for (int32_t j0 = tid; j0 < K; j0 += kQThreads * kJ) {
+        typedef float v4f_t __attribute__((ext_vector_type(4), aligned(4)));
+        typedef __attribute__((address_space(1))) const v4f_t gv4f_t;
+        for (int32_t j0 = kJ * tid; j0 < K; j0 += kQThreads * kJ) {
             float c[kJ];
-            int32_t w[kJ], jc[kJ];
+            int32_t w[kJ];
 #pragma unroll
-            for (int jj = 0; jj < kJ; ++jj) { c[jj] = -INFINITY; w[jj] = -1; jc[jj] = min(j0 + kQThreads * jj, K - 1); }
+            for (int jj = 0; jj < kJ; ++jj) { c[jj] = -INFINITY; w[jj] = -1; }
             for (int32_t b0 = 0; b0 < nb; b0 += 16) {
-                float av[kJ][16];
+                v4f_t av[16];
 #pragma unroll
                 for (int u = 0; u < 16; ++u) {
                     const int32_t sb = __builtin_amdgcn_readfirstlane(L.bs[min(b0 + u, nb - 1)]);
-                    gfloat_t* row = Ag + (int64_t)sb * Kp;
-#pragma unroll
-                    for (int jj = 0; jj < kJ; ++jj) av[jj][u] = row[jc[jj]];
+                    av[u] = *reinterpret_cast<gv4f_t*>(Ag + (int64_t)sb * Kp + j0);
                 }
 #pragma unroll
                 for (int u = 0; u < 16; ++u) {
@@ -2734,7 +2736,7 @@ __device__ __noinline__ void beam_row_q(cargs_t& a_in, const Row& r) {
                                               __builtin_bit_cast(int32_t, L.bv[b0 + u])));
 #pragma unroll
                         for (int jj = 0; jj < kJ; ++jj) {
-                            const float x = bvu + av[jj][u];
+                            const float x = bvu + av[u][jj];
                             if (w[jj] < 0 || x > c[jj]) { c[jj] = x; w[jj] = b0 + u; }
                         }
                     }
@@ -2742,7 +2744,7 @@ __device__ __noinline__ void beam_row_q(cargs_t& a_in, const Row& r) {
             }
 #pragma unroll
             for (int jj = 0; jj < kJ; ++jj) {
-                const int32_t j = j0 + kQThreads * jj;
+                const int32_t j = j0 + jj;
                 if (j < K) {
                     L.sc[j] = w[jj] < 0 ? -INFINITY : c[jj] + bt[j];
                     L.an[j] = w[jj] < 0 ? -1 : (mode == 1 ? L.bs[w[jj]] : (mode == 2 ? L.ba[w[jj]] : -1));
